@@ -1,0 +1,261 @@
+"""Seeded synthetic inputs for the implicit grey FLD step.
+
+This module only builds input fields (opacity, emissivity, initial radiation
+energy) and step parameters.  It holds none of the solver's arithmetic: it
+neither evaluates the limiter nor assembles or solves anything.  Both the
+oracle-side tests and the GPU-side tests and benchmark draw their inputs here.
+
+Inputs stand in for the paper's cosmological fields (Norman et al. 2014,
+Sec. 5), which are not available: a smoothed lognormal neutral-hydrogen
+density, opacity kappa = sigma_HI n_HI for monochromatic 13.6 eV radiation
+(Sec. 4.1.1 sets the source at the HI ionization threshold), and point sources
+of Ndot ionizing photons per second deposited as eta = sum Ndot h nu / V_cell
+in the cell that holds them (Sec. 2.2 accumulates emissivity per cell).
+
+All lengths are cm, times s, energies erg (CGS).  Randomness comes from numpy
+PCG64 with base seed 1306 + workload index; problem i of a workload uses
+SeedSequence([base, i]).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+C_LIGHT = 2.99792458e10          # cm / s
+KPC = 3.0857e21                  # cm
+MYR = 3.156e13                   # s
+EV = 1.602176634e-12             # erg
+HNU_HI = 13.6 * EV               # erg, HI ionization threshold
+SIGMA_HI = 6.3e-18               # cm^2, HI cross-section at 13.6 eV
+ALPHA_B = 2.59e-13               # cm^3 / s, case-B recombination at 1e4 K
+DX_TEST1 = 6.6 * KPC / 32        # 206 pc: the 6.6 kpc Test-1 box on 32 cells
+
+BASE_SEED = 1306
+
+
+def rng_for(workload: int, problem: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(
+        np.random.SeedSequence([BASE_SEED + workload, problem])))
+
+
+def smooth_gaussian(shape, sigma_cells: float, rng) -> np.ndarray:
+    """White Gaussian noise smoothed by a periodic Gaussian kernel of
+    ``sigma_cells``, renormalised to zero mean and unit variance."""
+    g = rng.standard_normal(shape)
+    if sigma_cells > 0:
+        G = np.fft.rfftn(g, axes=(0, 1, 2))
+        kz = np.fft.fftfreq(shape[0])[:, None, None]
+        ky = np.fft.fftfreq(shape[1])[None, :, None]
+        kx = np.fft.rfftfreq(shape[2])[None, None, :]
+        k2 = (2 * np.pi) ** 2 * (kx * kx + ky * ky + kz * kz)
+        G *= np.exp(-0.5 * sigma_cells ** 2 * k2)
+        g = np.fft.irfftn(G, s=shape, axes=(0, 1, 2))
+        del G
+    g -= g.mean()
+    sd = g.std()
+    if sd > 0:
+        g /= sd
+    return g
+
+
+def lognormal(shape, mean_density: float, sigma_ln: float, rng,
+              smooth_cells: float = 1.5) -> np.ndarray:
+    """n = exp(ln(mean_density) + sigma_ln * g), g smoothed Gaussian noise."""
+    g = smooth_gaussian(shape, smooth_cells, rng)
+    return np.exp(math.log(mean_density) + sigma_ln * g)
+
+
+def point_sources(shape, n_src: int, lum_lo: float, lum_hi: float, rng):
+    """(linear cell indices, Ndot) for sources at uniform random cells with
+    log-uniform photon rates in [lum_lo, lum_hi]."""
+    n = int(np.prod(shape))
+    cells = rng.integers(0, n, size=n_src, dtype=np.int64)
+    ndot = np.exp(rng.uniform(math.log(lum_lo), math.log(lum_hi), size=n_src))
+    return cells, ndot
+
+
+def emissivity(shape, cells, ndot, cell_volume: float) -> np.ndarray:
+    """eta [erg cm^-3 s^-1]: photon rate times h nu per cell volume, summed
+    over all sources that share a cell."""
+    eta = np.zeros(int(np.prod(shape)))
+    np.add.at(eta, np.asarray(cells, dtype=np.int64),
+              np.asarray(ndot) * HNU_HI / cell_volume)
+    return eta.reshape(shape)
+
+
+def _problem(shape, dx, kappa, eta, E, L_unit, dt, name, theta=1.0):
+    return {
+        "name": name, "shape": tuple(shape), "h": (dx, dx, dx),
+        "E": np.ascontiguousarray(E, dtype=np.float64),
+        "kappa": np.ascontiguousarray(kappa, dtype=np.float64),
+        "eta": np.ascontiguousarray(eta, dtype=np.float64),
+        "c": C_LIGHT, "L_unit": L_unit, "dt": dt, "theta": theta,
+        "a": 1.0, "adot": 0.0,
+    }
+
+
+def smooth_radiation(shape, eta, dt, rng, sigma_cells=8.0):
+    """E^n = E0 exp(g), g smoothed at 8 cells, E0 = mean(eta) dt."""
+    g = smooth_gaussian(shape, sigma_cells, rng)
+    return float(np.mean(eta)) * dt * np.exp(g)
+
+
+def single_source(n: int = 32, sigma_ln: float = 1.0, seed_problem: int = 0):
+    """Workload 1: one FP64 step on n^3 (default 32^3) with a lognormal HI
+    field (mean 1e-3 cm^-3), E^n = 0 and one 5e48 photon/s source in the
+    centre cell; dt = 1e-3 light-crossing times of the box."""
+    rng = rng_for(1, seed_problem)
+    shape = (n, n, n)
+    dx = DX_TEST1
+    L = n * dx
+    nH = lognormal(shape, 1e-3, sigma_ln, rng)
+    kappa = SIGMA_HI * nH
+    centre = (n // 2 * n + n // 2) * n + n // 2
+    eta = emissivity(shape, [centre], [5e48], dx ** 3)
+    dt = 1e-3 * L / C_LIGHT
+    return _problem(shape, dx, kappa, eta, np.zeros(shape), L, dt,
+                    f"single_source_{n}")
+
+
+def many_sources(n: int = 256, sigma_ln: float = 1.5, n_src: int = 64,
+                 seed_problem: int = 0):
+    """Workload 2: n^3 (default 256^3), lognormal HI (sigma_ln 1.5), n_src
+    sources with Ndot log-uniform in [1e47, 1e50] at random cells, smooth
+    random E^n; dt = 1e-3 light-crossing times of the box."""
+    rng = rng_for(2, seed_problem)
+    shape = (n, n, n)
+    dx = DX_TEST1
+    L = n * dx
+    nH = lognormal(shape, 1e-3, sigma_ln, rng)
+    kappa = SIGMA_HI * nH
+    del nH
+    cells, ndot = point_sources(shape, n_src, 1e47, 1e50, rng)
+    eta = emissivity(shape, cells, ndot, dx ** 3)
+    dt = 1e-3 * L / C_LIGHT
+    E = smooth_radiation(shape, eta, dt, rng)
+    return _problem(shape, dx, kappa, eta, E, L, dt, f"many_sources_{n}")
+
+
+def stromgren_radius(ndot, n_h, alpha_b=ALPHA_B):
+    """r_s = (3 Ndot / (4 pi alpha_B n_H^2))^(1/3)  (Sec. 4.1.1)."""
+    return (3.0 * np.asarray(ndot) / (4.0 * math.pi * alpha_b * n_h * n_h)) ** (1.0 / 3.0)
+
+
+def reionization_share(n: int = 640, n_src: int = 10000, sigma_ln: float = 2.0,
+                       seed_problem: int = 0, L_cells: int = 3200):
+    """Workload 3: one 640^3 share of a 3200^3 reionization box at z = 8
+    (proper dx = 2.78 kpc), lognormal HI (mean 1.43e-4 cm^-3, sigma_ln 2.0),
+    n_src sources with Ndot log-uniform in [1e46, 1e49], ionized bubbles of
+    the Stromgren radius of each source (x_HI = 1e-4 inside), E^n = 1e-45,
+    L_unit = 3200 dx, dt = 1e-3 L_unit / c."""
+    rng = rng_for(3, seed_problem)
+    shape = (n, n, n)
+    dx = 25.0 * KPC / 9.0
+    nbar = 1.43e-4
+    nH = lognormal(shape, nbar, sigma_ln, rng)
+    cells, ndot = point_sources(shape, n_src, 1e46, 1e49, rng)
+    # carve bubbles: x_HI = 1e-4 within r_s of each source (periodic)
+    rs_cells = stromgren_radius(ndot, nbar) / dx
+    xhi = np.ones(shape, dtype=np.float64)
+    cz, rem = np.divmod(cells, n * n)
+    cy, cx = np.divmod(rem, n)
+    for x0, y0, z0, r in zip(cx, cy, cz, rs_cells):
+        ri = int(math.ceil(r))
+        if ri < 1:
+            continue
+        o = np.arange(-ri, ri + 1)
+        d2 = (o[:, None, None] ** 2 + o[None, :, None] ** 2
+              + o[None, None, :] ** 2)
+        mask = d2 <= r * r
+        iz = (z0 + o) % n
+        iy = (y0 + o) % n
+        ix = (x0 + o) % n
+        sub = xhi[np.ix_(iz, iy, ix)]
+        sub[mask] = 1e-4
+        xhi[np.ix_(iz, iy, ix)] = sub
+    kappa = SIGMA_HI * nH * xhi
+    del nH, xhi
+    eta = emissivity(shape, cells, ndot, dx ** 3)
+    L = L_cells * dx
+    dt = 1e-3 * L / C_LIGHT
+    E = np.full(shape, 1e-45)
+    return _problem(shape, dx, kappa, eta, E, L, dt, f"reionization_{n}")
+
+
+BATCH_SIZES = (32, 48, 64, 96, 128)
+
+
+def batch_problem(i: int, sizes=BATCH_SIZES, max_src: int = 32,
+                  workload: int = 4):
+    """Problem i of the batched workload: n uniform over ``sizes``, sigma_ln
+    uniform in [0.5, 2], 1..max_src sources, smooth random E^n."""
+    rng = rng_for(workload, i)
+    n = int(rng.choice(sizes))
+    sigma_ln = float(rng.uniform(0.5, 2.0))
+    n_src = int(rng.integers(1, max_src + 1))
+    shape = (n, n, n)
+    dx = DX_TEST1
+    L = n * dx
+    kappa = SIGMA_HI * lognormal(shape, 1e-3, sigma_ln, rng)
+    cells, ndot = point_sources(shape, n_src, 1e47, 1e50, rng)
+    eta = emissivity(shape, cells, ndot, dx ** 3)
+    dt = 1e-3 * L / C_LIGHT
+    E = smooth_radiation(shape, eta, dt, rng)
+    return _problem(shape, dx, kappa, eta, E, L, dt, f"batch_{i}_{n}")
+
+
+def serve_request_shape(i: int, lo: int = 64, hi: int = 384, multiple: int = 16):
+    """Grid size, step count and source count of request i of the served
+    stream: n log-uniform in [lo, hi] rounded to a multiple of 16, 1-5 steps,
+    1-1000 sources."""
+    rng = rng_for(5, i)
+    n = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi))) / multiple)) * multiple
+    n = max(lo, min(hi, n))
+    steps = int(rng.integers(1, 6))
+    n_src = int(rng.integers(1, 1001))
+    sigma_ln = float(rng.uniform(0.5, 2.0))
+    return n, steps, n_src, sigma_ln
+
+
+def serve_request(i: int, lo: int = 64, hi: int = 384, n_override=None):
+    n, steps, n_src, sigma_ln = serve_request_shape(i, lo, hi)
+    if n_override is not None:
+        n = n_override
+    rng = rng_for(5, 100000 + i)
+    shape = (n, n, n)
+    dx = DX_TEST1
+    L = n * dx
+    kappa = SIGMA_HI * lognormal(shape, 1e-3, sigma_ln, rng)
+    cells, ndot = point_sources(shape, n_src, 1e47, 1e50, rng)
+    eta = emissivity(shape, cells, ndot, dx ** 3)
+    dt = 1e-3 * L / C_LIGHT
+    E = smooth_radiation(shape, eta, dt, rng)
+    p = _problem(shape, dx, kappa, eta, E, L, dt, f"request_{i}_{n}")
+    p["steps"] = steps
+    return p
+
+
+def random_problem(shape, seed: int, sigma_ln: float = 1.0, n_src: int = 4,
+                   E_mode: str = "smooth", dx=DX_TEST1, dt_factor=1e-3,
+                   L_unit=None, theta=1.0, iid=False):
+    """General small test problem on an arbitrary (nz, ny, nx) shape.
+    ``dt_factor`` scales dt in light-crossing times of L_unit (default: the
+    largest box side); ``iid`` draws an unsmoothed per-cell lognormal."""
+    rng = rng_for(10, seed)
+    shape = tuple(int(s) for s in shape)
+    L = (L_unit if L_unit is not None else max(shape) * dx)
+    nH = (np.exp(math.log(1e-3) + sigma_ln * rng.standard_normal(shape)) if iid
+          else lognormal(shape, 1e-3, sigma_ln, rng))
+    kappa = SIGMA_HI * nH
+    cells, ndot = point_sources(shape, n_src, 1e47, 1e50, rng)
+    eta = emissivity(shape, cells, ndot, dx ** 3)
+    dt = dt_factor * L / C_LIGHT
+    if E_mode == "zero":
+        E = np.zeros(shape)
+    elif E_mode == "smooth":
+        E = smooth_radiation(shape, eta, dt, rng, sigma_cells=2.0)
+    else:
+        raise ValueError(E_mode)
+    return _problem(shape, dx, kappa, eta, E, L, dt, f"random_{shape}_{seed}",
+                    theta=theta)
