@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the implicit grey FLD step on one MI355X.
+
+Default workload: 256^3 periodic grid, lognormal HI opacity (sigma_ln 1.5),
+64 point sources (Ndot log-uniform 1e47-1e50), smooth random E^n, dt = 1e-3
+light-crossing times, successive timesteps with the limiter recomputed from
+the new E each step, PCG + geometric multigrid to a 1e-8 relative residual.
+A "step" is one full timestep: assembly of the limiter system and every
+multigrid level, the preconditioned CG solve, and E += dE.
+
+Prints ONE JSON line: Mcell-updates/s of the mixed-precision form (the FP64
+form is reported beside it), the roofline of the dominant kernel timed live
+with hipEvents, and the oracle's CPU throughput on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+# Algorithmic (compulsory) bytes per finest-level cell of one launch of each
+# finest-level kernel: every input array read once, every output written
+# once; neighbours and 1/8-size coarse arrays included where they are read.
+# (FP64 V-cycle, FP32 V-cycle)
+BYTES_PER_CELL = {
+    "assemble": (80.0, 96.0),
+    "spmv_p": (64.0, 64.0),
+    "update": (48.0, 48.0),
+    "pre0_fine": (48.0, 28.0),
+    "half_fine": (56.0, 32.0),
+    "half_out": (56.0, 44.0),
+    "resid_restrict_fine": (49.0, 28.5),
+    "prolong_black_fine": (57.0, 32.5),
+    "true_resid": (56.0, 56.0),
+    "update_E": (24.0, 24.0),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=256, help="grid extent")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--tile-z", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=0)
+    return ap.parse_args()
+
+
+def run_form(fld, torch, p, prec, steps, warmup, args):
+    prm = fld.fld_default_params(p["c"], p["L_unit"], precision=prec,
+                                 tile_z=args.tile_z, use_graph=args.graph)
+    S = fld.Solver(p["shape"], p["h"], prm)
+    E = torch.from_numpy(p["E"]).cuda()
+    kap = torch.from_numpy(p["kappa"]).cuda()
+    eta = torch.from_numpy(p["eta"]).cuda()
+    names = fld.profile_kernels()
+    # warmup; the last warmup step also surveys every kernel's time
+    warmup = max(2, warmup)
+    for w in range(warmup):
+        if w == warmup - 1:
+            fld.fld_profile_select(-2)
+        st = S.step(E, kap, eta, p["dt"])
+    torch.cuda.synchronize()
+    totals = {n: fld.fld_profile_read(k)[0] for k, n in enumerate(names)}
+    fld.fld_profile_select(-1)
+    dom = max((n for n in totals if n in BYTES_PER_CELL), key=lambda n: totals[n])
+    dom_id = names.index(dom)
+    # timed region: K steps; the dominant kernel is timed with hipEvents
+    fld.fld_profile_select(dom_id)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, rels = [], []
+    for _ in range(steps):
+        st = S.step(E, kap, eta, p["dt"])
+        iters.append(st["iters"])
+        rels.append(st["rel_resid"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_total, launches = fld.fld_profile_read(dom_id)
+    fld.fld_profile_select(-1)
+    S.close()
+    cells = p["E"].size
+    sec = t1 - t0
+    avg_ms = ms_total / max(launches, 1)
+    bpc = BYTES_PER_CELL[dom][1 if prec == fld.FLD_PREC_MIXED else 0]
+    achieved = bpc * cells / (avg_ms * 1e-3) / 1e9
+    return {
+        "mcell_updates_per_s": cells * steps / sec / 1e6,
+        "ms_per_step": 1e3 * sec / steps,
+        "iters_per_step": sum(iters) / len(iters),
+        "max_rel_resid": max(rels),
+        "survey_ms": {k: round(v, 4) for k, v in sorted(
+            totals.items(), key=lambda kv: -kv[1]) if v > 0},
+        "dominant": dom,
+        "dominant_avg_ms": avg_ms,
+        "dominant_launches": launches,
+        "dominant_GBps": achieved,
+        "dominant_bytes_per_cell": bpc,
+    }
+
+
+def cpu_baseline(p):
+    import oracle
+    dmax, rmin = oracle.limits(p["c"], p["L_unit"])
+    O = oracle.Problem(p["E"], p["kappa"], p["eta"], p["h"], p["c"], dmax, rmin,
+                       p["dt"], p["theta"], p["a"], p["adot"])
+    t0 = time.perf_counter()
+    _, st, it, rel = O.solve(tol=1e-8, max_iter=1000)
+    sec = time.perf_counter() - t0
+    return {"value": p["E"].size / sec / 1e6, "unit": "Mcell-updates/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"one {p['shape'][0]}^3 step (limiter assembly + Jacobi-PCG "
+                      f"to 1e-8, {it} iterations, {sec:.1f} s), single thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build "
+              "has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1306_0645_amd as fld
+    import synth
+
+    log(f"[bench] generating the {args.n}^3 many-source workload")
+    p = synth.many_sources(args.n)
+    forms = {}
+    for name in args.forms.split(","):
+        prec = fld.FLD_PREC_MIXED if name == "mixed" else fld.FLD_PREC_FP64
+        log(f"[bench] form {name}: {args.warmup} warmup + {args.steps} timed steps")
+        forms[name] = run_form(fld, torch, p, prec, args.steps, args.warmup, args)
+        log(f"[bench] {name}: {json.dumps(forms[name])}")
+    head = forms.get("mixed") or forms[list(forms)[0]]
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on one step")
+        cpu = cpu_baseline(p)
+    roof = {
+        "bound": "hbm",
+        "kernel": head["dominant"],
+        "achieved": round(head["dominant_GBps"], 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(head["dominant_GBps"] / HBM_PEAK_GBS, 4),
+        "traffic": None,
+    }
+    out = {
+        "metric": "FLD solve Mcell-updates/s + % HBM roofline at 1e-8 residual; "
+                  "p50/p99 solve latency",
+        "value": round(head["mcell_updates_per_s"], 2),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32" if "mixed" in forms else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"many_sources_{args.n}^3", "grid": [args.n] * 3,
+                   "sources": 64, "sigma_ln": 1.5, "rtol": 1e-8,
+                   "precision": "mixed" if "mixed" in forms else "fp64",
+                   "steps_per_run": args.steps},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                      for kk, vv in v.items()} for k, v in forms.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

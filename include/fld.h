@@ -1,0 +1,271 @@
+/*
+ * fld.h -- C-ABI of the MI355X implicit grey flux-limited-diffusion (FLD)
+ * radiation step (Norman et al., arXiv:1306.0645).
+ *
+ * The operation (Sec. 3.3, eq. "fld"): advance the comoving grey radiation
+ * energy density E over one step dt of
+ *
+ *     dE/dt = div(D grad E) - (adot/a) E - c kappa E + eta
+ *
+ * on a uniform periodic Cartesian mesh, with the flux limiter (Sec. 2)
+ *
+ *     D = min{ c (9 kbar^2 + R^2)^(-1/2), D_max },  R = max{ |dE/dn| / Ebar, R_min },
+ *
+ * evaluated on each cell face from E^n (lagged), Ebar the arithmetic and kbar
+ * the harmonic mean of the two cells that share the face.  Finite volumes give
+ * a 7-point operator L; the theta-method (theta = 1 backward Euler, 1/2
+ * trapezoidal) in residual-correction form gives one symmetric positive
+ * definite system per step,
+ *
+ *     (I - theta dt L) dE = dt (L E^n + eta),     E^{n+1} = E^n + dE,
+ *
+ * solved by conjugate gradients preconditioned with a geometric multigrid
+ * V-cycle with red/black Gauss-Seidel smoothing (Sec. 3.3, Table 1).  On a
+ * failed solve fld_step cuts the radiation step by 10x and subcycles up to the
+ * requested step (Sec. 3.4).
+ *
+ * Conventions for every entry point:
+ *  - Field pointers are DEVICE pointers to FP64 arrays of nx*ny*nz cells in
+ *    C order [nz][ny][nx] (x fastest), interior cells only; the periodic wrap
+ *    is internal.  The caller owns all field memory and the workspace.
+ *  - Units are the caller's, but must be consistent: c, dx, 1/kappa, dt, and
+ *    D_max (length^2/time), R_min (1/length) in the same length/time units.
+ *  - Work is enqueued on the hipStream_t given at create time (NULL = the
+ *    default stream).  Calls that report convergence synchronise that stream.
+ *  - No entry point allocates device memory: handles carve the caller's
+ *    workspace.  Host-side metadata is malloc'd and freed by *_destroy.
+ *  - Errors: FLD_EINVAL for bad arguments (checked before any launch),
+ *    FLD_ENOMEM for a workspace or budget that is too small, FLD_ENOCONV when
+ *    the solve reaches max_iter, FLD_ENONFINITE when a residual norm is NaN/Inf
+ *    (NaN/Inf inputs), FLD_EDEVICE for a HIP runtime error, FLD_EBUSY for a
+ *    pending served request.  No entry point writes E on error.
+ *  - One handle per stream; handles are not thread-safe.
+ */
+#ifndef FLD_H_
+#define FLD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fld_status {
+  FLD_OK = 0,
+  FLD_EINVAL = -1,
+  FLD_ENOMEM = -2,
+  FLD_ENOCONV = -3,
+  FLD_ENONFINITE = -4,
+  FLD_EDEVICE = -5,
+  FLD_EBUSY = -6
+} fld_status;
+
+typedef enum fld_precision {
+  FLD_PREC_FP64 = 0,  /* FP64 everywhere: PCG with a symmetric FP64 V-cycle */
+  FLD_PREC_MIXED = 1  /* FP32 V-cycle (smoother, transfers, residuals);
+                         FP64 Krylov recurrences, outer residual, refinement
+                         and coarsest solve; flexible (Polak-Ribiere) PCG */
+} fld_precision;
+
+/* Periodic 3-D mesh.  Every extent must be even and >= 4 (red/black
+ * colouring of a periodic grid needs even extents); nx*ny*nz < 2^31. */
+typedef struct fld_grid {
+  int32_t nx, ny, nz, reserved;
+  double dx, dy, dz;  /* cell sizes, > 0 */
+} fld_grid;
+
+typedef struct fld_params {
+  double c;            /* speed of light, > 0 */
+  double theta;        /* time weight in [0.5, 1]; 1 = backward Euler (Sec. 3.3) */
+  double d_max;        /* limiter cap D_max; paper: 0.006 c L_unit (Sec. 2) */
+  double r_min;        /* limiter floor R_min; paper: 1e-20 / L_unit (Sec. 2) */
+  double rtol;         /* stop when ||b - A dE||_2 <= rtol ||b||_2; paper 1e-8 (Table 1) */
+  double tau_tol;      /* target RMS relative change per step; paper 1e-4 (Sec. 3.4) */
+  double e_floor;      /* floor on |E| in that relative change, >= 0 */
+  double coarse_scale; /* coarse-face scale: T_c = coarse_scale * (sum of the 4
+                          fine faces); 0.5 rediscretises the operator (default) */
+  int32_t max_iter;    /* PCG iteration cap; paper 50 (Table 1) */
+  int32_t mg_levels;   /* multigrid levels incl. the finest; 0 = automatic */
+  int32_t nu_pre;      /* red/black sweeps before restriction; paper 1 (Table 1) */
+  int32_t nu_post;     /* sweeps after prolongation; paper 1 (Table 1) */
+  int32_t precision;   /* fld_precision */
+  int32_t max_dt_cuts; /* fld_step: at most this many 10x cuts (Sec. 3.4) */
+  int32_t tile_z;      /* z-depth of one work tile; 0 = automatic */
+  int32_t check_every; /* PCG iterations between host convergence reads; 0 = auto */
+  int32_t use_graph;   /* 1 = replay the PCG iteration from a captured hipGraph */
+  int32_t reserved[7];
+} fld_params;
+
+typedef struct fld_stats {
+  int32_t status;       /* fld_status of this call */
+  int32_t iters;        /* PCG iterations (summed over substeps) */
+  int32_t subcycles;    /* substeps taken by fld_step (1 if no cut) */
+  int32_t dt_cuts;      /* 10x cuts taken by fld_step */
+  int32_t levels;       /* multigrid levels used */
+  int32_t restarts;     /* refinement restarts from the true FP64 residual */
+  double rel_resid;     /* true ||b - A dE||_2 / ||b||_2 of the last solve */
+  double err_bound;     /* ||b - A dE||_2 / ||dE||_2: bounds the relative 2-norm
+                           error of dE because ||A^-1||_2 <= 1 when adot >= 0 */
+  double rel_change_rms;/* RMS of dE / max(|E^{n+1}|, e_floor), last substep */
+  double dt_next;       /* suggested next step: dt * clamp(tau_tol/rho, 0.1, 2) */
+  double bnorm;         /* ||b||_2 of the last solve */
+  double dEnorm;        /* ||dE||_2 of the last solve */
+} fld_stats;
+
+typedef struct fld_handle fld_handle;
+typedef struct fld_batch fld_batch;
+typedef struct fld_server fld_server;
+
+/* Paper defaults (Sec. 2, Sec. 3.4, Table 1) for a run whose length unit is
+ * L_unit: d_max = 0.006 c L_unit, r_min = 1e-20 / L_unit, rtol = 1e-8,
+ * max_iter = 50, nu_pre = nu_post = 1, theta = 1, tau_tol = 1e-4, FP64. */
+void fld_default_params(fld_params *p, double c, double L_unit);
+
+const char *fld_strerror(fld_status s);
+
+/* Bytes of device workspace one handle needs for this grid and parameters
+ * (fields, multigrid hierarchy, Krylov vectors, descriptor tables).  Returns
+ * 0 for an invalid grid or parameter set. */
+size_t fld_workspace_bytes(const fld_grid *g, const fld_params *p);
+
+/* Create a solver handle for one grid.  workspace: device memory of at least
+ * fld_workspace_bytes(g, p) bytes, 256-byte aligned, owned by the caller and
+ * kept alive until fld_destroy.  hip_stream: hipStream_t or NULL.
+ * Errors: FLD_EINVAL (grid/params), FLD_ENOMEM (workspace too small),
+ * FLD_EDEVICE. */
+fld_status fld_create(const fld_grid *g, const fld_params *p, void *hip_stream,
+                      void *workspace, size_t workspace_bytes,
+                      fld_handle **out);
+
+/* Assemble one step's system (Sec. 2 limiter, Sec. 3.3 theta-method): face
+ * coefficients from the limiter at E^n, the diagonal, b = dt (L E^n + eta),
+ * and every coarse level of the multigrid hierarchy.  E_n, kappa, eta: device
+ * FP64 [nz][ny][nx], read only, kappa >= 0.  dt > 0, a > 0.  Enqueued; no
+ * synchronisation.  Errors: FLD_EINVAL, FLD_EDEVICE. */
+fld_status fld_assemble(fld_handle *h, const double *E_n, const double *kappa,
+                        const double *eta, double dt, double a, double adot);
+
+/* Solve the assembled system for dE = E^{n+1} - E^n by multigrid-
+ * preconditioned CG from dE = 0 (Sec. 3.3, Table 1) until the true FP64
+ * residual satisfies ||b - A dE||_2 <= rtol ||b||_2.  dE: device FP64 output,
+ * must not alias the inputs given to fld_assemble.  stats: host, nullable.
+ * Synchronises the stream.  Errors: FLD_ENOCONV (max_iter reached; dE holds
+ * the last iterate), FLD_ENONFINITE, FLD_EINVAL, FLD_EDEVICE. */
+fld_status fld_solve(fld_handle *h, double *dE, fld_stats *stats);
+
+/* One radiation step (Sec. 3.3-3.4): assemble at E, solve, E += dE.  If the
+ * solve fails, the radiation step is cut by 10x and subcycled until dt is
+ * covered, at most max_dt_cuts cuts.  E: device FP64, in E^n, out E^{n+1};
+ * on any error E is left unchanged.  stats: host, nullable.  Synchronises.
+ * Errors: FLD_ENOCONV (cuts exhausted), FLD_ENONFINITE, FLD_EINVAL,
+ * FLD_EDEVICE. */
+fld_status fld_step(fld_handle *h, double *E, const double *kappa,
+                    const double *eta, double dt, double a, double adot,
+                    fld_stats *stats);
+
+/* Release the handle's host metadata (the workspace stays the caller's). */
+fld_status fld_destroy(fld_handle *h);
+
+/* --- Components of the solve, exported for inspection and testing. ------ */
+
+/* Copy the assembled finest-level system to caller device buffers (any may
+ * be NULL): diag = A_pp, Tx/Ty/Tz = -A_{p,p+e_d} (the +x/+y/+z face of each
+ * cell), b.  Synchronises.  Errors: FLD_EINVAL (nothing assembled), FLD_EDEVICE. */
+fld_status fld_get_system(fld_handle *h, double *diag, double *Tx, double *Ty,
+                          double *Tz, double *b);
+
+/* out = A u with the assembled finest-level operator (7-point SpMV, Sec.
+ * 3.3).  u, out: device FP64, distinct.  Synchronises. */
+fld_status fld_apply(fld_handle *h, const double *u, double *out);
+
+/* z = B r: one multigrid V-cycle (the PCG preconditioner, Table 1) applied to
+ * r, in the handle's precision.  r, z: device FP64, distinct.  Synchronises. */
+fld_status fld_precondition(fld_handle *h, const double *r, double *z);
+
+/* --- Batched form: many independent problems of uneven sizes. ------------
+ * All problems share the parameters; each has its own grid, fields, dt, a,
+ * adot.  Every kernel of one multigrid level covers the tiles of all
+ * problems in one launch; PCG scalars, convergence and the 10x cut rule are
+ * per problem. */
+
+/* Workspace bytes for n problems with the given grids (0 if invalid). */
+size_t fld_batch_workspace_bytes(int32_t n, const fld_grid *grids,
+                                 const fld_params *p);
+
+fld_status fld_batch_create(int32_t n, const fld_grid *grids,
+                            const fld_params *p, void *hip_stream,
+                            void *workspace, size_t workspace_bytes,
+                            fld_batch **out);
+
+/* One step for every problem i: E[i] (in/out), kappa[i], eta[i] are device
+ * pointers (the pointer arrays themselves are host arrays of length n);
+ * dt, a, adot are host arrays of length n.  per_problem: host array of n
+ * stats, nullable.  Returns FLD_OK if every problem succeeded, else the first
+ * failing problem's status (each problem's own status is in its stats; a
+ * failed problem's E is unchanged).  Synchronises. */
+fld_status fld_batch_step(fld_batch *b, double *const *E,
+                          const double *const *kappa,
+                          const double *const *eta, const double *dt,
+                          const double *a, const double *adot,
+                          fld_stats *per_problem);
+
+fld_status fld_batch_destroy(fld_batch *b);
+
+/* --- Served form: continuous batching of solve requests. ----------------
+ * A server owns a device arena given by the caller.  Requests are admitted
+ * in arrival order while their workspace fits the arena; admitted requests
+ * keep their multigrid hierarchy resident and advance together, one PCG
+ * iteration per scheduler tick for all of them, level by level.  Finished
+ * requests free their arena space at tick boundaries and waiting requests
+ * join there.  A background host thread runs the scheduler. */
+
+typedef struct fld_request {
+  fld_grid grid;
+  int32_t n_steps;       /* steps of length dt to take, >= 1 */
+  int32_t reserved;
+  double dt, a, adot;
+  const double *E;       /* device FP64 E^0; read at admission */
+  const double *kappa;   /* device FP64; must stay valid until completion */
+  const double *eta;     /* device FP64; must stay valid until completion */
+  double *E_out;         /* device FP64 result E after n_steps */
+} fld_request;
+
+typedef struct fld_result {
+  int32_t status;        /* fld_status of the request */
+  int32_t steps_done;
+  int32_t iters;         /* PCG iterations over all steps */
+  int32_t dt_cuts;
+  double queue_s;        /* submit -> admission, seconds */
+  double latency_s;      /* submit -> result written, seconds */
+  double rel_resid;      /* last solve's true relative residual */
+  double err_bound;
+} fld_result;
+
+/* arena: device memory owned by the caller (the HBM budget for resident
+ * hierarchies).  Errors: FLD_EINVAL, FLD_ENOMEM (arena below the minimum),
+ * FLD_EDEVICE. */
+fld_status fld_server_create(const fld_params *p, void *arena,
+                             size_t arena_bytes, void *hip_stream,
+                             fld_server **out);
+
+/* Queue a request (copied; its pointers must stay valid until completion).
+ * Errors: FLD_EINVAL (bad grid/fields), FLD_ENOMEM (can never fit). */
+fld_status fld_server_submit(fld_server *s, const fld_request *r,
+                             uint64_t *ticket);
+
+/* FLD_OK with *res filled once the request is done (or its failure status in
+ * res->status), FLD_EBUSY while pending, FLD_EINVAL for an unknown ticket. */
+fld_status fld_server_poll(fld_server *s, uint64_t ticket, fld_result *res);
+
+/* Block until every submitted request is done. */
+fld_status fld_server_drain(fld_server *s);
+
+/* Stop the scheduler thread (after draining) and free host metadata. */
+fld_status fld_server_destroy(fld_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLD_H_ */

@@ -1,0 +1,516 @@
+// Host engine: hierarchy shapes, workspace layout, tile lists, and the PCG /
+// step drivers of the implicit FLD solve.
+#include "fld_engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace fld {
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? ST_OK : ST_EDEVICE; }
+
+#define HIP_TRY(expr)                           \
+  do {                                          \
+    if ((expr) != hipSuccess) return ST_EDEVICE; \
+  } while (0)
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+bool grid_ok(const fld_grid &g) {
+  const int d[3] = {g.nx, g.ny, g.nz};
+  for (int v : d)
+    if (v < 4 || (v & 1)) return false;
+  if ((long long)g.nx * g.ny * g.nz >= (1LL << 31)) return false;
+  return finite_pos(g.dx) && finite_pos(g.dy) && finite_pos(g.dz);
+}
+
+bool params_ok(const fld_params &p) {
+  if (!finite_pos(p.c)) return false;
+  if (!(p.theta >= 0.5 && p.theta <= 1.0)) return false;
+  if (!(p.d_max >= 0.0) || !(p.r_min >= 0.0)) return false;
+  if (!(p.rtol >= 0.0) || !std::isfinite(p.rtol)) return false;
+  if (!finite_pos(p.tau_tol) || !(p.e_floor >= 0.0)) return false;
+  if (!finite_pos(p.coarse_scale)) return false;
+  if (p.max_iter < 1 || p.mg_levels < 0 || p.mg_levels > kMaxLevels) return false;
+  if (p.nu_pre < 1 || p.nu_pre > 8 || p.nu_post < 1 || p.nu_post > 8) return false;
+  if (p.precision != FLD_PREC_FP64 && p.precision != FLD_PREC_MIXED) return false;
+  if (p.max_dt_cuts < 0 || p.tile_z < 0 || p.tile_z > 64 || p.check_every < 0)
+    return false;
+  return true;
+}
+
+// Full 2x coarsening while every extent stays even.  Automatic depth stops
+// once an extent would drop below 4; an explicit depth allows extents >= 2.
+Hier make_hier(const fld_grid &g, const fld_params &p) {
+  Hier h;
+  h.levels = 1;
+  h.n[0][0] = g.nx;
+  h.n[0][1] = g.ny;
+  h.n[0][2] = g.nz;
+  const int maxl = p.mg_levels > 0 ? p.mg_levels : kMaxLevels;
+  while (h.levels < maxl) {
+    const int *c = h.n[h.levels - 1];
+    if ((c[0] | c[1] | c[2]) & 1) break;
+    const int lim = p.mg_levels > 0 ? 4 : 8;
+    if (c[0] < lim || c[1] < lim || c[2] < lim) break;
+    for (int d = 0; d < 3; ++d) h.n[h.levels][d] = c[d] / 2;
+    ++h.levels;
+  }
+  for (int l = 0; l < h.levels; ++l)
+    h.tiles[l] = count_tiles(p, h.n[l][0], h.n[l][1], h.n[l][2]);
+  return h;
+}
+
+void tile_shape(const fld_params &p, int nx, int ny, int nz, int &tx, int &ty,
+                int &tz) {
+  tx = std::min(nx, 64);
+  ty = std::max(1, std::min(ny, kBlock / tx));
+  if (p.tile_z > 0) tz = std::min(p.tile_z, nz);
+  else tz = std::max(1, std::min(8, nz / 8));
+}
+
+int count_tiles(const fld_params &p, int nx, int ny, int nz) {
+  int tx, ty, tz;
+  tile_shape(p, nx, ny, nz, tx, ty, tz);
+  return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz);
+}
+
+void carve_problem(Carver &cv, const Hier &h, const fld_params &p, ProbMem &m) {
+  const bool mixed = p.precision == FLD_PREC_MIXED;
+  std::memset(&m, 0, sizeof(m));
+  for (int l = 0; l < h.levels; ++l) {
+    const size_t n = (size_t)h.cells(l);
+    LevelDev &L = m.lv[l];
+    L.nx = h.n[l][0];
+    L.ny = h.n[l][1];
+    L.nz = h.n[l][2];
+    L.n = (int)n;
+    L.Tx = cv.take<double>(n);
+    L.Ty = cv.take<double>(n);
+    L.Tz = cv.take<double>(n);
+    L.diag = cv.take<double>(n);
+    if (mixed) {
+      L.Tx32 = cv.take<float>(n);
+      L.Ty32 = cv.take<float>(n);
+      L.Tz32 = cv.take<float>(n);
+      L.diag32 = cv.take<float>(n);
+    }
+    if (l == 0) {
+      ProbDev &P = m.pd;
+      P.nx = L.nx;
+      P.ny = L.ny;
+      P.nz = L.nz;
+      P.n = L.n;
+      P.x = cv.take<double>(n);
+      P.r = cv.take<double>(n);
+      P.z = cv.take<double>(n);
+      P.p0 = cv.take<double>(n);
+      P.p1 = cv.take<double>(n);
+      P.q = cv.take<double>(n);
+      P.b = cv.take<double>(n);
+      L.x = mixed ? (void *)cv.take<float>(n) : (void *)P.z;
+      L.f = nullptr;
+    } else {
+      if (mixed) {
+        L.x = cv.take<float>(n);
+        L.f = cv.take<float>(n);
+      } else {
+        L.x = cv.take<double>(n);
+        L.f = cv.take<double>(n);
+      }
+    }
+  }
+  m.pd.levels = h.levels;
+  m.pd.cs = cv.take<double>(4 * (size_t)h.cells(h.levels - 1));
+  m.E_work = cv.take<double>((size_t)h.cells(0));
+}
+
+size_t problem_bytes(const Hier &h, const fld_params &p) {
+  Carver cv;
+  ProbMem m;
+  carve_problem(cv, h, p, m);
+  return align_up(cv.off);
+}
+
+static size_t tables_layout(Carver &cv, const std::vector<Hier> &hs,
+                            Engine *e) {
+  const int np = (int)hs.size();
+  size_t ntiles = 0, nfine = 0, nranges = 0;
+  for (const Hier &h : hs) {
+    for (int l = 0; l < h.levels; ++l) ntiles += h.tiles[l];
+    nfine += h.tiles[0];
+  }
+  // fine + smooth[l] + exist[l]: at most (2 * kMaxLevels + 1) ranges per
+  // problem and list set, 2 ints each, kListSlots sets
+  nranges = (size_t)(2 * kMaxLevels + 1) * np * 2 * kListSlots;
+  LevelDev *lv = cv.take<LevelDev>((size_t)kMaxLevels * np);
+  ProbDev *pd = cv.take<ProbDev>(np);
+  StepDev *sd = cv.take<StepDev>(np);
+  Scal *sc = cv.take<Scal>(np);
+  double *part = cv.take<double>(2 * std::max<size_t>(nfine, 1));
+  Tile *tiles = cv.take<Tile>(std::max<size_t>(ntiles, 1));
+  int *ranges = cv.take<int>(nranges);
+  if (e) {
+    e->T.lv = lv;
+    e->T.pd = pd;
+    e->T.sd = sd;
+    e->T.sc = sc;
+    e->T.part = part;
+    e->T.nprob = np;
+    e->d_tiles = tiles;
+    e->d_ranges = ranges;
+    e->ranges_cap = nranges;
+  }
+  return align_up(cv.off);
+}
+
+size_t tables_bytes(const std::vector<Hier> &hs) {
+  Carver cv;
+  return tables_layout(cv, hs, nullptr);
+}
+
+Engine::~Engine() { release_graph(); }
+
+int Engine::release_graph() {
+  if (gexec) hipGraphExecDestroy(gexec);
+  if (graph) hipGraphDestroy(graph);
+  gexec = nullptr;
+  graph = nullptr;
+  if (cap_stream) hipStreamDestroy(cap_stream);
+  cap_stream = nullptr;
+  return ST_OK;
+}
+
+int Engine::setup(const fld_params &p, hipStream_t s,
+                  const std::vector<fld_grid> &g, Carver &tbl,
+                  std::vector<Carver> &pm) {
+  prm = p;
+  stream = s;
+  mixed = p.precision == FLD_PREC_MIXED;
+  grids = g;
+  const int np = (int)g.size();
+  hier.resize(np);
+  mem.resize(np);
+  Lmax = 0;
+  for (int i = 0; i < np; ++i) {
+    hier[i] = make_hier(g[i], p);
+    Lmax = std::max(Lmax, hier[i].levels);
+  }
+  tables_layout(tbl, hier, this);
+  for (int i = 0; i < np; ++i) carve_problem(pm[i], hier[i], p, mem[i]);
+
+  // full tile table, level-major so the finest tiles come first
+  h_tiles.clear();
+  tbeg.assign((size_t)np * kMaxLevels, 0);
+  for (int l = 0; l < Lmax; ++l) {
+    for (int i = 0; i < np; ++i) {
+      if (l >= hier[i].levels) continue;
+      tbeg[(size_t)i * kMaxLevels + l] = (int)h_tiles.size();
+      const int nx = hier[i].n[l][0], ny = hier[i].n[l][1], nz = hier[i].n[l][2];
+      int tx, ty, tz;
+      tile_shape(prm, nx, ny, nz, tx, ty, tz);
+      for (int z0 = 0; z0 < nz; z0 += tz)
+        for (int y0 = 0; y0 < ny; y0 += ty)
+          for (int x0 = 0; x0 < nx; x0 += tx) {
+            Tile t;
+            t.prob = i;
+            t.x0 = x0;
+            t.y0 = y0;
+            t.z0 = z0;
+            t.tx = std::min(tx, nx - x0);
+            t.ty = std::min(ty, ny - y0);
+            t.tz = std::min(tz, nz - z0);
+            t.level = l;
+            h_tiles.push_back(t);
+          }
+    }
+  }
+  h_lv.assign((size_t)kMaxLevels * np, LevelDev{});
+  h_pd.resize(np);
+  h_sd.assign(np, StepDev{});
+  h_sc.assign(np, Scal{});
+  for (int i = 0; i < np; ++i) {
+    for (int l = 0; l < hier[i].levels; ++l) h_lv[(size_t)l * np + i] = mem[i].lv[l];
+    h_pd[i] = mem[i].pd;
+    h_pd[i].t0 = tbeg[(size_t)i * kMaxLevels];
+    h_pd[i].t1 = h_pd[i].t0 + hier[i].tiles[0];
+    h_sc[i].phase = PH_DONE;
+    h_sc[i].tol2 = prm.rtol * prm.rtol;
+    h_sc[i].max_iter = prm.max_iter;
+    h_sc[i].s = 1.0;
+    h_sc[i].inv_s = 1.0;
+  }
+  int st = upload_all();
+  if (st) return st;
+  std::vector<char> every(np, 1);
+  st = build_lists(every, 0, all);
+  if (st) return st;
+  HIP_TRY(hipStreamSynchronize(stream));
+  return ST_OK;
+}
+
+// Range lists of every launch kind for the problems flagged in member.
+int Engine::build_lists(const std::vector<char> &member, int slot, ListSet &out) {
+  const int np = (int)hier.size();
+  const size_t per_slot = ranges_cap / kListSlots;
+  int *slot_base = d_ranges + per_slot * slot;
+  h_ranges.clear();
+  auto make = [&](int level, auto pred) {
+    TileList L{};
+    L.base = d_tiles;
+    const int off = (int)h_ranges.size();
+    int blocks = 0, nr = 0;
+    for (int i = 0; i < np; ++i) {
+      if (!member[i] || level >= hier[i].levels || !pred(i)) continue;
+      h_ranges.push_back(blocks);
+      h_ranges.push_back(tbeg[(size_t)i * kMaxLevels + level]);
+      blocks += hier[i].tiles[level];
+      ++nr;
+    }
+    L.ranges = slot_base + off;
+    L.nranges = nr;
+    L.nblocks = blocks;
+    return L;
+  };
+  out.fine = make(0, [](int) { return true; });
+  for (int l = 0; l < kMaxLevels; ++l) {
+    out.smooth[l] = make(l, [&](int i) {
+      return l < hier[i].levels - 1 || (hier[i].levels == 1 && l == 0);
+    });
+    out.exist[l] = make(l, [&](int) { return l >= 1; });
+  }
+  if (h_ranges.size() > per_slot) return ST_EINVAL;
+  if (!h_ranges.empty())
+    HIP_TRY(hipMemcpyAsync(slot_base, h_ranges.data(), sizeof(int) * h_ranges.size(),
+                           hipMemcpyHostToDevice, stream));
+  return ST_OK;
+}
+
+int Engine::upload_all() {
+  const int np = (int)hier.size();
+  HIP_TRY(hipMemcpyAsync(T.lv, h_lv.data(), sizeof(LevelDev) * h_lv.size(),
+                         hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(T.pd, h_pd.data(), sizeof(ProbDev) * np,
+                         hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(d_tiles, h_tiles.data(), sizeof(Tile) * h_tiles.size(),
+                         hipMemcpyHostToDevice, stream));
+  int st = upload_sd_sc();
+  if (st) return st;
+  HIP_TRY(hipStreamSynchronize(stream));
+  return ST_OK;
+}
+
+int Engine::upload_sd_sc() {
+  const int np = (int)hier.size();
+  HIP_TRY(hipMemcpyAsync(T.sd, h_sd.data(), sizeof(StepDev) * np,
+                         hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(T.sc, h_sc.data(), sizeof(Scal) * np,
+                         hipMemcpyHostToDevice, stream));
+  return ST_OK;
+}
+
+int Engine::download_sc() {
+  const int np = (int)hier.size();
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(h_sc.data(), T.sc, sizeof(Scal) * np,
+                         hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  return ST_OK;
+}
+
+void Engine::fill_step(int p, const double *E, const double *kappa,
+                       const double *eta, double dt, double a, double adot) {
+  StepDev &S = h_sd[p];
+  S.E = E;
+  S.kappa = kappa;
+  S.eta = eta;
+  S.Eout = nullptr;
+  S.dt = dt;
+  S.adot_a = adot / a;
+  S.idx = 1.0 / grids[p].dx;
+  S.idy = 1.0 / grids[p].dy;
+  S.idz = 1.0 / grids[p].dz;
+  Scal &sc = h_sc[p];
+  sc.live = 1;
+  sc.tol2 = prm.rtol * prm.rtol;
+  sc.max_iter = prm.max_iter;
+}
+
+void Engine::enqueue_assemble(const ListSet &ls) {
+  launch_assemble(T, ls.fine, prm.c, prm.theta, prm.d_max, prm.r_min, mixed, stream);
+  for (int l = 1; l < Lmax; ++l)
+    launch_coarsen(T, ls.exist[l], l, prm.coarse_scale, mixed, stream);
+  launch_fin(T, FIN_BB, mixed, stream);
+}
+
+// One V-cycle for every active problem.  Pre-smoothing: red then black
+// (nu_pre sweeps); post-smoothing: black then red (nu_post sweeps), the
+// adjoint order, so the FP64 cycle is a symmetric preconditioner.
+void Engine::enqueue_vcycle(const ListSet &ls) {
+  const int prec = mixed;
+  const TileList *smooth = ls.smooth, *exist = ls.exist;
+  for (int l = 0; l < Lmax; ++l) {
+    if (smooth[l].nblocks == 0) continue;
+    launch_pre0(T, smooth[l], l, prec, stream);
+    for (int s = 1; s < prm.nu_pre; ++s) {
+      launch_half(T, smooth[l], l, 0, prec, stream);
+      launch_half(T, smooth[l], l, 1, prec, stream);
+    }
+    if (l + 1 < Lmax) launch_resid_restrict(T, exist[l + 1], l + 1, prec, stream);
+  }
+  if (Lmax > 1) launch_coarse_solve(T, prec, stream);
+  for (int l = Lmax - 1; l >= 0; --l) {
+    if (smooth[l].nblocks == 0) continue;
+    launch_prolong_black(T, smooth[l], l, prec, stream);
+    for (int s = 0; s < prm.nu_post; ++s) {
+      if (s > 0) launch_half(T, smooth[l], l, 1, prec, stream);
+      if (l == 0 && s == prm.nu_post - 1) launch_half_out(T, smooth[0], prec, mixed, stream);
+      else launch_half(T, smooth[l], l, 0, prec, stream);
+    }
+  }
+}
+
+void Engine::enqueue_iteration(const ListSet &ls) {
+  enqueue_vcycle(ls);
+  launch_fin(T, FIN_RZ, mixed, stream);
+  launch_spmv_p(T, ls.fine, stream);
+  launch_fin(T, FIN_PQ, mixed, stream);
+  launch_update(T, ls.fine, stream);
+  launch_fin(T, FIN_RR, mixed, stream);
+}
+
+int Engine::check_every() const {
+  if (prm.check_every > 0) return prm.check_every;
+  long long cells = 0;
+  for (const Hier &h : hier) cells += h.cells(0);
+  return cells >= (1LL << 22) ? 1 : 4;
+}
+
+// Iterate every problem in PH_ITER until each one is decided.  Problems whose
+// recursive residual meets the tolerance are verified with the true FP64
+// residual b - A x and restarted from it if it does not (refinement).
+int Engine::run_solve() {
+  int st = download_sc();
+  if (st) return st;
+  for (;;) {
+    int nact = 0, nver = 0;
+    for (const Scal &sc : h_sc) {
+      if (sc.phase == PH_ITER && sc.active) ++nact;
+      else if (sc.phase == PH_VERIFY) ++nver;
+    }
+    if (nver) {
+      launch_true_resid(T, all.fine, stream);
+      launch_fin(T, FIN_TRUE, mixed, stream);
+    } else if (nact) {
+      const int K = check_every();
+      if (prm.use_graph) {
+        if (!gexec) {
+          HIP_TRY(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+          HIP_TRY(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+          hipStream_t saved = stream;
+          stream = cap_stream;
+          enqueue_iteration(all);
+          stream = saved;
+          HIP_TRY(hipStreamEndCapture(cap_stream, &graph));
+          HIP_TRY(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        }
+        for (int k = 0; k < K; ++k) HIP_TRY(hipGraphLaunch(gexec, stream));
+      } else {
+        for (int k = 0; k < K; ++k) enqueue_iteration(all);
+      }
+    } else {
+      break;
+    }
+    st = download_sc();
+    if (st) return st;
+  }
+  return ST_OK;
+}
+
+// Steps for every job not done: assemble, solve, and on success E += dE;
+// on failure cut the job's radiation step by 10x and subcycle (Sec. 3.4).
+int Engine::run_steps(std::vector<Job> &jobs) {
+  const int np = (int)jobs.size();
+  std::vector<int> target(np, 0);  // 0: none, 1: caller E in place, 2: E_work
+  for (;;) {
+    bool any = false;
+    for (int p = 0; p < np; ++p) {
+      Job &j = jobs[p];
+      h_sc[p].live = 0;
+      if (j.done) continue;
+      any = true;
+      j.h = std::min(j.h, j.dt - j.t);
+      fill_step(p, j.in_work ? mem[p].E_work : j.E, j.kappa, j.eta, j.h, j.a, j.adot);
+    }
+    if (!any) break;
+    int st = upload_sd_sc();
+    if (st) return st;
+    enqueue_assemble(all);
+    st = run_solve();
+    if (st) return st;
+    bool commit = false;
+    for (int p = 0; p < np; ++p) {
+      Job &j = jobs[p];
+      target[p] = 0;
+      if (!h_sc[p].live) continue;
+      h_sc[p].live = 0;
+      j.iters += h_sc[p].iter;
+      j.restarts += h_sc[p].restarts;
+      if (h_sc[p].phase == PH_DONE && h_sc[p].status == ST_OK) {
+        const bool last = j.dt - (j.t + j.h) <= 1e-12 * j.dt;
+        target[p] = (!j.in_work && last) ? 1 : 2;
+        h_sd[p].Eout = target[p] == 1 ? j.E : mem[p].E_work;
+        h_sc[p].live = 1;
+        commit = true;
+      } else if (j.cuts < prm.max_dt_cuts) {
+        j.h *= 0.1;
+        j.cuts += 1;
+      } else {
+        j.done = true;
+        j.status = h_sc[p].status != ST_OK ? h_sc[p].status : ST_ENOCONV;
+      }
+    }
+    if (commit) {
+      st = upload_sd_sc();
+      if (st) return st;
+      launch_update_E(T, all.fine, prm.e_floor, 0, stream);
+      launch_fin(T, FIN_STEP, mixed, stream);
+      st = download_sc();
+      if (st) return st;
+      for (int p = 0; p < np; ++p) {
+        if (!target[p]) continue;
+        Job &j = jobs[p];
+        const Scal &sc = h_sc[p];
+        const double n = (double)hier[p].cells(0);
+        j.substeps += 1;
+        j.t += j.h;
+        j.rho = std::sqrt(sc.change2 / n);
+        double f = j.rho > 0.0 ? prm.tau_tol / j.rho : 2.0;
+        f = std::min(2.0, std::max(0.1, f));
+        j.bnorm = std::sqrt(sc.bb);
+        j.dEnorm = std::sqrt(sc.dEdE);
+        j.rel_resid = sc.bb > 0.0 ? std::sqrt(sc.rr_true / sc.bb) : 0.0;
+        j.err_bound = j.dEnorm > 0.0 ? std::sqrt(sc.rr_true) / j.dEnorm : 0.0;
+        if (target[p] == 2) j.in_work = true;
+        j.h *= f;
+        j.dt_next = j.h;
+        if (j.dt - j.t <= 1e-12 * j.dt) {
+          j.done = true;
+          j.status = ST_OK;
+          if (j.in_work)
+            HIP_TRY(hipMemcpyAsync(j.E, mem[p].E_work,
+                                   sizeof(double) * (size_t)hier[p].cells(0),
+                                   hipMemcpyDeviceToDevice, stream));
+        }
+      }
+      for (int p = 0; p < np; ++p) h_sc[p].live = 0;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(stream));
+  return ST_OK;
+}
+
+}  // namespace fld

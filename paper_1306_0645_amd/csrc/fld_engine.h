@@ -1,0 +1,130 @@
+// Host engine of the FLD library: owns a set of problems (one for a plain
+// handle, many for a batch, a changing set for a server), their multigrid
+// hierarchies carved from caller-provided device memory, the device tables
+// and tile lists, and drives assembly, the PCG iteration and the step logic.
+#pragma once
+
+#include <vector>
+
+#include "fld.h"
+#include "fld_internal.h"
+
+namespace fld {
+
+size_t align_up(size_t v, size_t a = 256);
+
+// bump allocator over caller memory (base == nullptr: size only)
+struct Carver {
+  char *base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T *take(size_t n) {
+    off = align_up(off);
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+// multigrid hierarchy shape of one grid
+struct Hier {
+  int levels = 0;
+  int n[kMaxLevels][3] = {};
+  int tiles[kMaxLevels] = {};   // tiles per level
+  long long cells(int l) const { return (long long)n[l][0] * n[l][1] * n[l][2]; }
+};
+
+bool grid_ok(const fld_grid &g);
+bool params_ok(const fld_params &p);
+Hier make_hier(const fld_grid &g, const fld_params &p);
+void tile_shape(const fld_params &p, int nx, int ny, int nz, int &tx, int &ty,
+                int &tz);
+int count_tiles(const fld_params &p, int nx, int ny, int nz);
+size_t problem_bytes(const Hier &h, const fld_params &p);
+size_t tables_bytes(const std::vector<Hier> &hs);
+
+// device memory of one problem
+struct ProbMem {
+  LevelDev lv[kMaxLevels];
+  ProbDev pd;
+  double *E_work = nullptr;
+};
+void carve_problem(Carver &cv, const Hier &h, const fld_params &p, ProbMem &m);
+
+// one step request inside the engine
+struct Job {
+  double *E = nullptr;
+  const double *kappa = nullptr, *eta = nullptr;
+  double dt = 0, a = 1, adot = 0;
+  double t = 0, h = 0;
+  int cuts = 0, substeps = 0, iters = 0, restarts = 0;
+  int status = ST_OK;
+  bool done = false, in_work = false;
+  double rho = 0, dt_next = 0, rel_resid = 0, err_bound = 0, bnorm = 0,
+         dEnorm = 0;
+};
+
+// Launch lists of every kernel kind for one subset of the problems.
+struct ListSet {
+  TileList fine{}, smooth[kMaxLevels]{}, exist[kMaxLevels]{};
+};
+
+constexpr int kListSlots = 4;  // independent range regions (server phases)
+
+class Engine {
+ public:
+  fld_params prm{};
+  hipStream_t stream = nullptr;
+  int mixed = 0;
+  std::vector<fld_grid> grids;
+  std::vector<Hier> hier;
+  std::vector<ProbMem> mem;
+  int Lmax = 0;
+
+  // host mirrors of the device tables
+  std::vector<LevelDev> h_lv;
+  std::vector<ProbDev> h_pd;
+  std::vector<StepDev> h_sd;
+  std::vector<Scal> h_sc;
+  std::vector<Tile> h_tiles;
+  std::vector<int> h_ranges;
+  std::vector<int> tbeg;   // [p * kMaxLevels + l] first tile of (p, l)
+
+  Tables T{};
+  Tile *d_tiles = nullptr;
+  int *d_ranges = nullptr;
+  size_t ranges_cap = 0;   // ints available at d_ranges (all slots)
+  ListSet all;             // every problem (slot 0)
+
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool assembled = false;
+  int last_status = ST_OK;
+
+  ~Engine();
+
+  // lay out tables (in tbl) and problems (in pm[i]) and upload descriptors
+  int setup(const fld_params &p, hipStream_t s, const std::vector<fld_grid> &g,
+            Carver &tbl, std::vector<Carver> &pm);
+  int upload_all();
+  int upload_sd_sc();
+  int download_sc();
+  // lists for the problems flagged in member, in range slot 'slot'; uploads
+  // the ranges (enqueued on the stream)
+  int build_lists(const std::vector<char> &member, int slot, ListSet &out);
+  int release_graph();
+
+  void enqueue_assemble(const ListSet &ls);
+  void enqueue_vcycle(const ListSet &ls);
+  void enqueue_iteration(const ListSet &ls);
+  int run_solve();
+  int run_steps(std::vector<Job> &jobs);
+  int check_every() const;
+  void fill_step(int p, const double *E, const double *kappa, const double *eta,
+                 double dt, double a, double adot);
+};
+
+int hip_ok(hipError_t e);
+
+}  // namespace fld

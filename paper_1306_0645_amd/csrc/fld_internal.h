@@ -1,0 +1,143 @@
+// Internal declarations of the FLD library: device-side descriptor tables
+// shared by the HIP kernels and the host engine, and the kernel launchers.
+//
+// Every kernel works on a list of tiles.  A tile is a box of at most 256
+// (x, y) columns and tz planes of one multigrid level of one problem, so the
+// same kernel serves one large problem, a batch of uneven problems, and the
+// changing set of a request server: the host only rebuilds the lists.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fld {
+
+constexpr int kBlock = 256;          // threads per tile block (4 wave64)
+constexpr int kCoarseBlock = 1024;   // threads of the coarsest-level solve
+constexpr int kMaxLevels = 12;
+
+// Status values (same numbers as the public fld_status).
+enum : int {
+  ST_OK = 0,
+  ST_EINVAL = -1,
+  ST_ENOMEM = -2,
+  ST_ENOCONV = -3,
+  ST_ENONFINITE = -4,
+  ST_EDEVICE = -5,
+  ST_EBUSY = -6
+};
+
+// Phase of one problem's PCG solve (Scal::phase).
+enum : int {
+  PH_ITER = 0,     // iterating
+  PH_VERIFY = 1,   // recursive residual met the tolerance; true residual pending
+  PH_DONE = 2      // final status decided
+};
+
+// One multigrid level of one problem.
+struct LevelDev {
+  int nx, ny, nz, n;
+  double *Tx, *Ty, *Tz, *diag;       // FP64: -A_{p,p+e_d} on +faces; A_pp
+  float *Tx32, *Ty32, *Tz32, *diag32;// FP32 copies (mixed precision)
+  void *x;                           // V-cycle iterate (level precision);
+                                     // finest level FP64 mode: aliases z
+  void *f;                           // V-cycle right-hand side (levels >= 1)
+};
+
+// One problem's finest-level Krylov state.
+struct ProbDev {
+  int nx, ny, nz, n;
+  double *x, *r, *z, *p0, *p1, *q, *b;
+  double *cs;            // coarsest-level CG scratch: 4 * n_coarsest doubles
+  int levels;            // number of multigrid levels
+  int t0, t1;            // range of this problem's tiles in the finest list
+  int pad;
+};
+
+// Per-step inputs of one problem (uploaded by the host at each assembly).
+struct StepDev {
+  const double *E, *kappa, *eta;
+  double *Eout;          // destination of E + dE (may equal E)
+  double dt, adot_a;     // dt and adot/a
+  double idx, idy, idz;  // 1 / dx, 1 / dy, 1 / dz
+};
+
+// Per-problem PCG scalars (device resident, read back by the host).
+struct Scal {
+  double bb, rr, rho, rho_old, rzo, pq, alpha, beta;
+  double s, inv_s;       // residual scale for the FP32 V-cycle
+  double rr_true, tol2;  // true residual^2; rtol^2
+  double change2;        // sum of (dE / max(|E|, floor))^2
+  double dEdE;           // ||dE||^2
+  int iter, max_iter, phase, status;
+  int active, restart, pbuf, restarts;
+  int live;              // takes part in the current assembly / update
+  int pad[3];
+};
+
+struct Tile {
+  int prob;
+  int x0, y0, z0;
+  int tx, ty, tz;
+  int level;
+};
+
+// Launch context: the tables live in device memory.
+struct Tables {
+  LevelDev *lv;     // [kMaxLevels][nprob]
+  ProbDev *pd;      // [nprob]
+  StepDev *sd;      // [nprob]
+  Scal *sc;         // [nprob]
+  double *part;     // [n finest tiles][2] block partial sums
+  int nprob;
+};
+
+// A launch covers a subset of the full tile table: ranges[2r] is the first
+// block of range r, ranges[2r+1] the tile it maps to; ranges are sorted by
+// block.  nblocks = total blocks of the launch.
+struct TileList {
+  const Tile *base;     // device: full tile table
+  const int *ranges;    // device: 2 * nranges ints
+  int nranges;
+  int nblocks;
+};
+
+// ---- launchers (fld_kernels.hip) ----------------------------------------
+// prec: 0 = FP64 V-cycle, 1 = FP32 V-cycle.
+void launch_assemble(const Tables &T, TileList L0, double c, double theta,
+                     double dmax, double rmin, int mixed, hipStream_t s);
+void launch_coarsen(const Tables &T, TileList coarse, int lc, double scale,
+                    int mixed, hipStream_t s);
+void launch_fin(const Tables &T, int which, int mixed, hipStream_t s);
+void launch_pre0(const Tables &T, TileList L, int l, int prec, hipStream_t s);
+void launch_half(const Tables &T, TileList L, int l, int colour, int prec,
+                 hipStream_t s);
+void launch_half_out(const Tables &T, TileList L0, int prec, int flexible,
+                     hipStream_t s);
+void launch_resid_restrict(const Tables &T, TileList coarse, int lc, int prec,
+                           hipStream_t s);
+void launch_prolong_black(const Tables &T, TileList L, int l, int prec,
+                          hipStream_t s);
+void launch_coarse_solve(const Tables &T, int prec, hipStream_t s);
+void launch_spmv_p(const Tables &T, TileList L0, hipStream_t s);
+void launch_update(const Tables &T, TileList L0, hipStream_t s);
+void launch_true_resid(const Tables &T, TileList L0, hipStream_t s);
+void launch_apply(const Tables &T, TileList L0, const double *u, double *out,
+                  hipStream_t s);
+void launch_set_r(const Tables &T, TileList L0, const double *r, int prec,
+                  hipStream_t s);
+void launch_update_E(const Tables &T, TileList L0, double floor, int copy_only,
+                     hipStream_t s);
+
+// finalize kernels (launch_fin 'which')
+enum : int {
+  FIN_BB = 0,     // after assembly: ||b||^2, start the solve
+  FIN_RZ = 1,     // after the V-cycle: rho = r.z, beta
+  FIN_PQ = 2,     // after the SpMV: alpha = rho / p.q
+  FIN_RR = 3,     // after the update: ||r||^2, convergence
+  FIN_TRUE = 4,   // after the true residual: verify or restart
+  FIN_STEP = 5,   // after E += dE: relative change and ||dE||^2
+  FIN_SETR = 6    // after loading an external r (preconditioner test)
+};
+
+}  // namespace fld

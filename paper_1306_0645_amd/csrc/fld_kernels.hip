@@ -1,0 +1,1062 @@
+// HIP kernels (gfx950 / CDNA4) of the implicit grey FLD step.
+//
+// What is computed (Norman et al., arXiv:1306.0645):
+//  - assembly: the flux limiter on every face from E^n (Sec. 2) and the
+//    theta-method system (I - theta dt L) dE = dt (L E^n + eta) in
+//    residual-correction form (Sec. 3.3);
+//  - the multigrid V-cycle preconditioner with red/black Gauss-Seidel
+//    smoothing (Table 1);
+//  - the preconditioned conjugate-gradient recurrences (Table 1).
+//
+// All of this is memory-bound stencil and vector work (well under 1 flop per
+// byte), so no kernel uses MFMA.  Every kernel processes a list of tiles;
+// one 256-thread block (4 wave64) handles one tile: each thread owns one
+// (x, y) column of the tile and walks its tz planes, so x-consecutive lanes
+// read x-consecutive cells (coalesced).  Blocks are remapped so that each of
+// the 8 XCDs gets a contiguous run of tiles and neighbouring tiles share an L2.
+// Reductions are deterministic: a fixed wave64 butterfly, a fixed LDS order,
+// one partial per tile, then a per-problem finalize kernel that sums the
+// partials in tile order.
+
+#include "fld_internal.h"
+#include "fld_profile.h"
+
+#include <math.h>
+
+#include <vector>
+
+namespace fld {
+
+// ---------------------------------------------------------------------------
+// tile addressing
+// ---------------------------------------------------------------------------
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Renumber them so
+// that XCD x processes the contiguous block range [start_x, start_x + cnt_x).
+__device__ __forceinline__ int xcd_block(int nb) {
+  const int b = blockIdx.x;
+  const int x = b & 7, q = nb >> 3, rem = nb & 7;
+  return x * q + (x < rem ? x : rem) + (b >> 3);
+}
+
+__device__ __forceinline__ Tile get_tile(const TileList &L) {
+  const int b = xcd_block(L.nblocks);
+  int lo = 0;
+  if (L.nranges > 1) {
+    int hi = L.nranges - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (L.ranges[2 * mid] <= b) lo = mid; else hi = mid - 1;
+    }
+  }
+  return L.base[L.ranges[2 * lo + 1] + (b - L.ranges[2 * lo])];
+}
+
+// index of the tile inside the full table (for per-tile partial sums)
+__device__ __forceinline__ int get_tile_index(const TileList &L) {
+  const int b = xcd_block(L.nblocks);
+  int lo = 0;
+  if (L.nranges > 1) {
+    int hi = L.nranges - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (L.ranges[2 * mid] <= b) lo = mid; else hi = mid - 1;
+    }
+  }
+  return L.ranges[2 * lo + 1] + (b - L.ranges[2 * lo]);
+}
+
+struct Col {
+  int i, j;
+  bool on;
+};
+
+__device__ __forceinline__ Col tile_col(const Tile &t) {
+  Col c;
+  const int lx = threadIdx.x % t.tx, ly = threadIdx.x / t.tx;
+  c.i = t.x0 + lx;
+  c.j = t.y0 + ly;
+  c.on = ly < t.ty;
+  return c;
+}
+
+// linear indices of a cell and its 6 periodic neighbours
+struct Nb {
+  int c, xm, xp, ym, yp, zm, zp;
+};
+
+__device__ __forceinline__ Nb nbrs(int i, int j, int k, int nx, int ny, int nz) {
+  Nb n;
+  const int plane = nx * ny;
+  const int row = k * plane + j * nx;
+  n.c = row + i;
+  n.xm = row + (i == 0 ? nx - 1 : i - 1);
+  n.xp = row + (i == nx - 1 ? 0 : i + 1);
+  n.ym = (j == 0) ? n.c + (ny - 1) * nx : n.c - nx;
+  n.yp = (j == ny - 1) ? n.c - (ny - 1) * nx : n.c + nx;
+  n.zm = (k == 0) ? n.c + (nz - 1) * plane : n.c - plane;
+  n.zp = (k == nz - 1) ? n.c - (nz - 1) * plane : n.c + plane;
+  return n;
+}
+
+// ---------------------------------------------------------------------------
+// reductions (deterministic)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the block; the result is valid in every thread.
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) s += sh[i];
+  return s;
+}
+
+__device__ __forceinline__ void write_partials(const Tables &T, int tile,
+                                               double a0, double a1) {
+  __shared__ double sh[kBlock / 64];
+  const double s0 = block_sum<kBlock / 64>(a0, sh);
+  const double s1 = block_sum<kBlock / 64>(a1, sh);
+  if (threadIdx.x == 0) {
+    T.part[2 * tile] = s0;
+    T.part[2 * tile + 1] = s1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// typed access to a level's coefficients
+// ---------------------------------------------------------------------------
+
+template <typename R>
+struct Coef {
+  const R *tx, *ty, *tz, *d;
+};
+
+template <typename R>
+__device__ __forceinline__ Coef<R> coefs(const LevelDev &L);
+
+template <>
+__device__ __forceinline__ Coef<double> coefs<double>(const LevelDev &L) {
+  return {L.Tx, L.Ty, L.Tz, L.diag};
+}
+
+template <>
+__device__ __forceinline__ Coef<float> coefs<float>(const LevelDev &L) {
+  return {L.Tx32, L.Ty32, L.Tz32, L.diag32};
+}
+
+// sum over the 6 neighbours of T_face * u_neighbour
+template <typename R, typename U>
+__device__ __forceinline__ R offsum(const Coef<R> &C, const Nb &n, const U &u) {
+  return C.tx[n.c] * u(n.xp) + C.tx[n.xm] * u(n.xm) + C.ty[n.c] * u(n.yp) +
+         C.ty[n.ym] * u(n.ym) + C.tz[n.c] * u(n.zp) + C.tz[n.zm] * u(n.zm);
+}
+
+__device__ __forceinline__ double recip(double d) { return 1.0 / d; }
+__device__ __forceinline__ float recip(float d) {
+  return __builtin_amdgcn_rcpf(d);  // ~1 ulp: ample for a preconditioner
+}
+
+// ---------------------------------------------------------------------------
+// assembly (Sec. 2 limiter, Sec. 3.3 theta-method)
+// ---------------------------------------------------------------------------
+
+// D on the face between cells 1 and 2: arithmetic-mean E, harmonic-mean
+// kappa, R from the face-normal difference (floored at R_min, and R_min when
+// the face mean is not positive), capped at D_max.  Comparisons are written
+// so that NaN inputs propagate.
+__device__ __forceinline__ double face_D(double e1, double e2, double k1,
+                                         double k2, double ih, double c,
+                                         double dmax, double rmin) {
+  const double ebar = 0.5 * (e1 + e2);
+  const double ks = k1 + k2;
+  const double kb = (ks != 0.0) ? 2.0 * k1 * k2 / ks : 0.0;
+  double R = (ebar > 0.0) ? fabs(e2 - e1) * ih / ebar : rmin;
+  R = (R < rmin) ? rmin : R;
+  const double D = c / sqrt(9.0 * kb * kb + R * R);
+  return (D > dmax) ? dmax : D;
+}
+
+__global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
+                                                     double c, double theta,
+                                                     double dmax, double rmin,
+                                                     int mixed) {
+  const int tid = get_tile_index(L0);
+  const Tile t = L0.base[tid];
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.live) return;
+  const LevelDev L = T.lv[t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const StepDev S = T.sd[t.prob];
+  const Col col = tile_col(t);
+  const double tdt = theta * S.dt;
+  const double ix2 = S.idx * S.idx, iy2 = S.idy * S.idy, iz2 = S.idz * S.idz;
+  double bb = 0.0;
+  if (col.on) {
+    for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+      const Nb n = nbrs(col.i, col.j, k, L.nx, L.ny, L.nz);
+      const double *E = S.E, *K = S.kappa;
+      const double Ec = E[n.c], Kc = K[n.c];
+      const double Exp = E[n.xp], Exm = E[n.xm], Eyp = E[n.yp], Eym = E[n.ym];
+      const double Ezp = E[n.zp], Ezm = E[n.zm];
+      const double Dxp = face_D(Ec, Exp, Kc, K[n.xp], S.idx, c, dmax, rmin);
+      const double Dxm = face_D(Exm, Ec, K[n.xm], Kc, S.idx, c, dmax, rmin);
+      const double Dyp = face_D(Ec, Eyp, Kc, K[n.yp], S.idy, c, dmax, rmin);
+      const double Dym = face_D(Eym, Ec, K[n.ym], Kc, S.idy, c, dmax, rmin);
+      const double Dzp = face_D(Ec, Ezp, Kc, K[n.zp], S.idz, c, dmax, rmin);
+      const double Dzm = face_D(Ezm, Ec, K[n.zm], Kc, S.idz, c, dmax, rmin);
+      const double mu = S.adot_a + c * Kc;
+      const double faces = (Dxp + Dxm) * ix2 + (Dyp + Dym) * iy2 + (Dzp + Dzm) * iz2;
+      const double diag = 1.0 + tdt * (mu + faces);
+      const double LE = (Dxp * (Exp - Ec) - Dxm * (Ec - Exm)) * ix2 +
+                        (Dyp * (Eyp - Ec) - Dym * (Ec - Eym)) * iy2 +
+                        (Dzp * (Ezp - Ec) - Dzm * (Ec - Ezm)) * iz2 - mu * Ec;
+      const double b = S.dt * (LE + S.eta[n.c]);
+      const double tx = tdt * Dxp * ix2, ty = tdt * Dyp * iy2, tz = tdt * Dzp * iz2;
+      L.Tx[n.c] = tx;
+      L.Ty[n.c] = ty;
+      L.Tz[n.c] = tz;
+      L.diag[n.c] = diag;
+      if (mixed) {
+        L.Tx32[n.c] = (float)tx;
+        L.Ty32[n.c] = (float)ty;
+        L.Tz32[n.c] = (float)tz;
+        L.diag32[n.c] = (float)diag;
+      }
+      P.b[n.c] = b;
+      P.r[n.c] = b;
+      P.x[n.c] = 0.0;
+      bb += b * b;
+    }
+  }
+  write_partials(T, tid, bb, 0.0);
+}
+
+// Coarse operator of level lc from level lc-1 (one thread per coarse cell):
+// coarse faces are coarse_scale times the sum of the 4 fine faces they cover,
+// the coarse "mass" (diagonal minus faces) is the sum of the 8 children's.
+__global__ __launch_bounds__(kBlock) void k_coarsen(Tables T, TileList LC,
+                                                    int lc, double scale,
+                                                    int mixed) {
+  const Tile t = get_tile(LC);
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.live) return;
+  const LevelDev F = T.lv[(lc - 1) * T.nprob + t.prob];
+  const LevelDev C = T.lv[lc * T.nprob + t.prob];
+  const Col col = tile_col(t);
+  if (!col.on) return;
+  const int fx = F.nx, fy = F.ny, fz = F.nz;
+  for (int K = t.z0; K < t.z0 + t.tz; ++K) {
+    const int I = col.i, J = col.j;
+    double mass = 0.0, txp = 0.0, txm = 0.0, typ = 0.0, tym = 0.0, tzp = 0.0,
+           tzm = 0.0;
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+      for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx) {
+          const Nb n = nbrs(2 * I + cx, 2 * J + cy, 2 * K + cz, fx, fy, fz);
+          const double fxp = F.Tx[n.c], fxm = F.Tx[n.xm];
+          const double fyp = F.Ty[n.c], fym = F.Ty[n.ym];
+          const double fzp = F.Tz[n.c], fzm = F.Tz[n.zm];
+          mass += F.diag[n.c] - (fxp + fxm + fyp + fym + fzp + fzm);
+          if (cx == 1) txp += fxp; else txm += fxm;
+          if (cy == 1) typ += fyp; else tym += fym;
+          if (cz == 1) tzp += fzp; else tzm += fzm;
+        }
+    txp *= scale; txm *= scale; typ *= scale; tym *= scale; tzp *= scale;
+    tzm *= scale;
+    const double diag = mass + txp + txm + typ + tym + tzp + tzm;
+    const int o = (K * C.ny + J) * C.nx + I;
+    C.Tx[o] = txp;
+    C.Ty[o] = typ;
+    C.Tz[o] = tzp;
+    C.diag[o] = diag;
+    if (mixed) {
+      C.Tx32[o] = (float)txp;
+      C.Ty32[o] = (float)typ;
+      C.Tz32[o] = (float)tzp;
+      C.diag32[o] = (float)diag;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle kernels.  R = level precision, L0 = finest level (right-hand side is
+// the FP64 Krylov residual scaled by 1/s).
+// ---------------------------------------------------------------------------
+
+template <typename R, bool L0>
+struct FSrc {
+  const R *f;
+  const double *r;
+  double inv_s;
+  __device__ __forceinline__ R operator()(int c) const {
+    if constexpr (L0) return (R)(r[c] * inv_s);
+    else return f[c];
+  }
+};
+
+template <typename R, bool L0>
+__device__ __forceinline__ FSrc<R, L0> fsrc(const LevelDev &L, const ProbDev &P,
+                                             const Scal &sc) {
+  FSrc<R, L0> s;
+  s.f = (const R *)L.f;
+  s.r = P.r;
+  s.inv_s = sc.inv_s;
+  return s;
+}
+
+// First pre-smoothing sweep from x = 0: red cells x = f/d, then black cells
+// from those red values (computed on the fly, so one pass suffices).
+template <typename R, bool L0>
+__global__ __launch_bounds__(kBlock) void k_pre0(Tables T, TileList TL, int l) {
+  const Tile t = get_tile(TL);
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.active) return;
+  const LevelDev L = T.lv[l * T.nprob + t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const Coef<R> C = coefs<R>(L);
+  const auto f = fsrc<R, L0>(L, P, sc);
+  R *x = (R *)L.x;
+  const Col col = tile_col(t);
+  if (!col.on) return;
+  for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+    const Nb n = nbrs(col.i, col.j, k, L.nx, L.ny, L.nz);
+    R v;
+    if (((col.i + col.j + k) & 1) == 0) {
+      v = f(n.c) * recip(C.d[n.c]);
+    } else {
+      auto red = [&](int q) { return f(q) * recip(C.d[q]); };
+      v = (f(n.c) + offsum(C, n, red)) * recip(C.d[n.c]);
+    }
+    x[n.c] = v;
+  }
+}
+
+// One half-sweep of red/black Gauss-Seidel on the cells of one colour
+// (colour 0 = red = even i+j+k), in place.
+template <typename R, bool L0>
+__global__ __launch_bounds__(kBlock) void k_half(Tables T, TileList TL, int l,
+                                                 int colour) {
+  const Tile t = get_tile(TL);
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.active) return;
+  const LevelDev L = T.lv[l * T.nprob + t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const Coef<R> C = coefs<R>(L);
+  const auto f = fsrc<R, L0>(L, P, sc);
+  R *x = (R *)L.x;
+  const Col col = tile_col(t);
+  if (!col.on) return;
+  auto xv = [&](int q) { return x[q]; };
+  for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+    if (((col.i + col.j + k) & 1) != colour) continue;
+    const Nb n = nbrs(col.i, col.j, k, L.nx, L.ny, L.nz);
+    x[n.c] = (f(n.c) + offsum(C, n, xv)) * recip(C.d[n.c]);
+  }
+}
+
+// Black half-sweep fused with the coarse-grid correction: the red
+// neighbours are read as x + e(parent).  (The black cells' own corrected
+// value is overwritten by the sweep, so it is never formed.)
+template <typename R, bool L0>
+__global__ __launch_bounds__(kBlock) void k_prolong_black(Tables T, TileList TL,
+                                                          int l) {
+  const Tile t = get_tile(TL);
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.active) return;
+  const LevelDev L = T.lv[l * T.nprob + t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const bool has_coarse = l + 1 < P.levels;
+  const LevelDev Cl = T.lv[(has_coarse ? l + 1 : l) * T.nprob + t.prob];
+  const Coef<R> C = coefs<R>(L);
+  const auto f = fsrc<R, L0>(L, P, sc);
+  R *x = (R *)L.x;
+  const R *e = (const R *)Cl.x;
+  const int cnx = Cl.nx, cny = Cl.ny;
+  const Col col = tile_col(t);
+  if (!col.on) return;
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+    if (((col.i + col.j + k) & 1) != 1) continue;
+    const int i = col.i, j = col.j;
+    const Nb n = nbrs(i, j, k, nx, ny, nz);
+    R s;
+    if (has_coarse) {
+      const int im = i == 0 ? nx - 1 : i - 1, ip = i == nx - 1 ? 0 : i + 1;
+      const int jm = j == 0 ? ny - 1 : j - 1, jp = j == ny - 1 ? 0 : j + 1;
+      const int km = k == 0 ? nz - 1 : k - 1, kp = k == nz - 1 ? 0 : k + 1;
+      auto par = [&](int a, int b2, int c2) {
+        return e[((c2 >> 1) * cny + (b2 >> 1)) * cnx + (a >> 1)];
+      };
+      s = C.tx[n.c] * (x[n.xp] + par(ip, j, k)) +
+          C.tx[n.xm] * (x[n.xm] + par(im, j, k)) +
+          C.ty[n.c] * (x[n.yp] + par(i, jp, k)) +
+          C.ty[n.ym] * (x[n.ym] + par(i, jm, k)) +
+          C.tz[n.c] * (x[n.zp] + par(i, j, kp)) +
+          C.tz[n.zm] * (x[n.zm] + par(i, j, km));
+    } else {
+      auto xv = [&](int q) { return x[q]; };
+      s = offsum(C, n, xv);
+    }
+    x[n.c] = (f(n.c) + s) * recip(C.d[n.c]);
+  }
+}
+
+// Last red half-sweep on the finest level, producing z = s * x in FP64 and
+// the partial sums r.z and (flexible PCG) r.z_old.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_half_out(Tables T, TileList TL,
+                                                     int flexible) {
+  const int tid = get_tile_index(TL);
+  const Tile t = TL.base[tid];
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.active) return;
+  const LevelDev L = T.lv[t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const Coef<R> C = coefs<R>(L);
+  const auto f = fsrc<R, true>(L, P, sc);
+  R *x = (R *)L.x;
+  const double s = sc.s;
+  const Col col = tile_col(t);
+  double rz = 0.0, rzo = 0.0;
+  if (col.on) {
+    auto xv = [&](int q) { return x[q]; };
+    for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+      const Nb n = nbrs(col.i, col.j, k, L.nx, L.ny, L.nz);
+      R v;
+      const bool red = ((col.i + col.j + k) & 1) == 0;
+      if (red) v = (f(n.c) + offsum(C, n, xv)) * recip(C.d[n.c]);
+      else v = x[n.c];
+      const double rv = P.r[n.c];
+      double zv;
+      if constexpr (sizeof(R) == 8) {
+        // FP64: the finest iterate is z itself
+        zv = (double)v * s;
+        if (red) x[n.c] = (R)zv;
+      } else {
+        zv = (double)v * s;
+        if (flexible) rzo += rv * P.z[n.c];
+        P.z[n.c] = zv;
+      }
+      rz += rv * zv;
+    }
+  }
+  write_partials(T, tid, rz, rzo);
+}
+
+// Residual f - A x on the fine level summed over the 8 children of each
+// coarse cell: the coarse right-hand side (restriction = transpose of the
+// piecewise-constant prolongation).  One thread per coarse cell.
+template <typename R, bool L0>
+__global__ __launch_bounds__(kBlock) void k_resid_restrict(Tables T,
+                                                           TileList LC, int lc) {
+  const Tile t = get_tile(LC);
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.active) return;
+  const LevelDev F = T.lv[(lc - 1) * T.nprob + t.prob];
+  const LevelDev Cv = T.lv[lc * T.nprob + t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const Coef<R> C = coefs<R>(F);
+  const auto f = fsrc<R, L0>(F, P, sc);
+  const R *x = (const R *)F.x;
+  R *fc = (R *)Cv.f;
+  const Col col = tile_col(t);
+  if (!col.on) return;
+  auto xv = [&](int q) { return x[q]; };
+  for (int K = t.z0; K < t.z0 + t.tz; ++K) {
+    R acc = 0;
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+      for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx) {
+          const Nb n = nbrs(2 * col.i + cx, 2 * col.j + cy, 2 * K + cz, F.nx,
+                            F.ny, F.nz);
+          acc += f(n.c) - (C.d[n.c] * x[n.c] - offsum(C, n, xv));
+        }
+    fc[(K * Cv.ny + col.j) * Cv.nx + col.i] = acc;
+  }
+}
+
+// Coarsest level: Jacobi-preconditioned CG in FP64 by one workgroup per
+// problem, to a relative residual of 1e-12 (an effectively exact solve).
+template <typename R>
+__global__ __launch_bounds__(kCoarseBlock) void k_coarse_solve(Tables T) {
+  const int p = blockIdx.x;
+  const Scal &sc = T.sc[p];
+  const ProbDev P = T.pd[p];
+  if (!sc.active || P.levels < 2) return;
+  const int lc = P.levels - 1;
+  const LevelDev L = T.lv[lc * T.nprob + p];
+  const int n = L.n, nx = L.nx, ny = L.ny, nz = L.nz;
+  double *xs = P.cs, *rs = P.cs + n, *ps = P.cs + 2 * n, *qs = P.cs + 3 * n;
+  const R *f = (const R *)L.f;
+  R *xo = (R *)L.x;
+  __shared__ double sh[kCoarseBlock / 64];
+  double acc = 0.0;
+  for (int c = threadIdx.x; c < n; c += kCoarseBlock) {
+    const double v = (double)f[c];
+    rs[c] = v;
+    xs[c] = 0.0;
+    acc += v * v;
+  }
+  const double bb = block_sum<kCoarseBlock / 64>(acc, sh);
+  double rz_old = 1.0;
+  if (bb > 0.0) {
+    for (int it = 0; it < 1000; ++it) {
+      acc = 0.0;
+      for (int c = threadIdx.x; c < n; c += kCoarseBlock) acc += rs[c] * rs[c] / L.diag[c];
+      const double rz = block_sum<kCoarseBlock / 64>(acc, sh);
+      const double beta = it == 0 ? 0.0 : rz / rz_old;
+      rz_old = rz;
+      for (int c = threadIdx.x; c < n; c += kCoarseBlock)
+        ps[c] = rs[c] / L.diag[c] + (it == 0 ? 0.0 : beta * ps[c]);
+      __syncthreads();
+      acc = 0.0;
+      for (int c = threadIdx.x; c < n; c += kCoarseBlock) {
+        const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+        const Nb nb = nbrs(i, j, k, nx, ny, nz);
+        const double q = L.diag[c] * ps[c] -
+                         (L.Tx[c] * ps[nb.xp] + L.Tx[nb.xm] * ps[nb.xm] +
+                          L.Ty[c] * ps[nb.yp] + L.Ty[nb.ym] * ps[nb.ym] +
+                          L.Tz[c] * ps[nb.zp] + L.Tz[nb.zm] * ps[nb.zm]);
+        qs[c] = q;
+        acc += ps[c] * q;
+      }
+      const double pq = block_sum<kCoarseBlock / 64>(acc, sh);
+      const double alpha = rz / pq;
+      acc = 0.0;
+      for (int c = threadIdx.x; c < n; c += kCoarseBlock) {
+        xs[c] += alpha * ps[c];
+        const double r = rs[c] - alpha * qs[c];
+        rs[c] = r;
+        acc += r * r;
+      }
+      const double rr = block_sum<kCoarseBlock / 64>(acc, sh);
+      if (!(rr > 1e-24 * bb)) break;  // converged (or NaN: stop)
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += kCoarseBlock) xo[c] = (R)xs[c];
+}
+
+// ---------------------------------------------------------------------------
+// Krylov kernels (FP64, finest level)
+// ---------------------------------------------------------------------------
+
+// p_new = z + beta p_old (formed at the cell and its neighbours on the fly),
+// q = A p_new, partial p_new . q.  p is double-buffered so neighbours read
+// the old direction while the new one is written.
+__global__ __launch_bounds__(kBlock) void k_spmv_p(Tables T, TileList TL) {
+  const int tid = get_tile_index(TL);
+  const Tile t = TL.base[tid];
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.active) return;
+  const LevelDev L = T.lv[t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const double beta = sc.beta;
+  const double *po = sc.pbuf ? P.p1 : P.p0;
+  double *pn = sc.pbuf ? P.p0 : P.p1;
+  const double *z = P.z;
+  const Coef<double> C = coefs<double>(L);
+  const Col col = tile_col(t);
+  double pq = 0.0;
+  if (col.on) {
+    for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+      const Nb n = nbrs(col.i, col.j, k, L.nx, L.ny, L.nz);
+      double pc, s;
+      if (beta != 0.0) {
+        auto pv = [&](int q) { return z[q] + beta * po[q]; };
+        pc = pv(n.c);
+        s = offsum(C, n, pv);
+      } else {
+        auto pv = [&](int q) { return z[q]; };
+        pc = pv(n.c);
+        s = offsum(C, n, pv);
+      }
+      const double q = C.d[n.c] * pc - s;
+      pn[n.c] = pc;
+      P.q[n.c] = q;
+      pq += pc * q;
+    }
+  }
+  write_partials(T, tid, pq, 0.0);
+}
+
+// x += alpha p, r -= alpha q, partial ||r||^2
+__global__ __launch_bounds__(kBlock) void k_update(Tables T, TileList TL) {
+  const int tid = get_tile_index(TL);
+  const Tile t = TL.base[tid];
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.active) return;
+  const LevelDev L = T.lv[t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const double alpha = sc.alpha;
+  const double *p = sc.pbuf ? P.p1 : P.p0;
+  const Col col = tile_col(t);
+  double rr = 0.0;
+  if (col.on) {
+    for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+      const int c = (k * L.ny + col.j) * L.nx + col.i;
+      P.x[c] += alpha * p[c];
+      const double r = P.r[c] - alpha * P.q[c];
+      P.r[c] = r;
+      rr += r * r;
+    }
+  }
+  write_partials(T, tid, rr, 0.0);
+}
+
+// true residual r = b - A x in FP64 (problems whose recursive residual met
+// the tolerance), partial ||r||^2
+__global__ __launch_bounds__(kBlock) void k_true_resid(Tables T, TileList TL) {
+  const int tid = get_tile_index(TL);
+  const Tile t = TL.base[tid];
+  const Scal &sc = T.sc[t.prob];
+  if (sc.phase != PH_VERIFY) return;
+  const LevelDev L = T.lv[t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const Coef<double> C = coefs<double>(L);
+  const Col col = tile_col(t);
+  double rr = 0.0;
+  if (col.on) {
+    auto xv = [&](int q) { return P.x[q]; };
+    for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+      const Nb n = nbrs(col.i, col.j, k, L.nx, L.ny, L.nz);
+      const double r = P.b[n.c] - (C.d[n.c] * P.x[n.c] - offsum(C, n, xv));
+      P.r[n.c] = r;
+      rr += r * r;
+    }
+  }
+  write_partials(T, tid, rr, 0.0);
+}
+
+// out = A u (single problem, inspection entry point)
+__global__ __launch_bounds__(kBlock) void k_apply(Tables T, TileList TL,
+                                                  const double *u, double *out) {
+  const Tile t = get_tile(TL);
+  const LevelDev L = T.lv[t.prob];
+  const Coef<double> C = coefs<double>(L);
+  const Col col = tile_col(t);
+  if (!col.on) return;
+  auto uv = [&](int q) { return u[q]; };
+  for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+    const Nb n = nbrs(col.i, col.j, k, L.nx, L.ny, L.nz);
+    out[n.c] = C.d[n.c] * u[n.c] - offsum(C, n, uv);
+  }
+}
+
+// load an external residual (preconditioner entry point): r = given, ||r||^2
+__global__ __launch_bounds__(kBlock) void k_set_r(Tables T, TileList TL,
+                                                  const double *rin) {
+  const int tid = get_tile_index(TL);
+  const Tile t = TL.base[tid];
+  const LevelDev L = T.lv[t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const Col col = tile_col(t);
+  double rr = 0.0;
+  if (col.on) {
+    for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+      const int c = (k * L.ny + col.j) * L.nx + col.i;
+      const double r = rin[c];
+      P.r[c] = r;
+      rr += r * r;
+    }
+  }
+  write_partials(T, tid, rr, 0.0);
+}
+
+// E_out = E + dE with the relative-change sum (dE / max(|E_out|, floor))^2
+// and ||dE||^2; copy_only: E_out = dE (solve entry point).
+__global__ __launch_bounds__(kBlock) void k_update_E(Tables T, TileList TL,
+                                                     double floor,
+                                                     int copy_only) {
+  const int tid = get_tile_index(TL);
+  const Tile t = TL.base[tid];
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.live) return;
+  const LevelDev L = T.lv[t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const StepDev S = T.sd[t.prob];
+  const Col col = tile_col(t);
+  double ch = 0.0, dd = 0.0;
+  if (col.on) {
+    for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+      const int c = (k * L.ny + col.j) * L.nx + col.i;
+      const double d = P.x[c];
+      dd += d * d;
+      if (copy_only) {
+        S.Eout[c] = d;
+      } else {
+        const double e = S.E[c] + d;
+        S.Eout[c] = e;
+        double w = fabs(e);
+        w = (w < floor) ? floor : w;
+        if (w > 0.0) {
+          const double q = d / w;
+          ch += q * q;
+        }
+      }
+    }
+  }
+  write_partials(T, tid, ch, dd);
+}
+
+// ---------------------------------------------------------------------------
+// per-problem finalize: sum the tile partials in tile order, update scalars
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool finite(double v) { return isfinite(v); }
+
+__device__ __forceinline__ void set_scale(Scal &sc, int n, int mixed) {
+  double s = 1.0;
+  if (mixed) {
+    s = sqrt(sc.rr / (double)n);
+    if (!(s > 0.0) || !finite(s)) s = 1.0;
+  }
+  sc.s = s;
+  sc.inv_s = 1.0 / s;
+}
+
+__device__ __forceinline__ void fail(Scal &sc, int status) {
+  sc.status = status;
+  sc.phase = PH_DONE;
+  sc.active = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fin(Tables T, int which, int mixed) {
+  const int p = blockIdx.x;
+  Scal &sc = T.sc[p];
+  const ProbDev P = T.pd[p];
+  bool part;
+  switch (which) {
+    case FIN_BB:
+    case FIN_STEP: part = sc.live != 0; break;
+    case FIN_TRUE: part = sc.phase == PH_VERIFY; break;
+    case FIN_SETR: part = true; break;
+    default: part = sc.active != 0; break;
+  }
+  if (!part) return;
+  double a0 = 0.0, a1 = 0.0;
+  for (int t = P.t0 + (int)threadIdx.x; t < P.t1; t += kBlock) {
+    a0 += T.part[2 * t];
+    a1 += T.part[2 * t + 1];
+  }
+  __shared__ double sh[kBlock / 64];
+  a0 = block_sum<kBlock / 64>(a0, sh);
+  a1 = block_sum<kBlock / 64>(a1, sh);
+  if (threadIdx.x != 0) return;
+  switch (which) {
+    case FIN_BB:
+      sc.bb = a0;
+      sc.rr = a0;
+      sc.rr_true = a0;
+      sc.iter = 0;
+      sc.restart = 1;
+      sc.restarts = 0;
+      sc.pbuf = 0;
+      sc.status = ST_OK;
+      sc.phase = PH_ITER;
+      sc.active = 1;
+      if (!finite(a0)) fail(sc, ST_ENONFINITE);
+      else if (a0 == 0.0) { sc.phase = PH_DONE; sc.active = 0; }
+      set_scale(sc, P.n, mixed);
+      break;
+    case FIN_RZ: {
+      sc.rho = a0;
+      sc.rzo = a1;
+      if (!finite(a0) || !finite(a1)) { fail(sc, ST_ENONFINITE); break; }
+      if (!(a0 > 0.0)) { fail(sc, ST_ENOCONV); break; }
+      double beta = 0.0;
+      if (!sc.restart) beta = mixed ? (a0 - a1) / sc.rho_old : a0 / sc.rho_old;
+      sc.beta = beta;
+      sc.restart = 0;
+      sc.rho_old = a0;
+      break;
+    }
+    case FIN_PQ:
+      sc.pq = a0;
+      if (!finite(a0)) { fail(sc, ST_ENONFINITE); break; }
+      if (!(a0 > 0.0)) { fail(sc, ST_ENOCONV); break; }
+      sc.alpha = sc.rho / a0;
+      sc.pbuf ^= 1;
+      break;
+    case FIN_RR:
+      sc.rr = a0;
+      sc.iter += 1;
+      if (!finite(a0)) { fail(sc, ST_ENONFINITE); break; }
+      if (a0 <= sc.tol2 * sc.bb) {
+        sc.phase = PH_VERIFY;
+        sc.active = 0;
+      } else if (sc.iter >= sc.max_iter) {
+        fail(sc, ST_ENOCONV);
+      }
+      set_scale(sc, P.n, mixed);
+      break;
+    case FIN_TRUE:
+      sc.rr_true = a0;
+      sc.rr = a0;
+      if (!finite(a0)) { fail(sc, ST_ENONFINITE); break; }
+      if (a0 <= sc.tol2 * sc.bb) {
+        sc.status = ST_OK;
+        sc.phase = PH_DONE;
+        sc.active = 0;
+      } else if (sc.iter < sc.max_iter) {
+        sc.phase = PH_ITER;
+        sc.active = 1;
+        sc.restart = 1;
+        sc.restarts += 1;
+        set_scale(sc, P.n, mixed);
+      } else {
+        fail(sc, ST_ENOCONV);
+      }
+      break;
+    case FIN_STEP:
+      sc.change2 = a0;
+      sc.dEdE = a1;
+      break;
+    case FIN_SETR:
+      sc.rr = a0;
+      sc.active = 1;
+      sc.phase = PH_ITER;
+      set_scale(sc, P.n, mixed);
+      break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-kernel timing hook (include/fld_profile.h)
+// ---------------------------------------------------------------------------
+
+enum : int {
+  K_ASSEMBLE, K_COARSEN, K_FIN, K_PRE0_F, K_PRE0_C, K_HALF_F, K_HALF_C,
+  K_HALF_OUT, K_RESTRICT_F, K_RESTRICT_C, K_PROLONG_F, K_PROLONG_C,
+  K_COARSE_SOLVE, K_SPMV_P, K_UPDATE, K_TRUE_RESID, K_APPLY, K_SET_R,
+  K_UPDATE_E, K_NUM
+};
+
+static const char *kKernelNames[K_NUM] = {
+    "assemble", "coarsen", "fin", "pre0_fine", "pre0_coarse", "half_fine",
+    "half_coarse", "half_out", "resid_restrict_fine", "resid_restrict_coarse",
+    "prolong_black_fine", "prolong_black_coarse", "coarse_solve", "spmv_p",
+    "update", "true_resid", "apply", "set_r", "update_E"};
+
+namespace prof {
+struct Rec {
+  hipEvent_t a, b;
+  int k;
+};
+static int sel = -1;
+static std::vector<Rec> recs;
+static std::vector<hipEvent_t> pool;
+
+static hipEvent_t get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+static bool on(int k, hipStream_t s) {
+  if (!(sel == k || sel == -2)) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return false;
+  return true;
+}
+
+struct Scope {
+  int k;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Scope(int k_, hipStream_t s_) : k(k_), s(s_) {
+    if (on(k, s)) {
+      a = get();
+      if (a) hipEventRecord(a, s);
+    }
+  }
+  ~Scope() {
+    if (!a) return;
+    hipEvent_t b = get();
+    if (!b) return;
+    hipEventRecord(b, s);
+    recs.push_back({a, b, k});
+  }
+};
+}  // namespace prof
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+#define LAUNCH(id, kern, grid, block, s, ...)                              \
+  do {                                                                     \
+    prof::Scope _ps((id), (s));                                            \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, __VA_ARGS__);  \
+  } while (0)
+
+void launch_assemble(const Tables &T, TileList L0, double c, double theta,
+                     double dmax, double rmin, int mixed, hipStream_t s) {
+  if (L0.nblocks) LAUNCH(K_ASSEMBLE, k_assemble, L0.nblocks, kBlock, s, T, L0, c, theta, dmax, rmin, mixed);
+}
+
+void launch_coarsen(const Tables &T, TileList LC, int lc, double scale,
+                    int mixed, hipStream_t s) {
+  if (LC.nblocks) LAUNCH(K_COARSEN, k_coarsen, LC.nblocks, kBlock, s, T, LC, lc, scale, mixed);
+}
+
+void launch_fin(const Tables &T, int which, int mixed, hipStream_t s) {
+  if (T.nprob) LAUNCH(K_FIN, k_fin, T.nprob, kBlock, s, T, which, mixed);
+}
+
+void launch_pre0(const Tables &T, TileList L, int l, int prec, hipStream_t s) {
+  if (!L.nblocks) return;
+  const int id = l == 0 ? K_PRE0_F : K_PRE0_C;
+  if (prec) {
+    if (l == 0) LAUNCH(id, (k_pre0<float, true>), L.nblocks, kBlock, s, T, L, l);
+    else LAUNCH(id, (k_pre0<float, false>), L.nblocks, kBlock, s, T, L, l);
+  } else {
+    if (l == 0) LAUNCH(id, (k_pre0<double, true>), L.nblocks, kBlock, s, T, L, l);
+    else LAUNCH(id, (k_pre0<double, false>), L.nblocks, kBlock, s, T, L, l);
+  }
+}
+
+void launch_half(const Tables &T, TileList L, int l, int colour, int prec,
+                 hipStream_t s) {
+  if (!L.nblocks) return;
+  const int id = l == 0 ? K_HALF_F : K_HALF_C;
+  if (prec) {
+    if (l == 0) LAUNCH(id, (k_half<float, true>), L.nblocks, kBlock, s, T, L, l, colour);
+    else LAUNCH(id, (k_half<float, false>), L.nblocks, kBlock, s, T, L, l, colour);
+  } else {
+    if (l == 0) LAUNCH(id, (k_half<double, true>), L.nblocks, kBlock, s, T, L, l, colour);
+    else LAUNCH(id, (k_half<double, false>), L.nblocks, kBlock, s, T, L, l, colour);
+  }
+}
+
+void launch_half_out(const Tables &T, TileList L0, int prec, int flexible,
+                     hipStream_t s) {
+  if (!L0.nblocks) return;
+  if (prec) LAUNCH(K_HALF_OUT, (k_half_out<float>), L0.nblocks, kBlock, s, T, L0, flexible);
+  else LAUNCH(K_HALF_OUT, (k_half_out<double>), L0.nblocks, kBlock, s, T, L0, flexible);
+}
+
+void launch_resid_restrict(const Tables &T, TileList LC, int lc, int prec,
+                           hipStream_t s) {
+  if (!LC.nblocks) return;
+  const int id = lc == 1 ? K_RESTRICT_F : K_RESTRICT_C;
+  if (prec) {
+    if (lc == 1) LAUNCH(id, (k_resid_restrict<float, true>), LC.nblocks, kBlock, s, T, LC, lc);
+    else LAUNCH(id, (k_resid_restrict<float, false>), LC.nblocks, kBlock, s, T, LC, lc);
+  } else {
+    if (lc == 1) LAUNCH(id, (k_resid_restrict<double, true>), LC.nblocks, kBlock, s, T, LC, lc);
+    else LAUNCH(id, (k_resid_restrict<double, false>), LC.nblocks, kBlock, s, T, LC, lc);
+  }
+}
+
+void launch_prolong_black(const Tables &T, TileList L, int l, int prec,
+                          hipStream_t s) {
+  if (!L.nblocks) return;
+  const int id = l == 0 ? K_PROLONG_F : K_PROLONG_C;
+  if (prec) {
+    if (l == 0) LAUNCH(id, (k_prolong_black<float, true>), L.nblocks, kBlock, s, T, L, l);
+    else LAUNCH(id, (k_prolong_black<float, false>), L.nblocks, kBlock, s, T, L, l);
+  } else {
+    if (l == 0) LAUNCH(id, (k_prolong_black<double, true>), L.nblocks, kBlock, s, T, L, l);
+    else LAUNCH(id, (k_prolong_black<double, false>), L.nblocks, kBlock, s, T, L, l);
+  }
+}
+
+void launch_coarse_solve(const Tables &T, int prec, hipStream_t s) {
+  if (!T.nprob) return;
+  if (prec) LAUNCH(K_COARSE_SOLVE, (k_coarse_solve<float>), T.nprob, kCoarseBlock, s, T);
+  else LAUNCH(K_COARSE_SOLVE, (k_coarse_solve<double>), T.nprob, kCoarseBlock, s, T);
+}
+
+void launch_spmv_p(const Tables &T, TileList L0, hipStream_t s) {
+  if (L0.nblocks) LAUNCH(K_SPMV_P, k_spmv_p, L0.nblocks, kBlock, s, T, L0);
+}
+
+void launch_update(const Tables &T, TileList L0, hipStream_t s) {
+  if (L0.nblocks) LAUNCH(K_UPDATE, k_update, L0.nblocks, kBlock, s, T, L0);
+}
+
+void launch_true_resid(const Tables &T, TileList L0, hipStream_t s) {
+  if (L0.nblocks) LAUNCH(K_TRUE_RESID, k_true_resid, L0.nblocks, kBlock, s, T, L0);
+}
+
+void launch_apply(const Tables &T, TileList L0, const double *u, double *out,
+                  hipStream_t s) {
+  if (L0.nblocks) LAUNCH(K_APPLY, k_apply, L0.nblocks, kBlock, s, T, L0, u, out);
+}
+
+void launch_set_r(const Tables &T, TileList L0, const double *r, int prec,
+                  hipStream_t s) {
+  (void)prec;
+  if (L0.nblocks) LAUNCH(K_SET_R, k_set_r, L0.nblocks, kBlock, s, T, L0, r);
+}
+
+void launch_update_E(const Tables &T, TileList L0, double floor, int copy_only,
+                     hipStream_t s) {
+  if (L0.nblocks) LAUNCH(K_UPDATE_E, k_update_E, L0.nblocks, kBlock, s, T, L0, floor, copy_only);
+}
+
+}  // namespace fld
+
+extern "C" {
+
+int32_t fld_profile_num_kernels(void) { return fld::K_NUM; }
+
+const char *fld_profile_kernel_name(int32_t k) {
+  return (k >= 0 && k < fld::K_NUM) ? fld::kKernelNames[k] : nullptr;
+}
+
+int32_t fld_profile_select(int32_t k) {
+  if (k < -2 || k >= fld::K_NUM) return -1;
+  for (auto &r : fld::prof::recs) {
+    hipEventSynchronize(r.b);
+    fld::prof::pool.push_back(r.a);
+    fld::prof::pool.push_back(r.b);
+  }
+  fld::prof::recs.clear();
+  fld::prof::sel = k;
+  return 0;
+}
+
+int32_t fld_profile_read(int32_t k, double *total_ms, int64_t *launches) {
+  if (k < 0 || k >= fld::K_NUM) return -1;
+  double tot = 0.0;
+  int64_t cnt = 0;
+  for (auto &r : fld::prof::recs) {
+    if (r.k != k) continue;
+    if (hipEventSynchronize(r.b) != hipSuccess) return -1;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return -1;
+    tot += ms;
+    ++cnt;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = cnt;
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point include/fld.h declares, and its pure-host calls (defaults,
+workspace sizing, argument validation) behave as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT, read_golden
+
+HEADERS = [os.path.join(ROOT, "include", h)
+           for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
+
+
+def declared_functions():
+    names = set()
+    for hdr in HEADERS:
+        src = open(hdr).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(fld_[a-z_]+)\s*\(", src))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def fld():
+    import paper_1306_0645_amd as m
+    return m
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("fld_assemble", "fld_solve", "fld_step", "fld_create",
+                 "fld_destroy", "fld_batch_step", "fld_server_submit"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(fld):
+    lib = ctypes.CDLL(fld.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_functions()) == set(fld.EXPORTS)
+
+
+def test_default_params_follow_the_paper(fld):
+    t1 = read_golden("solver_table1.txt")
+    lc = read_golden("limiter_constants.txt")
+    c, L = 2.99792458e10, 2.037e22
+    p = fld.fld_default_params(c, L)
+    assert p.d_max == pytest.approx(float(lc["dmax_factor"]) * c * L, rel=1e-15)
+    assert p.r_min == pytest.approx(float(lc["rmin_factor"]) / L, rel=1e-15)
+    assert p.tau_tol == float(lc["tau_tol"])
+    assert p.rtol == float(t1["cg_tolerance"])
+    assert p.max_iter == int(t1["cg_max_iterations"])
+    assert p.nu_pre == int(t1["mg_pre_sweeps"])
+    assert p.nu_post == int(t1["mg_post_sweeps"])
+    assert p.theta == 1.0 and p.precision == fld.FLD_PREC_FP64
+
+
+def test_workspace_sizing_and_validation(fld):
+    p = fld.fld_default_params(1.0, 1.0)
+    g = fld.make_grid((32, 32, 32), (1.0, 1.0, 1.0))
+    b64 = fld.fld_workspace_bytes(g, p)
+    # 7 Krylov vectors + 4 coefficient arrays + E copy on the finest level
+    assert b64 >= 12 * 8 * 32 ** 3
+    pm = fld.fld_default_params(1.0, 1.0, precision=fld.FLD_PREC_MIXED)
+    assert fld.fld_workspace_bytes(g, pm) > b64
+    for bad in [(31, 32, 32), (32, 2, 32), (0, 32, 32)]:
+        assert fld.fld_workspace_bytes(fld.make_grid(bad, (1, 1, 1)), p) == 0
+    assert fld.fld_workspace_bytes(fld.make_grid((8, 8, 8), (1, -1, 1)), p) == 0
+    for field, val in [("theta", 0.3), ("c", 0.0), ("nu_pre", 0),
+                       ("precision", 7), ("max_iter", 0)]:
+        q = fld.fld_default_params(1.0, 1.0, **{field: val})
+        assert fld.fld_workspace_bytes(g, q) == 0, field
+
+
+def test_create_rejects_bad_arguments_before_any_launch(fld):
+    lib = fld._lib
+    p = fld.fld_default_params(1.0, 1.0)
+    h = ctypes.c_void_p()
+    bad = fld.make_grid((8, 8, 7), (1, 1, 1))
+    assert lib.fld_create(ctypes.byref(bad), ctypes.byref(p), None,
+                          ctypes.c_void_p(256), 1 << 30,
+                          ctypes.byref(h)) == fld.FLD_EINVAL
+    good = fld.make_grid((8, 8, 8), (1, 1, 1))
+    # misaligned workspace
+    assert lib.fld_create(ctypes.byref(good), ctypes.byref(p), None,
+                          ctypes.c_void_p(4096 + 8), 1 << 30,
+                          ctypes.byref(h)) == fld.FLD_EINVAL
+    # too small
+    assert lib.fld_create(ctypes.byref(good), ctypes.byref(p), None,
+                          ctypes.c_void_p(4096), 16,
+                          ctypes.byref(h)) == fld.FLD_ENOMEM
+    assert fld.fld_strerror(fld.FLD_ENOCONV).startswith("linear solve")

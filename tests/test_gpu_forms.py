@@ -1,0 +1,130 @@
+"""GPU tests of the batched and served forms: each problem's result is the
+same in a batch or a server mix as when solved alone (bit for bit: per-problem
+reductions run in a fixed tile order), and matches the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import dev, host, log_case, oracle_problem, params, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(16, 16, 16), (32, 32, 32), (24, 24, 24), (48, 48, 48), (32, 16, 64)]
+
+
+@pytest.fixture(scope="module")
+def fld():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1306_0645_amd as m
+    return m
+
+
+def _probs(seed0=40, dtf=0.02):
+    ps = []
+    for i, sh in enumerate(SHAPES):
+        p = synth.random_problem(sh, seed0 + i, sigma_ln=0.5 + 0.3 * i,
+                                 n_src=1 + 3 * i, dt_factor=dtf)
+        ps.append(p)
+    return ps
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_equals_single_and_oracle(fld, oracle_mod, prec):
+    log_case("batch", prec=prec)
+    ps = _probs()
+    prm = params(fld, ps[0], precision=prec)
+    # per-problem paper limits differ with the box size: use one set for all
+    singles = []
+    for p in ps:
+        S = fld.Solver(p["shape"], p["h"], prm)
+        E = dev(p["E"])
+        st = S.step(E, dev(p["kappa"]), dev(p["eta"]), p["dt"])
+        singles.append((host(E), st))
+    B = fld.Batch([p["shape"] for p in ps], [p["h"] for p in ps], prm)
+    Es = [dev(p["E"]) for p in ps]
+    sts = B.step(Es, [dev(p["kappa"]) for p in ps], [dev(p["eta"]) for p in ps],
+                 [p["dt"] for p in ps])
+    for p, E, st, (Es1, st1) in zip(ps, Es, sts, singles):
+        assert st["status"] == 0
+        assert st["iters"] == st1["iters"]
+        assert np.array_equal(host(E), Es1)
+        dEo, _, _, _ = oracle_problem(oracle_mod, p, prm).solve(tol=1e-13)
+        assert rel_l2(host(E), p["E"] + dEo) <= (1e-6 if prec == 0 else 1e-5)
+
+
+def _oracle_steps(oracle_mod, p, prm, n):
+    E = p["E"].copy()
+    for _ in range(n):
+        q = dict(p)
+        q["E"] = E
+        dEo, st, _, _ = oracle_problem(oracle_mod, q, prm).solve(tol=1e-13)
+        E = E + dEo
+    return E
+
+
+@pytest.mark.parametrize("prec", [1])
+def test_server_alone_equals_mix(fld, oracle_mod, prec):
+    import torch
+    log_case("server", prec=prec)
+    ps = _probs(seed0=60)
+    steps = [1, 2, 3, 1, 2]
+    prm = params(fld, ps[0], precision=prec)
+    srv = fld.Server(prm, 1 << 30)
+    dp = [(dev(p["E"]), dev(p["kappa"]), dev(p["eta"])) for p in ps]
+    torch.cuda.synchronize()
+    alone = []
+    for p, (E, K, H), n in zip(ps, dp, steps):
+        out = torch.empty_like(E)
+        t = srv.submit(p["shape"], p["h"], E, K, H, out, p["dt"], n_steps=n)
+        srv.drain()
+        res = srv.poll(t)
+        assert res is not None and res["status"] == 0, res
+        assert res["steps_done"] == n
+        alone.append(host(out))
+    outs, tickets = [], []
+    for p, (E, K, H), n in zip(ps, dp, steps):
+        out = torch.empty_like(E)
+        outs.append(out)
+        tickets.append(srv.submit(p["shape"], p["h"], E, K, H, out, p["dt"],
+                                  n_steps=n))
+    srv.drain()
+    for i, t in enumerate(tickets):
+        res = srv.poll(t)
+        assert res["status"] == 0
+        assert res["latency_s"] >= res["queue_s"] >= 0
+        assert np.array_equal(host(outs[i]), alone[i]), i
+    srv.close()
+    # parity of the served results against the oracle
+    for p, n, a in zip(ps, steps, alone):
+        assert rel_l2(a, _oracle_steps(oracle_mod, p, prm, n)) <= 1e-5
+
+
+def test_server_admission_under_a_small_budget(fld):
+    """An arena that holds only a couple of requests at a time: later requests
+    wait for space, every request completes, and results equal the alone run."""
+    import torch
+    log_case("server_budget")
+    ps = _probs(seed0=80)
+    prm = params(fld, ps[0], precision=1)
+    need = max(fld.fld_workspace_bytes(fld.make_grid(p["shape"], p["h"]), prm)
+               for p in ps)
+    srv = fld.Server(prm, int(2.2 * need))
+    dp = [(dev(p["E"]), dev(p["kappa"]), dev(p["eta"])) for p in ps]
+    torch.cuda.synchronize()
+    outs, tickets = [], []
+    for p, (E, K, H) in zip(ps, dp):
+        out = torch.empty_like(E)
+        outs.append(out)
+        tickets.append(srv.submit(p["shape"], p["h"], E, K, H, out, p["dt"]))
+    srv.drain()
+    ref = fld.Server(prm, 1 << 30)
+    for i, (p, (E, K, H)) in enumerate(zip(ps, dp)):
+        assert srv.poll(tickets[i])["status"] == 0
+        o = torch.empty_like(E)
+        t = ref.submit(p["shape"], p["h"], E, K, H, o, p["dt"])
+        ref.drain()
+        assert ref.poll(t)["status"] == 0
+        assert np.array_equal(host(o), host(outs[i]))
+    srv.close()
+    ref.close()

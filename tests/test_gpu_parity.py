@@ -1,0 +1,300 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle.
+
+Gates (from the method's required accuracy): relative L2 error of dE (or
+E^{n+1}) at most 1e-6 in FP64 and 1e-5 in mixed precision, the true FP64
+residual of the GPU result (computed by the oracle's own operator) at most the
+1e-8 PCG tolerance, and the a-posteriori bound ||dE - dE*|| <= ||b - A dE||
+(since ||A^-1||_2 <= 1 for adot >= 0) holding.  Inputs are seeded synthetic
+fields of the paper's kind (lognormal opacity, point-source emissivity).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import dev, host, log_case, oracle_problem, params, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+GATE = {0: 1e-6, 1: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def fld():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1306_0645_amd as m
+    return m
+
+
+def _problem(shape, seed, theta=1.0, aniso=True, adot_frac=0.0, dt_factor=0.05,
+             E_mode="smooth", sigma_ln=1.5):
+    p = synth.random_problem(shape, seed, sigma_ln=sigma_ln, n_src=3,
+                             dt_factor=dt_factor, E_mode=E_mode, theta=theta)
+    if aniso:
+        dx = p["h"][0]
+        p["h"] = (dx, 1.25 * dx, 0.8 * dx)
+    p["adot"] = adot_frac / p["dt"]
+    return p
+
+
+def _solver(fld, p, **kw):
+    prm = params(fld, p, **kw)
+    return fld.Solver(p["shape"], p["h"], prm), prm
+
+
+def _assemble(S, p):
+    S.assemble(dev(p["E"]), dev(p["kappa"]), dev(p["eta"]), p["dt"], p["a"],
+               p["adot"])
+
+
+ASM_CASES = [((8, 8, 8), 1.0), ((12, 16, 20), 0.5), ((48, 48, 48), 1.0),
+             ((40, 64, 96), 1.0)]
+
+
+@pytest.mark.parametrize("shape,theta", ASM_CASES)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_assembly_matches_oracle(fld, oracle_mod, shape, theta, prec):
+    log_case("assembly", shape=shape, theta=theta, prec=prec)
+    p = _problem(shape, 11, theta=theta, adot_frac=0.05)
+    S, prm = _solver(fld, p, precision=prec)
+    _assemble(S, p)
+    got = {k: host(v) for k, v in S.fld_get_system().items()}
+    diag, Ax, Ay, Az, b = oracle_problem(oracle_mod, p, prm).system()
+    np.testing.assert_allclose(got["diag"], diag, rtol=1e-13)
+    for g, w in ((got["Tx"], Ax), (got["Ty"], Ay), (got["Tz"], Az)):
+        np.testing.assert_allclose(g, w, rtol=1e-13, atol=1e-16 * np.abs(w).max())
+    np.testing.assert_allclose(got["b"], b, rtol=0, atol=1e-12 * np.abs(b).max())
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (12, 16, 20), (40, 64, 96)])
+def test_spmv_matches_oracle(fld, oracle_mod, shape):
+    log_case("spmv", shape=shape)
+    p = _problem(shape, 12, dt_factor=0.5)
+    S, prm = _solver(fld, p)
+    _assemble(S, p)
+    u = np.random.default_rng(3).normal(size=shape)
+    got = host(S.fld_apply(dev(u)))
+    want = oracle_problem(oracle_mod, p, prm).apply_A(u)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-13 * np.abs(want).max())
+
+
+SOLVE_CASES = [
+    ((8, 8, 8), 1.0, 0.05, "zero"),
+    ((12, 16, 20), 0.5, 0.2, "smooth"),
+    ((32, 32, 32), 1.0, 0.05, "zero"),
+    ((48, 48, 48), 1.0, 1.0, "smooth"),
+    ((40, 64, 96), 1.0, 2.0, "smooth"),
+    ((64, 64, 64), 0.5, 4.0, "smooth"),
+]
+
+
+def _check_solution(oracle_mod, p, prm, dE, st, prec, tag):
+    O = oracle_problem(oracle_mod, p, prm)
+    dEo, sto, it, rel = O.solve(tol=1e-13)
+    assert sto == oracle_mod.OK
+    err = rel_l2(dE, dEo)
+    diag, Ax, Ay, Az, b = O.system()
+    r = b - O.apply_A(dE)
+    true_rel = np.linalg.norm(r) / np.linalg.norm(b)
+    print(f"[{tag}] iters={st['iters']} levels={st['levels']} err={err:.3e} "
+          f"bound={st['err_bound']:.3e} true_rel={true_rel:.3e}", flush=True)
+    assert st["status"] == 0
+    assert true_rel <= prm.rtol * (1 + 1e-6)
+    assert abs(st["rel_resid"] - true_rel) <= 1e-3 * prm.rtol + 1e-6 * true_rel
+    assert err <= GATE[prec]
+    # a-posteriori bound: ||dE - dE*|| <= ||r||  (||A^-1|| <= 1)
+    assert np.linalg.norm(dE - dEo) <= np.linalg.norm(r) * (1 + 1e-6) + 1e-13 * np.linalg.norm(dEo)
+    return err
+
+
+@pytest.mark.parametrize("shape,theta,dtf,emode", SOLVE_CASES)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solve_matches_oracle(fld, oracle_mod, shape, theta, dtf, emode, prec):
+    log_case("solve", shape=shape, theta=theta, dtf=dtf, prec=prec)
+    p = _problem(shape, 13, theta=theta, dt_factor=dtf, E_mode=emode)
+    S, prm = _solver(fld, p, precision=prec)
+    _assemble(S, p)
+    dE, st = S.solve()
+    _check_solution(oracle_mod, p, prm, host(dE), st, prec, f"solve{shape}")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_step_matches_oracle(fld, oracle_mod, prec):
+    log_case("step", prec=prec)
+    p = _problem((32, 24, 16), 14, dt_factor=0.5)
+    S, prm = _solver(fld, p, precision=prec)
+    E = dev(p["E"])
+    st = S.step(E, dev(p["kappa"]), dev(p["eta"]), p["dt"], p["a"], p["adot"])
+    assert st["status"] == 0 and st["subcycles"] == 1 and st["dt_cuts"] == 0
+    dEo, sto, _, _ = oracle_problem(oracle_mod, p, prm).solve(tol=1e-13)
+    assert rel_l2(host(E), p["E"] + dEo) <= GATE[prec]
+    # the step controller's relative change, from its definition
+    En = p["E"] + dEo
+    rho = math.sqrt(np.mean((dEo / np.abs(En)) ** 2))
+    assert st["rel_change_rms"] == pytest.approx(rho, rel=1e-4)
+    f = min(2.0, max(0.1, prm.tau_tol / rho))
+    assert st["dt_next"] == pytest.approx(p["dt"] * f, rel=1e-4)
+
+
+def test_single_source_workload(fld, oracle_mod):
+    """The 32^3 single-source step in FP64 with a 4-level V(2,2) cycle."""
+    log_case("single_source_32")
+    p = synth.single_source(32)
+    S, prm = _solver(fld, p, mg_levels=4, nu_pre=2, nu_post=2)
+    _assemble(S, p)
+    dE, st = S.solve()
+    assert st["levels"] == 4
+    _check_solution(oracle_mod, p, prm, host(dE), st, 0, "c1")
+
+
+def test_fp64_preconditioner_is_symmetric_positive(fld):
+    log_case("vcycle_symmetry")
+    p = _problem((32, 32, 48), 15, dt_factor=2.0)
+    S, prm = _solver(fld, p)
+    rng = np.random.default_rng(5)
+    u = rng.normal(size=p["shape"])
+    v = rng.normal(size=p["shape"])
+    _assemble(S, p)
+    Bu = host(S.fld_precondition(dev(u)))
+    _assemble(S, p)
+    Bv = host(S.fld_precondition(dev(v)))
+    a, b = np.vdot(u, Bv), np.vdot(v, Bu)
+    assert abs(a - b) <= 1e-12 * abs(a)
+    assert np.vdot(u, Bu) > 0 and np.vdot(v, Bv) > 0
+    # and it is a contraction in the A-norm: ||(I - B A) e||_A < ||e||_A
+    _assemble(S, p)
+    Ae = host(S.fld_apply(dev(u)))
+    _assemble(S, p)
+    BAe = host(S.fld_precondition(dev(Ae)))
+    e2 = u - BAe
+    _assemble(S, p)
+    Ae2 = host(S.fld_apply(dev(e2)))
+    ratio = math.sqrt(np.vdot(e2, Ae2) / np.vdot(u, Ae))
+    print(f"[vcycle] A-norm contraction {ratio:.3f}", flush=True)
+    assert ratio < 0.5
+
+
+def test_graph_replay_is_bit_identical(fld):
+    log_case("graph")
+    p = _problem((48, 48, 48), 16, dt_factor=1.0)
+    out = []
+    for g in (0, 1):
+        S, prm = _solver(fld, p, precision=1, use_graph=g, check_every=2)
+        _assemble(S, p)
+        dE, st = S.solve()
+        out.append((host(dE), st["iters"]))
+        # a second solve on the same handle replays the captured graph again
+        _assemble(S, p)
+        dE2, st2 = S.solve()
+        assert np.array_equal(host(dE2), out[-1][0])
+    assert out[0][1] == out[1][1]
+    assert np.array_equal(out[0][0], out[1][0])
+
+
+def test_failure_paths(fld):
+    import torch
+    log_case("failures")
+    p = _problem((16, 16, 16), 17, dt_factor=1.0)
+    # NaN opacity -> non-finite residual, E untouched
+    S, prm = _solver(fld, p, max_dt_cuts=0)
+    kap = p["kappa"].copy()
+    kap[3, 4, 5] = np.nan
+    E = dev(p["E"])
+    st = S.step(E, dev(kap), dev(p["eta"]), p["dt"], check=False)
+    assert st["status"] == fld.FLD_ENONFINITE
+    assert np.array_equal(host(E), p["E"])
+    # iteration cap with no cuts allowed -> ENOCONV, E untouched
+    S, prm = _solver(fld, p, max_iter=1, rtol=1e-14, max_dt_cuts=0)
+    E = dev(p["E"])
+    st = S.step(E, dev(p["kappa"]), dev(p["eta"]), p["dt"], check=False)
+    assert st["status"] == fld.FLD_ENOCONV
+    assert np.array_equal(host(E), p["E"])
+    # invalid arguments are rejected before any launch
+    with pytest.raises(fld.FLDError) as ei:
+        S.step(E, dev(p["kappa"]), dev(p["eta"]), -1.0)
+    assert ei.value.status == fld.FLD_EINVAL
+    S2, _ = _solver(fld, p)
+    with pytest.raises(fld.FLDError):
+        S2.solve()  # nothing assembled on this handle yet
+    torch.cuda.synchronize()
+
+
+def test_subcycling_matches_oracle_substeps(fld, oracle_mod):
+    """A step whose full-length solve fails is cut 10x and subcycled; the
+    result equals oracle solves over the same substeps.  The iteration cap is
+    the count a 0.1 dt solve needs (so dt fails and 0.1 dt succeeds); the
+    substep sequence is replayed with single GPU solves under the same cap
+    (tau_tol is huge, so the step doubles after every success)."""
+    log_case("subcycle")
+    p = _problem((32, 32, 32), 18, dt_factor=2.0, E_mode="smooth")
+    kap, eta = dev(p["kappa"]), dev(p["eta"])
+    U, _ = _solver(fld, p)
+    its = []
+    for h in (p["dt"], 0.1 * p["dt"]):
+        U.assemble(dev(p["E"]), kap, eta, h)
+        its.append(U.solve()[1]["iters"])
+    print(f"[subcycle] iterations at dt, 0.1 dt: {its}", flush=True)
+    assert its[1] < its[0]
+    cap = dict(max_iter=its[1], tau_tol=1e30, max_dt_cuts=60)
+    S, prm = _solver(fld, p, **cap)
+    E = dev(p["E"])
+    st = S.step(E, kap, eta, p["dt"])
+    assert st["dt_cuts"] >= 1 and st["subcycles"] >= 2, st
+    R, _ = _solver(fld, p, **cap)
+    t, h, seq, cuts, Ecur = 0.0, p["dt"], [], 0, dev(p["E"])
+    while p["dt"] - t > 1e-12 * p["dt"]:
+        h = min(h, p["dt"] - t)
+        R.assemble(Ecur, kap, eta, h)
+        dE, s = R.solve(check=False)
+        if s["status"] != 0:
+            h *= 0.1
+            cuts += 1
+            continue
+        Ecur = Ecur + dE
+        seq.append(h)
+        t += h
+        h *= 2.0
+    assert len(seq) == st["subcycles"] and cuts == st["dt_cuts"]
+    assert np.array_equal(host(Ecur), host(E))
+    En = p["E"].copy()
+    for hh in seq:
+        q = dict(p)
+        q["E"], q["dt"] = En, hh
+        dEo, sto, _, _ = oracle_problem(oracle_mod, q, prm).solve(tol=1e-13)
+        En = En + dEo
+    assert rel_l2(host(E), En) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_full_size_many_sources_residual(fld, oracle_mod, prec):
+    """256^3, 64 sources (the benchmark workload), two successive steps in the
+    benchmark's launch configuration: the oracle evaluates b - A dE at every
+    cell, one cell at a time, from its own limiter and operator."""
+    import torch
+    log_case("many_sources_256", prec=prec)
+    p = synth.many_sources(256)
+    S, prm = _solver(fld, p, precision=prec)
+    E = dev(p["E"])
+    kap, eta = dev(p["kappa"]), dev(p["eta"])
+    cells = np.arange(E.numel(), dtype=np.int64)
+    En = p["E"]
+    for step in range(2):
+        S.assemble(E, kap, eta, p["dt"])
+        dE, st = S.solve()
+        q = dict(p)
+        q["E"] = En
+        O = oracle_problem(oracle_mod, q, prm)
+        dEh = host(dE)
+        res, rhs = O.residual_at(dEh, cells)
+        true_rel = np.linalg.norm(res) / np.linalg.norm(rhs)
+        bound = np.linalg.norm(res) / np.linalg.norm(dEh)
+        print(f"[c2 step {step} prec {prec}] iters={st['iters']} "
+              f"true_rel={true_rel:.3e} err_bound={bound:.3e}", flush=True)
+        assert st["status"] == 0
+        assert true_rel <= prm.rtol * (1 + 1e-6)
+        assert bound <= GATE[prec]
+        E += dE
+        torch.cuda.synchronize()
+        En = En + dEh
