@@ -39,6 +39,8 @@ BYTES_PER_CELL = {
     "prolong_black_fine": (57.0, 32.5),
     "true_resid": (56.0, 56.0),
     "update_E": (24.0, 24.0),
+    "vdown_fine": (41.0, 24.5),
+    "vup_fine": (49.0, 40.5),
 }
 
 
@@ -55,7 +57,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--tile-z", type=int, default=0)
-    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=1)
     return ap.parse_args()
 
 

@@ -93,7 +93,8 @@ typedef struct fld_params {
   int32_t max_dt_cuts; /* fld_step: at most this many 10x cuts (Sec. 3.4) */
   int32_t tile_z;      /* z-depth of one work tile; 0 = automatic */
   int32_t check_every; /* PCG iterations between host convergence reads; 0 = auto */
-  int32_t use_graph;   /* 1 = replay the PCG iteration from a captured hipGraph */
+  int32_t use_graph;   /* 1 (default) = replay the PCG iteration from a captured
+                          hipGraph; 0 = launch its kernels one by one */
   int32_t reserved[7];
 } fld_params;
 
@@ -119,7 +120,8 @@ typedef struct fld_server fld_server;
 
 /* Paper defaults (Sec. 2, Sec. 3.4, Table 1) for a run whose length unit is
  * L_unit: d_max = 0.006 c L_unit, r_min = 1e-20 / L_unit, rtol = 1e-8,
- * max_iter = 50, nu_pre = nu_post = 1, theta = 1, tau_tol = 1e-4, FP64. */
+ * max_iter = 50, nu_pre = nu_post = 1, theta = 1, tau_tol = 1e-4, FP64,
+ * coarse_scale = 0.5, max_dt_cuts = 8, graph replay on. */
 void fld_default_params(fld_params *p, double c, double L_unit);
 
 const char *fld_strerror(fld_status s);

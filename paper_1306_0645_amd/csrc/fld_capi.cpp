@@ -71,7 +71,7 @@ void fld_default_params(fld_params *p, double c, double L_unit) {
   p->max_dt_cuts = 8;
   p->tile_z = 0;
   p->check_every = 0;
-  p->use_graph = 0;
+  p->use_graph = 1;
 }
 
 const char *fld_strerror(fld_status s) {

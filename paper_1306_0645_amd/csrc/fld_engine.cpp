@@ -59,17 +59,45 @@ Hier make_hier(const fld_grid &g, const fld_params &p) {
     for (int d = 0; d < 3; ++d) h.n[h.levels][d] = c[d] / 2;
     ++h.levels;
   }
-  for (int l = 0; l < h.levels; ++l)
+  for (int l = 0; l < h.levels; ++l) {
     h.tiles[l] = count_tiles(p, h.n[l][0], h.n[l][1], h.n[l][2]);
+    h.ftiles[l] = count_fused_tiles(h.n[l][0], h.n[l][1], h.n[l][2]);
+  }
   return h;
 }
 
+// Tiles of the fused one-sweep V-cycle kernels: 64 x 16 cells in x, y (their
+// LDS buffers are sized for that) and up to 16 planes in z.
+void fused_shape(int nx, int ny, int nz, int &tx, int &ty, int &tz) {
+  tx = std::min(nx, 64);
+  ty = std::min(ny, 16);
+  tz = std::min(nz, 16);
+}
+
+int count_fused_tiles(int nx, int ny, int nz) {
+  int tx, ty, tz;
+  fused_shape(nx, ny, nz, tx, ty, tz);
+  return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz);
+}
+
+bool fused_cycle(const fld_params &p) { return p.nu_pre == 1 && p.nu_post == 1; }
+
+// Tiles are up to 64 cells wide in x (one wave per row, one cell per lane,
+// so each load instruction covers consecutive addresses) and 4+ rows.
 void tile_shape(const fld_params &p, int nx, int ny, int nz, int &tx, int &ty,
                 int &tz) {
   tx = std::min(nx, 64);
   ty = std::max(1, std::min(ny, kBlock / tx));
-  if (p.tile_z > 0) tz = std::min(p.tile_z, nz);
-  else tz = std::max(1, std::min(8, nz / 8));
+  if (p.tile_z > 0) {
+    tz = std::min(p.tile_z, nz);
+  } else {
+    // deepest power of two (<= 8) that still leaves >= 2048 tiles, so small
+    // levels get enough workgroups to cover 256 CUs
+    const long long xy = (long long)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
+    tz = 8;
+    while (tz > 1 && xy * ((nz + tz - 1) / tz) < 2048) tz >>= 1;
+    tz = std::min(tz, nz);
+  }
 }
 
 int count_tiles(const fld_params &p, int nx, int ny, int nz) {
@@ -140,12 +168,12 @@ static size_t tables_layout(Carver &cv, const std::vector<Hier> &hs,
   const int np = (int)hs.size();
   size_t ntiles = 0, nfine = 0, nranges = 0;
   for (const Hier &h : hs) {
-    for (int l = 0; l < h.levels; ++l) ntiles += h.tiles[l];
-    nfine += h.tiles[0];
+    for (int l = 0; l < h.levels; ++l) ntiles += h.tiles[l] + h.ftiles[l];
+    nfine += h.tiles[0] + h.ftiles[0];  // partial slots: both finest tilings
   }
-  // fine + smooth[l] + exist[l]: at most (2 * kMaxLevels + 1) ranges per
-  // problem and list set, 2 ints each, kListSlots sets
-  nranges = (size_t)(2 * kMaxLevels + 1) * np * 2 * kListSlots;
+  // fine + smooth/exist/fsm/fdn per level: at most (4 kMaxLevels + 1) ranges
+  // per problem and list set, 2 ints each, kListSlots sets
+  nranges = (size_t)(4 * kMaxLevels + 1) * np * 2 * kListSlots;
   LevelDev *lv = cv.take<LevelDev>((size_t)kMaxLevels * np);
   ProbDev *pd = cv.take<ProbDev>(np);
   StepDev *sd = cv.take<StepDev>(np);
@@ -202,9 +230,29 @@ int Engine::setup(const fld_params &p, hipStream_t s,
   tables_layout(tbl, hier, this);
   for (int i = 0; i < np; ++i) carve_problem(pm[i], hier[i], p, mem[i]);
 
-  // full tile table, level-major so the finest tiles come first
+  // full tile table, level-major; within a level the standard tiles of every
+  // problem, then the fused-cycle tiles, so both finest tilings come first
+  // (their indices are the partial-sum slots)
+  fused = fused_cycle(p);
   h_tiles.clear();
   tbeg.assign((size_t)np * kMaxLevels, 0);
+  fbeg.assign((size_t)np * kMaxLevels, 0);
+  auto emit = [&](int i, int nx, int ny, int nz, int tx, int ty, int tz) {
+    for (int z0 = 0; z0 < nz; z0 += tz)
+      for (int y0 = 0; y0 < ny; y0 += ty)
+        for (int x0 = 0; x0 < nx; x0 += tx) {
+          Tile t;
+          t.prob = i;
+          t.x0 = x0;
+          t.y0 = y0;
+          t.z0 = z0;
+          t.tx = std::min(tx, nx - x0);
+          t.ty = std::min(ty, ny - y0);
+          t.tz = std::min(tz, nz - z0);
+          t.cpt = 1;
+          h_tiles.push_back(t);
+        }
+  };
   for (int l = 0; l < Lmax; ++l) {
     for (int i = 0; i < np; ++i) {
       if (l >= hier[i].levels) continue;
@@ -212,20 +260,15 @@ int Engine::setup(const fld_params &p, hipStream_t s,
       const int nx = hier[i].n[l][0], ny = hier[i].n[l][1], nz = hier[i].n[l][2];
       int tx, ty, tz;
       tile_shape(prm, nx, ny, nz, tx, ty, tz);
-      for (int z0 = 0; z0 < nz; z0 += tz)
-        for (int y0 = 0; y0 < ny; y0 += ty)
-          for (int x0 = 0; x0 < nx; x0 += tx) {
-            Tile t;
-            t.prob = i;
-            t.x0 = x0;
-            t.y0 = y0;
-            t.z0 = z0;
-            t.tx = std::min(tx, nx - x0);
-            t.ty = std::min(ty, ny - y0);
-            t.tz = std::min(tz, nz - z0);
-            t.level = l;
-            h_tiles.push_back(t);
-          }
+      emit(i, nx, ny, nz, tx, ty, tz);
+    }
+    for (int i = 0; i < np; ++i) {
+      if (l >= hier[i].levels) continue;
+      fbeg[(size_t)i * kMaxLevels + l] = (int)h_tiles.size();
+      const int nx = hier[i].n[l][0], ny = hier[i].n[l][1], nz = hier[i].n[l][2];
+      int tx, ty, tz;
+      fused_shape(nx, ny, nz, tx, ty, tz);
+      emit(i, nx, ny, nz, tx, ty, tz);
     }
   }
   h_lv.assign((size_t)kMaxLevels * np, LevelDev{});
@@ -237,6 +280,8 @@ int Engine::setup(const fld_params &p, hipStream_t s,
     h_pd[i] = mem[i].pd;
     h_pd[i].t0 = tbeg[(size_t)i * kMaxLevels];
     h_pd[i].t1 = h_pd[i].t0 + hier[i].tiles[0];
+    h_pd[i].f0 = fbeg[(size_t)i * kMaxLevels];
+    h_pd[i].f1 = h_pd[i].f0 + hier[i].ftiles[0];
     h_sc[i].phase = PH_DONE;
     h_sc[i].tol2 = prm.rtol * prm.rtol;
     h_sc[i].max_iter = prm.max_iter;
@@ -258,7 +303,7 @@ int Engine::build_lists(const std::vector<char> &member, int slot, ListSet &out)
   const size_t per_slot = ranges_cap / kListSlots;
   int *slot_base = d_ranges + per_slot * slot;
   h_ranges.clear();
-  auto make = [&](int level, auto pred) {
+  auto make_any = [&](int level, bool fz, auto pred) {
     TileList L{};
     L.base = d_tiles;
     const int off = (int)h_ranges.size();
@@ -266,8 +311,8 @@ int Engine::build_lists(const std::vector<char> &member, int slot, ListSet &out)
     for (int i = 0; i < np; ++i) {
       if (!member[i] || level >= hier[i].levels || !pred(i)) continue;
       h_ranges.push_back(blocks);
-      h_ranges.push_back(tbeg[(size_t)i * kMaxLevels + level]);
-      blocks += hier[i].tiles[level];
+      h_ranges.push_back((fz ? fbeg : tbeg)[(size_t)i * kMaxLevels + level]);
+      blocks += fz ? hier[i].ftiles[level] : hier[i].tiles[level];
       ++nr;
     }
     L.ranges = slot_base + off;
@@ -275,12 +320,21 @@ int Engine::build_lists(const std::vector<char> &member, int slot, ListSet &out)
     L.nblocks = blocks;
     return L;
   };
+  auto make = [&](int level, auto pred) { return make_any(level, false, pred); };
   out.fine = make(0, [](int) { return true; });
   for (int l = 0; l < kMaxLevels; ++l) {
-    out.smooth[l] = make(l, [&](int i) {
+    auto smoothed = [&](int i) {
       return l < hier[i].levels - 1 || (hier[i].levels == 1 && l == 0);
-    });
+    };
+    out.smooth[l] = make(l, smoothed);
     out.exist[l] = make(l, [&](int) { return l >= 1; });
+    if (fused) {
+      out.fsm[l] = make_any(l, true, smoothed);
+      out.fdn[l] = make_any(l, true, [&](int i) { return l < hier[i].levels - 1; });
+    } else {
+      out.fsm[l] = TileList{d_tiles, slot_base, 0, 0};
+      out.fdn[l] = TileList{d_tiles, slot_base, 0, 0};
+    }
   }
   if (h_ranges.size() > per_slot) return ST_EINVAL;
   if (!h_ranges.empty())
@@ -351,6 +405,25 @@ void Engine::enqueue_assemble(const ListSet &ls) {
 // adjoint order, so the FP64 cycle is a symmetric preconditioner.
 void Engine::enqueue_vcycle(const ListSet &ls) {
   const int prec = mixed;
+  if (fused) {
+    // one sweep each way: the finest level runs the two fused passes (they
+    // never store the pre-smoothed x); coarse levels, latency-bound small
+    // grids, run the per-half-sweep kernels
+    launch_vdown(T, ls.fdn[0], 0, prec, stream);
+    for (int l = 1; l < Lmax; ++l) {
+      if (ls.smooth[l].nblocks == 0) continue;
+      launch_pre0(T, ls.smooth[l], l, prec, stream);
+      if (l + 1 < Lmax) launch_resid_restrict(T, ls.exist[l + 1], l + 1, prec, stream);
+    }
+    if (Lmax > 1) launch_coarse_solve(T, prec, stream);
+    for (int l = Lmax - 1; l >= 1; --l) {
+      if (ls.smooth[l].nblocks == 0) continue;
+      launch_prolong_black(T, ls.smooth[l], l, prec, stream);
+      launch_half(T, ls.smooth[l], l, 0, prec, stream);
+    }
+    launch_vup(T, ls.fsm[0], 0, prec, mixed, stream);
+    return;
+  }
   const TileList *smooth = ls.smooth, *exist = ls.exist;
   for (int l = 0; l < Lmax; ++l) {
     if (smooth[l].nblocks == 0) continue;
@@ -375,7 +448,7 @@ void Engine::enqueue_vcycle(const ListSet &ls) {
 
 void Engine::enqueue_iteration(const ListSet &ls) {
   enqueue_vcycle(ls);
-  launch_fin(T, FIN_RZ, mixed, stream);
+  launch_fin(T, FIN_RZ, mixed, stream, fused ? 1 : 0);
   launch_spmv_p(T, ls.fine, stream);
   launch_fin(T, FIN_PQ, mixed, stream);
   launch_update(T, ls.fine, stream);

@@ -31,6 +31,7 @@ struct Hier {
   int levels = 0;
   int n[kMaxLevels][3] = {};
   int tiles[kMaxLevels] = {};   // tiles per level
+  int ftiles[kMaxLevels] = {};  // fused-cycle tiles per level
   long long cells(int l) const { return (long long)n[l][0] * n[l][1] * n[l][2]; }
 };
 
@@ -40,6 +41,9 @@ Hier make_hier(const fld_grid &g, const fld_params &p);
 void tile_shape(const fld_params &p, int nx, int ny, int nz, int &tx, int &ty,
                 int &tz);
 int count_tiles(const fld_params &p, int nx, int ny, int nz);
+void fused_shape(int nx, int ny, int nz, int &tx, int &ty, int &tz);
+int count_fused_tiles(int nx, int ny, int nz);
+bool fused_cycle(const fld_params &p);
 size_t problem_bytes(const Hier &h, const fld_params &p);
 size_t tables_bytes(const std::vector<Hier> &hs);
 
@@ -67,6 +71,8 @@ struct Job {
 // Launch lists of every kernel kind for one subset of the problems.
 struct ListSet {
   TileList fine{}, smooth[kMaxLevels]{}, exist[kMaxLevels]{};
+  TileList fsm[kMaxLevels]{};   // fused tiles of smoothed levels
+  TileList fdn[kMaxLevels]{};   // fused tiles of smoothed levels with a coarser one
 };
 
 constexpr int kListSlots = 4;  // independent range regions (server phases)
@@ -89,6 +95,8 @@ class Engine {
   std::vector<Tile> h_tiles;
   std::vector<int> h_ranges;
   std::vector<int> tbeg;   // [p * kMaxLevels + l] first tile of (p, l)
+  std::vector<int> fbeg;   // [p * kMaxLevels + l] first fused tile of (p, l)
+  bool fused = false;      // one-sweep fused V-cycle kernels
 
   Tables T{};
   Tile *d_tiles = nullptr;

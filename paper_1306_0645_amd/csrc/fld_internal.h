@@ -14,6 +14,7 @@ namespace fld {
 
 constexpr int kBlock = 256;          // threads per tile block (4 wave64)
 constexpr int kCoarseBlock = 1024;   // threads of the coarsest-level solve
+constexpr int kFinBlock = 1024;      // threads of the per-problem finalize
 constexpr int kMaxLevels = 12;
 
 // Status values (same numbers as the public fld_status).
@@ -51,6 +52,7 @@ struct ProbDev {
   double *cs;            // coarsest-level CG scratch: 4 * n_coarsest doubles
   int levels;            // number of multigrid levels
   int t0, t1;            // range of this problem's tiles in the finest list
+  int f0, f1;            // range of its fused-cycle finest tiles
   int pad;
 };
 
@@ -75,11 +77,14 @@ struct Scal {
   int pad[3];
 };
 
+// A tile: cells [x0, x0+tx) x [y0, y0+ty) x [z0, z0+tz) of one level of one
+// problem.  Each thread owns cpt consecutive x cells of one row and walks the
+// tile's planes.
 struct Tile {
   int prob;
   int x0, y0, z0;
   int tx, ty, tz;
-  int level;
+  int cpt;
 };
 
 // Launch context: the tables live in device memory.
@@ -102,13 +107,38 @@ struct TileList {
   int nblocks;
 };
 
-// ---- launchers (fld_kernels.hip) ----------------------------------------
+// ---- kernel ids of the timing hook (include/fld_profile.h) ----------------
+enum : int {
+  K_ASSEMBLE, K_COARSEN, K_FIN, K_PRE0_F, K_PRE0_C, K_HALF_F, K_HALF_C,
+  K_HALF_OUT, K_RESTRICT_F, K_RESTRICT_C, K_PROLONG_F, K_PROLONG_C,
+  K_COARSE_SOLVE, K_SPMV_P, K_UPDATE, K_TRUE_RESID, K_APPLY, K_SET_R,
+  K_UPDATE_E, K_VDOWN_F, K_VDOWN_C, K_VUP_F, K_VUP_C, K_NUM
+};
+
+// Brackets one launch with hipEvents when its kernel id is selected.
+struct ProfScope {
+  ProfScope(int k, hipStream_t s);
+  ~ProfScope();
+  int k;
+  hipStream_t s;
+  hipEvent_t a;
+};
+
+#define FLD_LAUNCH(id, kern, grid, block, s, ...)                         \
+  do {                                                                    \
+    ::fld::ProfScope _ps((id), (s));                                      \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, __VA_ARGS__); \
+  } while (0)
+
+// ---- launchers (fld_kernels.hip, fld_fused.hip) ---------------------------
 // prec: 0 = FP64 V-cycle, 1 = FP32 V-cycle.
 void launch_assemble(const Tables &T, TileList L0, double c, double theta,
                      double dmax, double rmin, int mixed, hipStream_t s);
 void launch_coarsen(const Tables &T, TileList coarse, int lc, double scale,
                     int mixed, hipStream_t s);
-void launch_fin(const Tables &T, int which, int mixed, hipStream_t s);
+// alt: FIN_RZ reads the partials of the fused finest tiles
+void launch_fin(const Tables &T, int which, int mixed, hipStream_t s,
+                int alt = 0);
 void launch_pre0(const Tables &T, TileList L, int l, int prec, hipStream_t s);
 void launch_half(const Tables &T, TileList L, int l, int colour, int prec,
                  hipStream_t s);
@@ -128,6 +158,10 @@ void launch_set_r(const Tables &T, TileList L0, const double *r, int prec,
                   hipStream_t s);
 void launch_update_E(const Tables &T, TileList L0, double floor, int copy_only,
                      hipStream_t s);
+// fused one-sweep V-cycle passes (fld_fused.hip)
+void launch_vdown(const Tables &T, TileList L, int l, int prec, hipStream_t s);
+void launch_vup(const Tables &T, TileList L, int l, int prec, int flexible,
+                hipStream_t s);
 
 // finalize kernels (launch_fin 'which')
 enum : int {

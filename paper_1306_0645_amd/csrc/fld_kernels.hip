@@ -18,7 +18,7 @@
 // one partial per tile, then a per-problem finalize kernel that sums the
 // partials in tile order.
 
-#include "fld_internal.h"
+#include "fld_device.h"
 #include "fld_profile.h"
 
 #include <math.h>
@@ -26,147 +26,6 @@
 #include <vector>
 
 namespace fld {
-
-// ---------------------------------------------------------------------------
-// tile addressing
-// ---------------------------------------------------------------------------
-
-// Workgroups are dispatched round-robin over the 8 XCDs.  Renumber them so
-// that XCD x processes the contiguous block range [start_x, start_x + cnt_x).
-__device__ __forceinline__ int xcd_block(int nb) {
-  const int b = blockIdx.x;
-  const int x = b & 7, q = nb >> 3, rem = nb & 7;
-  return x * q + (x < rem ? x : rem) + (b >> 3);
-}
-
-__device__ __forceinline__ Tile get_tile(const TileList &L) {
-  const int b = xcd_block(L.nblocks);
-  int lo = 0;
-  if (L.nranges > 1) {
-    int hi = L.nranges - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (L.ranges[2 * mid] <= b) lo = mid; else hi = mid - 1;
-    }
-  }
-  return L.base[L.ranges[2 * lo + 1] + (b - L.ranges[2 * lo])];
-}
-
-// index of the tile inside the full table (for per-tile partial sums)
-__device__ __forceinline__ int get_tile_index(const TileList &L) {
-  const int b = xcd_block(L.nblocks);
-  int lo = 0;
-  if (L.nranges > 1) {
-    int hi = L.nranges - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (L.ranges[2 * mid] <= b) lo = mid; else hi = mid - 1;
-    }
-  }
-  return L.ranges[2 * lo + 1] + (b - L.ranges[2 * lo]);
-}
-
-struct Col {
-  int i, j;
-  bool on;
-};
-
-__device__ __forceinline__ Col tile_col(const Tile &t) {
-  Col c;
-  const int lx = threadIdx.x % t.tx, ly = threadIdx.x / t.tx;
-  c.i = t.x0 + lx;
-  c.j = t.y0 + ly;
-  c.on = ly < t.ty;
-  return c;
-}
-
-// linear indices of a cell and its 6 periodic neighbours
-struct Nb {
-  int c, xm, xp, ym, yp, zm, zp;
-};
-
-__device__ __forceinline__ Nb nbrs(int i, int j, int k, int nx, int ny, int nz) {
-  Nb n;
-  const int plane = nx * ny;
-  const int row = k * plane + j * nx;
-  n.c = row + i;
-  n.xm = row + (i == 0 ? nx - 1 : i - 1);
-  n.xp = row + (i == nx - 1 ? 0 : i + 1);
-  n.ym = (j == 0) ? n.c + (ny - 1) * nx : n.c - nx;
-  n.yp = (j == ny - 1) ? n.c - (ny - 1) * nx : n.c + nx;
-  n.zm = (k == 0) ? n.c + (nz - 1) * plane : n.c - plane;
-  n.zp = (k == nz - 1) ? n.c - (nz - 1) * plane : n.c + plane;
-  return n;
-}
-
-// ---------------------------------------------------------------------------
-// reductions (deterministic)
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Sum over the block; the result is valid in every thread.
-template <int NW>
-__device__ __forceinline__ double block_sum(double v, double *sh) {
-  v = wave_sum(v);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
-  __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int i = 0; i < NW; ++i) s += sh[i];
-  return s;
-}
-
-__device__ __forceinline__ void write_partials(const Tables &T, int tile,
-                                               double a0, double a1) {
-  __shared__ double sh[kBlock / 64];
-  const double s0 = block_sum<kBlock / 64>(a0, sh);
-  const double s1 = block_sum<kBlock / 64>(a1, sh);
-  if (threadIdx.x == 0) {
-    T.part[2 * tile] = s0;
-    T.part[2 * tile + 1] = s1;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// typed access to a level's coefficients
-// ---------------------------------------------------------------------------
-
-template <typename R>
-struct Coef {
-  const R *tx, *ty, *tz, *d;
-};
-
-template <typename R>
-__device__ __forceinline__ Coef<R> coefs(const LevelDev &L);
-
-template <>
-__device__ __forceinline__ Coef<double> coefs<double>(const LevelDev &L) {
-  return {L.Tx, L.Ty, L.Tz, L.diag};
-}
-
-template <>
-__device__ __forceinline__ Coef<float> coefs<float>(const LevelDev &L) {
-  return {L.Tx32, L.Ty32, L.Tz32, L.diag32};
-}
-
-// sum over the 6 neighbours of T_face * u_neighbour
-template <typename R, typename U>
-__device__ __forceinline__ R offsum(const Coef<R> &C, const Nb &n, const U &u) {
-  return C.tx[n.c] * u(n.xp) + C.tx[n.xm] * u(n.xm) + C.ty[n.c] * u(n.yp) +
-         C.ty[n.ym] * u(n.ym) + C.tz[n.c] * u(n.zp) + C.tz[n.zm] * u(n.zm);
-}
-
-__device__ __forceinline__ double recip(double d) { return 1.0 / d; }
-__device__ __forceinline__ float recip(float d) {
-  return __builtin_amdgcn_rcpf(d);  // ~1 ulp: ample for a preconditioner
-}
 
 // ---------------------------------------------------------------------------
 // assembly (Sec. 2 limiter, Sec. 3.3 theta-method)
@@ -205,39 +64,42 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
   double bb = 0.0;
   if (col.on) {
     for (int k = t.z0; k < t.z0 + t.tz; ++k) {
-      const Nb n = nbrs(col.i, col.j, k, L.nx, L.ny, L.nz);
-      const double *E = S.E, *K = S.kappa;
-      const double Ec = E[n.c], Kc = K[n.c];
-      const double Exp = E[n.xp], Exm = E[n.xm], Eyp = E[n.yp], Eym = E[n.ym];
-      const double Ezp = E[n.zp], Ezm = E[n.zm];
-      const double Dxp = face_D(Ec, Exp, Kc, K[n.xp], S.idx, c, dmax, rmin);
-      const double Dxm = face_D(Exm, Ec, K[n.xm], Kc, S.idx, c, dmax, rmin);
-      const double Dyp = face_D(Ec, Eyp, Kc, K[n.yp], S.idy, c, dmax, rmin);
-      const double Dym = face_D(Eym, Ec, K[n.ym], Kc, S.idy, c, dmax, rmin);
-      const double Dzp = face_D(Ec, Ezp, Kc, K[n.zp], S.idz, c, dmax, rmin);
-      const double Dzm = face_D(Ezm, Ec, K[n.zm], Kc, S.idz, c, dmax, rmin);
-      const double mu = S.adot_a + c * Kc;
-      const double faces = (Dxp + Dxm) * ix2 + (Dyp + Dym) * iy2 + (Dzp + Dzm) * iz2;
-      const double diag = 1.0 + tdt * (mu + faces);
-      const double LE = (Dxp * (Exp - Ec) - Dxm * (Ec - Exm)) * ix2 +
-                        (Dyp * (Eyp - Ec) - Dym * (Ec - Eym)) * iy2 +
-                        (Dzp * (Ezp - Ec) - Dzm * (Ec - Ezm)) * iz2 - mu * Ec;
-      const double b = S.dt * (LE + S.eta[n.c]);
-      const double tx = tdt * Dxp * ix2, ty = tdt * Dyp * iy2, tz = tdt * Dzp * iz2;
-      L.Tx[n.c] = tx;
-      L.Ty[n.c] = ty;
-      L.Tz[n.c] = tz;
-      L.diag[n.c] = diag;
-      if (mixed) {
-        L.Tx32[n.c] = (float)tx;
-        L.Ty32[n.c] = (float)ty;
-        L.Tz32[n.c] = (float)tz;
-        L.diag32[n.c] = (float)diag;
+      for (int e = 0; e < t.cpt; ++e) {
+        const Nb n = nbrs(col.i + e, col.j, k, L.nx, L.ny, L.nz);
+        const double *E = S.E, *K = S.kappa;
+        const double Ec = E[n.c], Kc = K[n.c];
+        const double Exp = E[n.xp], Exm = E[n.xm], Eyp = E[n.yp], Eym = E[n.ym];
+        const double Ezp = E[n.zp], Ezm = E[n.zm];
+        const double Dxp = face_D(Ec, Exp, Kc, K[n.xp], S.idx, c, dmax, rmin);
+        const double Dxm = face_D(Exm, Ec, K[n.xm], Kc, S.idx, c, dmax, rmin);
+        const double Dyp = face_D(Ec, Eyp, Kc, K[n.yp], S.idy, c, dmax, rmin);
+        const double Dym = face_D(Eym, Ec, K[n.ym], Kc, S.idy, c, dmax, rmin);
+        const double Dzp = face_D(Ec, Ezp, Kc, K[n.zp], S.idz, c, dmax, rmin);
+        const double Dzm = face_D(Ezm, Ec, K[n.zm], Kc, S.idz, c, dmax, rmin);
+        const double mu = S.adot_a + c * Kc;
+        const double faces =
+            (Dxp + Dxm) * ix2 + (Dyp + Dym) * iy2 + (Dzp + Dzm) * iz2;
+        const double diag = 1.0 + tdt * (mu + faces);
+        const double LE = (Dxp * (Exp - Ec) - Dxm * (Ec - Exm)) * ix2 +
+                          (Dyp * (Eyp - Ec) - Dym * (Ec - Eym)) * iy2 +
+                          (Dzp * (Ezp - Ec) - Dzm * (Ec - Ezm)) * iz2 - mu * Ec;
+        const double b = S.dt * (LE + S.eta[n.c]);
+        const double tx = tdt * Dxp * ix2, ty = tdt * Dyp * iy2, tz = tdt * Dzp * iz2;
+        L.Tx[n.c] = tx;
+        L.Ty[n.c] = ty;
+        L.Tz[n.c] = tz;
+        L.diag[n.c] = diag;
+        if (mixed) {
+          L.Tx32[n.c] = (float)tx;
+          L.Ty32[n.c] = (float)ty;
+          L.Tz32[n.c] = (float)tz;
+          L.diag32[n.c] = (float)diag;
+        }
+        P.b[n.c] = b;
+        P.r[n.c] = b;
+        P.x[n.c] = 0.0;
+        bb += b * b;
       }
-      P.b[n.c] = b;
-      P.r[n.c] = b;
-      P.x[n.c] = 0.0;
-      bb += b * b;
     }
   }
   write_partials(T, tid, bb, 0.0);
@@ -258,66 +120,46 @@ __global__ __launch_bounds__(kBlock) void k_coarsen(Tables T, TileList LC,
   if (!col.on) return;
   const int fx = F.nx, fy = F.ny, fz = F.nz;
   for (int K = t.z0; K < t.z0 + t.tz; ++K) {
-    const int I = col.i, J = col.j;
-    double mass = 0.0, txp = 0.0, txm = 0.0, typ = 0.0, tym = 0.0, tzp = 0.0,
-           tzm = 0.0;
+    for (int e = 0; e < t.cpt; ++e) {
+      const int I = col.i + e, J = col.j;
+      double mass = 0.0, txp = 0.0, txm = 0.0, typ = 0.0, tym = 0.0,
+             tzp = 0.0, tzm = 0.0;
 #pragma unroll
-    for (int cz = 0; cz < 2; ++cz)
+      for (int cz = 0; cz < 2; ++cz)
 #pragma unroll
-      for (int cy = 0; cy < 2; ++cy)
+        for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
-        for (int cx = 0; cx < 2; ++cx) {
-          const Nb n = nbrs(2 * I + cx, 2 * J + cy, 2 * K + cz, fx, fy, fz);
-          const double fxp = F.Tx[n.c], fxm = F.Tx[n.xm];
-          const double fyp = F.Ty[n.c], fym = F.Ty[n.ym];
-          const double fzp = F.Tz[n.c], fzm = F.Tz[n.zm];
-          mass += F.diag[n.c] - (fxp + fxm + fyp + fym + fzp + fzm);
-          if (cx == 1) txp += fxp; else txm += fxm;
-          if (cy == 1) typ += fyp; else tym += fym;
-          if (cz == 1) tzp += fzp; else tzm += fzm;
-        }
-    txp *= scale; txm *= scale; typ *= scale; tym *= scale; tzp *= scale;
-    tzm *= scale;
-    const double diag = mass + txp + txm + typ + tym + tzp + tzm;
-    const int o = (K * C.ny + J) * C.nx + I;
-    C.Tx[o] = txp;
-    C.Ty[o] = typ;
-    C.Tz[o] = tzp;
-    C.diag[o] = diag;
-    if (mixed) {
-      C.Tx32[o] = (float)txp;
-      C.Ty32[o] = (float)typ;
-      C.Tz32[o] = (float)tzp;
-      C.diag32[o] = (float)diag;
+          for (int cx = 0; cx < 2; ++cx) {
+            const Nb n = nbrs(2 * I + cx, 2 * J + cy, 2 * K + cz, fx, fy, fz);
+            const double fxp = F.Tx[n.c], fxm = F.Tx[n.xm];
+            const double fyp = F.Ty[n.c], fym = F.Ty[n.ym];
+            const double fzp = F.Tz[n.c], fzm = F.Tz[n.zm];
+            mass += F.diag[n.c] - (fxp + fxm + fyp + fym + fzp + fzm);
+            if (cx == 1) txp += fxp; else txm += fxm;
+            if (cy == 1) typ += fyp; else tym += fym;
+            if (cz == 1) tzp += fzp; else tzm += fzm;
+          }
+      txp *= scale; txm *= scale; typ *= scale; tym *= scale; tzp *= scale;
+      tzm *= scale;
+      const double diag = mass + txp + txm + typ + tym + tzp + tzm;
+      const int o = (K * C.ny + J) * C.nx + I;
+      C.Tx[o] = txp;
+      C.Ty[o] = typ;
+      C.Tz[o] = tzp;
+      C.diag[o] = diag;
+      if (mixed) {
+        C.Tx32[o] = (float)txp;
+        C.Ty32[o] = (float)typ;
+        C.Tz32[o] = (float)tzp;
+        C.diag32[o] = (float)diag;
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// V-cycle kernels.  R = level precision, L0 = finest level (right-hand side is
-// the FP64 Krylov residual scaled by 1/s).
+// V-cycle kernels (any sweep count; one cell per lane, colour test per cell)
 // ---------------------------------------------------------------------------
-
-template <typename R, bool L0>
-struct FSrc {
-  const R *f;
-  const double *r;
-  double inv_s;
-  __device__ __forceinline__ R operator()(int c) const {
-    if constexpr (L0) return (R)(r[c] * inv_s);
-    else return f[c];
-  }
-};
-
-template <typename R, bool L0>
-__device__ __forceinline__ FSrc<R, L0> fsrc(const LevelDev &L, const ProbDev &P,
-                                             const Scal &sc) {
-  FSrc<R, L0> s;
-  s.f = (const R *)L.f;
-  s.r = P.r;
-  s.inv_s = sc.inv_s;
-  return s;
-}
 
 // First pre-smoothing sweep from x = 0: red cells x = f/d, then black cells
 // from those red values (computed on the fly, so one pass suffices).
@@ -460,7 +302,8 @@ __global__ __launch_bounds__(kBlock) void k_half_out(Tables T, TileList TL,
 
 // Residual f - A x on the fine level summed over the 8 children of each
 // coarse cell: the coarse right-hand side (restriction = transpose of the
-// piecewise-constant prolongation).  One thread per coarse cell.
+// piecewise-constant prolongation).  One thread per coarse cell (cpt of them
+// along x).
 template <typename R, bool L0>
 __global__ __launch_bounds__(kBlock) void k_resid_restrict(Tables T,
                                                            TileList LC, int lc) {
@@ -478,18 +321,21 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(Tables T,
   if (!col.on) return;
   auto xv = [&](int q) { return x[q]; };
   for (int K = t.z0; K < t.z0 + t.tz; ++K) {
-    R acc = 0;
+    for (int e = 0; e < t.cpt; ++e) {
+      const int I = col.i + e;
+      R acc = 0;
 #pragma unroll
-    for (int cz = 0; cz < 2; ++cz)
+      for (int cz = 0; cz < 2; ++cz)
 #pragma unroll
-      for (int cy = 0; cy < 2; ++cy)
+        for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
-        for (int cx = 0; cx < 2; ++cx) {
-          const Nb n = nbrs(2 * col.i + cx, 2 * col.j + cy, 2 * K + cz, F.nx,
-                            F.ny, F.nz);
-          acc += f(n.c) - (C.d[n.c] * x[n.c] - offsum(C, n, xv));
-        }
-    fc[(K * Cv.ny + col.j) * Cv.nx + col.i] = acc;
+          for (int cx = 0; cx < 2; ++cx) {
+            const Nb n = nbrs(2 * I + cx, 2 * col.j + cy, 2 * K + cz, F.nx,
+                              F.ny, F.nz);
+            acc += f(n.c) - (C.d[n.c] * x[n.c] - offsum(C, n, xv));
+          }
+      fc[(K * Cv.ny + col.j) * Cv.nx + I] = acc;
+    }
   }
 }
 
@@ -556,7 +402,7 @@ __global__ __launch_bounds__(kCoarseBlock) void k_coarse_solve(Tables T) {
 }
 
 // ---------------------------------------------------------------------------
-// Krylov kernels (FP64, finest level)
+// Krylov kernels (FP64, finest level; two x-consecutive cells per thread)
 // ---------------------------------------------------------------------------
 
 // p_new = z + beta p_old (formed at the cell and its neighbours on the fly),
@@ -578,21 +424,23 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(Tables T, TileList TL) {
   double pq = 0.0;
   if (col.on) {
     for (int k = t.z0; k < t.z0 + t.tz; ++k) {
-      const Nb n = nbrs(col.i, col.j, k, L.nx, L.ny, L.nz);
-      double pc, s;
-      if (beta != 0.0) {
-        auto pv = [&](int q) { return z[q] + beta * po[q]; };
-        pc = pv(n.c);
-        s = offsum(C, n, pv);
-      } else {
-        auto pv = [&](int q) { return z[q]; };
-        pc = pv(n.c);
-        s = offsum(C, n, pv);
+      for (int e = 0; e < t.cpt; ++e) {
+        const Nb n = nbrs(col.i + e, col.j, k, L.nx, L.ny, L.nz);
+        double pc, s;
+        if (beta != 0.0) {
+          auto pv = [&](int q) { return z[q] + beta * po[q]; };
+          pc = pv(n.c);
+          s = offsum(C, n, pv);
+        } else {
+          auto pv = [&](int q) { return z[q]; };
+          pc = pv(n.c);
+          s = offsum(C, n, pv);
+        }
+        const double q = C.d[n.c] * pc - s;
+        pn[n.c] = pc;
+        P.q[n.c] = q;
+        pq += pc * q;
       }
-      const double q = C.d[n.c] * pc - s;
-      pn[n.c] = pc;
-      P.q[n.c] = q;
-      pq += pc * q;
     }
   }
   write_partials(T, tid, pq, 0.0);
@@ -612,11 +460,14 @@ __global__ __launch_bounds__(kBlock) void k_update(Tables T, TileList TL) {
   double rr = 0.0;
   if (col.on) {
     for (int k = t.z0; k < t.z0 + t.tz; ++k) {
-      const int c = (k * L.ny + col.j) * L.nx + col.i;
-      P.x[c] += alpha * p[c];
-      const double r = P.r[c] - alpha * P.q[c];
-      P.r[c] = r;
-      rr += r * r;
+      const int c0 = (k * L.ny + col.j) * L.nx + col.i;
+      for (int e = 0; e < t.cpt; ++e) {
+        const int c = c0 + e;
+        P.x[c] += alpha * p[c];
+        const double r = P.r[c] - alpha * P.q[c];
+        P.r[c] = r;
+        rr += r * r;
+      }
     }
   }
   write_partials(T, tid, rr, 0.0);
@@ -637,10 +488,12 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Tables T, TileList TL) {
   if (col.on) {
     auto xv = [&](int q) { return P.x[q]; };
     for (int k = t.z0; k < t.z0 + t.tz; ++k) {
-      const Nb n = nbrs(col.i, col.j, k, L.nx, L.ny, L.nz);
-      const double r = P.b[n.c] - (C.d[n.c] * P.x[n.c] - offsum(C, n, xv));
-      P.r[n.c] = r;
-      rr += r * r;
+      for (int e = 0; e < t.cpt; ++e) {
+        const Nb n = nbrs(col.i + e, col.j, k, L.nx, L.ny, L.nz);
+        const double r = P.b[n.c] - (C.d[n.c] * P.x[n.c] - offsum(C, n, xv));
+        P.r[n.c] = r;
+        rr += r * r;
+      }
     }
   }
   write_partials(T, tid, rr, 0.0);
@@ -656,8 +509,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(Tables T, TileList TL,
   if (!col.on) return;
   auto uv = [&](int q) { return u[q]; };
   for (int k = t.z0; k < t.z0 + t.tz; ++k) {
-    const Nb n = nbrs(col.i, col.j, k, L.nx, L.ny, L.nz);
-    out[n.c] = C.d[n.c] * u[n.c] - offsum(C, n, uv);
+    for (int e = 0; e < t.cpt; ++e) {
+      const Nb n = nbrs(col.i + e, col.j, k, L.nx, L.ny, L.nz);
+      out[n.c] = C.d[n.c] * u[n.c] - offsum(C, n, uv);
+    }
   }
 }
 
@@ -672,10 +527,12 @@ __global__ __launch_bounds__(kBlock) void k_set_r(Tables T, TileList TL,
   double rr = 0.0;
   if (col.on) {
     for (int k = t.z0; k < t.z0 + t.tz; ++k) {
-      const int c = (k * L.ny + col.j) * L.nx + col.i;
-      const double r = rin[c];
-      P.r[c] = r;
-      rr += r * r;
+      const int c0 = (k * L.ny + col.j) * L.nx + col.i;
+      for (int e = 0; e < t.cpt; ++e) {
+        const double r = rin[c0 + e];
+        P.r[c0 + e] = r;
+        rr += r * r;
+      }
     }
   }
   write_partials(T, tid, rr, 0.0);
@@ -697,19 +554,22 @@ __global__ __launch_bounds__(kBlock) void k_update_E(Tables T, TileList TL,
   double ch = 0.0, dd = 0.0;
   if (col.on) {
     for (int k = t.z0; k < t.z0 + t.tz; ++k) {
-      const int c = (k * L.ny + col.j) * L.nx + col.i;
-      const double d = P.x[c];
-      dd += d * d;
-      if (copy_only) {
-        S.Eout[c] = d;
-      } else {
-        const double e = S.E[c] + d;
-        S.Eout[c] = e;
-        double w = fabs(e);
-        w = (w < floor) ? floor : w;
-        if (w > 0.0) {
-          const double q = d / w;
-          ch += q * q;
+      const int c0 = (k * L.ny + col.j) * L.nx + col.i;
+      for (int e = 0; e < t.cpt; ++e) {
+        const int c = c0 + e;
+        const double d = P.x[c];
+        dd += d * d;
+        if (copy_only) {
+          S.Eout[c] = d;
+        } else {
+          const double en = S.E[c] + d;
+          S.Eout[c] = en;
+          double w = fabs(en);
+          w = (w < floor) ? floor : w;
+          if (w > 0.0) {
+            const double q = d / w;
+            ch += q * q;
+          }
         }
       }
     }
@@ -739,10 +599,13 @@ __device__ __forceinline__ void fail(Scal &sc, int status) {
   sc.active = 0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_fin(Tables T, int which, int mixed) {
+__global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixed,
+                                                  int alt) {
   const int p = blockIdx.x;
   Scal &sc = T.sc[p];
   const ProbDev P = T.pd[p];
+  const int t0 = (alt && which == FIN_RZ) ? P.f0 : P.t0;
+  const int t1 = (alt && which == FIN_RZ) ? P.f1 : P.t1;
   bool part;
   switch (which) {
     case FIN_BB:
@@ -752,14 +615,29 @@ __global__ __launch_bounds__(kBlock) void k_fin(Tables T, int which, int mixed) 
     default: part = sc.active != 0; break;
   }
   if (!part) return;
+  // independent loads in flight: 4 per thread per round, summed in order
   double a0 = 0.0, a1 = 0.0;
-  for (int t = P.t0 + (int)threadIdx.x; t < P.t1; t += kBlock) {
+  int t = t0 + (int)threadIdx.x;
+  for (; t + 3 * kFinBlock < t1; t += 4 * kFinBlock) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      v[2 * u] = T.part[2 * (t + u * kFinBlock)];
+      v[2 * u + 1] = T.part[2 * (t + u * kFinBlock) + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a0 += v[2 * u];
+      a1 += v[2 * u + 1];
+    }
+  }
+  for (; t < t1; t += kFinBlock) {
     a0 += T.part[2 * t];
     a1 += T.part[2 * t + 1];
   }
-  __shared__ double sh[kBlock / 64];
-  a0 = block_sum<kBlock / 64>(a0, sh);
-  a1 = block_sum<kBlock / 64>(a1, sh);
+  __shared__ double sh[kFinBlock / 64];
+  a0 = block_sum<kFinBlock / 64>(a0, sh);
+  a1 = block_sum<kFinBlock / 64>(a1, sh);
   if (threadIdx.x != 0) return;
   switch (which) {
     case FIN_BB:
@@ -843,18 +721,12 @@ __global__ __launch_bounds__(kBlock) void k_fin(Tables T, int which, int mixed) 
 // per-kernel timing hook (include/fld_profile.h)
 // ---------------------------------------------------------------------------
 
-enum : int {
-  K_ASSEMBLE, K_COARSEN, K_FIN, K_PRE0_F, K_PRE0_C, K_HALF_F, K_HALF_C,
-  K_HALF_OUT, K_RESTRICT_F, K_RESTRICT_C, K_PROLONG_F, K_PROLONG_C,
-  K_COARSE_SOLVE, K_SPMV_P, K_UPDATE, K_TRUE_RESID, K_APPLY, K_SET_R,
-  K_UPDATE_E, K_NUM
-};
-
 static const char *kKernelNames[K_NUM] = {
     "assemble", "coarsen", "fin", "pre0_fine", "pre0_coarse", "half_fine",
     "half_coarse", "half_out", "resid_restrict_fine", "resid_restrict_coarse",
     "prolong_black_fine", "prolong_black_coarse", "coarse_solve", "spmv_p",
-    "update", "true_resid", "apply", "set_r", "update_E"};
+    "update", "true_resid", "apply", "set_r", "update_E", "vdown_fine",
+    "vdown_coarse", "vup_fine", "vup_coarse"};
 
 namespace prof {
 struct Rec {
@@ -884,35 +756,28 @@ static bool on(int k, hipStream_t s) {
   return true;
 }
 
-struct Scope {
-  int k;
-  hipStream_t s;
-  hipEvent_t a = nullptr;
-  Scope(int k_, hipStream_t s_) : k(k_), s(s_) {
-    if (on(k, s)) {
-      a = get();
-      if (a) hipEventRecord(a, s);
-    }
-  }
-  ~Scope() {
-    if (!a) return;
-    hipEvent_t b = get();
-    if (!b) return;
-    hipEventRecord(b, s);
-    recs.push_back({a, b, k});
-  }
-};
 }  // namespace prof
+
+ProfScope::ProfScope(int k_, hipStream_t s_) : k(k_), s(s_), a(nullptr) {
+  if (prof::on(k, s)) {
+    a = prof::get();
+    if (a) hipEventRecord(a, s);
+  }
+}
+
+ProfScope::~ProfScope() {
+  if (!a) return;
+  hipEvent_t b = prof::get();
+  if (!b) return;
+  hipEventRecord(b, s);
+  prof::recs.push_back({a, b, k});
+}
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
-#define LAUNCH(id, kern, grid, block, s, ...)                              \
-  do {                                                                     \
-    prof::Scope _ps((id), (s));                                            \
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, __VA_ARGS__);  \
-  } while (0)
+#define LAUNCH FLD_LAUNCH
 
 void launch_assemble(const Tables &T, TileList L0, double c, double theta,
                      double dmax, double rmin, int mixed, hipStream_t s) {
@@ -924,8 +789,8 @@ void launch_coarsen(const Tables &T, TileList LC, int lc, double scale,
   if (LC.nblocks) LAUNCH(K_COARSEN, k_coarsen, LC.nblocks, kBlock, s, T, LC, lc, scale, mixed);
 }
 
-void launch_fin(const Tables &T, int which, int mixed, hipStream_t s) {
-  if (T.nprob) LAUNCH(K_FIN, k_fin, T.nprob, kBlock, s, T, which, mixed);
+void launch_fin(const Tables &T, int which, int mixed, hipStream_t s, int alt) {
+  if (T.nprob) LAUNCH(K_FIN, k_fin, T.nprob, kFinBlock, s, T, which, mixed, alt);
 }
 
 void launch_pre0(const Tables &T, TileList L, int l, int prec, hipStream_t s) {

@@ -10,7 +10,7 @@ Sec. 5), which are not available: a smoothed lognormal neutral-hydrogen
 density, opacity kappa = sigma_HI n_HI for monochromatic 13.6 eV radiation
 (Sec. 4.1.1 sets the source at the HI ionization threshold), and point sources
 of Ndot ionizing photons per second deposited as eta = sum Ndot h nu / V_cell
-in the cell that holds them (Sec. 2.2 accumulates emissivity per cell).
+in the cell that holds them (Sec. 3.2 accumulates emissivity per cell).
 
 All lengths are cm, times s, energies erg (CGS).  Randomness comes from numpy
 PCG64 with base seed 1306 + workload index; problem i of a workload uses

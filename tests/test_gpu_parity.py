@@ -226,18 +226,20 @@ def test_subcycling_matches_oracle_substeps(fld, oracle_mod):
     result equals oracle solves over the same substeps.  The iteration cap is
     the count a 0.1 dt solve needs (so dt fails and 0.1 dt succeeds); the
     substep sequence is replayed with single GPU solves under the same cap
-    (tau_tol is huge, so the step doubles after every success)."""
+    (tau_tol is huge, so the step doubles after every success).  A one-level
+    cycle (symmetric Gauss-Seidel) is used because its iteration count grows
+    with dt, unlike multigrid's."""
     log_case("subcycle")
     p = _problem((32, 32, 32), 18, dt_factor=2.0, E_mode="smooth")
     kap, eta = dev(p["kappa"]), dev(p["eta"])
-    U, _ = _solver(fld, p)
+    U, _ = _solver(fld, p, mg_levels=1)
     its = []
     for h in (p["dt"], 0.1 * p["dt"]):
         U.assemble(dev(p["E"]), kap, eta, h)
         its.append(U.solve()[1]["iters"])
     print(f"[subcycle] iterations at dt, 0.1 dt: {its}", flush=True)
     assert its[1] < its[0]
-    cap = dict(max_iter=its[1], tau_tol=1e30, max_dt_cuts=60)
+    cap = dict(max_iter=its[1], tau_tol=1e30, max_dt_cuts=60, mg_levels=1)
     S, prm = _solver(fld, p, **cap)
     E = dev(p["E"])
     st = S.step(E, kap, eta, p["dt"])
