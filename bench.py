@@ -58,30 +58,36 @@ def parse():
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--tile-z", type=int, default=0)
     ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--workload", default="many_sources",
+                    choices=["many_sources", "single_source", "reionization",
+                             "batch", "served"])
+    ap.add_argument("--reps", type=int, default=300,
+                    help="single_source: timed solves for the latency quantiles")
+    ap.add_argument("--batch", type=int, default=96, help="batch: problems")
+    ap.add_argument("--autotune", type=int, default=1)
+    ap.add_argument("--requests", type=int, default=500, help="served: requests")
+    ap.add_argument("--load", type=float, default=0.7,
+                    help="served: arrival rate as a fraction of saturation")
     return ap.parse_args()
 
 
 def run_form(fld, torch, p, prec, steps, warmup, args):
-    prm = fld.fld_default_params(p["c"], p["L_unit"], precision=prec,
-                                 tile_z=args.tile_z, use_graph=args.graph)
-    S = fld.Solver(p["shape"], p["h"], prm)
+    """Timed steps with graph replay (the throughput), then the same number of
+    steps with per-kernel launches so hipEvents can time the dominant kernel
+    on its stream (a graph replay hides its kernels from the timing hook)."""
     E = torch.from_numpy(p["E"]).cuda()
     kap = torch.from_numpy(p["kappa"]).cuda()
     eta = torch.from_numpy(p["eta"]).cuda()
     names = fld.profile_kernels()
-    # warmup; the last warmup step also surveys every kernel's time
-    warmup = max(2, warmup)
-    for w in range(warmup):
-        if w == warmup - 1:
-            fld.fld_profile_select(-2)
-        st = S.step(E, kap, eta, p["dt"])
-    torch.cuda.synchronize()
-    totals = {n: fld.fld_profile_read(k)[0] for k, n in enumerate(names)}
-    fld.fld_profile_select(-1)
-    dom = max((n for n in totals if n in BYTES_PER_CELL), key=lambda n: totals[n])
-    dom_id = names.index(dom)
-    # timed region: K steps; the dominant kernel is timed with hipEvents
-    fld.fld_profile_select(dom_id)
+
+    def solver(graph):
+        prm = fld.fld_default_params(p["c"], p["L_unit"], precision=prec,
+                                     tile_z=args.tile_z, use_graph=graph)
+        return fld.Solver(p["shape"], p["h"], prm)
+
+    S = solver(args.graph)
+    for w in range(max(1, warmup)):
+        S.step(E, kap, eta, p["dt"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters, rels = [], []
@@ -91,9 +97,26 @@ def run_form(fld, torch, p, prec, steps, warmup, args):
         rels.append(st["rel_resid"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    S.close()
+    # kernel timing pass: survey one step, then time the dominant kernel
+    P = solver(0)
+    P.step(E, kap, eta, p["dt"])
+    fld.fld_profile_select(-2)
+    P.step(E, kap, eta, p["dt"])
+    torch.cuda.synchronize()
+    totals = {n: fld.fld_profile_read(k)[0] for k, n in enumerate(names)}
+    dom = max((n for n in totals if n in BYTES_PER_CELL), key=lambda n: totals[n])
+    dom_id = names.index(dom)
+    fld.fld_profile_select(dom_id)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for _ in range(steps):
+        P.step(E, kap, eta, p["dt"])
+    torch.cuda.synchronize()
+    tp1 = time.perf_counter()
     ms_total, launches = fld.fld_profile_read(dom_id)
     fld.fld_profile_select(-1)
-    S.close()
+    P.close()
     cells = p["E"].size
     sec = t1 - t0
     avg_ms = ms_total / max(launches, 1)
@@ -102,6 +125,7 @@ def run_form(fld, torch, p, prec, steps, warmup, args):
     return {
         "mcell_updates_per_s": cells * steps / sec / 1e6,
         "ms_per_step": 1e3 * sec / steps,
+        "ms_per_step_unfused_launches": 1e3 * (tp1 - tp0) / steps,
         "iters_per_step": sum(iters) / len(iters),
         "max_rel_resid": max(rels),
         "survey_ms": {k: round(v, 4) for k, v in sorted(
@@ -137,6 +161,12 @@ def main():
     import torch
     import paper_1306_0645_amd as fld
     import synth
+
+    if args.workload != "many_sources":
+        import bench_workloads
+        out = getattr(bench_workloads, args.workload)(args, fld, torch, synth, log)
+        print(json.dumps(out), flush=True)
+        return
 
     log(f"[bench] generating the {args.n}^3 many-source workload")
     p = synth.many_sources(args.n)

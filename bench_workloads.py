@@ -1,0 +1,346 @@
+"""Workloads of bench.py beyond the default 256^3 many-source run.
+
+single_source  32^3, one source, FP64 V(2,2) 4 levels: latency p50/p99 of
+               one step over many repetitions (fields cache-resident)
+reionization   one 640^3 share of a 3200^3 box with ionized bubbles around
+               10^4 sources, mixed precision, 6 levels, successive steps
+batch          96 independent problems of 32..128^3 in one batched step,
+               autotuned, against the same problems solved one by one
+served         Poisson stream of 64..384^3 requests of 1-5 steps through the
+               continuous-batching server: p50/p99 latency and throughput
+
+Each function returns the JSON object bench.py prints.
+"""
+import math
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _base(metric_note, value, ms, steps, warmup, dtype, config, roofline=None,
+          extra=None):
+    out = {
+        "metric": "FLD solve Mcell-updates/s + % HBM roofline at 1e-8 residual; "
+                  "p50/p99 solve latency",
+        "value": round(value, 2),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": config,
+        "roofline": roofline,
+        "cpu_baseline": None,
+        "note": metric_note,
+    }
+    if extra:
+        out.update(extra)
+    return out
+
+
+def _dominant(fld, names, totals, cells, bytes_table, prec_idx):
+    cand = [n for n in totals if n in bytes_table and totals[n] > 0]
+    if not cand:
+        return None
+    return max(cand, key=lambda n: totals[n])
+
+
+def _survey(fld, fn):
+    """Run fn() once with every kernel timed; return {kernel: total ms}."""
+    names = fld.profile_kernels()
+    fld.fld_profile_select(-2)
+    fn()
+    import torch
+    torch.cuda.synchronize()
+    totals = {n: fld.fld_profile_read(k)[0] for k, n in enumerate(names)}
+    fld.fld_profile_select(-1)
+    return names, totals
+
+
+def single_source(args, fld, torch, synth, log):
+    from bench import BYTES_PER_CELL
+    p = synth.single_source(32)
+    prm = fld.fld_default_params(p["c"], p["L_unit"], mg_levels=4, nu_pre=2,
+                                 nu_post=2, use_graph=args.graph)
+    S = fld.Solver(p["shape"], p["h"], prm)
+    E0 = torch.from_numpy(p["E"]).cuda()
+    K = torch.from_numpy(p["kappa"]).cuda()
+    H = torch.from_numpy(p["eta"]).cuda()
+    E = E0.clone()
+    lat, iters, rel = [], [], []
+    reps = max(args.reps, 200)
+    log(f"[bench] single_source 32^3: {args.warmup} warmup + {reps} timed steps")
+    for r in range(args.warmup + reps):
+        E.copy_(E0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = S.step(E, K, H, p["dt"])
+        t1 = time.perf_counter()
+        if r >= args.warmup:
+            lat.append(t1 - t0)
+            iters.append(st["iters"])
+            rel.append(st["rel_resid"])
+    names, totals = _survey(fld, lambda: (E.copy_(E0), S.step(E, K, H, p["dt"])))
+    dom = _dominant(fld, names, totals, E.numel(), BYTES_PER_CELL, 0)
+    lat_ms = np.array(lat) * 1e3
+    p50, p99 = np.percentile(lat_ms, [50, 99])
+    mean_s = float(np.mean(lat))
+    cells = E.numel()
+    return _base(
+        "32^3 fields are cache-resident; the HBM roofline does not apply",
+        cells / mean_s / 1e6, mean_s * 1e3, reps, args.warmup, "f64",
+        {"workload": "single_source_32^3", "grid": [32, 32, 32], "sources": 1,
+         "precision": "fp64", "levels": 4, "cycle": "V(2,2)", "rtol": 1e-8},
+        None,
+        {"latency_ms": {"p50": round(float(p50), 4), "p99": round(float(p99), 4),
+                        "mean": round(float(lat_ms.mean()), 4)},
+         "iters_per_step": float(np.mean(iters)), "max_rel_resid": max(rel),
+         "survey_ms": {k: round(v, 4) for k, v in sorted(
+             totals.items(), key=lambda kv: -kv[1]) if v > 0},
+         "dominant": dom})
+
+
+def reionization(args, fld, torch, synth, log):
+    from bench import BYTES_PER_CELL
+    n = args.n if args.n != 256 else 640
+    log(f"[bench] generating the {n}^3 reionization share on the GPU")
+    t0 = time.perf_counter()
+    p = synth.t_reionization_share(n=n, device="cuda")
+    torch.cuda.synchronize()
+    log(f"[bench]   generated in {time.perf_counter() - t0:.1f} s; "
+        f"ionized fraction {float((p['kappa'] < 1e-22).double().mean()):.4f}")
+    prm = fld.fld_default_params(p["c"], p["L_unit"], precision=fld.FLD_PREC_MIXED,
+                                 mg_levels=6, use_graph=args.graph)
+    S = fld.Solver(p["shape"], p["h"], prm)
+    E, K, H = p["E"], p["kappa"], p["eta"]
+    steps = args.steps if args.steps != 10 else 20
+    for w in range(args.warmup):
+        st = S.step(E, K, H, p["dt"])
+        log(f"[bench]   warmup step {w}: iters {st['iters']} rel {st['rel_resid']:.2e}")
+    names = fld.profile_kernels()
+    names, totals = _survey(fld, lambda: S.step(E, K, H, p["dt"]))
+    dom = _dominant(fld, names, totals, E.numel(), BYTES_PER_CELL, 1)
+    dom_id = names.index(dom)
+    fld.fld_profile_select(dom_id)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, rel = [], []
+    for k in range(steps):
+        st = S.step(E, K, H, p["dt"])
+        iters.append(st["iters"])
+        rel.append(st["rel_resid"])
+        if k % 5 == 4:
+            log(f"[bench]   step {k + 1}/{steps}: iters {st['iters']}")
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    ms_tot, launches = fld.fld_profile_read(dom_id)
+    fld.fld_profile_select(-1)
+    cells = E.numel()
+    avg_ms = ms_tot / max(launches, 1)
+    achieved = BYTES_PER_CELL[dom][1] * cells / (avg_ms * 1e-3) / 1e9
+    # spot check of the last step against the oracle at sampled cells
+    spot = None
+    try:
+        import oracle
+        En = E.clone()
+        S.assemble(En, K, H, p["dt"])
+        dE, st = S.solve()
+        rng = np.random.default_rng(3)
+        cells_s = rng.choice(cells, size=20000, replace=False).astype(np.int64)
+        O = oracle.Problem(En.cpu().numpy(), K.cpu().numpy(), H.cpu().numpy(),
+                           p["h"], p["c"], prm.d_max, prm.r_min, p["dt"])
+        res, rhs = O.residual_at(dE.cpu().numpy(), cells_s)
+        spot = {"sampled_cells": int(cells_s.size),
+                "max_abs_resid_over_max_abs_b": float(np.abs(res).max() / np.abs(rhs).max()),
+                "solver_rel_resid": st["rel_resid"]}
+    except Exception as e:  # spot check only; never alters the timed result
+        spot = {"error": repr(e)}
+    return _base(
+        "one 640^3 share of a 3200^3 box; inputs resident in HBM",
+        cells * steps / sec / 1e6, 1e3 * sec / steps, steps, args.warmup,
+        "f64+f32",
+        {"workload": f"reionization_share_{n}^3", "grid": [n] * 3,
+         "sources": 10000, "sigma_ln": 2.0, "levels": 6, "precision": "mixed",
+         "rtol": 1e-8, "steps_per_run": steps},
+        {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+         "traffic": None},
+        {"iters_per_step": float(np.mean(iters)), "max_rel_resid": max(rel),
+         "survey_ms": {k: round(v, 3) for k, v in sorted(
+             totals.items(), key=lambda kv: -kv[1]) if v > 0},
+         "oracle_spot_check": spot})
+
+
+def _batch_problems(synth, torch, nprob):
+    probs = []
+    for i in range(nprob):
+        rng = synth.rng_for(4, i)
+        n = int(rng.choice(synth.BATCH_SIZES))
+        sigma = float(rng.uniform(0.5, 2.0))
+        nsrc = int(rng.integers(1, 33))
+        probs.append(synth.t_problem((n, n, n), sigma, nsrc, (1e47, 1e50), 4, i,
+                                     "cuda"))
+    torch.cuda.synchronize()
+    return probs
+
+
+def batch(args, fld, torch, synth, log):
+    from paper_1306_0645_amd import autotune
+    log(f"[bench] generating {args.batch} batch problems on the GPU")
+    probs = _batch_problems(synth, torch, args.batch)
+    shapes = [p["shape"] for p in probs]
+    hs = [p["h"] for p in probs]
+    cells = sum(int(np.prod(s)) for s in shapes)
+    K = [p["kappa"] for p in probs]
+    H = [p["eta"] for p in probs]
+    dts = [p["dt"] for p in probs]
+    # one length unit for the batch parameters (limits from the largest box)
+    ref = max(probs, key=lambda p: p["L_unit"])
+    base = fld.fld_default_params(ref["c"], ref["L_unit"],
+                                  precision=fld.FLD_PREC_MIXED, use_graph=args.graph)
+    report = None
+    if args.autotune:
+        log("[bench] autotuning tile depth and sweep counts")
+        base, report = autotune.tune_batch(shapes, hs, base,
+                                           ([p["E"] for p in probs], K, H), dts,
+                                           log=log)
+    B = fld.Batch(shapes, hs, base)
+    Es = [p["E"].clone() for p in probs]
+    for _ in range(args.warmup):
+        B.step(Es, K, H, dts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for _ in range(args.steps):
+        sts = B.step(Es, K, H, dts)
+        iters += [s["iters"] for s in sts]
+        assert all(s["status"] == 0 for s in sts)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    batched = cells * args.steps / sec / 1e6
+    B.close()
+
+    def one_by_one(prec, steps):
+        solvers = []
+        for p in probs:
+            q = fld.fld_default_params(ref["c"], ref["L_unit"], precision=prec,
+                                       use_graph=args.graph)
+            solvers.append(fld.Solver(p["shape"], p["h"], q))
+        Es1 = [p["E"].clone() for p in probs]
+        for S, E, k, h, dt in zip(solvers, Es1, K, H, dts):
+            S.step(E, k, h, dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for S, E, k, h, dt in zip(solvers, Es1, K, H, dts):
+                S.step(E, k, h, dt)
+        torch.cuda.synchronize()
+        s = time.perf_counter() - t0
+        for S in solvers:
+            S.close()
+        return cells * steps / s / 1e6
+
+    log("[bench] the same problems one by one (mixed, then FP64)")
+    single_mixed = one_by_one(fld.FLD_PREC_MIXED, max(1, args.steps // 2))
+    single_fp64 = one_by_one(fld.FLD_PREC_FP64, max(1, args.steps // 2))
+    return _base(
+        "aggregate over the batch; per-problem working sets up to 128^3",
+        batched, 1e3 * sec / args.steps, args.steps, args.warmup, "f64+f32",
+        {"workload": f"batch_{args.batch}x{{32..128}}^3", "problems": args.batch,
+         "cells": cells, "precision": "mixed", "rtol": 1e-8,
+         "tuned": {"tile_z": base.tile_z, "nu_pre": base.nu_pre,
+                   "nu_post": base.nu_post}},
+        None,
+        {"forms": {"batched_mixed": round(batched, 2),
+                   "one_by_one_mixed": round(single_mixed, 2),
+                   "one_by_one_fp64": round(single_fp64, 2)},
+         "iters_per_problem": float(np.mean(iters)), "autotune": report})
+
+
+def served(args, fld, torch, synth, log):
+    nreq = args.requests
+    shapes = [synth.serve_request_shape(i) for i in range(nreq)]
+    sizes = sorted({s[0] for s in shapes})
+    log(f"[bench] served: {nreq} requests over {len(sizes)} grid sizes; "
+        "generating one field set per size on the GPU")
+    pool = {}
+    for n in sizes:
+        p = synth.t_problem((n, n, n), 1.25, 500, (1e47, 1e50), 5, n, "cuda")
+        pool[n] = p
+    torch.cuda.synchronize()
+    ref = pool[max(sizes)]
+    prm = fld.fld_default_params(ref["c"], ref["L_unit"],
+                                 precision=fld.FLD_PREC_MIXED)
+    free, total = torch.cuda.mem_get_info()
+    arena = int(0.6 * free) // 256 * 256
+    stream = torch.cuda.Stream()
+    srv = fld.Server(prm, arena, stream=stream)
+    log(f"[bench]   arena {arena / 2**30:.1f} GiB")
+
+    def submit(i):
+        n, steps, _, _ = shapes[i]
+        p = pool[n]
+        out = torch.empty_like(p["E"])
+        t = srv.submit(p["shape"], p["h"], p["E"], p["kappa"], p["eta"], out,
+                       p["dt"], n_steps=steps)
+        return t, out
+
+    def work(idx):
+        return sum(shapes[i][0] ** 3 * shapes[i][1] for i in idx)
+
+    # closed loop: everything at once -> saturation throughput
+    nsat = min(64, nreq)
+    t0 = time.perf_counter()
+    ts = [submit(i) for i in range(nsat)]
+    srv.drain()
+    sat_s = time.perf_counter() - t0
+    for t, _ in ts:
+        r = srv.poll(t)
+        assert r is not None and r["status"] == 0, r
+    sat_rate = nsat / sat_s
+    sat_mcells = work(range(nsat)) / sat_s / 1e6
+    log(f"[bench]   saturation: {sat_rate:.1f} req/s, {sat_mcells:.0f} Mcell-updates/s")
+    # open loop: Poisson arrivals at load x saturation
+    lam = args.load * sat_rate
+    rng = np.random.default_rng(1311)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=nreq))
+    tickets = []
+    t0 = time.perf_counter()
+    for i in range(nreq):
+        now = time.perf_counter() - t0
+        if arrivals[i] > now:
+            time.sleep(arrivals[i] - now)
+        tickets.append(submit(i))
+        if i % 100 == 99:
+            log(f"[bench]   submitted {i + 1}/{nreq}")
+    srv.drain()
+    wall = time.perf_counter() - t0
+    res = [srv.poll(t) for t, _ in tickets]
+    srv.close()
+    assert all(r is not None and r["status"] == 0 for r in res)
+    lat = np.array([r["latency_s"] for r in res]) * 1e3
+    que = np.array([r["queue_s"] for r in res]) * 1e3
+    thr = work(range(nreq)) / wall / 1e6
+    p50, p99 = np.percentile(lat, [50, 99])
+    return _base(
+        "open-loop Poisson arrivals; latency = submit -> result",
+        thr, 1e3 * wall / nreq, nreq, 0, "f64+f32",
+        {"workload": f"served_{nreq}_requests_64..384^3", "requests": nreq,
+         "load": args.load, "arrival_rate_per_s": round(lam, 2),
+         "precision": "mixed", "rtol": 1e-8, "arena_GiB": round(arena / 2**30, 1)},
+        None,
+        {"latency_ms": {"p50": round(float(p50), 3), "p99": round(float(p99), 3),
+                        "mean": round(float(lat.mean()), 3)},
+         "queue_ms": {"p50": round(float(np.percentile(que, 50)), 3),
+                      "p99": round(float(np.percentile(que, 99)), 3)},
+         "saturation": {"req_per_s": round(sat_rate, 2),
+                        "mcell_updates_per_s": round(sat_mcells, 1)},
+         "max_rel_resid": max(r["rel_resid"] for r in res),
+         "iters_mean": float(np.mean([r["iters"] for r in res]))})

@@ -1,0 +1,109 @@
+"""Autotuner for the batched FLD step: picks the work-tile depth and the
+red/black sweep counts of the V-cycle for a given set of problem shapes by
+timing whole batch steps (each to the same 1e-8 residual) through the C-ABI,
+and caches the winner per (shape multiset, precision, GPU arch) in a JSON
+file.
+
+Candidates: tile depth in {0 (automatic), 1, 2, 4, 8} x (nu_pre, nu_post) in
+{(1, 1), (2, 2)}.  (1, 1) runs the fused finest-level passes; (2, 2) the
+per-half-sweep kernels.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+
+import torch
+
+import paper_1306_0645_amd as fld
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "fld_mi355x",
+                             "autotune.json")
+
+CANDIDATES = [dict(tile_z=tz, nu_pre=nu, nu_post=nu)
+              for nu in (1, 2) for tz in (0, 1, 2, 4, 8)]
+
+
+def _key(shapes, params):
+    arch = torch.cuda.get_device_properties(0).gcnArchName if torch.cuda.is_available() else "cpu"
+    sig = sorted(tuple(int(v) for v in s) for s in shapes)
+    h = hashlib.sha1(json.dumps(sig).encode()).hexdigest()[:16]
+    return f"{arch}:{params.precision}:{len(shapes)}:{h}"
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _time_batch(shapes, hs, params, fields, dts, reps):
+    B = fld.Batch(shapes, hs, params)
+    E0, K, H = fields
+    best = float("inf")
+    for r in range(reps + 1):
+        Es = [e.clone() for e in E0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = B.step(Es, K, H, dts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if any(s["status"] != 0 for s in sts):
+            B.close()
+            return float("inf")
+        if r > 0:  # the first run captures the graph and warms up
+            best = min(best, dt)
+    B.close()
+    return best
+
+
+def tune_batch(shapes, hs, base: "fld.Params", fields, dts, reps=2,
+               cache_path=DEFAULT_CACHE, log=None):
+    """Return (params, report): the fastest candidate for this batch, from the
+    cache when present.  fields = (E list, kappa list, eta list) on the GPU;
+    E is cloned for every timed run."""
+    key = _key(shapes, base)
+    cache = _load(cache_path)
+
+    def make(c):
+        p = fld.Params()
+        ctypes_copy(p, base)
+        for k, v in c.items():
+            setattr(p, k, v)
+        return p
+
+    if key in cache:
+        c = cache[key]["best"]
+        return make(c), {"cached": True, "best": c, "key": key}
+    results = []
+    for c in CANDIDATES:
+        t = _time_batch(shapes, hs, make(c), fields, dts, reps)
+        results.append((t, c))
+        if log:
+            log(f"[autotune] {c} -> {t * 1e3:.2f} ms")
+    results.sort(key=lambda tc: tc[0])
+    best = results[0][1]
+    cache[key] = {"best": best, "ms": {json.dumps(c): round(t * 1e3, 3)
+                                       for t, c in results}}
+    try:
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+    except OSError:
+        pass
+    return make(best), {"cached": False, "best": best, "key": key,
+                        "ms": {json.dumps(c): round(t * 1e3, 3) for t, c in results}}
+
+
+def ctypes_copy(dst, src):
+    for name, _ in src._fields_:
+        v = getattr(src, name)
+        if hasattr(v, "_length_"):
+            for i in range(len(v)):
+                getattr(dst, name)[i] = v[i]
+        else:
+            setattr(dst, name, v)

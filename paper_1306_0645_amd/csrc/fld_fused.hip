@@ -159,6 +159,27 @@ __global__ __launch_bounds__(kBlock) void k_vdown(Tables T, TileList TL, int l) 
     if (m + 1 < t.tz + 4)
       load_plane<R, L0, false>(pr, t, pz + 1, nx, ny, nz, f, C.d, nullptr, false, 0, 0);
     __syncthreads();
+    // coefficients of the red cells of plane pz - 2, loaded before the black
+    // pass so their latency overlaps it
+    const int pr2 = pz - 2;
+    const bool out = m >= 4 && cown;
+    R ctx[2], ctxm[2], cty[2], ctym[2], ctz[2], ctzm[2];
+    int cs[2];
+    if (out) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int a = (b + pr2) & 1;  // the red cell of row b
+        const int lx = 2 * ci + a, ly = 2 * cj + b;
+        const Nb n = nbrs(t.x0 + lx, t.y0 + ly, pr2, nx, ny, nz);
+        cs[b] = (ly + 1) * kE1X + (lx + 1);
+        ctx[b] = C.tx[n.c];
+        ctxm[b] = C.tx[n.xm];
+        cty[b] = C.ty[n.c];
+        ctym[b] = C.ty[n.ym];
+        ctz[b] = C.tz[n.c];
+        ctzm[b] = C.tz[n.zm];
+      }
+    }
     // (2) black cells of plane pz - 1 over the tile + 1
     if (m >= 2) {
       black_plane<R>(t, pz - 1, nx, ny, nz, C, ys[(m + 1) % 3], ys[(m + 2) % 3],
@@ -166,18 +187,13 @@ __global__ __launch_bounds__(kBlock) void k_vdown(Tables T, TileList TL, int l) 
       __syncthreads();
     }
     // (3) red residuals of plane pz - 2, summed into the coarse cell
-    if (m >= 4 && cown) {
-      const int pr2 = pz - 2;
+    if (out) {
       const R *xm = xs[(m + 1) % 3], *x0 = xs[(m + 2) % 3], *xp = xs[m % 3];
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const int a = (b + pr2) & 1;  // the red cell of row b
-        const int lx = 2 * ci + a, ly = 2 * cj + b;
-        const Nb n = nbrs(t.x0 + lx, t.y0 + ly, pr2, nx, ny, nz);
-        const int s = (ly + 1) * kE1X + (lx + 1);
-        acc += C.tx[n.c] * x0[s + 1] + C.tx[n.xm] * x0[s - 1] +
-               C.ty[n.c] * x0[s + kE1X] + C.ty[n.ym] * x0[s - kE1X] +
-               C.tz[n.c] * xp[s] + C.tz[n.zm] * xm[s];
+        const int s = cs[b];
+        acc += ctx[b] * x0[s + 1] + ctxm[b] * x0[s - 1] + cty[b] * x0[s + kE1X] +
+               ctym[b] * x0[s - kE1X] + ctz[b] * xp[s] + ctzm[b] * xm[s];
       }
       if ((pr2 - t.z0) & 1) {
         fc[((pr2 >> 1) * Cv.ny + (t.y0 >> 1) + cj) * Cv.nx + (t.x0 >> 1) + ci] = acc;
@@ -232,30 +248,28 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
       const int pr2 = pz - 2;
       const R *xm = xs[(m + 1) % 3], *x0 = xs[(m + 2) % 3], *xp = xs[m % 3];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const int lx = 2 * ci + a, ly = 2 * cj + b;
-          const int s = (ly + 1) * kE1X + (lx + 1);
-          const Nb n = nbrs(t.x0 + lx, t.y0 + ly, pr2, nx, ny, nz);
-          R v;
-          if (((a + b + pr2) & 1) == 0) {
-            const R sum = C.tx[n.c] * x0[s + 1] + C.tx[n.xm] * x0[s - 1] +
-                          C.ty[n.c] * x0[s + kE1X] + C.ty[n.ym] * x0[s - kE1X] +
-                          C.tz[n.c] * xp[s] + C.tz[n.zm] * xm[s];
-            v = (f(n.c) + sum) * recip(C.d[n.c]);
-          } else {
-            v = x0[s];
-          }
-          if constexpr (L0) {
-            const double z = (double)v * s_out;
-            const double r = P.r[n.c];
-            if (flexible) rzo += r * P.z[n.c];
-            P.z[n.c] = z;
-            rz += r * z;
-          } else {
-            xout[n.c] = v;
-          }
+      for (int u = 0; u < 4; ++u) {
+        const int a = u & 1, b = u >> 1;
+        const int lx = 2 * ci + a, ly = 2 * cj + b;
+        const int s = (ly + 1) * kE1X + (lx + 1);
+        const Nb n = nbrs(t.x0 + lx, t.y0 + ly, pr2, nx, ny, nz);
+        R v;
+        if (((a + b + pr2) & 1) == 0) {
+          const R sum = C.tx[n.c] * x0[s + 1] + C.tx[n.xm] * x0[s - 1] +
+                        C.ty[n.c] * x0[s + kE1X] + C.ty[n.ym] * x0[s - kE1X] +
+                        C.tz[n.c] * xp[s] + C.tz[n.zm] * xm[s];
+          v = (f(n.c) + sum) * recip(C.d[n.c]);
+        } else {
+          v = x0[s];
+        }
+        if constexpr (L0) {
+          const double z = (double)v * s_out;
+          const double r = P.r[n.c];
+          if (flexible) rzo += r * P.z[n.c];
+          P.z[n.c] = z;
+          rz += r * z;
+        } else {
+          xout[n.c] = v;
         }
       }
     }

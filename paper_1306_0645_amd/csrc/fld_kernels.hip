@@ -407,7 +407,43 @@ __global__ __launch_bounds__(kCoarseBlock) void k_coarse_solve(Tables T) {
 
 // p_new = z + beta p_old (formed at the cell and its neighbours on the fly),
 // q = A p_new, partial p_new . q.  p is double-buffered so neighbours read
-// the old direction while the new one is written.
+// the old direction while the new one is written.  Each thread walks its
+// column in z keeping p_new at planes k-1, k, k+1 and the -z face in
+// registers.
+template <bool BETA>
+__device__ __forceinline__ double spmv_column(
+    const Tile &t, const Col &col, int nx, int ny, int nz, double beta,
+    const double *__restrict__ z, const double *__restrict__ po,
+    double *__restrict__ pn, double *__restrict__ q,
+    const double *__restrict__ Tx, const double *__restrict__ Ty,
+    const double *__restrict__ Tz, const double *__restrict__ Dg) {
+  auto pv = [&](int g) { return BETA ? z[g] + beta * po[g] : z[g]; };
+  const int plane = nx * ny, i = col.i, j = col.j;
+  const int dxm = (i == 0) ? nx - 1 : -1, dxp = (i == nx - 1) ? 1 - nx : 1;
+  const int dym = (j == 0) ? (ny - 1) * nx : -nx;
+  const int dyp = (j == ny - 1) ? -(ny - 1) * nx : nx;
+  int c = t.z0 * plane + j * nx + i;
+  const int cm0 = (t.z0 == 0) ? c + (nz - 1) * plane : c - plane;
+  double p_m = pv(cm0), p_c = pv(c), tz_m = Tz[cm0];
+  double acc = 0.0;
+  for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+    const int cp = (k == nz - 1) ? c - (nz - 1) * plane : c + plane;
+    const double p_p = pv(cp);
+    const double s = Tx[c] * pv(c + dxp) + Tx[c + dxm] * pv(c + dxm) +
+                     Ty[c] * pv(c + dyp) + Ty[c + dym] * pv(c + dym) +
+                     Tz[c] * p_p + tz_m * p_m;
+    const double qq = Dg[c] * p_c - s;
+    pn[c] = p_c;
+    q[c] = qq;
+    acc += p_c * qq;
+    tz_m = Tz[c];
+    p_m = p_c;
+    p_c = p_p;
+    c = cp;
+  }
+  return acc;
+}
+
 __global__ __launch_bounds__(kBlock) void k_spmv_p(Tables T, TileList TL) {
   const int tid = get_tile_index(TL);
   const Tile t = TL.base[tid];
@@ -418,30 +454,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(Tables T, TileList TL) {
   const double beta = sc.beta;
   const double *po = sc.pbuf ? P.p1 : P.p0;
   double *pn = sc.pbuf ? P.p0 : P.p1;
-  const double *z = P.z;
-  const Coef<double> C = coefs<double>(L);
   const Col col = tile_col(t);
   double pq = 0.0;
   if (col.on) {
-    for (int k = t.z0; k < t.z0 + t.tz; ++k) {
-      for (int e = 0; e < t.cpt; ++e) {
-        const Nb n = nbrs(col.i + e, col.j, k, L.nx, L.ny, L.nz);
-        double pc, s;
-        if (beta != 0.0) {
-          auto pv = [&](int q) { return z[q] + beta * po[q]; };
-          pc = pv(n.c);
-          s = offsum(C, n, pv);
-        } else {
-          auto pv = [&](int q) { return z[q]; };
-          pc = pv(n.c);
-          s = offsum(C, n, pv);
-        }
-        const double q = C.d[n.c] * pc - s;
-        pn[n.c] = pc;
-        P.q[n.c] = q;
-        pq += pc * q;
-      }
-    }
+    if (beta != 0.0)
+      pq = spmv_column<true>(t, col, L.nx, L.ny, L.nz, beta, P.z, po, pn, P.q,
+                             L.Tx, L.Ty, L.Tz, L.diag);
+    else
+      pq = spmv_column<false>(t, col, L.nx, L.ny, L.nz, beta, P.z, po, pn, P.q,
+                              L.Tx, L.Ty, L.Tz, L.diag);
   }
   write_partials(T, tid, pq, 0.0);
 }
@@ -455,19 +476,21 @@ __global__ __launch_bounds__(kBlock) void k_update(Tables T, TileList TL) {
   const LevelDev L = T.lv[t.prob];
   const ProbDev P = T.pd[t.prob];
   const double alpha = sc.alpha;
-  const double *p = sc.pbuf ? P.p1 : P.p0;
+  const double *__restrict__ p = sc.pbuf ? P.p1 : P.p0;
+  const double *__restrict__ q = P.q;
+  double *__restrict__ x = P.x;
+  double *__restrict__ r = P.r;
   const Col col = tile_col(t);
   double rr = 0.0;
   if (col.on) {
-    for (int k = t.z0; k < t.z0 + t.tz; ++k) {
-      const int c0 = (k * L.ny + col.j) * L.nx + col.i;
-      for (int e = 0; e < t.cpt; ++e) {
-        const int c = c0 + e;
-        P.x[c] += alpha * p[c];
-        const double r = P.r[c] - alpha * P.q[c];
-        P.r[c] = r;
-        rr += r * r;
-      }
+    const int plane = L.nx * L.ny;
+    int c = t.z0 * plane + col.j * L.nx + col.i;
+    for (int k = 0; k < t.tz; ++k, c += plane) {
+      const double pc = p[c], qc = q[c], xc = x[c], rc = r[c];
+      x[c] = xc + alpha * pc;
+      const double rn = rc - alpha * qc;
+      r[c] = rn;
+      rr += rn * rn;
     }
   }
   write_partials(T, tid, rr, 0.0);

@@ -259,3 +259,112 @@ def random_problem(shape, seed: int, sigma_ln: float = 1.0, n_src: int = 4,
         raise ValueError(E_mode)
     return _problem(shape, dx, kappa, eta, E, L, dt, f"random_{shape}_{seed}",
                     theta=theta)
+
+
+# ---------------------------------------------------------------------------
+# Device-side generators for large workloads (same recipe, drawn with torch's
+# seeded generator on the GPU so 640^3 fields and hundreds of requests can be
+# made in seconds).  They return torch float64 tensors on `device`.
+# ---------------------------------------------------------------------------
+
+def t_smooth_gaussian(shape, sigma_cells, gen, device):
+    import torch
+    g = torch.randn(shape, generator=gen, device=device, dtype=torch.float64)
+    if sigma_cells > 0:
+        G = torch.fft.rfftn(g)
+        kz = torch.fft.fftfreq(shape[0], device=device, dtype=torch.float64)[:, None, None]
+        ky = torch.fft.fftfreq(shape[1], device=device, dtype=torch.float64)[None, :, None]
+        kx = torch.fft.rfftfreq(shape[2], device=device, dtype=torch.float64)[None, None, :]
+        k2 = (2 * math.pi) ** 2 * (kx * kx + ky * ky + kz * kz)
+        G *= torch.exp(-0.5 * sigma_cells ** 2 * k2)
+        del k2
+        g = torch.fft.irfftn(G, s=shape)
+        del G
+    g -= g.mean()
+    sd = g.std()
+    if sd > 0:
+        g /= sd
+    return g
+
+
+def t_generator(workload, problem, device):
+    import torch
+    seed = int(np.random.SeedSequence([BASE_SEED + workload, problem]).generate_state(1)[0])
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    return gen
+
+
+def t_emissivity(shape, cells, ndot, cell_volume, device):
+    import torch
+    eta = torch.zeros(int(np.prod(shape)), dtype=torch.float64, device=device)
+    eta.index_add_(0, torch.as_tensor(np.asarray(cells, dtype=np.int64), device=device),
+                   torch.as_tensor(np.asarray(ndot) * HNU_HI / cell_volume,
+                                   dtype=torch.float64, device=device))
+    return eta.reshape(shape)
+
+
+def t_problem(shape, sigma_ln, n_src, lum, workload, problem, device, dx=DX_TEST1,
+              mean_density=1e-3, E_mode="smooth", L_cells=None):
+    """One problem of the lognormal / point-source recipe on the device:
+    kappa = sigma_HI n_HI, n_HI lognormal (1.5-cell smoothing), n_src sources
+    with Ndot log-uniform in lum at random cells, E^n smooth (8-cell) around
+    mean(eta) dt, dt = 1e-3 light-crossing times of L_unit."""
+    import torch
+    gen = t_generator(workload, problem, device)
+    rng = rng_for(workload, 200000 + problem)
+    shape = tuple(int(s) for s in shape)
+    g = t_smooth_gaussian(shape, 1.5, gen, device)
+    kappa = SIGMA_HI * torch.exp(math.log(mean_density) + sigma_ln * g)
+    del g
+    cells, ndot = point_sources(shape, n_src, lum[0], lum[1], rng)
+    eta = t_emissivity(shape, cells, ndot, dx ** 3, device)
+    L = (L_cells if L_cells is not None else max(shape)) * dx
+    dt = 1e-3 * L / C_LIGHT
+    if E_mode == "smooth":
+        E = float(eta.mean()) * dt * torch.exp(t_smooth_gaussian(shape, 8.0, gen, device))
+    else:
+        E = torch.full(shape, float(E_mode), dtype=torch.float64, device=device)
+    return {"name": f"t_{workload}_{problem}_{shape[0]}", "shape": shape,
+            "h": (dx, dx, dx), "E": E, "kappa": kappa, "eta": eta,
+            "c": C_LIGHT, "L_unit": L, "dt": dt, "theta": 1.0, "a": 1.0,
+            "adot": 0.0, "cells": cells, "ndot": ndot}
+
+
+def t_reionization_share(n=640, n_src=10000, sigma_ln=2.0, device="cuda",
+                         L_cells=3200):
+    """Workload 3 on the device (see reionization_share)."""
+    import torch
+    shape = (n, n, n)
+    dx = 25.0 * KPC / 9.0
+    nbar = 1.43e-4
+    gen = t_generator(3, 0, device)
+    rng = rng_for(3, 0)
+    g = t_smooth_gaussian(shape, 1.5, gen, device)
+    nH = torch.exp(math.log(nbar) + sigma_ln * g)
+    del g
+    cells, ndot = point_sources(shape, n_src, 1e46, 1e49, rng)
+    rs = stromgren_radius(ndot, nbar) / dx
+    cz, rem = np.divmod(cells, n * n)
+    cy, cx = np.divmod(rem, n)
+    ionized = torch.zeros(shape, dtype=torch.bool, device=device)
+    for x0, y0, z0, r in zip(cx, cy, cz, rs):
+        ri = int(math.ceil(r))
+        if ri < 1:
+            continue
+        o = torch.arange(-ri, ri + 1, device=device)
+        d2 = o[:, None, None] ** 2 + o[None, :, None] ** 2 + o[None, None, :] ** 2
+        iz = ((int(z0) + o) % n)[:, None, None]
+        iy = ((int(y0) + o) % n)[None, :, None]
+        ix = ((int(x0) + o) % n)[None, None, :]
+        ionized[iz, iy, ix] |= d2 <= r * r
+    # x_HI = 1e-4 inside the bubbles
+    kappa = SIGMA_HI * nH * torch.where(ionized, 1e-4, 1.0)
+    del nH, ionized
+    eta = t_emissivity(shape, cells, ndot, dx ** 3, device)
+    L = L_cells * dx
+    dt = 1e-3 * L / C_LIGHT
+    E = torch.full(shape, 1e-45, dtype=torch.float64, device=device)
+    return {"name": f"reionization_{n}", "shape": shape, "h": (dx, dx, dx),
+            "E": E, "kappa": kappa, "eta": eta, "c": C_LIGHT, "L_unit": L,
+            "dt": dt, "theta": 1.0, "a": 1.0, "adot": 0.0}
