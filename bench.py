@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--tile-z", type=int, default=0)
     ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--fused-tile-z", type=int, default=0)
     ap.add_argument("--workload", default="many_sources",
                     choices=["many_sources", "single_source", "reionization",
                              "batch", "served"])
@@ -68,6 +69,9 @@ def parse():
     ap.add_argument("--requests", type=int, default=500, help="served: requests")
     ap.add_argument("--load", type=float, default=0.7,
                     help="served: arrival rate as a fraction of saturation")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run a plain copy kernel of 2 GiB read + 2 GiB "
+                         "written, to calibrate the HBM byte counters")
     return ap.parse_args()
 
 
@@ -82,7 +86,8 @@ def run_form(fld, torch, p, prec, steps, warmup, args):
 
     def solver(graph):
         prm = fld.fld_default_params(p["c"], p["L_unit"], precision=prec,
-                                     tile_z=args.tile_z, use_graph=graph)
+                                     tile_z=args.tile_z, use_graph=graph,
+                                     fused_tile_z=args.fused_tile_z)
         return fld.Solver(p["shape"], p["h"], prm)
 
     S = solver(args.graph)
@@ -168,6 +173,12 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
+    if args.copy_probe:
+        # y = x + 0 over 2^28 doubles: one kernel reading 2 GiB and writing 2 GiB
+        x = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+        y = x.add(0.0)
+        torch.cuda.synchronize()
+        del x, y
     log(f"[bench] generating the {args.n}^3 many-source workload")
     p = synth.many_sources(args.n)
     forms = {}

@@ -95,7 +95,19 @@ typedef struct fld_params {
   int32_t check_every; /* PCG iterations between host convergence reads; 0 = auto */
   int32_t use_graph;   /* 1 (default) = replay the PCG iteration from a captured
                           hipGraph; 0 = launch its kernels one by one */
-  int32_t reserved[7];
+  int32_t fused_tile_z;/* z-depth of the fused finest-level V-cycle tiles (even);
+                          0 = automatic */
+  int32_t cycle_switch;/* > 0: when a V(1,1) solve needs more PCG iterations
+                          than this, later solves of the handle use V(2,2); a
+                          V(2,2) solve needing at most a third of it switches
+                          back.  0: the cycle stays nu_pre/nu_post.  Default 12 */
+  int32_t prolongation;/* coarse-grid correction of the FP32 (mixed) cycle:
+                          0 = piecewise constant, 1 = cell-centred trilinear,
+                          2 = trilinear only while the handle runs V(2,2)
+                          after a cycle switch (default).  The FP64 cycle is
+                          always piecewise constant with restriction = its
+                          transpose, so it stays a symmetric preconditioner */
+  int32_t reserved[4];
 } fld_params;
 
 typedef struct fld_stats {
@@ -105,6 +117,7 @@ typedef struct fld_stats {
   int32_t dt_cuts;      /* 10x cuts taken by fld_step */
   int32_t levels;       /* multigrid levels used */
   int32_t restarts;     /* refinement restarts from the true FP64 residual */
+  int32_t cycle_nu;     /* red/black sweeps per side of the V-cycle used last */
   double rel_resid;     /* true ||b - A dE||_2 / ||b||_2 of the last solve */
   double err_bound;     /* ||b - A dE||_2 / ||dE||_2: bounds the relative 2-norm
                            error of dE because ||A^-1||_2 <= 1 when adot >= 0 */
@@ -121,7 +134,8 @@ typedef struct fld_server fld_server;
 /* Paper defaults (Sec. 2, Sec. 3.4, Table 1) for a run whose length unit is
  * L_unit: d_max = 0.006 c L_unit, r_min = 1e-20 / L_unit, rtol = 1e-8,
  * max_iter = 50, nu_pre = nu_post = 1, theta = 1, tau_tol = 1e-4, FP64,
- * coarse_scale = 0.5, max_dt_cuts = 8, graph replay on. */
+ * coarse_scale = 0.5, max_dt_cuts = 8, graph replay on, cycle_switch = 12,
+ * trilinear prolongation in the mixed cycle. */
 void fld_default_params(fld_params *p, double c, double L_unit);
 
 const char *fld_strerror(fld_status s);

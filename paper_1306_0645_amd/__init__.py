@@ -52,13 +52,16 @@ class Params(ctypes.Structure):
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("max_dt_cuts", ctypes.c_int32),
                 ("tile_z", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("use_graph", ctypes.c_int32), ("fused_tile_z", ctypes.c_int32),
+                ("cycle_switch", ctypes.c_int32), ("prolongation", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("subcycles", ctypes.c_int32), ("dt_cuts", ctypes.c_int32),
                 ("levels", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("cycle_nu", ctypes.c_int32),
                 ("rel_resid", ctypes.c_double), ("err_bound", ctypes.c_double),
                 ("rel_change_rms", ctypes.c_double), ("dt_next", ctypes.c_double),
                 ("bnorm", ctypes.c_double), ("dEnorm", ctypes.c_double)]

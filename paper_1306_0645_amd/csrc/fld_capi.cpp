@@ -31,9 +31,10 @@ bool step_args_ok(double dt, double a, double adot) {
          std::isfinite(adot);
 }
 
-void fill_stats(fld_stats *s, const Job &j, int levels) {
+void fill_stats(fld_stats *s, const Job &j, int levels, int nu) {
   if (!s) return;
   std::memset(s, 0, sizeof(*s));
+  s->cycle_nu = nu;
   s->status = j.status;
   s->iters = j.iters;
   s->subcycles = j.substeps;
@@ -72,6 +73,9 @@ void fld_default_params(fld_params *p, double c, double L_unit) {
   p->tile_z = 0;
   p->check_every = 0;
   p->use_graph = 1;
+  p->fused_tile_z = 0;
+  p->cycle_switch = 12;
+  p->prolongation = 2;
 }
 
 const char *fld_strerror(fld_status s) {
@@ -163,7 +167,7 @@ fld_status fld_solve(fld_handle *h, double *dE, fld_stats *stats) {
   const double rr = sc.phase == PH_DONE && sc.status == ST_OK ? sc.rr_true : sc.rr;
   j.rel_resid = sc.bb > 0.0 ? std::sqrt(rr / sc.bb) : 0.0;
   j.err_bound = j.dEnorm > 0.0 ? std::sqrt(rr) / j.dEnorm : 0.0;
-  fill_stats(stats, j, e.hier[0].levels);
+  fill_stats(stats, j, e.hier[0].levels, e.last_nu);
   e.h_sc[0].live = 1;  // the assembled system stays available
   return (fld_status)sc.status;
 }
@@ -187,7 +191,7 @@ fld_status fld_step(fld_handle *h, double *E, const double *kappa,
   const int st = e.run_steps(jobs);
   if (st) return (fld_status)st;
   e.assembled = true;
-  fill_stats(stats, j, e.hier[0].levels);
+  fill_stats(stats, j, e.hier[0].levels, e.last_nu);
   return (fld_status)j.status;
 }
 
@@ -323,7 +327,7 @@ fld_status fld_batch_step(fld_batch *b, double *const *E,
   e.assembled = true;
   int first = FLD_OK;
   for (int i = 0; i < n; ++i) {
-    if (per_problem) fill_stats(&per_problem[i], jobs[i], e.hier[i].levels);
+    if (per_problem) fill_stats(&per_problem[i], jobs[i], e.hier[i].levels, e.last_nu);
     if (jobs[i].status != FLD_OK && first == FLD_OK) first = jobs[i].status;
   }
   return (fld_status)first;

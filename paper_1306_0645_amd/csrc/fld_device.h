@@ -181,4 +181,29 @@ __device__ __forceinline__ FSrc<R, L0> fsrc(const LevelDev &L, const ProbDev &P,
   return s;
 }
 
+// Coarse-grid correction at fine cell (gx, gy, gz) of a level whose coarse
+// level has extents (cnx, cny, cnz) = half the fine ones.
+//  trilinear = false: piecewise constant, e(parent)
+//  trilinear = true:  cell-centred trilinear interpolation from the 8 nearest
+//                     coarse cells, weights 3/4 (own parent) and 1/4 (the
+//                     neighbour on the fine cell's side) per direction
+template <typename R>
+__device__ __forceinline__ R coarse_corr(const R *e, int gx, int gy, int gz,
+                                         int cnx, int cny, int cnz,
+                                         bool trilinear) {
+  const int I = gx >> 1, J = gy >> 1, K = gz >> 1;
+  if (!trilinear) return e[(K * cny + J) * cnx + I];
+  const int I2 = (gx & 1) ? (I + 1 == cnx ? 0 : I + 1) : (I == 0 ? cnx - 1 : I - 1);
+  const int J2 = (gy & 1) ? (J + 1 == cny ? 0 : J + 1) : (J == 0 ? cny - 1 : J - 1);
+  const int K2 = (gz & 1) ? (K + 1 == cnz ? 0 : K + 1) : (K == 0 ? cnz - 1 : K - 1);
+  const R a = (R)0.75, b = (R)0.25;
+  const int r00 = (K * cny + J) * cnx, r01 = (K * cny + J2) * cnx;
+  const int r10 = (K2 * cny + J) * cnx, r11 = (K2 * cny + J2) * cnx;
+  const R zK = a * (a * e[r00 + I] + b * e[r00 + I2]) +
+               b * (a * e[r01 + I] + b * e[r01 + I2]);
+  const R zK2 = a * (a * e[r10 + I] + b * e[r10 + I2]) +
+                b * (a * e[r11 + I] + b * e[r11 + I2]);
+  return a * zK + b * zK2;
+}
+
 }  // namespace fld

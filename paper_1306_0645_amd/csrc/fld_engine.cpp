@@ -39,6 +39,9 @@ bool params_ok(const fld_params &p) {
   if (p.precision != FLD_PREC_FP64 && p.precision != FLD_PREC_MIXED) return false;
   if (p.max_dt_cuts < 0 || p.tile_z < 0 || p.tile_z > 64 || p.check_every < 0)
     return false;
+  if (p.fused_tile_z < 0 || p.fused_tile_z > 256 || (p.fused_tile_z & 1)) return false;
+  if (p.cycle_switch < 0) return false;
+  if (p.prolongation < 0 || p.prolongation > 2) return false;
   return true;
 }
 
@@ -61,22 +64,27 @@ Hier make_hier(const fld_grid &g, const fld_params &p) {
   }
   for (int l = 0; l < h.levels; ++l) {
     h.tiles[l] = count_tiles(p, h.n[l][0], h.n[l][1], h.n[l][2]);
-    h.ftiles[l] = count_fused_tiles(h.n[l][0], h.n[l][1], h.n[l][2]);
+    h.ftiles[l] = count_fused_tiles(p, h.n[l][0], h.n[l][1], h.n[l][2]);
   }
   return h;
 }
 
 // Tiles of the fused one-sweep V-cycle kernels: 64 x 16 cells in x, y (their
-// LDS buffers are sized for that) and up to 16 planes in z.
-void fused_shape(int nx, int ny, int nz, int &tx, int &ty, int &tz) {
+// LDS buffers are sized for that) and fused_tile_z planes in z.  Deeper tiles
+// cut the z-halo but leave fewer tiles to hide latency: measured on gfx950 at
+// 256^3, 16 planes suit the FP32 cycle and 32 the FP64 one (whose LDS use
+// already limits it to two tiles per CU).
+void fused_shape(const fld_params &p, int nx, int ny, int nz, int &tx, int &ty,
+                 int &tz) {
   tx = std::min(nx, 64);
   ty = std::min(ny, 16);
-  tz = std::min(nz, 16);
+  const int def = p.precision == FLD_PREC_MIXED ? 16 : 32;
+  tz = std::min(nz, p.fused_tile_z > 0 ? p.fused_tile_z : def);
 }
 
-int count_fused_tiles(int nx, int ny, int nz) {
+int count_fused_tiles(const fld_params &p, int nx, int ny, int nz) {
   int tx, ty, tz;
-  fused_shape(nx, ny, nz, tx, ty, tz);
+  fused_shape(p, nx, ny, nz, tx, ty, tz);
   return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz);
 }
 
@@ -267,7 +275,7 @@ int Engine::setup(const fld_params &p, hipStream_t s,
       fbeg[(size_t)i * kMaxLevels + l] = (int)h_tiles.size();
       const int nx = hier[i].n[l][0], ny = hier[i].n[l][1], nz = hier[i].n[l][2];
       int tx, ty, tz;
-      fused_shape(nx, ny, nz, tx, ty, tz);
+      fused_shape(prm, nx, ny, nz, tx, ty, tz);
       emit(i, nx, ny, nz, tx, ty, tz);
     }
   }
@@ -328,13 +336,8 @@ int Engine::build_lists(const std::vector<char> &member, int slot, ListSet &out)
     };
     out.smooth[l] = make(l, smoothed);
     out.exist[l] = make(l, [&](int) { return l >= 1; });
-    if (fused) {
-      out.fsm[l] = make_any(l, true, smoothed);
-      out.fdn[l] = make_any(l, true, [&](int i) { return l < hier[i].levels - 1; });
-    } else {
-      out.fsm[l] = TileList{d_tiles, slot_base, 0, 0};
-      out.fdn[l] = TileList{d_tiles, slot_base, 0, 0};
-    }
+    out.fsm[l] = make_any(l, true, smoothed);
+    out.fdn[l] = make_any(l, true, [&](int i) { return l < hier[i].levels - 1; });
   }
   if (h_ranges.size() > per_slot) return ST_EINVAL;
   if (!h_ranges.empty())
@@ -375,6 +378,22 @@ int Engine::download_sc() {
   return ST_OK;
 }
 
+int Engine::set_cycle(int nu) {
+  if (prm.nu_pre == nu && prm.nu_post == nu) return ST_OK;
+  switched = nu > 1;
+  prm.nu_pre = prm.nu_post = nu;
+  fused = fused_cycle(prm);
+  return release_graph();
+}
+
+int Engine::adapt_cycle(int max_iters) {
+  const int thr = prm.cycle_switch;
+  if (thr <= 0) return ST_OK;
+  if (prm.nu_pre == 1 && prm.nu_post == 1 && max_iters > thr) return set_cycle(2);
+  if (prm.nu_pre == 2 && prm.nu_post == 2 && max_iters * 3 <= thr) return set_cycle(1);
+  return ST_OK;
+}
+
 void Engine::fill_step(int p, const double *E, const double *kappa,
                        const double *eta, double dt, double a, double adot) {
   StepDev &S = h_sd[p];
@@ -405,6 +424,8 @@ void Engine::enqueue_assemble(const ListSet &ls) {
 // adjoint order, so the FP64 cycle is a symmetric preconditioner.
 void Engine::enqueue_vcycle(const ListSet &ls) {
   const int prec = mixed;
+  const int tri = (mixed && (prm.prolongation == 1 ||
+                             (prm.prolongation == 2 && switched))) ? 1 : 0;
   if (fused) {
     // one sweep each way: the finest level runs the two fused passes (they
     // never store the pre-smoothed x); coarse levels, latency-bound small
@@ -418,10 +439,10 @@ void Engine::enqueue_vcycle(const ListSet &ls) {
     if (Lmax > 1) launch_coarse_solve(T, prec, stream);
     for (int l = Lmax - 1; l >= 1; --l) {
       if (ls.smooth[l].nblocks == 0) continue;
-      launch_prolong_black(T, ls.smooth[l], l, prec, stream);
+      launch_prolong_black(T, ls.smooth[l], l, prec, tri, stream);
       launch_half(T, ls.smooth[l], l, 0, prec, stream);
     }
-    launch_vup(T, ls.fsm[0], 0, prec, mixed, stream);
+    launch_vup(T, ls.fsm[0], 0, prec, mixed, tri, stream);
     return;
   }
   const TileList *smooth = ls.smooth, *exist = ls.exist;
@@ -437,7 +458,7 @@ void Engine::enqueue_vcycle(const ListSet &ls) {
   if (Lmax > 1) launch_coarse_solve(T, prec, stream);
   for (int l = Lmax - 1; l >= 0; --l) {
     if (smooth[l].nblocks == 0) continue;
-    launch_prolong_black(T, smooth[l], l, prec, stream);
+    launch_prolong_black(T, smooth[l], l, prec, tri, stream);
     for (int s = 0; s < prm.nu_post; ++s) {
       if (s > 0) launch_half(T, smooth[l], l, 1, prec, stream);
       if (l == 0 && s == prm.nu_post - 1) launch_half_out(T, smooth[0], prec, mixed, stream);
@@ -466,6 +487,7 @@ int Engine::check_every() const {
 // recursive residual meets the tolerance are verified with the true FP64
 // residual b - A x and restarted from it if it does not (refinement).
 int Engine::run_solve() {
+  last_nu = prm.nu_pre;
   int st = download_sc();
   if (st) return st;
   for (;;) {
@@ -524,6 +546,13 @@ int Engine::run_steps(std::vector<Job> &jobs) {
     enqueue_assemble(all);
     st = run_solve();
     if (st) return st;
+    {
+      int mx = 0;
+      for (int p = 0; p < np; ++p)
+        if (h_sc[p].live) mx = std::max(mx, h_sc[p].iter);
+      st = adapt_cycle(mx);
+      if (st) return st;
+    }
     bool commit = false;
     for (int p = 0; p < np; ++p) {
       Job &j = jobs[p];

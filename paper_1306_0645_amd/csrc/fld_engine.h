@@ -41,8 +41,9 @@ Hier make_hier(const fld_grid &g, const fld_params &p);
 void tile_shape(const fld_params &p, int nx, int ny, int nz, int &tx, int &ty,
                 int &tz);
 int count_tiles(const fld_params &p, int nx, int ny, int nz);
-void fused_shape(int nx, int ny, int nz, int &tx, int &ty, int &tz);
-int count_fused_tiles(int nx, int ny, int nz);
+void fused_shape(const fld_params &p, int nx, int ny, int nz, int &tx, int &ty,
+                 int &tz);
+int count_fused_tiles(const fld_params &p, int nx, int ny, int nz);
 bool fused_cycle(const fld_params &p);
 size_t problem_bytes(const Hier &h, const fld_params &p);
 size_t tables_bytes(const std::vector<Hier> &hs);
@@ -97,6 +98,8 @@ class Engine {
   std::vector<int> tbeg;   // [p * kMaxLevels + l] first tile of (p, l)
   std::vector<int> fbeg;   // [p * kMaxLevels + l] first fused tile of (p, l)
   bool fused = false;      // one-sweep fused V-cycle kernels
+  int last_nu = 1;         // sweeps per side of the cycle used by the last solve
+  bool switched = false;   // the adaptive switch moved the handle to V(2,2)
 
   Tables T{};
   Tile *d_tiles = nullptr;
@@ -122,6 +125,11 @@ class Engine {
   // the ranges (enqueued on the stream)
   int build_lists(const std::vector<char> &member, int slot, ListSet &out);
   int release_graph();
+
+  // switch the V-cycle sweep counts (re-captures the graph next solve)
+  int set_cycle(int nu);
+  // adaptive cycle choice after a solve that took max_iters iterations
+  int adapt_cycle(int max_iters);
 
   void enqueue_assemble(const ListSet &ls);
   void enqueue_vcycle(const ListSet &ls);

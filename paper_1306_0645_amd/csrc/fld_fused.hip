@@ -58,7 +58,8 @@ __device__ __forceinline__ void load_plane(PlaneRegs<R, L0> &pr, const Tile &t,
                                            int pz, int nx, int ny, int nz,
                                            const FSrc<R, L0> &f, const R *d,
                                            const R *e, bool has_coarse, int cnx,
-                                           int cny) {
+                                           int cny, int cnz = 1,
+                                           bool trilinear = false) {
   const int e2x = t.tx + 4, n2 = e2x * (t.ty + 4);
   const int kz = wrapi(pz, nz);
 #pragma unroll
@@ -74,7 +75,7 @@ __device__ __forceinline__ void load_plane(PlaneRegs<R, L0> &pr, const Tile &t,
       pr.d[u] = d[g];
       if constexpr (UP) {
         pr.e[u] = (has_coarse && ((ux + uy + pz) & 1) == 0)
-                      ? e[((kz >> 1) * cny + (gy >> 1)) * cnx + (gx >> 1)]
+                      ? coarse_corr(e, gx, gy, kz, cnx, cny, cnz, trilinear)
                       : (R)0;
       }
     }
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_vdown(Tables T, TileList TL, int l) 
 
 template <typename R, bool L0>
 __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
-                                                int flexible) {
+                                                int flexible, int trilinear) {
   const int tid = get_tile_index(TL);
   const Tile t = TL.base[tid];
   const Scal &sc = T.sc[t.prob];
@@ -223,18 +224,21 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
   __shared__ R vs[3][kE2];
   __shared__ R xs[3][kE1];
   const int nx = L.nx, ny = L.ny, nz = L.nz;
-  const int cnx = Cl.nx, cny = Cl.ny;
+  const int cnx = Cl.nx, cny = Cl.ny, cnz = Cl.nz;
+  const bool tri = trilinear != 0;
   const int ci = threadIdx.x & 31, cj = threadIdx.x >> 5;
   const bool cown = 2 * ci < t.tx && 2 * cj < t.ty;
   PlaneRegs<R, L0> pr;
-  load_plane<R, L0, true>(pr, t, t.z0 - 2, nx, ny, nz, f, C.d, e, has_coarse, cnx, cny);
+  load_plane<R, L0, true>(pr, t, t.z0 - 2, nx, ny, nz, f, C.d, e, has_coarse, cnx,
+                          cny, cnz, tri);
   double rz = 0.0, rzo = 0.0;
   for (int m = 0; m < t.tz + 4; ++m) {
     const int pz = t.z0 - 2 + m;
     // (1) v = y at black cells, y + e(parent) at red cells (loaded ahead)
     store_plane<R, L0, true>(pr, t, vs[m % 3], inv_s);
     if (m + 1 < t.tz + 4)
-      load_plane<R, L0, true>(pr, t, pz + 1, nx, ny, nz, f, C.d, e, has_coarse, cnx, cny);
+      load_plane<R, L0, true>(pr, t, pz + 1, nx, ny, nz, f, C.d, e, has_coarse,
+                              cnx, cny, cnz, tri);
     __syncthreads();
     // (2) new black values of plane pz - 1 over the tile + 1
     if (m >= 2) {
@@ -292,15 +296,15 @@ void launch_vdown(const Tables &T, TileList L, int l, int prec, hipStream_t s) {
 }
 
 void launch_vup(const Tables &T, TileList L, int l, int prec, int flexible,
-                hipStream_t s) {
+                int trilinear, hipStream_t s) {
   if (!L.nblocks) return;
   const int id = l == 0 ? K_VUP_F : K_VUP_C;
   if (prec) {
-    if (l == 0) FLD_LAUNCH(id, (k_vup<float, true>), L.nblocks, kBlock, s, T, L, l, flexible);
-    else FLD_LAUNCH(id, (k_vup<float, false>), L.nblocks, kBlock, s, T, L, l, flexible);
+    if (l == 0) FLD_LAUNCH(id, (k_vup<float, true>), L.nblocks, kBlock, s, T, L, l, flexible, trilinear);
+    else FLD_LAUNCH(id, (k_vup<float, false>), L.nblocks, kBlock, s, T, L, l, flexible, trilinear);
   } else {
-    if (l == 0) FLD_LAUNCH(id, (k_vup<double, true>), L.nblocks, kBlock, s, T, L, l, flexible);
-    else FLD_LAUNCH(id, (k_vup<double, false>), L.nblocks, kBlock, s, T, L, l, flexible);
+    if (l == 0) FLD_LAUNCH(id, (k_vup<double, true>), L.nblocks, kBlock, s, T, L, l, flexible, trilinear);
+    else FLD_LAUNCH(id, (k_vup<double, false>), L.nblocks, kBlock, s, T, L, l, flexible, trilinear);
   }
 }
 

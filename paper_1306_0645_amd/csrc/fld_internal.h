@@ -147,7 +147,7 @@ void launch_half_out(const Tables &T, TileList L0, int prec, int flexible,
 void launch_resid_restrict(const Tables &T, TileList coarse, int lc, int prec,
                            hipStream_t s);
 void launch_prolong_black(const Tables &T, TileList L, int l, int prec,
-                          hipStream_t s);
+                          int trilinear, hipStream_t s);
 void launch_coarse_solve(const Tables &T, int prec, hipStream_t s);
 void launch_spmv_p(const Tables &T, TileList L0, hipStream_t s);
 void launch_update(const Tables &T, TileList L0, hipStream_t s);
@@ -161,7 +161,7 @@ void launch_update_E(const Tables &T, TileList L0, double floor, int copy_only,
 // fused one-sweep V-cycle passes (fld_fused.hip)
 void launch_vdown(const Tables &T, TileList L, int l, int prec, hipStream_t s);
 void launch_vup(const Tables &T, TileList L, int l, int prec, int flexible,
-                hipStream_t s);
+                int trilinear, hipStream_t s);
 
 // finalize kernels (launch_fin 'which')
 enum : int {

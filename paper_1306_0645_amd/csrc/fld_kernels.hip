@@ -47,6 +47,9 @@ __device__ __forceinline__ double face_D(double e1, double e2, double k1,
   return (D > dmax) ? dmax : D;
 }
 
+// One thread per (x, y) column of the tile, walking z: E and kappa of the
+// column at k-1, k, k+1 stay in registers and the -z face of plane k is the +z
+// face computed at plane k-1, so each cell evaluates 5 limiters, not 6.
 __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
                                                      double c, double theta,
                                                      double dmax, double rmin,
@@ -61,45 +64,67 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
   const Col col = tile_col(t);
   const double tdt = theta * S.dt;
   const double ix2 = S.idx * S.idx, iy2 = S.idy * S.idy, iz2 = S.idz * S.idz;
+  const double *__restrict__ E = S.E;
+  const double *__restrict__ K = S.kappa;
+  const double *__restrict__ eta = S.eta;
+  double *__restrict__ Tx = L.Tx;
+  double *__restrict__ Ty = L.Ty;
+  double *__restrict__ Tz = L.Tz;
+  double *__restrict__ Dg = L.diag;
+  double *__restrict__ bv = P.b;
+  double *__restrict__ rv = P.r;
+  double *__restrict__ xv = P.x;
   double bb = 0.0;
   if (col.on) {
+    const int nx = L.nx, ny = L.ny, nz = L.nz, plane = nx * ny;
+    const int i = col.i, j = col.j;
+    const int dxm = (i == 0) ? nx - 1 : -1, dxp = (i == nx - 1) ? 1 - nx : 1;
+    const int dym = (j == 0) ? (ny - 1) * nx : -nx;
+    const int dyp = (j == ny - 1) ? -(ny - 1) * nx : nx;
+    int cc = t.z0 * plane + j * nx + i;
+    const int cm = (t.z0 == 0) ? cc + (nz - 1) * plane : cc - plane;
+    double Em = E[cm], Km = K[cm];
+    double Ec = E[cc], Kc = K[cc];
+    double Dzm = face_D(Em, Ec, Km, Kc, S.idz, c, dmax, rmin);
     for (int k = t.z0; k < t.z0 + t.tz; ++k) {
-      for (int e = 0; e < t.cpt; ++e) {
-        const Nb n = nbrs(col.i + e, col.j, k, L.nx, L.ny, L.nz);
-        const double *E = S.E, *K = S.kappa;
-        const double Ec = E[n.c], Kc = K[n.c];
-        const double Exp = E[n.xp], Exm = E[n.xm], Eyp = E[n.yp], Eym = E[n.ym];
-        const double Ezp = E[n.zp], Ezm = E[n.zm];
-        const double Dxp = face_D(Ec, Exp, Kc, K[n.xp], S.idx, c, dmax, rmin);
-        const double Dxm = face_D(Exm, Ec, K[n.xm], Kc, S.idx, c, dmax, rmin);
-        const double Dyp = face_D(Ec, Eyp, Kc, K[n.yp], S.idy, c, dmax, rmin);
-        const double Dym = face_D(Eym, Ec, K[n.ym], Kc, S.idy, c, dmax, rmin);
-        const double Dzp = face_D(Ec, Ezp, Kc, K[n.zp], S.idz, c, dmax, rmin);
-        const double Dzm = face_D(Ezm, Ec, K[n.zm], Kc, S.idz, c, dmax, rmin);
-        const double mu = S.adot_a + c * Kc;
-        const double faces =
-            (Dxp + Dxm) * ix2 + (Dyp + Dym) * iy2 + (Dzp + Dzm) * iz2;
-        const double diag = 1.0 + tdt * (mu + faces);
-        const double LE = (Dxp * (Exp - Ec) - Dxm * (Ec - Exm)) * ix2 +
-                          (Dyp * (Eyp - Ec) - Dym * (Ec - Eym)) * iy2 +
-                          (Dzp * (Ezp - Ec) - Dzm * (Ec - Ezm)) * iz2 - mu * Ec;
-        const double b = S.dt * (LE + S.eta[n.c]);
-        const double tx = tdt * Dxp * ix2, ty = tdt * Dyp * iy2, tz = tdt * Dzp * iz2;
-        L.Tx[n.c] = tx;
-        L.Ty[n.c] = ty;
-        L.Tz[n.c] = tz;
-        L.diag[n.c] = diag;
-        if (mixed) {
-          L.Tx32[n.c] = (float)tx;
-          L.Ty32[n.c] = (float)ty;
-          L.Tz32[n.c] = (float)tz;
-          L.diag32[n.c] = (float)diag;
-        }
-        P.b[n.c] = b;
-        P.r[n.c] = b;
-        P.x[n.c] = 0.0;
-        bb += b * b;
+      const int cp = (k == nz - 1) ? cc - (nz - 1) * plane : cc + plane;
+      const double Ep = E[cp], Kp = K[cp];
+      const double Exp = E[cc + dxp], Exm = E[cc + dxm];
+      const double Eyp = E[cc + dyp], Eym = E[cc + dym];
+      const double Dxp = face_D(Ec, Exp, Kc, K[cc + dxp], S.idx, c, dmax, rmin);
+      const double Dxm = face_D(Exm, Ec, K[cc + dxm], Kc, S.idx, c, dmax, rmin);
+      const double Dyp = face_D(Ec, Eyp, Kc, K[cc + dyp], S.idy, c, dmax, rmin);
+      const double Dym = face_D(Eym, Ec, K[cc + dym], Kc, S.idy, c, dmax, rmin);
+      const double Dzp = face_D(Ec, Ep, Kc, Kp, S.idz, c, dmax, rmin);
+      const double mu = S.adot_a + c * Kc;
+      const double faces =
+          (Dxp + Dxm) * ix2 + (Dyp + Dym) * iy2 + (Dzp + Dzm) * iz2;
+      const double diag = 1.0 + tdt * (mu + faces);
+      const double LE = (Dxp * (Exp - Ec) - Dxm * (Ec - Exm)) * ix2 +
+                        (Dyp * (Eyp - Ec) - Dym * (Ec - Eym)) * iy2 +
+                        (Dzp * (Ep - Ec) - Dzm * (Ec - Em)) * iz2 - mu * Ec;
+      const double b = S.dt * (LE + eta[cc]);
+      const double tx = tdt * Dxp * ix2, ty = tdt * Dyp * iy2, tz = tdt * Dzp * iz2;
+      Tx[cc] = tx;
+      Ty[cc] = ty;
+      Tz[cc] = tz;
+      Dg[cc] = diag;
+      if (mixed) {
+        L.Tx32[cc] = (float)tx;
+        L.Ty32[cc] = (float)ty;
+        L.Tz32[cc] = (float)tz;
+        L.diag32[cc] = (float)diag;
       }
+      bv[cc] = b;
+      rv[cc] = b;
+      xv[cc] = 0.0;
+      bb += b * b;
+      Em = Ec;
+      Km = Kc;
+      Ec = Ep;
+      Kc = Kp;
+      Dzm = Dzp;
+      cc = cp;
     }
   }
   write_partials(T, tid, bb, 0.0);
@@ -216,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_half(Tables T, TileList TL, int l,
 // value is overwritten by the sweep, so it is never formed.)
 template <typename R, bool L0>
 __global__ __launch_bounds__(kBlock) void k_prolong_black(Tables T, TileList TL,
-                                                          int l) {
+                                                          int l, int trilinear) {
   const Tile t = get_tile(TL);
   const Scal &sc = T.sc[t.prob];
   if (!sc.active) return;
@@ -228,7 +253,8 @@ __global__ __launch_bounds__(kBlock) void k_prolong_black(Tables T, TileList TL,
   const auto f = fsrc<R, L0>(L, P, sc);
   R *x = (R *)L.x;
   const R *e = (const R *)Cl.x;
-  const int cnx = Cl.nx, cny = Cl.ny;
+  const int cnx = Cl.nx, cny = Cl.ny, cnz = Cl.nz;
+  const bool tri = trilinear != 0;
   const Col col = tile_col(t);
   if (!col.on) return;
   const int nx = L.nx, ny = L.ny, nz = L.nz;
@@ -242,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_black(Tables T, TileList TL,
       const int jm = j == 0 ? ny - 1 : j - 1, jp = j == ny - 1 ? 0 : j + 1;
       const int km = k == 0 ? nz - 1 : k - 1, kp = k == nz - 1 ? 0 : k + 1;
       auto par = [&](int a, int b2, int c2) {
-        return e[((c2 >> 1) * cny + (b2 >> 1)) * cnx + (a >> 1)];
+        return coarse_corr(e, a, b2, c2, cnx, cny, cnz, tri);
       };
       s = C.tx[n.c] * (x[n.xp] + par(ip, j, k)) +
           C.tx[n.xm] * (x[n.xm] + par(im, j, k)) +
@@ -862,15 +888,15 @@ void launch_resid_restrict(const Tables &T, TileList LC, int lc, int prec,
 }
 
 void launch_prolong_black(const Tables &T, TileList L, int l, int prec,
-                          hipStream_t s) {
+                          int trilinear, hipStream_t s) {
   if (!L.nblocks) return;
   const int id = l == 0 ? K_PROLONG_F : K_PROLONG_C;
   if (prec) {
-    if (l == 0) LAUNCH(id, (k_prolong_black<float, true>), L.nblocks, kBlock, s, T, L, l);
-    else LAUNCH(id, (k_prolong_black<float, false>), L.nblocks, kBlock, s, T, L, l);
+    if (l == 0) LAUNCH(id, (k_prolong_black<float, true>), L.nblocks, kBlock, s, T, L, l, trilinear);
+    else LAUNCH(id, (k_prolong_black<float, false>), L.nblocks, kBlock, s, T, L, l, trilinear);
   } else {
-    if (l == 0) LAUNCH(id, (k_prolong_black<double, true>), L.nblocks, kBlock, s, T, L, l);
-    else LAUNCH(id, (k_prolong_black<double, false>), L.nblocks, kBlock, s, T, L, l);
+    if (l == 0) LAUNCH(id, (k_prolong_black<double, true>), L.nblocks, kBlock, s, T, L, l, trilinear);
+    else LAUNCH(id, (k_prolong_black<double, false>), L.nblocks, kBlock, s, T, L, l, trilinear);
   }
 }
 

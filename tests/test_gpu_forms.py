@@ -33,7 +33,9 @@ def _probs(seed0=40, dtf=0.02):
 def test_batch_equals_single_and_oracle(fld, oracle_mod, prec):
     log_case("batch", prec=prec)
     ps = _probs()
-    prm = params(fld, ps[0], precision=prec)
+    # fixed cycle: a batch adapts its cycle on its hardest problem, a single
+    # handle on its own, so bit-equality needs the switch off
+    prm = params(fld, ps[0], precision=prec, cycle_switch=0)
     # per-problem paper limits differ with the box size: use one set for all
     singles = []
     for p in ps:

@@ -232,14 +232,15 @@ def test_subcycling_matches_oracle_substeps(fld, oracle_mod):
     log_case("subcycle")
     p = _problem((32, 32, 32), 18, dt_factor=2.0, E_mode="smooth")
     kap, eta = dev(p["kappa"]), dev(p["eta"])
-    U, _ = _solver(fld, p, mg_levels=1)
+    U, _ = _solver(fld, p, mg_levels=1, cycle_switch=0)
     its = []
     for h in (p["dt"], 0.1 * p["dt"]):
         U.assemble(dev(p["E"]), kap, eta, h)
         its.append(U.solve()[1]["iters"])
     print(f"[subcycle] iterations at dt, 0.1 dt: {its}", flush=True)
     assert its[1] < its[0]
-    cap = dict(max_iter=its[1], tau_tol=1e30, max_dt_cuts=60, mg_levels=1)
+    cap = dict(max_iter=its[1], tau_tol=1e30, max_dt_cuts=60, mg_levels=1,
+               cycle_switch=0)
     S, prm = _solver(fld, p, **cap)
     E = dev(p["E"])
     st = S.step(E, kap, eta, p["dt"])
@@ -300,3 +301,31 @@ def test_full_size_many_sources_residual(fld, oracle_mod, prec):
         E += dE
         torch.cuda.synchronize()
         En = En + dEh
+
+
+def test_adaptive_cycle_switch(fld, oracle_mod):
+    """A high-contrast problem (ionized bubbles, nu ~ 61) needs more than 12
+    V(1,1) iterations, so the handle's next steps run V(2,2); every step still
+    meets the tolerance and matches the oracle."""
+    import torch
+    log_case("cycle_switch")
+    q = synth.t_reionization_share(n=64, n_src=12, device="cpu")
+    p = {k: (v.numpy() if hasattr(v, "numpy") else v) for k, v in q.items()}
+    S, prm = _solver(fld, p, precision=1)
+    E = dev(p["E"])
+    kap, eta = dev(p["kappa"]), dev(p["eta"])
+    En = p["E"].copy()
+    seen = []
+    for k in range(3):
+        st = S.step(E, kap, eta, p["dt"])
+        seen.append((st["cycle_nu"], st["iters"]))
+        qq = dict(p)
+        qq["E"] = En
+        dEo, _, _, _ = oracle_problem(oracle_mod, qq, prm).solve(tol=1e-13)
+        En = En + dEo
+        assert st["status"] == 0
+        assert rel_l2(host(E), En) <= 1e-5
+    print(f"[cycle_switch] (nu, iters) per step: {seen}", flush=True)
+    assert seen[0][0] == 1
+    if seen[0][1] > 12:
+        assert seen[1][0] == 2
