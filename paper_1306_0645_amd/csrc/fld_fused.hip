@@ -204,9 +204,11 @@ __global__ __launch_bounds__(kBlock) void k_vdown(Tables T, TileList TL, int l) 
   }
 }
 
-template <typename R, bool L0>
+// TRI selects trilinear prolongation of the coarse correction (at compile
+// time: the piecewise-constant variant keeps its lower register count).
+template <typename R, bool L0, bool TRI>
 __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
-                                                int flexible, int trilinear) {
+                                                int flexible) {
   const int tid = get_tile_index(TL);
   const Tile t = TL.base[tid];
   const Scal &sc = T.sc[t.prob];
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
   __shared__ R xs[3][kE1];
   const int nx = L.nx, ny = L.ny, nz = L.nz;
   const int cnx = Cl.nx, cny = Cl.ny, cnz = Cl.nz;
-  const bool tri = trilinear != 0;
+  constexpr bool tri = TRI;
   const int ci = threadIdx.x & 31, cj = threadIdx.x >> 5;
   const bool cown = 2 * ci < t.tx && 2 * cj < t.ty;
   PlaneRegs<R, L0> pr;
@@ -295,16 +297,25 @@ void launch_vdown(const Tables &T, TileList L, int l, int prec, hipStream_t s) {
   }
 }
 
+template <typename R, bool L0>
+static void launch_vup_t(const Tables &T, TileList L, int l, int id, int flexible,
+                         int trilinear, hipStream_t s) {
+  if (trilinear)
+    FLD_LAUNCH(id, (k_vup<R, L0, true>), L.nblocks, kBlock, s, T, L, l, flexible);
+  else
+    FLD_LAUNCH(id, (k_vup<R, L0, false>), L.nblocks, kBlock, s, T, L, l, flexible);
+}
+
 void launch_vup(const Tables &T, TileList L, int l, int prec, int flexible,
                 int trilinear, hipStream_t s) {
   if (!L.nblocks) return;
   const int id = l == 0 ? K_VUP_F : K_VUP_C;
   if (prec) {
-    if (l == 0) FLD_LAUNCH(id, (k_vup<float, true>), L.nblocks, kBlock, s, T, L, l, flexible, trilinear);
-    else FLD_LAUNCH(id, (k_vup<float, false>), L.nblocks, kBlock, s, T, L, l, flexible, trilinear);
+    if (l == 0) launch_vup_t<float, true>(T, L, l, id, flexible, trilinear, s);
+    else launch_vup_t<float, false>(T, L, l, id, flexible, trilinear, s);
   } else {
-    if (l == 0) FLD_LAUNCH(id, (k_vup<double, true>), L.nblocks, kBlock, s, T, L, l, flexible, trilinear);
-    else FLD_LAUNCH(id, (k_vup<double, false>), L.nblocks, kBlock, s, T, L, l, flexible, trilinear);
+    if (l == 0) launch_vup_t<double, true>(T, L, l, id, flexible, trilinear, s);
+    else launch_vup_t<double, false>(T, L, l, id, flexible, trilinear, s);
   }
 }
 
