@@ -18,10 +18,15 @@ arXiv:1306.0645):
 * ``residual_at`` -- b - A x at chosen cells, each computed on its own.
 * ``step`` -- one radiation step with the 10x cut-and-subcycle rule
   (Sec. 3.4); its dt estimator is a reading of ours and is PARITY UNPINNED.
+* ``chem_h`` -- the loosely coupled chemistry update (Sec. 3.3) for isothermal
+  pure hydrogen, the gas of Test 1 (Sec. 4.1.1).
+* ``hii_run`` -- radiation then chemistry per step in the order of Sec. 3.4,
+  pinned by the Stromgren-sphere growth law of Test 1.
 """
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -82,6 +87,8 @@ def _load():
         lib.oracle_step.restype = i
         lib.oracle_step.argtypes = [i, i, i, d, d, d, p, p, p, d, d, d, d, d,
                                     d, d, d, i, d, d, i, p]
+        lib.oracle_chem_h.restype = None
+        lib.oracle_chem_h.argtypes = [i64, p, p, p, p, d, i, d, d, d, d]
         _lib = lib
     return _lib
 
@@ -206,3 +213,70 @@ def step(E, kappa, eta, h, c, d_max, r_min, dt, theta=1.0, a=1.0, adot=0.0,
                              _ptr(stats))
     keys = ("substeps", "cuts", "iters", "relres", "rho", "dt_next")
     return E, st, dict(zip(keys, stats.tolist()))
+
+
+# ---------------------------------------------------------------------------
+# Isothermal hydrogen chemistry and the operator-split Test-1 driver
+# ---------------------------------------------------------------------------
+
+def chem_h(E, n_h, x, dt, c, sigma, hnu, alpha_b, substeps=1):
+    """Loosely coupled chemistry update of the ionized fraction (Sec. 3.3) for
+    pure hydrogen at fixed temperature; returns (x_new, kappa_new) with
+    kappa = sigma n_HI.  See ``oracle_chem_h`` for the update."""
+    E = _arr(E)
+    n_h = _arr(n_h, E.shape)
+    xo = _arr(x, E.shape).copy()
+    kappa = np.empty_like(E)
+    _load().oracle_chem_h(E.size, _ptr(E), _ptr(n_h), _ptr(xo), _ptr(kappa),
+                          float(dt), int(substeps), float(c), float(sigma),
+                          float(hnu), float(alpha_b))
+    return xo, kappa
+
+
+def ionized_radius(x, cell_volume):
+    """Radius of the sphere whose volume is the ionized volume sum(x) V_cell."""
+    return (3.0 * float(np.sum(x)) * cell_volume / (4.0 * math.pi)) ** (1.0 / 3.0)
+
+
+def hii_run(E, x, n_h, eta, h, c, d_max, r_min, sigma, hnu, alpha_b, outputs,
+            dt0, tau_tol, e_floor, chem_substeps=1, tol=1e-13, max_cuts=8,
+            dts=None, max_steps=10 ** 7):
+    """Radiation + chemistry in the operator-split order of Sec. 3.4.
+
+    Each step t -> t + dt: the radiation step (with its 10x cut-and-subcycle
+    rule) evolves E with kappa held at the current ionization state; the new E
+    then drives the chemistry over the same dt, which gives the opacity of
+    the next step.  With static gas the radiation estimate alone sets the
+    next dt (Sec. 3.4 takes the minimum over the processes), clipped so that
+    steps land on the output times.  ``dts`` replays a given sequence of step
+    sizes instead.  Returns the final fields, the ionized radius at every
+    output time and the step sizes taken."""
+    E = _arr(E).copy()
+    x = _arr(x, E.shape).copy()
+    n_h = _arr(n_h, E.shape)
+    eta = _arr(eta, E.shape)
+    kappa = sigma * n_h * (1.0 - x)
+    vcell = h[0] * h[1] * h[2]
+    outputs = [float(o) for o in outputs]
+    t, dt, k, i = 0.0, float(dt0), 0, 0
+    radii, taken, iters = [], [], 0
+    while k < len(outputs) and i < max_steps:
+        target = outputs[k]
+        step_dt = float(dts[i]) if dts is not None else min(dt, target - t)
+        E, st, s = step(E, kappa, eta, h, c, d_max, r_min, step_dt, tol=tol,
+                        tau_tol=tau_tol, e_floor=e_floor, max_cuts=max_cuts)
+        if st != OK:
+            raise RuntimeError(f"oracle radiation step failed with status {st}")
+        x, kappa = chem_h(E, n_h, x, step_dt, c, sigma, hnu, alpha_b,
+                          chem_substeps)
+        iters += int(s["iters"])
+        taken.append(step_dt)
+        t += step_dt
+        dt = s["dt_next"]
+        i += 1
+        if t >= target * (1.0 - 1e-12):
+            t = target
+            radii.append(ionized_radius(x, vcell))
+            k += 1
+    return {"E": E, "x": x, "kappa": kappa, "times": outputs[:len(radii)],
+            "radii": radii, "dts": taken, "iters": iters}

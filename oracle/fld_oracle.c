@@ -394,3 +394,40 @@ int oracle_step(int nx, int ny, int nz, double dx, double dy, double dz,
   free(dE);
   return st;
 }
+
+/* ---------------------------------------------------------------------------
+ * Isothermal hydrogen chemistry: the loosely coupled chemistry solver of
+ * Sec. 3.3 (one linearly implicit backward-Euler update per species and cell)
+ * for the hydrogen-only, fixed-temperature gas of Test 1 (Sec. 4.1.1).
+ *
+ * Pure hydrogen leaves one independent species, the ionized fraction
+ * x = n_HII / n_H, with n_HI = n_H (1 - x) and n_e = n_HII = n_H x.  The rate
+ * equation of eq. "heat_chem" for it is
+ *   dx/dt = Gamma (1 - x) - alpha_B n_H x^2,
+ * with the photo-ionization rate of monochromatic radiation of energy
+ * density E at the ionization threshold (Sec. 2: photon number density
+ * E / (h nu), each photon ionizing at rate c sigma n_HI):
+ *   Gamma = c sigma E / (h nu).
+ * The linearly implicit update takes x at the new time wherever it enters
+ * linearly and holds the electron density of the recombination term at the
+ * old value:
+ *   x+ - x = h [ Gamma (1 - x+) - alpha_B n_H x x+ ]
+ *   =>  x+ = (x + h Gamma) / (1 + h (Gamma + alpha_B n_H x)).
+ * E (and so Gamma) is the radiation field at the end of the radiation step,
+ * frozen over the chemistry step (Sec. 3.4 processes the new E into the
+ * rates first).  The step dt is taken in `substeps` equal pieces.  Finally
+ * the opacity seen by the next radiation step is kappa = sigma n_HI.
+ * ------------------------------------------------------------------------- */
+void oracle_chem_h(int64_t n, const double *E, const double *n_h, double *x,
+                   double *kappa, double dt, int substeps, double c,
+                   double sigma, double hnu, double alpha_b) {
+  double h = dt / (double)substeps;
+  for (int64_t p = 0; p < n; ++p) {
+    double gamma = c * sigma * E[p] / hnu;
+    double xp = x[p];
+    for (int s = 0; s < substeps; ++s)
+      xp = (xp + h * gamma) / (1.0 + h * (gamma + alpha_b * n_h[p] * xp));
+    x[p] = xp;
+    kappa[p] = sigma * n_h[p] * (1.0 - xp);
+  }
+}

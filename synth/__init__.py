@@ -183,6 +183,44 @@ def reionization_share(n: int = 640, n_src: int = 10000, sigma_ln: float = 2.0,
     return _problem(shape, dx, kappa, eta, E, L, dt, f"reionization_{n}")
 
 
+def hii_test1(n_oct: int = 16, t_end_myr: float = 500.0, n_out: int = 50):
+    """Test 1 (Sec. 4.1.1): a 5e48 photon/s source in static uniform hydrogen
+    (n_H = 1e-3 cm^-3, T = 1e4 K), E = 1e-45 erg cm^-3 and x = n_HII/n_H =
+    0.0012 at t = 0, over [0, t_end] with n_out evenly spaced outputs.
+
+    The paper runs the octant [0, 6.6 kpc]^3 on n_oct^3 cells with the
+    source at the origin and reflecting faces there.  The periodic solver
+    runs the mirror image: (2 n_oct)^3 cells of the same width on a 13.2 kpc
+    box, the source split evenly over the 8 cells that meet at the centre.
+    The I-front stays inside 6.6 kpc of the source (r_s = 5.39 kpc), so the
+    periodic images do not interact.  L_unit is the octant side (6.6 kpc).
+    The relative-change floor of the step estimator is 1e-3 of the
+    optically thin energy density at the Stromgren radius,
+    Ndot h nu / (4 pi r_s^2 c)."""
+    n = 2 * n_oct
+    shape = (n, n, n)
+    L = 6.6 * KPC
+    dx = L / n_oct
+    ndot, n_h, x0 = 5e48, 1e-3, 0.0012
+    c0 = n_oct
+    cells = [((c0 - 1 + k) * n + (c0 - 1 + j)) * n + (c0 - 1 + i)
+             for k in (0, 1) for j in (0, 1) for i in (0, 1)]
+    eta = emissivity(shape, cells, [ndot / 8.0] * 8, dx ** 3)
+    rs = float(stromgren_radius(ndot, n_h))
+    t_end = t_end_myr * MYR
+    return {
+        "name": f"hii_test1_{n_oct}", "shape": shape, "h": (dx, dx, dx),
+        "E": np.full(shape, 1e-45), "x": np.full(shape, x0),
+        "n_h": np.full(shape, n_h), "eta": eta, "L_unit": L, "ndot": ndot,
+        "n_h_mean": n_h, "r_s": rs, "t_rec": 1.0 / (ALPHA_B * n_h),
+        "dt0": 1e-3 * L / C_LIGHT,
+        "e_floor": 1e-3 * ndot * HNU_HI / (4.0 * math.pi * rs * rs * C_LIGHT),
+        "outputs": [t_end * (k + 1) / n_out for k in range(n_out)],
+        "sigma": SIGMA_HI, "hnu": HNU_HI, "alpha_b": ALPHA_B,
+        "cell_volume": dx ** 3,
+    }
+
+
 BATCH_SIZES = (32, 48, 64, 96, 128)
 
 
