@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--fused-tile-z", type=int, default=0)
     ap.add_argument("--workload", default="many_sources",
                     choices=["many_sources", "single_source", "reionization",
-                             "batch", "served"])
+                             "batch", "served", "hii_test1"])
     ap.add_argument("--reps", type=int, default=300,
                     help="single_source: timed solves for the latency quantiles")
     ap.add_argument("--batch", type=int, default=96, help="batch: problems")
@@ -69,6 +69,15 @@ def parse():
     ap.add_argument("--requests", type=int, default=500, help="served: requests")
     ap.add_argument("--load", type=float, default=0.7,
                     help="served: arrival rate as a fraction of saturation")
+    ap.add_argument("--hii-meshes", default="16,32,64",
+                    help="hii_test1: octant meshes")
+    ap.add_argument("--hii-taus", default="1e-2,1e-3,1e-4",
+                    help="hii_test1: step tolerances")
+    ap.add_argument("--hii-t-end", type=float, default=500.0,
+                    help="hii_test1: end time [Myr]")
+    ap.add_argument("--hii-cap-s", type=float, default=60.0,
+                    help="hii_test1: wall-clock cap per run [s]")
+    ap.add_argument("--hii-precision", default="mixed")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain copy kernel of 2 GiB read + 2 GiB "
                          "written, to calibrate the HBM byte counters")

@@ -8,9 +8,12 @@ batch          96 independent problems of 32..128^3 in one batched step,
                autotuned, against the same problems solved one by one
 served         Poisson stream of 64..384^3 requests of 1-5 steps through the
                continuous-batching server: p50/p99 latency and throughput
+hii_test1      Test 1 end to end (radiation + hydrogen chemistry): I-front
+               error, average step and run time over a tau_tol sweep
 
 Each function returns the JSON object bench.py prints.
 """
+import json
 import math
 import time
 
@@ -344,3 +347,65 @@ def served(args, fld, torch, synth, log):
                         "mcell_updates_per_s": round(sat_mcells, 1)},
          "max_rel_resid": max(r["rel_resid"] for r in res),
          "iters_mean": float(np.mean([r["iters"] for r in res]))})
+
+
+def hii_test1(args, fld, torch, synth, log):
+    """Test 1 (Sec. 4.1.1) end to end: radiation + isothermal hydrogen
+    chemistry, operator split, over [0, t_end] on the paper's octant meshes
+    (mirrored periodic boxes of twice the extent), for each step tolerance
+    tau_tol.  Reports the I-front error norm of eq. "i1_error", the average
+    step, and the run time per configuration (the paper's Fig. "i1_stats"),
+    with a wall-clock cap per run (a capped run reports the time reached)."""
+    from paper_1306_0645_amd.ionization import IsothermalHII
+    meshes = [int(v) for v in args.hii_meshes.split(",")]
+    taus = [float(v) for v in args.hii_taus.split(",")]
+    prec = fld.FLD_PREC_MIXED if args.hii_precision == "mixed" else fld.FLD_PREC_FP64
+    rows, cells_steps, wall_total = [], 0.0, 0.0
+    for n_oct in meshes:
+        for tau in taus:
+            d = synth.hii_test1(n_oct, t_end_myr=args.hii_t_end, n_out=50)
+            prm = fld.fld_default_params(synth.C_LIGHT, d["L_unit"],
+                                         precision=prec, tau_tol=tau,
+                                         e_floor=d["e_floor"])
+            chem = fld.fld_chem_default_params()
+            drv = IsothermalHII(d["shape"], d["h"], prm, chem)
+            E, x = (torch.from_numpy(d[k]).cuda() for k in ("E", "x"))
+            nh, eta = (torch.from_numpy(d[k]).cuda() for k in ("n_h", "eta"))
+            t_start = time.perf_counter()
+
+            def on_output(t, r, i, n_oct=n_oct, tau=tau, t_start=t_start):
+                if i and round(t / d["outputs"][0]) % 10 == 0:
+                    log(f"[hii] n={n_oct} tau={tau:g} t={t / synth.MYR:.0f} Myr "
+                        f"steps={i} r={r / synth.KPC:.3f} kpc "
+                        f"wall={time.perf_counter() - t_start:.1f}s")
+
+            res = drv.run(E, x, nh, eta, d["outputs"], d["dt0"],
+                          on_output=on_output, wall_cap_s=args.hii_cap_s)
+            drv.close()
+            t = np.array(res["times"])
+            rr = np.array(res["radii"])
+            r_true = d["r_s"] * (1.0 - np.exp(-t / d["t_rec"])) ** (1.0 / 3.0)
+            err = float(math.sqrt(np.mean(((rr - r_true) / d["r_s"]) ** 2))) if len(t) else None
+            cells = int(np.prod(d["shape"]))
+            cells_steps += cells * res["steps"]
+            wall_total += res["wall_s"]
+            row = {"octant": n_oct, "cells": list(d["shape"]), "tau_tol": tau,
+                   "t_reached_myr": round(float(t[-1]) / synth.MYR, 2) if len(t) else 0.0,
+                   "capped": res["capped"], "steps": res["steps"],
+                   "dt_avg_myr": (float(t[-1]) / res["steps"] / synth.MYR) if res["steps"] else None,
+                   "iters_per_step": res["iters"] / max(res["steps"], 1),
+                   "error_rms": err, "wall_s": round(res["wall_s"], 3),
+                   "ms_per_step": 1e3 * res["wall_s"] / max(res["steps"], 1)}
+            log(f"[hii] {json.dumps(row)}")
+            rows.append(row)
+    value = cells_steps / wall_total / 1e6 if wall_total > 0 else 0.0
+    total_steps = sum(r["steps"] for r in rows)
+    return _base(
+        "operator-split radiation + chemistry; small grids are launch-latency "
+        "bound, so no HBM roofline is reported for this workload",
+        value, 1e3 * wall_total / max(total_steps, 1), total_steps, 0,
+        "f64+f32" if prec else "f64",
+        {"workload": "hii_test1", "octant_meshes": meshes, "tau_tol": taus,
+         "t_end_myr": args.hii_t_end, "precision": args.hii_precision,
+         "rtol": 1e-8},
+        None, {"sweep": rows})

@@ -33,6 +33,7 @@ EXPORTS = (
     "fld_server_drain", "fld_server_destroy",
     "fld_profile_num_kernels", "fld_profile_kernel_name", "fld_profile_select",
     "fld_profile_read",
+    "fld_chem_default_params", "fld_chem_h_update", "fld_chem_ionized_sum",
 )
 
 
@@ -88,6 +89,12 @@ class Result(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ChemParams(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("hnu", ctypes.c_double), ("alpha_b", ctypes.c_double),
+                ("substeps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class FLDError(RuntimeError):
     def __init__(self, status, what=""):
         self.status = status
@@ -128,6 +135,10 @@ def _load():
         "fld_profile_kernel_name": (ctypes.c_char_p, [i32]),
         "fld_profile_select": (i32, [i32]),
         "fld_profile_read": (i32, [i32, P(d), P(ctypes.c_int64)]),
+        "fld_chem_default_params": (None, [P(ChemParams)]),
+        "fld_chem_h_update": (i32, [P(Grid), P(ChemParams), vp, vp, vp, vp, vp,
+                                    d]),
+        "fld_chem_ionized_sum": (i32, [P(Grid), vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -399,3 +410,40 @@ class Server:
             pass
 
     submit, poll, drain = fld_server_submit, fld_server_poll, fld_server_drain
+
+
+# ---------------------------------------------------------------------------
+# Isothermal hydrogen chemistry (include/fld_chem.h)
+# ---------------------------------------------------------------------------
+
+def fld_chem_default_params(**overrides) -> ChemParams:
+    """Test-1 chemistry constants (CGS), with any field overridden."""
+    p = ChemParams()
+    _lib.fld_chem_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def fld_chem_h_update(grid: Grid, params: ChemParams, E, n_h, x, kappa, dt,
+                      stream=None):
+    """x and kappa updated in place over dt (see include/fld_chem.h)."""
+    n = grid.nx * grid.ny * grid.nz
+    _check(_lib.fld_chem_h_update(ctypes.byref(grid), ctypes.byref(params),
+                                  _stream_ptr(stream), _dptr(E, n, "E"),
+                                  _dptr(n_h, n, "n_h"), _dptr(x, n, "x"),
+                                  _dptr(kappa, n, "kappa"), float(dt)),
+           "fld_chem_h_update")
+
+
+def fld_chem_ionized_sum(grid: Grid, x, out=None, stream=None):
+    """Device scalar (1-element float64 tensor) holding sum(x)."""
+    n = grid.nx * grid.ny * grid.nz
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=x.device)
+    _check(_lib.fld_chem_ionized_sum(ctypes.byref(grid), _stream_ptr(stream),
+                                     _dptr(x, n, "x"), _dptr(out, 1, "out")),
+           "fld_chem_ionized_sum")
+    return out

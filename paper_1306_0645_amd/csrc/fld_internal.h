@@ -112,7 +112,8 @@ enum : int {
   K_ASSEMBLE, K_COARSEN, K_FIN, K_PRE0_F, K_PRE0_C, K_HALF_F, K_HALF_C,
   K_HALF_OUT, K_RESTRICT_F, K_RESTRICT_C, K_PROLONG_F, K_PROLONG_C,
   K_COARSE_SOLVE, K_SPMV_P, K_UPDATE, K_TRUE_RESID, K_APPLY, K_SET_R,
-  K_UPDATE_E, K_VDOWN_F, K_VDOWN_C, K_VUP_F, K_VUP_C, K_NUM
+  K_UPDATE_E, K_VDOWN_F, K_VDOWN_C, K_VUP_F, K_VUP_C, K_CHEM_H, K_ION_SUM,
+  K_NUM
 };
 
 // Brackets one launch with hipEvents when its kernel id is selected.

@@ -775,7 +775,7 @@ static const char *kKernelNames[K_NUM] = {
     "half_coarse", "half_out", "resid_restrict_fine", "resid_restrict_coarse",
     "prolong_black_fine", "prolong_black_coarse", "coarse_solve", "spmv_p",
     "update", "true_resid", "apply", "set_r", "update_E", "vdown_fine",
-    "vdown_coarse", "vup_fine", "vup_coarse"};
+    "vdown_coarse", "vup_fine", "vup_coarse", "chem_h", "ionized_sum"};
 
 namespace prof {
 struct Rec {

@@ -93,3 +93,40 @@ def test_create_rejects_bad_arguments_before_any_launch(fld):
                           ctypes.c_void_p(4096), 16,
                           ctypes.byref(h)) == fld.FLD_ENOMEM
     assert fld.fld_strerror(fld.FLD_ENOCONV).startswith("linear solve")
+
+
+def test_chem_defaults_and_validation(fld):
+    g = read_golden("test1_parameters.txt")
+    p = fld.fld_chem_default_params()
+    assert p.alpha_b == float(g["alpha_b_cm3_s"])
+    assert p.hnu == pytest.approx(float(g["photon_energy_ev"]) * 1.602176634e-12,
+                                  rel=1e-15)
+    assert p.sigma == 6.3e-18 and p.substeps == 1 and p.reserved == 0
+    grid = fld.make_grid((8, 8, 8), (1.0, 1.0, 1.0))
+    n = 8 * 8 * 8 * 8
+    # fake, never dereferenced addresses: every call below fails validation
+    # before any launch
+    E, nh, x, k = (ctypes.c_void_p(0x10000000 + i * 0x100000) for i in range(4))
+    upd = fld._lib.fld_chem_h_update
+
+    def call(pp, dt=1.0, ptrs=(E, nh, x, k), gr=grid):
+        return upd(ctypes.byref(gr), ctypes.byref(pp), None, *ptrs, dt)
+
+    EINVAL = fld.FLD_EINVAL
+    assert call(p, ptrs=(None, nh, x, k)) == EINVAL
+    assert call(p, ptrs=(E, nh, x, None)) == EINVAL
+    assert call(p, dt=-1.0) == EINVAL
+    assert call(p, dt=float("nan")) == EINVAL
+    for field, bad in (("substeps", 0), ("substeps", 2000000), ("c", 0.0),
+                       ("hnu", 0.0), ("sigma", -1.0), ("alpha_b", float("inf")),
+                       ("reserved", 1)):
+        q = fld.fld_chem_default_params(**{field: bad})
+        assert call(q) == EINVAL, field
+    # x and kappa overlapping, or x overlapping an input
+    assert call(p, ptrs=(E, nh, x, ctypes.c_void_p(x.value + n // 2))) == EINVAL
+    assert call(p, ptrs=(E, x, x, k)) == EINVAL
+    bad_grid = fld.make_grid((8, 8, 0), (1.0, 1.0, 1.0))
+    assert call(p, gr=bad_grid) == EINVAL
+    s = fld._lib.fld_chem_ionized_sum
+    assert s(ctypes.byref(grid), None, None, x) == EINVAL
+    assert s(ctypes.byref(grid), None, x, ctypes.c_void_p(x.value + 8)) == EINVAL
