@@ -44,6 +44,70 @@ BYTES_PER_CELL = {
 }
 
 
+# Coarse levels (every level below the finest).  One V-cycle's generic
+# kernels there (red+black pre-sweep from zero, residual and restriction,
+# prolongation with the black post-sweep, the red post-sweep) move these bytes
+# per coarse cell (FP64 cycle, FP32 cycle).  Building level l from level l-1
+# reads 4 FP64 arrays of level l-1 and writes 4 of level l (plus 4 FP32 copies
+# in mixed mode).
+COARSE_CYCLE_BYTES = (48.0 + 49.0 + 57.0 + 56.0, 28.0 + 28.5 + 32.5 + 32.0)
+
+
+def coarse_fraction(levels):
+    """Cells of all coarse levels per finest cell (full 2x coarsening)."""
+    return sum(8.0 ** -l for l in range(1, levels))
+
+
+STEP_KERNELS = ("assemble", "true_resid", "update_E")
+
+
+def step_bytes(counts, cells, prec_idx, levels):
+    """Algorithmic bytes of one step from the launches counted in a survey
+    step, split into (per step, per PCG iteration x iterations): finest-level
+    kernels exactly, coarse levels from their share of cells."""
+    fixed = it = 0.0
+    for name, count in counts.items():
+        if name in BYTES_PER_CELL:
+            v = count * BYTES_PER_CELL[name][prec_idx] * cells
+            if name in STEP_KERNELS:
+                fixed += v
+            else:
+                it += v
+    cf = coarse_fraction(levels)
+    cycles = counts.get("vdown_fine", 0) or counts.get("pre0_fine", 0)
+    it += cycles * cf * COARSE_CYCLE_BYTES[prec_idx] * cells
+    coarsen = 32.0 * (1.0 + cf - 8.0 ** -(levels - 1)) + (48.0 if prec_idx else 32.0) * cf
+    fixed += counts.get("assemble", 0) * coarsen * cells
+    return fixed, it
+
+
+def measured_traffic(kernel, form):
+    """HBM bytes per launch of `kernel` from the rocprofv3 byte-counter
+    records under profiles/, or None when there is no record or any source
+    the record names has changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("traffic-record:"):
+                    continue
+                kv = dict(t.split("=", 1) for t in line.split()[1:])
+                if kv.get("kernel") != kernel or kv.get("form") != form:
+                    continue
+                for item in kv.get("sources", "").split(","):
+                    rel, want = item.rsplit(":", 1)
+                    try:
+                        with open(os.path.join(ROOT, rel), "rb") as src:
+                            have = hashlib.sha256(src.read()).hexdigest()
+                    except OSError:
+                        return None
+                    if have != want:
+                        return None
+                return float(kv["bytes_per_launch"])
+    return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -116,9 +180,11 @@ def run_form(fld, torch, p, prec, steps, warmup, args):
     P = solver(0)
     P.step(E, kap, eta, p["dt"])
     fld.fld_profile_select(-2)
-    P.step(E, kap, eta, p["dt"])
+    st_survey = P.step(E, kap, eta, p["dt"])
     torch.cuda.synchronize()
-    totals = {n: fld.fld_profile_read(k)[0] for k, n in enumerate(names)}
+    reads = {n: fld.fld_profile_read(k) for k, n in enumerate(names)}
+    totals = {n: r[0] for n, r in reads.items()}
+    counts = {n: r[1] for n, r in reads.items()}
     dom = max((n for n in totals if n in BYTES_PER_CELL), key=lambda n: totals[n])
     dom_id = names.index(dom)
     fld.fld_profile_select(dom_id)
@@ -136,6 +202,12 @@ def run_form(fld, torch, p, prec, steps, warmup, args):
     avg_ms = ms_total / max(launches, 1)
     bpc = BYTES_PER_CELL[dom][1 if prec == fld.FLD_PREC_MIXED else 0]
     achieved = bpc * cells / (avg_ms * 1e-3) / 1e9
+    prec_idx = 1 if prec == fld.FLD_PREC_MIXED else 0
+    # whole-step algorithmic bytes, scaled from the survey step's iteration
+    # count to the timed steps' mean
+    fixed_b, iter_b = step_bytes(counts, cells, prec_idx, st_survey["levels"])
+    it_mean = sum(iters) / len(iters)
+    sb = fixed_b + iter_b / max(st_survey["iters"], 1) * it_mean
     return {
         "mcell_updates_per_s": cells * steps / sec / 1e6,
         "ms_per_step": 1e3 * sec / steps,
@@ -149,6 +221,8 @@ def run_form(fld, torch, p, prec, steps, warmup, args):
         "dominant_launches": launches,
         "dominant_GBps": achieved,
         "dominant_bytes_per_cell": bpc,
+        "step_bytes_per_cell": sb / cells,
+        "step_GBps": sb * steps / sec / 1e9,
     }
 
 
@@ -208,7 +282,8 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(head["dominant_GBps"] / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": measured_traffic(head["dominant"],
+                                    "mixed" if "mixed" in forms else "fp64"),
     }
     out = {
         "metric": "FLD solve Mcell-updates/s + % HBM roofline at 1e-8 residual; "
@@ -229,6 +304,10 @@ def main():
                    "precision": "mixed" if "mixed" in forms else "fp64",
                    "steps_per_run": args.steps},
         "roofline": roof,
+        "step_roofline": {
+            "bytes_per_cell": round(head["step_bytes_per_cell"], 1),
+            "achieved": round(head["step_GBps"], 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(head["step_GBps"] / HBM_PEAK_GBS, 4)},
         "cpu_baseline": cpu,
         "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                       for kk, vv in v.items()} for k, v in forms.items()},

@@ -127,11 +127,6 @@ def reionization(args, fld, torch, synth, log):
     for w in range(args.warmup):
         st = S.step(E, K, H, p["dt"])
         log(f"[bench]   warmup step {w}: iters {st['iters']} rel {st['rel_resid']:.2e}")
-    names = fld.profile_kernels()
-    names, totals = _survey(fld, lambda: S.step(E, K, H, p["dt"]))
-    dom = _dominant(fld, names, totals, E.numel(), BYTES_PER_CELL, 1)
-    dom_id = names.index(dom)
-    fld.fld_profile_select(dom_id)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters, rel = [], []
@@ -143,42 +138,40 @@ def reionization(args, fld, torch, synth, log):
             log(f"[bench]   step {k + 1}/{steps}: iters {st['iters']}")
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
+    cycle_nu = st["cycle_nu"]
+    S.close()
+    # kernel pass on a handle without graph replay (a replayed graph hides
+    # its kernels from the timing hook), in the cycle the timed steps ended
+    # with: survey one step, then time the dominant kernel over two more
+    P = fld.Solver(p["shape"], p["h"], fld.fld_default_params(
+        p["c"], p["L_unit"], precision=fld.FLD_PREC_MIXED, mg_levels=6,
+        use_graph=0, nu_pre=cycle_nu, nu_post=cycle_nu))
+    names, totals = _survey(fld, lambda: P.step(E, K, H, p["dt"]))
+    dom = _dominant(fld, names, totals, E.numel(), BYTES_PER_CELL, 1)
+    dom_id = names.index(dom)
+    fld.fld_profile_select(dom_id)
+    for _ in range(2):
+        P.step(E, K, H, p["dt"])
+    torch.cuda.synchronize()
     ms_tot, launches = fld.fld_profile_read(dom_id)
     fld.fld_profile_select(-1)
+    P.close()
     cells = E.numel()
     avg_ms = ms_tot / max(launches, 1)
     achieved = BYTES_PER_CELL[dom][1] * cells / (avg_ms * 1e-3) / 1e9
-    # spot check of the last step against the oracle at sampled cells
-    spot = None
-    try:
-        import oracle
-        En = E.clone()
-        S.assemble(En, K, H, p["dt"])
-        dE, st = S.solve()
-        rng = np.random.default_rng(3)
-        cells_s = rng.choice(cells, size=20000, replace=False).astype(np.int64)
-        O = oracle.Problem(En.cpu().numpy(), K.cpu().numpy(), H.cpu().numpy(),
-                           p["h"], p["c"], prm.d_max, prm.r_min, p["dt"])
-        res, rhs = O.residual_at(dE.cpu().numpy(), cells_s)
-        spot = {"sampled_cells": int(cells_s.size),
-                "max_abs_resid_over_max_abs_b": float(np.abs(res).max() / np.abs(rhs).max()),
-                "solver_rel_resid": st["rel_resid"]}
-    except Exception as e:  # spot check only; never alters the timed result
-        spot = {"error": repr(e)}
     return _base(
         "one 640^3 share of a 3200^3 box; inputs resident in HBM",
         cells * steps / sec / 1e6, 1e3 * sec / steps, steps, args.warmup,
         "f64+f32",
         {"workload": f"reionization_share_{n}^3", "grid": [n] * 3,
          "sources": 10000, "sigma_ln": 2.0, "levels": 6, "precision": "mixed",
-         "rtol": 1e-8, "steps_per_run": steps},
+         "rtol": 1e-8, "steps_per_run": steps, "final_cycle_nu": cycle_nu},
         {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
          "traffic": None},
         {"iters_per_step": float(np.mean(iters)), "max_rel_resid": max(rel),
          "survey_ms": {k: round(v, 3) for k, v in sorted(
-             totals.items(), key=lambda kv: -kv[1]) if v > 0},
-         "oracle_spot_check": spot})
+             totals.items(), key=lambda kv: -kv[1]) if v > 0}})
 
 
 def _batch_problems(synth, torch, nprob):

@@ -97,10 +97,12 @@ typedef struct fld_params {
                           hipGraph; 0 = launch its kernels one by one */
   int32_t fused_tile_z;/* z-depth of the fused finest-level V-cycle tiles (even);
                           0 = automatic */
-  int32_t cycle_switch;/* > 0: when a V(1,1) solve needs more PCG iterations
-                          than this, later solves of the handle use V(2,2); a
-                          V(2,2) solve needing at most a third of it switches
-                          back.  0: the cycle stays nu_pre/nu_post.  Default 12 */
+  int32_t cycle_switch;/* > 0 and nu_pre = nu_post = 1: when a solve needs
+                          more PCG iterations than this, later solves of the
+                          handle use V(2,2), until one needs at most a third
+                          of it and the handle returns to V(1,1).  0, or any
+                          other configured cycle: the cycle stays
+                          nu_pre/nu_post.  Default 12 */
   int32_t prolongation;/* coarse-grid correction of the FP32 (mixed) cycle:
                           0 = piecewise constant, 1 = cell-centred trilinear,
                           2 = trilinear only while the handle runs V(2,2)
@@ -135,7 +137,8 @@ typedef struct fld_server fld_server;
  * L_unit: d_max = 0.006 c L_unit, r_min = 1e-20 / L_unit, rtol = 1e-8,
  * max_iter = 50, nu_pre = nu_post = 1, theta = 1, tau_tol = 1e-4, FP64,
  * coarse_scale = 0.5, max_dt_cuts = 8, graph replay on, cycle_switch = 12,
- * trilinear prolongation in the mixed cycle. */
+ * prolongation = 2 (trilinear in the mixed cycle once it has switched to
+ * V(2,2)). */
 void fld_default_params(fld_params *p, double c, double L_unit);
 
 const char *fld_strerror(fld_status s);

@@ -386,11 +386,15 @@ int Engine::set_cycle(int nu) {
   return release_graph();
 }
 
+// Only a handle configured for V(1,1) adapts: up to V(2,2) after a solve
+// that needed more than cycle_switch iterations, and back once a V(2,2) solve
+// needs at most a third of that.  Any other configured cycle is kept as is.
 int Engine::adapt_cycle(int max_iters) {
   const int thr = prm.cycle_switch;
   if (thr <= 0) return ST_OK;
-  if (prm.nu_pre == 1 && prm.nu_post == 1 && max_iters > thr) return set_cycle(2);
-  if (prm.nu_pre == 2 && prm.nu_post == 2 && max_iters * 3 <= thr) return set_cycle(1);
+  if (!switched && prm.nu_pre == 1 && prm.nu_post == 1 && max_iters > thr)
+    return set_cycle(2);
+  if (switched && max_iters * 3 <= thr) return set_cycle(1);
   return ST_OK;
 }
 

@@ -303,6 +303,40 @@ def test_full_size_many_sources_residual(fld, oracle_mod, prec):
         En = En + dEh
 
 
+def test_full_size_reionization_share_residual(fld, oracle_mod):
+    """640^3 reionization share (10^4 sources, ionized bubbles), mixed
+    precision, 6 levels: the benchmark's launch configuration.  Two
+    successive steps; the oracle evaluates b - A dE one cell at a time at
+    200 000 sampled cells of each."""
+    import torch
+    log_case("reionization_640", prec=1)
+    q = synth.t_reionization_share(n=640, device="cuda")
+    prm = fld.fld_default_params(q["c"], q["L_unit"], precision=1, mg_levels=6)
+    S = fld.Solver(q["shape"], q["h"], prm)
+    E, kap, eta = q["E"], q["kappa"], q["eta"]
+    Kh, Hh = host(kap), host(eta)
+    rng = np.random.default_rng(640)
+    cells = rng.choice(E.numel(), size=200000, replace=False).astype(np.int64)
+    for step in range(2):
+        En = host(E)
+        S.assemble(E, kap, eta, q["dt"])
+        dE, st = S.solve()
+        torch.cuda.synchronize()
+        O = oracle_mod.Problem(En, Kh, Hh, q["h"], q["c"], prm.d_max,
+                               prm.r_min, q["dt"])
+        res, rhs = O.residual_at(host(dE), cells)
+        ratio = np.linalg.norm(res) / np.linalg.norm(rhs)
+        print(f"[c3 step {step}] iters={st['iters']} nu={st['cycle_nu']} "
+              f"solver_rel={st['rel_resid']:.3e} sampled_rel={ratio:.3e}",
+              flush=True)
+        assert st["status"] == 0
+        assert st["rel_resid"] <= prm.rtol
+        # a sample of 200 000 of 2.6e8 cells estimates the global ratio
+        assert ratio <= 10 * prm.rtol
+        E += dE
+    S.close()
+
+
 def test_adaptive_cycle_switch(fld, oracle_mod):
     """A high-contrast problem (ionized bubbles, nu ~ 61) needs more than 12
     V(1,1) iterations, so the handle's next steps run V(2,2); every step still
