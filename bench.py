@@ -81,6 +81,37 @@ def step_bytes(counts, cells, prec_idx, levels):
     return fixed, it
 
 
+def model_step_bytes(cells, iters, nu, prec_idx, levels, steps=1):
+    """Algorithmic bytes of `steps` steps of one problem taking `iters` PCG
+    iterations in all, from the cycle structure:
+    assembly and coarse operators, the true-residual check and E += dE once,
+    then per PCG iteration one V(nu,nu) cycle (fused finest-level passes for
+    nu = 1), the SpMV and the vector update."""
+    B = {k: v[prec_idx] for k, v in BYTES_PER_CELL.items()}
+    cf = coarse_fraction(levels)
+    coarse = (COARSE_CYCLE_BYTES[prec_idx]
+              + (4 * (nu - 1)) * (56.0, 32.0)[prec_idx])
+    if nu == 1:
+        fine = B["vdown_fine"] + B["vup_fine"]
+    else:
+        fine = (B["pre0_fine"] + B["resid_restrict_fine"] + B["prolong_black_fine"]
+                + B["half_out"] + (4 * (nu - 1)) * B["half_fine"])
+    per_iter = fine + cf * coarse + B["spmv_p"] + B["update"]
+    coarsen = 32.0 * (1.0 + cf - 8.0 ** -(levels - 1)) + (48.0 if prec_idx else 32.0) * cf
+    fixed = B["assemble"] + coarsen + B["true_resid"] + B["update_E"]
+    return cells * (steps * fixed + iters * per_iter)
+
+
+def auto_levels(n):
+    """Levels of the automatic hierarchy of an n^3 grid: halve while the
+    extent is even and the coarse extent stays >= 4."""
+    lv = 1
+    while n % 2 == 0 and n // 2 >= 4:
+        n //= 2
+        lv += 1
+    return lv
+
+
 def measured_traffic(kernel, form):
     """HBM bytes per launch of `kernel` from the rocprofv3 byte-counter
     records under profiles/, or None when there is no record or any source
@@ -125,7 +156,7 @@ def parse():
     ap.add_argument("--fused-tile-z", type=int, default=0)
     ap.add_argument("--workload", default="many_sources",
                     choices=["many_sources", "single_source", "reionization",
-                             "batch", "served", "hii_test1"])
+                             "batch", "served", "hii_test1", "multigroup"])
     ap.add_argument("--reps", type=int, default=300,
                     help="single_source: timed solves for the latency quantiles")
     ap.add_argument("--batch", type=int, default=96, help="batch: problems")
@@ -133,6 +164,7 @@ def parse():
     ap.add_argument("--requests", type=int, default=500, help="served: requests")
     ap.add_argument("--load", type=float, default=0.7,
                     help="served: arrival rate as a fraction of saturation")
+    ap.add_argument("--groups", type=int, default=4, help="multigroup: groups")
     ap.add_argument("--hii-meshes", default="16,32,64",
                     help="hii_test1: octant meshes")
     ap.add_argument("--hii-taus", default="1e-2,1e-3,1e-4",

@@ -10,6 +10,8 @@ served         Poisson stream of 64..384^3 requests of 1-5 steps through the
                continuous-batching server: p50/p99 latency and throughput
 hii_test1      Test 1 end to end (radiation + hydrogen chemistry): I-front
                error, average step and run time over a tau_tol sweep
+multigroup     G frequency groups on one 256^3 mesh stepped together,
+               against the same groups one by one
 
 Each function returns the JSON object bench.py prints.
 """
@@ -211,16 +213,22 @@ def batch(args, fld, torch, synth, log):
     Es = [p["E"].clone() for p in probs]
     for _ in range(args.warmup):
         B.step(Es, K, H, dts)
+    from bench import model_step_bytes
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = []
+    step_bytes = 0.0
     for _ in range(args.steps):
         sts = B.step(Es, K, H, dts)
         iters += [s["iters"] for s in sts]
         assert all(s["status"] == 0 for s in sts)
+        step_bytes += sum(model_step_bytes(int(np.prod(shp)), s["iters"],
+                                           s["cycle_nu"], 1, s["levels"])
+                          for shp, s in zip(shapes, sts))
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     batched = cells * args.steps / sec / 1e6
+    step_gbps = step_bytes / sec / 1e9
     B.close()
 
     def one_by_one(prec, steps):
@@ -254,7 +262,12 @@ def batch(args, fld, torch, synth, log):
          "tuned": {"tile_z": base.tile_z, "nu_pre": base.nu_pre,
                    "nu_post": base.nu_post}},
         None,
-        {"forms": {"batched_mixed": round(batched, 2),
+        {"step_roofline": {"bytes_per_cell": round(step_bytes / (cells * args.steps), 1),
+                           "achieved": round(step_gbps, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(step_gbps / HBM_PEAK_GBS, 4),
+                           "model": "algorithmic bytes of each problem's step "
+                                    "from its iterations and cycle"},
+         "forms": {"batched_mixed": round(batched, 2),
                    "one_by_one_mixed": round(single_mixed, 2),
                    "one_by_one_fp64": round(single_fp64, 2)},
          "iters_per_problem": float(np.mean(iters)), "autotune": report})
@@ -321,6 +334,11 @@ def served(args, fld, torch, synth, log):
     res = [srv.poll(t) for t, _ in tickets]
     srv.close()
     assert all(r is not None and r["status"] == 0 for r in res)
+    from bench import auto_levels, model_step_bytes
+    sbytes = sum(model_step_bytes(shapes[i][0] ** 3, r["iters"], 1, 1,
+                                  auto_levels(shapes[i][0]), steps=shapes[i][1])
+                 for i, r in enumerate(res))
+    sgbps = sbytes / wall / 1e9
     lat = np.array([r["latency_s"] for r in res]) * 1e3
     que = np.array([r["queue_s"] for r in res]) * 1e3
     thr = work(range(nreq)) / wall / 1e6
@@ -339,7 +357,12 @@ def served(args, fld, torch, synth, log):
          "saturation": {"req_per_s": round(sat_rate, 2),
                         "mcell_updates_per_s": round(sat_mcells, 1)},
          "max_rel_resid": max(r["rel_resid"] for r in res),
-         "iters_mean": float(np.mean([r["iters"] for r in res]))})
+         "iters_mean": float(np.mean([r["iters"] for r in res])),
+         "step_roofline": {"bytes_per_cell": round(sbytes / work(range(nreq)), 1),
+                           "achieved": round(sgbps, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(sgbps / HBM_PEAK_GBS, 4),
+                           "model": "algorithmic bytes of each request from its "
+                                    "iterations, V(1,1)"}})
 
 
 def hii_test1(args, fld, torch, synth, log):
@@ -402,3 +425,65 @@ def hii_test1(args, fld, torch, synth, log):
          "t_end_myr": args.hii_t_end, "precision": args.hii_precision,
          "rtol": 1e-8},
         None, {"sweep": rows})
+
+
+def multigroup(args, fld, torch, synth, log):
+    """Multigroup FLD: G group systems on one 256^3 mesh stepped together in
+    the batched engine, against the same groups stepped one by one."""
+    from bench import model_step_bytes
+    from paper_1306_0645_amd.multigroup import MultigroupFLD
+    n = args.n
+    G = args.groups
+    log(f"[bench] multigroup {n}^3 x {G} groups: generating on the GPU")
+    q = synth.t_multigroup(n, G, device="cuda")
+    prm = fld.fld_default_params(q["c"], q["L_unit"], precision=fld.FLD_PREC_MIXED,
+                                 use_graph=args.graph)
+    mg = MultigroupFLD(q["shape"], q["h"], G, prm)
+    E = q["E"].clone()
+    for _ in range(args.warmup):
+        mg.step(E, q["kappa"], q["eta"], q["dt"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sbytes, iters = 0.0, []
+    for k in range(args.steps):
+        sts = mg.step(E, q["kappa"], q["eta"], q["dt"])
+        assert all(s["status"] == 0 for s in sts)
+        iters += [s["iters"] for s in sts]
+        sbytes += sum(model_step_bytes(n ** 3, s["iters"], s["cycle_nu"], 1,
+                                       s["levels"]) for s in sts)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    mg.close()
+    cells = G * n ** 3
+    value = cells * args.steps / sec / 1e6
+    # the same groups one after another on single-problem handles
+    solvers = [fld.Solver(q["shape"], q["h"], prm) for _ in range(G)]
+    E1 = q["E"].clone()
+    Ks = [q["kappa"][g] for g in range(G)]
+    Hs = [q["eta"][g] for g in range(G)]
+    for g in range(G):
+        solvers[g].step(E1[g], Ks[g], Hs[g], q["dt"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        for g in range(G):
+            solvers[g].step(E1[g], Ks[g], Hs[g], q["dt"])
+    torch.cuda.synchronize()
+    seq = cells * args.steps / (time.perf_counter() - t1) / 1e6
+    for S in solvers:
+        S.close()
+    gbps = sbytes / sec / 1e9
+    return _base(
+        "Mcell-updates/s counts every group's cells (G x n^3 per step)",
+        value, 1e3 * sec / args.steps, args.steps, args.warmup, "f64+f32",
+        {"workload": f"multigroup_{n}^3_x{G}", "grid": [n] * 3, "groups": G,
+         "sources": 64, "sigma_ln": 1.5, "precision": "mixed", "rtol": 1e-8},
+        None,
+        {"step_roofline": {"bytes_per_cell": round(sbytes / (cells * args.steps), 1),
+                           "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBS, 4),
+                           "model": "algorithmic bytes of each group's step "
+                                    "from its iterations and cycle"},
+         "forms": {"groups_batched": round(value, 2),
+                   "groups_one_by_one": round(seq, 2)},
+         "iters_per_group_step": float(np.mean(iters))})

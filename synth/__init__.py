@@ -406,3 +406,58 @@ def t_reionization_share(n=640, n_src=10000, sigma_ln=2.0, device="cuda",
     return {"name": f"reionization_{n}", "shape": shape, "h": (dx, dx, dx),
             "E": E, "kappa": kappa, "eta": eta, "c": C_LIGHT, "L_unit": L,
             "dt": dt, "theta": 1.0, "a": 1.0, "adot": 0.0}
+
+
+def group_structure(G: int, e_lo_ev: float = 13.6, e_hi_ev: float = 13.6 * 8.0,
+                    T_source: float = 1e5):
+    """G frequency groups log-spaced in photon energy over [e_lo, e_hi] eV:
+    (mean photon energy per group [erg], HI cross-section per group [cm^2],
+    fraction of a T_source blackbody's ionizing photons in each group).
+    The cross-section follows the hydrogenic nu^-3 fall-off from 6.3e-18 cm^2
+    at the threshold; photons above e_hi are dropped."""
+    kT = 8.617333262e-5 * T_source  # eV
+    edges = np.geomspace(e_lo_ev, e_hi_ev, G + 1)
+    e_mid = np.sqrt(edges[:-1] * edges[1:])
+    fine = np.geomspace(e_lo_ev, 40.0 * e_hi_ev, 20001)
+    planck = fine ** 2 / np.expm1(fine / kT)  # photon number per unit energy
+    total = np.trapezoid(planck, fine)
+    frac = np.empty(G)
+    for g in range(G):
+        m = (fine >= edges[g]) & (fine <= edges[g + 1])
+        frac[g] = np.trapezoid(planck[m], fine[m]) / total
+    sigma = SIGMA_HI * (e_mid / e_lo_ev) ** -3
+    return e_mid * EV, sigma, frac
+
+
+def t_multigroup(n: int, G: int, n_src: int = 64, sigma_ln: float = 1.5,
+                 device="cuda", problem: int = 0):
+    """Multigroup stand-in: one lognormal HI field (mean 1e-3 cm^-3) on n^3
+    cells of 206 pc, n_src sources with Ndot log-uniform in [1e47, 1e50] and a
+    1e5 K blackbody spectrum split over G groups; per group
+    kappa_g = sigma_g n_HI, eta_g = sum Ndot f_g h nu_g / V_cell and a smooth
+    E_g^n; dt = 1e-3 light-crossing times.  Fields are (G, n, n, n)."""
+    import torch
+    shape = (n, n, n)
+    gen = t_generator(6, problem, device)
+    rng = rng_for(6, 100000 + problem)
+    dx = DX_TEST1
+    g = t_smooth_gaussian(shape, 1.5, gen, device)
+    nH = torch.exp(math.log(1e-3) + sigma_ln * g)
+    del g
+    hnu, sig, frac = group_structure(G)
+    cells, ndot = point_sources(shape, n_src, 1e47, 1e50, rng)
+    L = n * dx
+    dt = 1e-3 * L / C_LIGHT
+    kappa = torch.empty((G,) + shape, dtype=torch.float64, device=device)
+    eta = torch.empty_like(kappa)
+    E = torch.empty_like(kappa)
+    for k in range(G):
+        kappa[k] = sig[k] * nH
+        e1 = t_emissivity(shape, cells, ndot * frac[k], dx ** 3, device)
+        eta[k] = e1 * (hnu[k] / HNU_HI)
+        E[k] = float(eta[k].mean()) * dt * torch.exp(
+            t_smooth_gaussian(shape, 8.0, gen, device))
+    return {"name": f"multigroup_{n}_G{G}", "shape": shape, "groups": G,
+            "h": (dx, dx, dx), "E": E, "kappa": kappa, "eta": eta,
+            "c": C_LIGHT, "L_unit": L, "dt": dt, "theta": 1.0, "a": 1.0,
+            "adot": 0.0, "hnu": hnu, "sigma": sig, "frac": frac}
