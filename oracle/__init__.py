@@ -88,7 +88,7 @@ def _load():
         lib.oracle_step.argtypes = [i, i, i, d, d, d, p, p, p, d, d, d, d, d,
                                     d, d, d, i, d, d, i, p]
         lib.oracle_chem_h.restype = None
-        lib.oracle_chem_h.argtypes = [i64, p, p, p, p, d, i, d, d, d, d]
+        lib.oracle_chem_h.argtypes = [i64, p, p, p, p, d, i, d, d, d, d, d]
         _lib = lib
     return _lib
 
@@ -219,17 +219,18 @@ def step(E, kappa, eta, h, c, d_max, r_min, dt, theta=1.0, a=1.0, adot=0.0,
 # Isothermal hydrogen chemistry and the operator-split Test-1 driver
 # ---------------------------------------------------------------------------
 
-def chem_h(E, n_h, x, dt, c, sigma, hnu, alpha_b, substeps=1):
+def chem_h(E, n_h, x, dt, c, sigma, hnu, alpha_b, substeps=1, a=1.0):
     """Loosely coupled chemistry update of the ionized fraction (Sec. 3.3) for
     pure hydrogen at fixed temperature; returns (x_new, kappa_new) with
-    kappa = sigma n_HI.  See ``oracle_chem_h`` for the update."""
+    kappa = sigma n_HI (proper).  E and n_h are comoving densities at
+    expansion factor a.  See ``oracle_chem_h`` for the update."""
     E = _arr(E)
     n_h = _arr(n_h, E.shape)
     xo = _arr(x, E.shape).copy()
     kappa = np.empty_like(E)
     _load().oracle_chem_h(E.size, _ptr(E), _ptr(n_h), _ptr(xo), _ptr(kappa),
                           float(dt), int(substeps), float(c), float(sigma),
-                          float(hnu), float(alpha_b))
+                          float(hnu), float(alpha_b), float(a))
     return xo, kappa
 
 
@@ -238,9 +239,17 @@ def ionized_radius(x, cell_volume):
     return (3.0 * float(np.sum(x)) * cell_volume / (4.0 * math.pi)) ** (1.0 / 3.0)
 
 
+def eds_expansion(t, H0):
+    """Expansion factor and its rate in an Einstein-de Sitter universe (the
+    Friedmann solution for Omega_m = 1): a = (3 H0 t / 2)^(2/3) with a = 1 at
+    the present, adot = (2 / (3 t)) a."""
+    a = (1.5 * H0 * t) ** (2.0 / 3.0)
+    return a, a * 2.0 / (3.0 * t)
+
+
 def hii_run(E, x, n_h, eta, h, c, d_max, r_min, sigma, hnu, alpha_b, outputs,
             dt0, tau_tol, e_floor, chem_substeps=1, tol=1e-13, max_cuts=8,
-            dts=None, max_steps=10 ** 7):
+            dts=None, max_steps=10 ** 7, t0=0.0, H0=None, theta=1.0):
     """Radiation + chemistry in the operator-split order of Sec. 3.4.
 
     Each step t -> t + dt: the radiation step (with its 10x cut-and-subcycle
@@ -248,27 +257,32 @@ def hii_run(E, x, n_h, eta, h, c, d_max, r_min, sigma, hnu, alpha_b, outputs,
     then drives the chemistry over the same dt, which gives the opacity of
     the next step.  With static gas the radiation estimate alone sets the
     next dt (Sec. 3.4 takes the minimum over the processes), clipped so that
-    steps land on the output times.  ``dts`` replays a given sequence of step
-    sizes instead.  Returns the final fields, the ionized radius at every
-    output time and the step sizes taken."""
+    steps land on the output times (absolute times, the run starts at t0).
+    ``dts`` replays a given sequence of step sizes instead.  With H0 the
+    fields are comoving in an Einstein-de Sitter background: each step uses
+    a and adot at its midpoint.  Returns the final fields, the ionized radius
+    (comoving) at every output time and the step sizes taken."""
     E = _arr(E).copy()
     x = _arr(x, E.shape).copy()
     n_h = _arr(n_h, E.shape)
     eta = _arr(eta, E.shape)
-    kappa = sigma * n_h * (1.0 - x)
     vcell = h[0] * h[1] * h[2]
+    a0 = eds_expansion(t0, H0)[0] if H0 else 1.0
+    kappa = sigma * (n_h / a0 ** 3) * (1.0 - x)
     outputs = [float(o) for o in outputs]
-    t, dt, k, i = 0.0, float(dt0), 0, 0
+    t, dt, k, i = float(t0), float(dt0), 0, 0
     radii, taken, iters = [], [], 0
     while k < len(outputs) and i < max_steps:
         target = outputs[k]
         step_dt = float(dts[i]) if dts is not None else min(dt, target - t)
-        E, st, s = step(E, kappa, eta, h, c, d_max, r_min, step_dt, tol=tol,
+        a, adot = eds_expansion(t + 0.5 * step_dt, H0) if H0 else (1.0, 0.0)
+        E, st, s = step(E, kappa, eta, h, c, d_max, r_min, step_dt,
+                        theta=theta, a=a, adot=adot, tol=tol,
                         tau_tol=tau_tol, e_floor=e_floor, max_cuts=max_cuts)
         if st != OK:
             raise RuntimeError(f"oracle radiation step failed with status {st}")
         x, kappa = chem_h(E, n_h, x, step_dt, c, sigma, hnu, alpha_b,
-                          chem_substeps)
+                          chem_substeps, a)
         iters += int(s["iters"])
         taken.append(step_dt)
         t += step_dt

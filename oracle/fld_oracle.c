@@ -34,7 +34,12 @@
  *   - R uses the one-sided face-normal difference |E_q - E_p| / dx_d.
  *   - Ebar <= 0 (including E_p = E_q = 0) gives R = R_min.
  *   - kbar = 0 when either cell has kappa = 0 (the limit of the harmonic mean).
- *   - kappa, eta, a, adot are frozen over the step; a enters only via adot/a.
+ *   - kappa, eta, a, adot are frozen over the step.
+ *   - The mesh is comoving (Sec. 2 takes spatial derivatives with respect to
+ *     the comoving position and E is the comoving energy density), so the
+ *     step's operator uses the proper separation a*dx of neighbouring cells:
+ *     every cell size below is multiplied by a (a = 1: static problems),
+ *     and a enters otherwise only through adot/a.
  *   - The time-step estimator the paper defers to prior work is replaced by
  *     rho = RMS(dE / max(|E^{n+1}|, e_floor)), dt_next = dt * clamp(tau/rho,
  *     0.1, 2).  This controller is PARITY UNPINNED (only its mechanism is
@@ -212,6 +217,8 @@ static int sys_init(or_system *s, int nx, int ny, int nz, double dx, double dy,
                     double d_max, double r_min, double theta, double dt,
                     double a, double adot) {
   int64_t n = (int64_t)nx * ny * nz;
+  /* proper separation of the comoving cells */
+  dx *= a; dy *= a; dz *= a;
   s->nx = nx; s->ny = ny; s->nz = nz;
   s->dx = dx; s->dy = dy; s->dz = dz;
   s->c = c; s->theta = theta; s->dt = dt; s->adot_over_a = adot / a;
@@ -305,8 +312,9 @@ void oracle_residual_at(int nx, int ny, int nz, double dx, double dy, double dz,
                         double dt, double a, double adot, const double *x,
                         const int64_t *cells, int64_t ncells, double *res,
                         double *rhs) {
-  double h2[3] = {dx * dx, dy * dy, dz * dz};
-  double hd[3] = {dx, dy, dz};
+  /* proper separation of the comoving cells, as in sys_init */
+  double hd[3] = {a * dx, a * dy, a * dz};
+  double h2[3] = {hd[0] * hd[0], hd[1] * hd[1], hd[2] * hd[2]};
   double aa = adot / a;
   for (int64_t t = 0; t < ncells; ++t) {
     int64_t p = cells[t];
@@ -417,17 +425,24 @@ int oracle_step(int nx, int ny, int nz, double dx, double dy, double dz,
  * frozen over the chemistry step (Sec. 3.4 processes the new E into the
  * rates first).  The step dt is taken in `substeps` equal pieces.  Finally
  * the opacity seen by the next radiation step is kappa = sigma n_HI.
+ *
+ * E and n_H are comoving densities (Sec. 2: comoving = proper a^3), so the
+ * rates use the proper values E / a^3 and n_H / a^3, and kappa is the proper
+ * opacity (per proper length) that the radiation step takes; a = 1 for a
+ * static problem.
  * ------------------------------------------------------------------------- */
 void oracle_chem_h(int64_t n, const double *E, const double *n_h, double *x,
                    double *kappa, double dt, int substeps, double c,
-                   double sigma, double hnu, double alpha_b) {
+                   double sigma, double hnu, double alpha_b, double a) {
   double h = dt / (double)substeps;
+  double inv_a3 = 1.0 / (a * a * a);
   for (int64_t p = 0; p < n; ++p) {
-    double gamma = c * sigma * E[p] / hnu;
+    double nh = n_h[p] * inv_a3;
+    double gamma = c * sigma * (E[p] * inv_a3) / hnu;
     double xp = x[p];
     for (int s = 0; s < substeps; ++s)
-      xp = (xp + h * gamma) / (1.0 + h * (gamma + alpha_b * n_h[p] * xp));
+      xp = (xp + h * gamma) / (1.0 + h * (gamma + alpha_b * nh * xp));
     x[p] = xp;
-    kappa[p] = sigma * n_h[p] * (1.0 - xp);
+    kappa[p] = sigma * nh * (1.0 - xp);
   }
 }

@@ -461,3 +461,47 @@ def t_multigroup(n: int, G: int, n_src: int = 64, sigma_ln: float = 1.5,
             "h": (dx, dx, dx), "E": E, "kappa": kappa, "eta": eta,
             "c": C_LIGHT, "L_unit": L, "dt": dt, "theta": 1.0, "a": 1.0,
             "adot": 0.0, "hnu": hnu, "sigma": sig, "frac": frac}
+
+
+GYR = 1e3 * MYR
+
+
+def cosmo_test2(n_oct: int = 16, ndot: float = 5e46, z_end: float = 0.0,
+                n_out: int = 50, z0: float = 4.0):
+    """Test 2 (Sec. 4.1.2): a point source in uniform hydrogen in an
+    Einstein-de Sitter universe (Omega_m = 1, q0 = 1/2, H0 = 50 km/s/Mpc,
+    Omega_b = 0.2), from z0 = 4 to z_end; proper density 1.175e-28 g cm^-3 at
+    z0 (pure hydrogen), T = 1e4 K, E = 1e-45 erg cm^-3, x = 0.0012 (as in
+    Test 1).  The comoving domain [0, 80 kpc]^3 (comoving lengths in units of
+    the present, a = 1/(1+z)) is run as its periodic mirror image: (2 n_oct)^3
+    cells with the source split over the 8 central cells.  Fields are
+    comoving (proper x a^3); outputs are evenly spaced in cosmic time."""
+    n = 2 * n_oct
+    shape = (n, n, n)
+    L = 80.0 * KPC
+    dx = L / n_oct
+    H0 = 50.0 * 1e5 / (1e3 * KPC)          # s^-1
+    t_of_z = lambda z: (2.0 / (3.0 * H0)) * (1.0 + z) ** -1.5
+    a0 = 1.0 / (1.0 + z0)
+    m_h = 1.6726e-24
+    n_h0 = 1.175e-28 / m_h                  # proper, at z0
+    n_h_com = n_h0 * a0 ** 3
+    c0 = n_oct
+    cells = [((c0 - 1 + k) * n + (c0 - 1 + j)) * n + (c0 - 1 + i)
+             for k in (0, 1) for j in (0, 1) for i in (0, 1)]
+    eta = emissivity(shape, cells, [ndot / 8.0] * 8, dx ** 3)  # comoving
+    t0, t1 = t_of_z(z0), t_of_z(z_end)
+    rs0 = float(stromgren_radius(ndot, n_h0))                   # proper, z0
+    e_floor = 1e-3 * ndot * HNU_HI / (4.0 * math.pi * rs0 * rs0 * C_LIGHT) * a0 ** 3
+    return {
+        "name": f"cosmo_test2_{n_oct}", "shape": shape, "h": (dx, dx, dx),
+        "E": np.full(shape, 1e-45), "x": np.full(shape, 0.0012),
+        "n_h": np.full(shape, n_h_com), "eta": eta, "L_unit": L, "ndot": ndot,
+        "z0": z0, "H0": H0, "t0": t0, "t1": t1, "n_h0": n_h0, "r_s0": rs0,
+        "lambda": ALPHA_B * n_h0 / H0 / (1.0 + z0), "q0": 0.5,
+        "dt0": 1e-3 * a0 * L / C_LIGHT, "e_floor": e_floor,
+        "outputs": [t0 + (t1 - t0) * (k + 1) / n_out for k in range(n_out)],
+        "sigma": SIGMA_HI, "hnu": HNU_HI, "alpha_b": ALPHA_B,
+        "cell_volume": dx ** 3,
+    }
+

@@ -33,22 +33,25 @@ def _gamma(E):
     return C * SIGMA * E / HNU
 
 
+@pytest.mark.parametrize("a", [1.0, 0.2])
 @pytest.mark.parametrize("substeps", [1, 3, 7])
-def test_chem_pure_recombination_is_exact(oracle_mod, substeps):
+def test_chem_pure_recombination_is_exact(oracle_mod, substeps, a):
     # E = 0: dx/dt = -alpha n x^2 has x(t) = x0 / (1 + alpha n x0 t), and
-    # 1/x grows linearly, which the linearly implicit step reproduces exactly
+    # 1/x grows linearly, which the linearly implicit step reproduces exactly;
+    # n is the proper density, the comoving n_h over a^3
     alpha = 2.59e-13
     _, x0, n_h = _fields(4096, 1)
+    n_p = n_h / a ** 3
     E = np.zeros_like(x0)
     x = x0.copy()
     t = 0.0
     for dt in (1e12, 3e13, 2e15):
         x, kappa = oracle_mod.chem_h(E, n_h, x, dt, C, SIGMA, HNU, alpha,
-                                     substeps)
+                                     substeps, a)
         t += dt
-        exact = x0 / (1.0 + alpha * n_h * x0 * t)
+        exact = x0 / (1.0 + alpha * n_p * x0 * t)
         np.testing.assert_allclose(x, exact, rtol=1e-13)
-        np.testing.assert_allclose(kappa, SIGMA * n_h * (1.0 - exact),
+        np.testing.assert_allclose(kappa, SIGMA * n_p * (1.0 - exact),
                                    rtol=1e-12)
 
 
@@ -59,6 +62,10 @@ def test_chem_pure_photoionization(oracle_mod):
     rng, x0, n_h = _fields(2048, 2)
     E = np.exp(rng.uniform(math.log(1e-20), math.log(1e-16), x0.shape))
     g = _gamma(E)
+    # comoving E = a^3 x the proper E that sets the rate (a = 0.5)
+    x, _ = oracle_mod.chem_h(0.125 * E, n_h, x0, 5e10, C, SIGMA, HNU, 0.0, 4, 0.5)
+    exact = 1.0 - (1.0 - x0) / (1.0 + (5e10 / 4) * g) ** 4
+    np.testing.assert_allclose(1.0 - x, 1.0 - exact, rtol=1e-10)
     for dt, m in ((1e9, 1), (5e10, 4), (3e11, 9)):
         x, _ = oracle_mod.chem_h(E, n_h, x0, dt, C, SIGMA, HNU, 0.0, m)
         exact = 1.0 - (1.0 - x0) / (1.0 + (dt / m) * g) ** m
@@ -135,3 +142,63 @@ def test_stromgren_sphere_growth(oracle_mod):
     np.testing.assert_allclose(x, x[::-1, :, :], rtol=1e-6, atol=1e-12)
     np.testing.assert_allclose(x, np.transpose(x, (2, 1, 0)), rtol=1e-6,
                                atol=1e-12)
+
+
+def _shapiro_giroux(t, H0, z0, lam, q0, r_s0):
+    """Comoving I-front radius (present-day units) of eq. "radius_cosmo":
+    r = r_s0 (lam e^-tau(a) int_1^a e^tau(b) (1 - 2q0 + 2q0 (1+z0)/b)^-1/2 db)^1/3
+    with tau from eq. "tau" and F from eq. "Fa", a the expansion factor
+    normalised to 1 at z0 (the paper's integrand prints (1 - z0); F's (1 + z0)
+    is the consistent reading), and r_s0 the proper Stromgren radius at z0,
+    which is comoving in units of z0; times (1 + z0) for present-day units."""
+    from scipy.integrate import quad
+    F = lambda a: ((2 - 4 * q0 - 2 * q0 / a * (1 + z0))
+                   * (1 - 2 * q0 + 2 * q0 / a * (1 + z0)) ** 0.5)
+    tau = lambda a: lam * (F(a) - F(1.0)) / (6 * q0 ** 2 * (1 + z0) ** 2)
+    a_abs = (1.5 * H0 * t) ** (2.0 / 3.0)   # Einstein-de Sitter, a = 1 today
+    an = a_abs * (1 + z0)
+    integral = quad(lambda b: math.exp(tau(b))
+                    * (1 - 2 * q0 + 2 * q0 / b * (1 + z0)) ** -0.5, 1.0, an)[0]
+    y = lam * math.exp(-tau(an)) * integral
+    return r_s0 * y ** (1.0 / 3.0) * (1 + z0)
+
+
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_cosmological_front(oracle_mod, theta):
+    """Test 2 on the 8^3 octant (16^3 mirrored), tau_tol = 1e-2, z = 4 -> 2:
+    the comoving ionized radius follows the Shapiro-Giroux solution with the
+    error norm of eq. "i1_error" (relative to the comoving r_s at z0) <= 0.05
+    for backward Euler and the trapezoidal rule."""
+    g = read_golden("test2_parameters.txt")
+    h = float(g["hubble_h"])
+    H0 = 100.0 * h * 1e5 / (1e3 * synth.KPC)
+    z0, q0 = float(g["z_start"]), float(g["q0"])
+    n_h0 = float(g["rho_g_cm3"]) / 1.6726e-24
+    alpha = float(g["alpha_b_cm3_s"])
+    ndot = float(g["ndot_photons_per_s"])
+    lam = alpha * n_h0 / H0 / (1 + z0)
+    r_s0 = (3 * ndot / (4 * math.pi * alpha * n_h0 ** 2)) ** (1.0 / 3.0)
+    # the printed density is the proper baryon density at z0 for h = 0.5,
+    # Omega_b = 0.2: Omega_b rho_crit (1 + z0)^3
+    rho_crit = 3 * H0 ** 2 / (8 * math.pi * 6.674e-8)
+    assert float(g["rho_g_cm3"]) == pytest.approx(
+        float(g["omega_b"]) * rho_crit * (1 + z0) ** 3, rel=2e-3)
+
+    d = synth.cosmo_test2(8, ndot=ndot, z_end=2.0, n_out=10)
+    assert d["H0"] == pytest.approx(H0, rel=1e-12)
+    d_max, r_min = oracle_mod.limits(C, d["L_unit"])
+    run = oracle_mod.hii_run(d["E"], d["x"], d["n_h"], d["eta"], d["h"], C,
+                             d_max, r_min, SIGMA, HNU, alpha, d["outputs"],
+                             d["dt0"], 1e-2, d["e_floor"], t0=d["t0"], H0=H0,
+                             theta=theta)
+    t = np.array(run["times"])
+    r = np.array(run["radii"])
+    r_true = np.array([_shapiro_giroux(tt, H0, z0, lam, q0, r_s0) for tt in t])
+    err = math.sqrt(np.mean(((r - r_true) / (r_s0 * (1 + z0))) ** 2))
+    assert err <= 0.05, (err, r / synth.KPC, r_true / synth.KPC)
+    assert np.all(np.diff(r) > 0)
+    # the front first approaches the Stromgren radius r_s(t) and then falls
+    # behind it as expansion drives r_s outward (comoving r_s grows as a)
+    a = (1.5 * H0 * t) ** (2.0 / 3.0)
+    frac = r / (r_s0 * (1 + z0) * (1 + z0) * a)
+    assert frac[1] > frac[0] and frac[-1] < frac[-2]

@@ -151,17 +151,20 @@ def test_expansion_term(oracle_mod, theta):
         rtol=1e-13)
 
 
+@pytest.mark.parametrize("a", [1.0, 0.4])
 @pytest.mark.parametrize("theta", [1.0, 0.5])
-def test_fourier_mode_decay(oracle_mod, theta):
+def test_fourier_mode_decay(oracle_mod, theta, a):
     """Constant kappa, D pinned at D_max, E = E0 (1 + eps cos(k.x)) on a
     ragged anisotropic grid: A is circulant, so the mean and the mode evolve
     separately with growth factors (1 - (1-theta) dt mu)/(1 + theta dt mu),
-    mu_k = adot/a + c kappa + D_max sum_d 4 sin^2(k_d dx_d / 2) / dx_d^2."""
+    mu_k = adot/a + c kappa + D_max sum_d 4 sin^2(k_d h_d / 2) / h_d^2, where
+    h_d = a dx_d is the proper separation of the comoving cells."""
     nz, ny, nx = 8, 12, 10
-    h = (0.9, 1.4, 0.6)
+    hc = (0.9, 1.4, 0.6)
+    h = tuple(a * v for v in hc)  # proper spacing
     m = (2, 1, 3)  # mode numbers along x, y, z
     k0, E0, eps, c = 0.05, 1.0, 0.1, 2.0
-    a, adot, dt = 1.0, 0.03, 0.7
+    adot, dt = 0.03 * a, 0.7
     x = np.arange(nx)[None, None, :]
     y = np.arange(ny)[None, :, None]
     z = np.arange(nz)[:, None, None]
@@ -182,7 +185,7 @@ def test_fourier_mode_decay(oracle_mod, theta):
     zero = np.zeros(E.shape)
     mean, amp = E0, E0 * eps
     for n in range(5):
-        P = _prob(oracle_mod, E, kap, zero, h, dt, theta, a, adot, d_max=d_max,
+        P = _prob(oracle_mod, E, kap, zero, hc, dt, theta, a, adot, d_max=d_max,
                   c=c)
         Dx, Dy, Dz = oracle_mod.faces(E, kap, h, c, d_max, 1e-20)
         assert np.all(Dx == d_max) and np.all(Dy == d_max) and np.all(Dz == d_max)
@@ -193,22 +196,25 @@ def test_fourier_mode_decay(oracle_mod, theta):
         np.testing.assert_allclose(E, mean + amp * mode, rtol=0, atol=1e-12)
 
 
-def test_nyquist_mode_limiter_active(oracle_mod):
+@pytest.mark.parametrize("a", [1.0, 0.25])
+def test_nyquist_mode_limiter_active(oracle_mod, a):
     """E = E0 (1 + eps (-1)^i) with D_max out of reach: every x face has
-    Ebar = E0 and |dE| = 2 eps E0, so R = 2 eps / dx and
-    D_x = c / sqrt(9 k0^2 + 4 eps^2 / dx^2).  The x-Nyquist mode then has
-    mu_N = c k0 + 4 D_x / dx^2 and the mean mu_0 = c k0."""
+    Ebar = E0 and |dE| = 2 eps E0, so with the proper spacing hx = a dx,
+    R = 2 eps / hx and D_x = c / sqrt(9 k0^2 + 4 eps^2 / hx^2).  The
+    x-Nyquist mode then has mu_N = c k0 + 4 D_x / hx^2 and the mean
+    mu_0 = c k0 (adot = 0)."""
     nz, ny, nx = 4, 6, 8
     h = (0.5, 1.0, 1.5)
+    hx = a * h[0]
     k0, E0, eps, c, dt, theta = 0.4, 3.0, 0.2, 1.5, 0.25, 1.0
     s = (-1.0) ** np.arange(nx)[None, None, :] * np.ones((nz, ny, 1))
     E = E0 * (1 + eps * s)
     kap = np.full(E.shape, k0)
-    P = _prob(oracle_mod, E, kap, np.zeros(E.shape), h, dt, theta, c=c)
+    P = _prob(oracle_mod, E, kap, np.zeros(E.shape), h, dt, theta, a, 0.0, c=c)
     dE, st, _, _ = P.solve()
-    Dx = c / math.sqrt(9 * k0 ** 2 + 4 * eps ** 2 / h[0] ** 2)
+    Dx = c / math.sqrt(9 * k0 ** 2 + 4 * eps ** 2 / hx ** 2)
     mu0 = c * k0
-    muN = mu0 + 4 * Dx / h[0] ** 2
+    muN = mu0 + 4 * Dx / hx ** 2
     want = (dt * (-mu0 * E0) / (1 + theta * dt * mu0)
             + dt * (-muN * E0 * eps) * s / (1 + theta * dt * muN))
     np.testing.assert_allclose(dE, want, rtol=1e-12)
@@ -330,15 +336,16 @@ def test_dense_solve_8cubed(oracle_mod):
     assert np.linalg.norm(dE.ravel() - x_lapack) <= np.linalg.norm(r) * (1 + 1e-6) + 1e-30
 
 
-def test_residual_at_matches_assembled(oracle_mod):
+@pytest.mark.parametrize("a", [1.0, 0.3])
+def test_residual_at_matches_assembled(oracle_mod, a):
     """The cell-by-cell residual used for spot checks on large grids agrees
-    with b - A x from the assembled system."""
+    with b - A x from the assembled system (also on a comoving mesh)."""
     import synth
     p = synth.random_problem((6, 8, 10), seed=6, sigma_ln=1.0, n_src=2,
                              dt_factor=5e-2)
     dmax, rmin = oracle_mod.limits(p["c"], p["L_unit"])
     P = oracle_mod.Problem(p["E"], p["kappa"], p["eta"], p["h"], p["c"], dmax,
-                           rmin, p["dt"])
+                           rmin, p["dt"], 1.0, a, 0.2 / p["dt"])
     rng = np.random.default_rng(7)
     x = rng.normal(size=p["E"].shape) * np.abs(p["E"]).max()
     diag, Ax, Ay, Az, b = P.system()
