@@ -254,10 +254,11 @@ void oracle_system(int nx, int ny, int nz, double dx, double dy, double dz,
   sys_init(&s, nx, ny, nz, dx, dy, dz, E, kappa, c, d_max, r_min, theta, dt, a,
            adot);
   sys_diag(&s, diag);
+  /* s.dx, s.dy, s.dz: the proper separation used by the operator */
   for (int64_t p = 0; p < n; ++p) {
-    Ax[p] = theta * dt * s.Dx[p] / (dx * dx);
-    Ay[p] = theta * dt * s.Dy[p] / (dy * dy);
-    Az[p] = theta * dt * s.Dz[p] / (dz * dz);
+    Ax[p] = theta * dt * s.Dx[p] / (s.dx * s.dx);
+    Ay[p] = theta * dt * s.Dy[p] / (s.dy * s.dy);
+    Az[p] = theta * dt * s.Dz[p] / (s.dz * s.dz);
   }
   sys_rhs(&s, E, eta, b);
   sys_free(&s);

@@ -280,13 +280,16 @@ def _dense_by_columns(P):
     return M
 
 
-def test_matrix_structure(oracle_mod):
+@pytest.mark.parametrize("a", [1.0, 0.5])
+def test_matrix_structure(oracle_mod, a):
+    """Brute-force columns A e_j against the exported system, on a static and
+    on a comoving mesh (proper separation a h)."""
     rng = np.random.default_rng(4)
     shape = (4, 6, 8)
     E = np.exp(rng.normal(0.0, 1.0, shape))
     kap = np.exp(rng.normal(-1.0, 1.5, shape))
     h = (0.9, 1.1, 1.6)
-    dt, theta, a, adot, c, d_max = 0.8, 1.0, 1.0, 0.05, 1.0, 0.4
+    dt, theta, adot, c, d_max = 0.8, 1.0, 0.05 * a, 1.0, 0.4
     P = _prob(oracle_mod, E, kap, np.zeros(shape), h, dt, theta, a, adot,
               d_max=d_max, c=c)
     M = _dense_by_columns(P)
@@ -307,7 +310,7 @@ def test_matrix_structure(oracle_mod):
     lam = np.linalg.eigvalsh(0.5 * (M + M.T))
     assert lam.min() >= 1.0 - 1e-12  # adot >= 0 -> lambda_min(A) >= 1
     gersh = 1 + theta * dt * (c * kap.max() + adot / a
-                              + 4 * d_max * sum(1 / hh ** 2 for hh in h))
+                              + 4 * d_max * sum(1 / (a * hh) ** 2 for hh in h))
     assert lam.max() <= gersh * (1 + 1e-12)
 
 
