@@ -156,7 +156,8 @@ def parse():
     ap.add_argument("--fused-tile-z", type=int, default=0)
     ap.add_argument("--workload", default="many_sources",
                     choices=["many_sources", "single_source", "reionization",
-                             "batch", "served", "hii_test1", "multigroup"])
+                             "batch", "served", "hii_test1", "multigroup",
+                             "cosmo_test2"])
     ap.add_argument("--reps", type=int, default=300,
                     help="single_source: timed solves for the latency quantiles")
     ap.add_argument("--batch", type=int, default=96, help="batch: problems")

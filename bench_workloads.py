@@ -12,6 +12,8 @@ hii_test1      Test 1 end to end (radiation + hydrogen chemistry): I-front
                error, average step and run time over a tau_tol sweep
 multigroup     G frequency groups on one 256^3 mesh stepped together,
                against the same groups one by one
+cosmo_test2    Test 2 end to end (comoving, Einstein-de Sitter): error
+               against the Shapiro-Giroux front over a tau_tol sweep
 
 Each function returns the JSON object bench.py prints.
 """
@@ -487,3 +489,84 @@ def multigroup(args, fld, torch, synth, log):
          "forms": {"groups_batched": round(value, 2),
                    "groups_one_by_one": round(seq, 2)},
          "iters_per_group_step": float(np.mean(iters))})
+
+
+def _shapiro_giroux(t, H0, z0, lam, q0, r_s0):
+    """Comoving (present-day units) I-front radius of the Shapiro-Giroux
+    solution, eq. "radius_cosmo", in an Einstein-de Sitter background."""
+    from scipy.integrate import quad
+    F = lambda a: ((2 - 4 * q0 - 2 * q0 / a * (1 + z0))
+                   * (1 - 2 * q0 + 2 * q0 / a * (1 + z0)) ** 0.5)
+    tau = lambda a: lam * (F(a) - F(1.0)) / (6 * q0 ** 2 * (1 + z0) ** 2)
+    an = (1.5 * H0 * t) ** (2.0 / 3.0) * (1 + z0)
+    integral = quad(lambda b: math.exp(tau(b))
+                    * (1 - 2 * q0 + 2 * q0 / b * (1 + z0)) ** -0.5, 1.0, an)[0]
+    return r_s0 * (lam * math.exp(-tau(an)) * integral) ** (1.0 / 3.0) * (1 + z0)
+
+
+def cosmo_test2(args, fld, torch, synth, log):
+    """Test 2 (Sec. 4.1.2) end to end: comoving radiation + hydrogen
+    chemistry in an Einstein-de Sitter background from z = 4 to 0, on the
+    octant meshes for each tau_tol; the error norm against the Shapiro-Giroux
+    front, the average step and the run time (the paper's Fig. "sg_stats"),
+    with a wall-clock cap per run."""
+    from paper_1306_0645_amd.ionization import IsothermalHII, eds_expansion
+    meshes = [int(v) for v in args.hii_meshes.split(",")]
+    taus = [float(v) for v in args.hii_taus.split(",")]
+    prec = fld.FLD_PREC_MIXED if args.hii_precision == "mixed" else fld.FLD_PREC_FP64
+    rows, cells_steps, wall_total = [], 0.0, 0.0
+    for n_oct in meshes:
+        for tau in taus:
+            d = synth.cosmo_test2(n_oct, z_end=0.0, n_out=50)
+            prm = fld.fld_default_params(synth.C_LIGHT, d["L_unit"],
+                                         precision=prec, tau_tol=tau,
+                                         e_floor=d["e_floor"])
+            drv = IsothermalHII(d["shape"], d["h"], prm,
+                                fld.fld_chem_default_params(),
+                                expansion=eds_expansion(d["H0"]))
+            E, x = (torch.from_numpy(d[k]).cuda() for k in ("E", "x"))
+            nh, eta = (torch.from_numpy(d[k]).cuda() for k in ("n_h", "eta"))
+            t_start = time.perf_counter()
+
+            def on_output(t, r, i, n_oct=n_oct, tau=tau, t_start=t_start, d=d):
+                k = round((t - d["t0"]) / (d["outputs"][0] - d["t0"]))
+                if k % 10 == 0:
+                    z = 1.0 / (1.5 * d["H0"] * t) ** (2.0 / 3.0) - 1.0
+                    log(f"[cosmo] n={n_oct} tau={tau:g} z={z:.2f} steps={i} "
+                        f"r={r / synth.KPC:.2f} kpc(comoving) "
+                        f"wall={time.perf_counter() - t_start:.1f}s")
+
+            res = drv.run(E, x, nh, eta, d["outputs"], d["dt0"], t0=d["t0"],
+                          on_output=on_output, wall_cap_s=args.hii_cap_s)
+            drv.close()
+            t = np.array(res["times"])
+            rr = np.array(res["radii"])
+            r_true = np.array([_shapiro_giroux(tt, d["H0"], d["z0"], d["lambda"],
+                                               d["q0"], d["r_s0"]) for tt in t])
+            norm = d["r_s0"] * (1 + d["z0"])
+            err = float(math.sqrt(np.mean(((rr - r_true) / norm) ** 2))) if len(t) else None
+            cells = int(np.prod(d["shape"]))
+            cells_steps += cells * res["steps"]
+            wall_total += res["wall_s"]
+            z_reached = (1.0 / (1.5 * d["H0"] * t[-1]) ** (2.0 / 3.0) - 1.0) if len(t) else 4.0
+            row = {"octant": n_oct, "cells": list(d["shape"]), "tau_tol": tau,
+                   "z_reached": round(float(z_reached), 3), "capped": res["capped"],
+                   "steps": res["steps"],
+                   "dt_avg_myr": (float(t[-1] - d["t0"]) / res["steps"] / synth.MYR)
+                   if res["steps"] else None,
+                   "iters_per_step": res["iters"] / max(res["steps"], 1),
+                   "error_rms": err, "wall_s": round(res["wall_s"], 3),
+                   "ms_per_step": 1e3 * res["wall_s"] / max(res["steps"], 1)}
+            log(f"[cosmo] {json.dumps(row)}")
+            rows.append(row)
+    value = cells_steps / wall_total / 1e6 if wall_total > 0 else 0.0
+    total_steps = sum(r["steps"] for r in rows)
+    return _base(
+        "comoving radiation + chemistry, Einstein-de Sitter; small grids are "
+        "launch-latency bound, so no HBM roofline is reported",
+        value, 1e3 * wall_total / max(total_steps, 1), total_steps, 0,
+        "f64+f32" if prec else "f64",
+        {"workload": "cosmo_test2", "octant_meshes": meshes, "tau_tol": taus,
+         "z": [4.0, 0.0], "ndot": 5e46, "precision": args.hii_precision,
+         "rtol": 1e-8},
+        None, {"sweep": rows})

@@ -57,16 +57,18 @@ void fld_chem_default_params(fld_chem_params *p);
 
 /* One chemistry step of length dt >= 0 over every cell of the grid (only
  * its extents are used; each must be >= 1, the product < 2^31):
- *   E      in : radiation energy density after the radiation step
- *   n_h    in : hydrogen number density
+ *   E      in : comoving radiation energy density after the radiation step
+ *   n_h    in : comoving hydrogen number density
  *   x      in/out : ionized fraction, in [0, 1]
- *   kappa  out : sigma n_H (1 - x) with the new x
+ *   kappa  out : proper opacity sigma n_H (1 - x) / a^3 with the new x
+ *   a      : expansion factor, > 0 (comoving = proper * a^3, Sec. 2); the
+ *            rates use E / a^3 and n_h / a^3; a = 1 for a static problem
  * dt = 0 leaves x unchanged and only recomputes kappa.  x and kappa must
  * not overlap each other or the inputs. */
 fld_status fld_chem_h_update(const fld_grid *grid, const fld_chem_params *p,
                              void *hip_stream, const double *E,
                              const double *n_h, double *x, double *kappa,
-                             double dt);
+                             double dt, double a);
 
 /* sum_out[0] = sum of x over all cells (device pointer, one double), summed
  * in a fixed order so that the result is reproducible.  With V_cell the

@@ -137,7 +137,7 @@ def _load():
         "fld_profile_read": (i32, [i32, P(d), P(ctypes.c_int64)]),
         "fld_chem_default_params": (None, [P(ChemParams)]),
         "fld_chem_h_update": (i32, [P(Grid), P(ChemParams), vp, vp, vp, vp, vp,
-                                    d]),
+                                    d, d]),
         "fld_chem_ionized_sum": (i32, [P(Grid), vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -428,13 +428,15 @@ def fld_chem_default_params(**overrides) -> ChemParams:
 
 
 def fld_chem_h_update(grid: Grid, params: ChemParams, E, n_h, x, kappa, dt,
-                      stream=None):
-    """x and kappa updated in place over dt (see include/fld_chem.h)."""
+                      a=1.0, stream=None):
+    """x and kappa updated in place over dt at expansion factor a (see
+    include/fld_chem.h)."""
     n = grid.nx * grid.ny * grid.nz
     _check(_lib.fld_chem_h_update(ctypes.byref(grid), ctypes.byref(params),
                                   _stream_ptr(stream), _dptr(E, n, "E"),
                                   _dptr(n_h, n, "n_h"), _dptr(x, n, "x"),
-                                  _dptr(kappa, n, "kappa"), float(dt)),
+                                  _dptr(kappa, n, "kappa"), float(dt),
+                                  float(a)),
            "fld_chem_h_update")
 
 

@@ -27,17 +27,20 @@ constexpr int kSumBlock = 1024;
 __global__ __launch_bounds__(kChemBlock) void k_chem_h(
     const double *__restrict__ E, const double *__restrict__ nh,
     double *__restrict__ x, double *__restrict__ kappa, int64_t n, double h,
-    int substeps, double c, double sigma, double hnu, double alpha) {
+    int substeps, double c, double sigma, double hnu, double alpha,
+    double inv_a3) {
   const double c_sigma = c * sigma;
   for (int64_t i = (int64_t)blockIdx.x * kChemBlock + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kChemBlock) {
-    const double gamma = c_sigma * E[i] / hnu;  // photo-ionization rate
-    const double an = alpha * nh[i];
+    // proper densities from the comoving fields
+    const double np = nh[i] * inv_a3;
+    const double gamma = c_sigma * (E[i] * inv_a3) / hnu;  // photo-ionization
+    const double an = alpha * np;
     double xv = x[i];
     for (int s = 0; s < substeps; ++s)
       xv = (xv + h * gamma) / (1.0 + h * (gamma + an * xv));
     x[i] = xv;
-    kappa[i] = sigma * nh[i] * (1.0 - xv);
+    kappa[i] = sigma * np * (1.0 - xv);
   }
 }
 
@@ -87,7 +90,7 @@ void fld_chem_default_params(fld_chem_params *p) {
 fld_status fld_chem_h_update(const fld_grid *grid, const fld_chem_params *p,
                              void *hip_stream, const double *E,
                              const double *n_h, double *x, double *kappa,
-                             double dt) {
+                             double dt, double a) {
   using namespace fld;
   int64_t n = 0;
   if (!extents_ok(grid, &n) || !p || !E || !n_h || !x || !kappa)
@@ -99,6 +102,7 @@ fld_status fld_chem_h_update(const fld_grid *grid, const fld_chem_params *p,
       p->substeps > 1000000 || p->reserved != 0)
     return FLD_EINVAL;
   if (!(std::isfinite(dt) && dt >= 0.0)) return FLD_EINVAL;
+  if (!(std::isfinite(a) && a > 0.0)) return FLD_EINVAL;
   const int64_t bytes = n * (int64_t)sizeof(double);
   if (!disjoint(x, bytes, kappa, bytes) || !disjoint(x, bytes, E, bytes) ||
       !disjoint(x, bytes, n_h, bytes) || !disjoint(kappa, bytes, E, bytes) ||
@@ -109,7 +113,7 @@ fld_status fld_chem_h_update(const fld_grid *grid, const fld_chem_params *p,
   const int blocks = (int)(want < kChemMaxBlocks ? want : kChemMaxBlocks);
   FLD_LAUNCH(K_CHEM_H, k_chem_h, blocks, kChemBlock, s, E, n_h, x, kappa, n,
              dt / (double)p->substeps, p->substeps, p->c, p->sigma, p->hnu,
-             p->alpha_b);
+             p->alpha_b, 1.0 / (a * a * a));
   return hipGetLastError() == hipSuccess ? FLD_OK : FLD_EDEVICE;
 }
 

@@ -407,9 +407,10 @@ void Engine::fill_step(int p, const double *E, const double *kappa,
   S.Eout = nullptr;
   S.dt = dt;
   S.adot_a = adot / a;
-  S.idx = 1.0 / grids[p].dx;
-  S.idy = 1.0 / grids[p].dy;
-  S.idz = 1.0 / grids[p].dz;
+  // the mesh is comoving: the operator uses the proper separation a * dx
+  S.idx = 1.0 / (a * grids[p].dx);
+  S.idy = 1.0 / (a * grids[p].dy);
+  S.idz = 1.0 / (a * grids[p].dz);
   Scal &sc = h_sc[p];
   sc.live = 1;
   sc.tol2 = prm.rtol * prm.rtol;

@@ -109,14 +109,16 @@ def test_chem_defaults_and_validation(fld):
     E, nh, x, k = (ctypes.c_void_p(0x10000000 + i * 0x100000) for i in range(4))
     upd = fld._lib.fld_chem_h_update
 
-    def call(pp, dt=1.0, ptrs=(E, nh, x, k), gr=grid):
-        return upd(ctypes.byref(gr), ctypes.byref(pp), None, *ptrs, dt)
+    def call(pp, dt=1.0, ptrs=(E, nh, x, k), gr=grid, a=1.0):
+        return upd(ctypes.byref(gr), ctypes.byref(pp), None, *ptrs, dt, a)
 
     EINVAL = fld.FLD_EINVAL
     assert call(p, ptrs=(None, nh, x, k)) == EINVAL
     assert call(p, ptrs=(E, nh, x, None)) == EINVAL
     assert call(p, dt=-1.0) == EINVAL
     assert call(p, dt=float("nan")) == EINVAL
+    assert call(p, a=0.0) == EINVAL
+    assert call(p, a=float("inf")) == EINVAL
     for field, bad in (("substeps", 0), ("substeps", 2000000), ("c", 0.0),
                        ("hnu", 0.0), ("sigma", -1.0), ("alpha_b", float("inf")),
                        ("reserved", 1)):

@@ -363,3 +363,29 @@ def test_adaptive_cycle_switch(fld, oracle_mod):
     assert seen[0][0] == 1
     if seen[0][1] > 12:
         assert seen[1][0] == 2
+
+
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_comoving_step_matches_oracle(fld, oracle_mod, theta, prec):
+    """a != 1: the operator on the proper separation a dx of the comoving
+    cells plus adot/a; assembly and the solve against the oracle."""
+    log_case("comoving", theta=theta, prec=prec)
+    p = _problem((24, 32, 40), 23, theta=theta, dt_factor=0.1)
+    p["a"] = 0.3
+    p["adot"] = 0.3 * 0.05 / p["dt"]
+    S, prm = _solver(fld, p, precision=prec)
+    _assemble(S, p)
+    got = {k: host(v) for k, v in S.fld_get_system().items()}
+    O = oracle_problem(oracle_mod, p, prm)
+    diag, Ax, Ay, Az, b = O.system()
+    np.testing.assert_allclose(got["diag"], diag, rtol=1e-13)
+    for g, w in ((got["Tx"], Ax), (got["Ty"], Ay), (got["Tz"], Az)):
+        np.testing.assert_allclose(g, w, rtol=1e-13, atol=1e-16 * np.abs(w).max())
+    np.testing.assert_allclose(got["b"], b, rtol=0, atol=1e-12 * np.abs(b).max())
+    dE, st = S.solve()
+    dEo, _, _, _ = O.solve(tol=1e-13)
+    err = rel_l2(host(dE), dEo)
+    print(f"[comoving] iters={st['iters']} err={err:.2e}", flush=True)
+    assert st["status"] == 0
+    assert err <= GATE[prec]
