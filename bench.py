@@ -41,6 +41,7 @@ BYTES_PER_CELL = {
     "update_E": (24.0, 24.0),
     "vdown_fine": (41.0, 24.5),
     "vup_fine": (49.0, 40.5),
+    "warm_resid": (56.0, 56.0),
 }
 
 
@@ -58,7 +59,7 @@ def coarse_fraction(levels):
     return sum(8.0 ** -l for l in range(1, levels))
 
 
-STEP_KERNELS = ("assemble", "true_resid", "update_E")
+STEP_KERNELS = ("assemble", "true_resid", "update_E", "warm_resid")
 
 
 def step_bytes(counts, cells, prec_idx, levels):
@@ -81,7 +82,7 @@ def step_bytes(counts, cells, prec_idx, levels):
     return fixed, it
 
 
-def model_step_bytes(cells, iters, nu, prec_idx, levels, steps=1):
+def model_step_bytes(cells, iters, nu, prec_idx, levels, steps=1, warm=False):
     """Algorithmic bytes of `steps` steps of one problem taking `iters` PCG
     iterations in all, from the cycle structure:
     assembly and coarse operators, the true-residual check and E += dE once,
@@ -99,6 +100,8 @@ def model_step_bytes(cells, iters, nu, prec_idx, levels, steps=1):
     per_iter = fine + cf * coarse + B["spmv_p"] + B["update"]
     coarsen = 32.0 * (1.0 + cf - 8.0 ** -(levels - 1)) + (48.0 if prec_idx else 32.0) * cf
     fixed = B["assemble"] + coarsen + B["true_resid"] + B["update_E"]
+    if warm:  # the residual of the seeded initial guess
+        fixed += B["warm_resid"]
     return cells * (steps * fixed + iters * per_iter)
 
 
@@ -154,6 +157,10 @@ def parse():
     ap.add_argument("--tile-z", type=int, default=0)
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--fused-tile-z", type=int, default=0)
+    ap.add_argument("--warm-start", type=int, default=1,
+                    help="start each step's PCG from the previous dE")
+    ap.add_argument("--prolongation", type=int, default=2,
+                    help="mixed cycle: 0 constant, 1 trilinear, 2 automatic")
     ap.add_argument("--workload", default="many_sources",
                     choices=["many_sources", "single_source", "reionization",
                              "batch", "served", "hii_test1", "multigroup",
@@ -193,7 +200,9 @@ def run_form(fld, torch, p, prec, steps, warmup, args):
     def solver(graph):
         prm = fld.fld_default_params(p["c"], p["L_unit"], precision=prec,
                                      tile_z=args.tile_z, use_graph=graph,
-                                     fused_tile_z=args.fused_tile_z)
+                                     fused_tile_z=args.fused_tile_z,
+                                     warm_start=args.warm_start,
+                                     prolongation=args.prolongation)
         return fld.Solver(p["shape"], p["h"], prm)
 
     S = solver(args.graph)

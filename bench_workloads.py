@@ -225,7 +225,8 @@ def batch(args, fld, torch, synth, log):
         iters += [s["iters"] for s in sts]
         assert all(s["status"] == 0 for s in sts)
         step_bytes += sum(model_step_bytes(int(np.prod(shp)), s["iters"],
-                                           s["cycle_nu"], 1, s["levels"])
+                                           s["cycle_nu"], 1, s["levels"],
+                                           warm=True)
                           for shp, s in zip(shapes, sts))
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
@@ -452,7 +453,7 @@ def multigroup(args, fld, torch, synth, log):
         assert all(s["status"] == 0 for s in sts)
         iters += [s["iters"] for s in sts]
         sbytes += sum(model_step_bytes(n ** 3, s["iters"], s["cycle_nu"], 1,
-                                       s["levels"]) for s in sts)
+                                       s["levels"], warm=True) for s in sts)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     mg.close()

@@ -114,7 +114,12 @@ typedef struct fld_params {
                           after a cycle switch (default).  The FP64 cycle is
                           always piecewise constant with restriction = its
                           transpose, so it stays a symmetric preconditioner */
-  int32_t reserved[4];
+  int32_t warm_start;  /* fld_step / fld_batch_step: 1 (default) = start each
+                          step's PCG from the handle's previous successful dE
+                          scaled by the ratio of the step sizes (the residual
+                          b - A dE0 is formed first, the stopping rule is
+                          unchanged); 0 = start from dE = 0 */
+  int32_t reserved[3];
 } fld_params;
 
 typedef struct fld_stats {
@@ -143,7 +148,7 @@ typedef struct fld_server fld_server;
  * max_iter = 50, nu_pre = nu_post = 1, theta = 1, tau_tol = 1e-4, FP64,
  * coarse_scale = 0.5, max_dt_cuts = 8, graph replay on, cycle_switch = 12,
  * prolongation = 2 (trilinear in the mixed cycle once it has switched to
- * V(2,2)). */
+ * V(2,2)), warm_start = 1. */
 void fld_default_params(fld_params *p, double c, double L_unit);
 
 const char *fld_strerror(fld_status s);

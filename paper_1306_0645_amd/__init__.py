@@ -55,7 +55,7 @@ class Params(ctypes.Structure):
                 ("tile_z", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("fused_tile_z", ctypes.c_int32),
                 ("cycle_switch", ctypes.c_int32), ("prolongation", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("warm_start", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):

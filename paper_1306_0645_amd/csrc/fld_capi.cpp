@@ -76,6 +76,7 @@ void fld_default_params(fld_params *p, double c, double L_unit) {
   p->fused_tile_z = 0;
   p->cycle_switch = 12;
   p->prolongation = 2;
+  p->warm_start = 1;
 }
 
 const char *fld_strerror(fld_status s) {
@@ -129,6 +130,7 @@ fld_status fld_assemble(fld_handle *h, const double *E_n, const double *kappa,
   if (!h || !E_n || !kappa || !eta || !step_args_ok(dt, a, adot)) return FLD_EINVAL;
   Engine &e = h->eng;
   e.fill_step(0, E_n, kappa, eta, dt, a, adot);
+  e.prev_ok[0] = 0;  // a cold solve overwrites the warm-start guess
   int st = e.upload_sd_sc();
   if (st) return (fld_status)st;
   e.enqueue_assemble(e.all);

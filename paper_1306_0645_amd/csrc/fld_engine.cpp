@@ -41,6 +41,7 @@ bool params_ok(const fld_params &p) {
     return false;
   if (p.fused_tile_z < 0 || p.fused_tile_z > 256 || (p.fused_tile_z & 1)) return false;
   if (p.cycle_switch < 0) return false;
+  if (p.warm_start < 0 || p.warm_start > 1) return false;
   if (p.prolongation < 0 || p.prolongation > 2) return false;
   return true;
 }
@@ -283,6 +284,8 @@ int Engine::setup(const fld_params &p, hipStream_t s,
   h_pd.resize(np);
   h_sd.assign(np, StepDev{});
   h_sc.assign(np, Scal{});
+  prev_ok.assign(np, 0);
+  prev_h.assign(np, 0.0);
   for (int i = 0; i < np; ++i) {
     for (int l = 0; l < hier[i].levels; ++l) h_lv[(size_t)l * np + i] = mem[i].lv[l];
     h_pd[i] = mem[i].pd;
@@ -411,6 +414,7 @@ void Engine::fill_step(int p, const double *E, const double *kappa,
   S.idx = 1.0 / (a * grids[p].dx);
   S.idy = 1.0 / (a * grids[p].dy);
   S.idz = 1.0 / (a * grids[p].dz);
+  S.warm = 0.0;
   Scal &sc = h_sc[p];
   sc.live = 1;
   sc.tol2 = prm.rtol * prm.rtol;
@@ -535,6 +539,7 @@ int Engine::run_solve() {
 int Engine::run_steps(std::vector<Job> &jobs) {
   const int np = (int)jobs.size();
   std::vector<int> target(np, 0);  // 0: none, 1: caller E in place, 2: E_work
+  bool warm = false;
   for (;;) {
     bool any = false;
     for (int p = 0; p < np; ++p) {
@@ -544,11 +549,20 @@ int Engine::run_steps(std::vector<Job> &jobs) {
       any = true;
       j.h = std::min(j.h, j.dt - j.t);
       fill_step(p, j.in_work ? mem[p].E_work : j.E, j.kappa, j.eta, j.h, j.a, j.adot);
+      if (prm.warm_start && prev_ok[p] && prev_h[p] > 0.0) {
+        h_sd[p].warm = j.h / prev_h[p];
+        warm = true;
+      }
     }
     if (!any) break;
     int st = upload_sd_sc();
     if (st) return st;
     enqueue_assemble(all);
+    if (warm) {
+      launch_warm_resid(T, all.fine, stream);
+      launch_fin(T, FIN_WARM, mixed, stream);
+      warm = false;
+    }
     st = run_solve();
     if (st) return st;
     {
@@ -567,15 +581,19 @@ int Engine::run_steps(std::vector<Job> &jobs) {
       j.iters += h_sc[p].iter;
       j.restarts += h_sc[p].restarts;
       if (h_sc[p].phase == PH_DONE && h_sc[p].status == ST_OK) {
+        prev_ok[p] = 1;  // dE of this substep seeds the next one
+        prev_h[p] = j.h;
         const bool last = j.dt - (j.t + j.h) <= 1e-12 * j.dt;
         target[p] = (!j.in_work && last) ? 1 : 2;
         h_sd[p].Eout = target[p] == 1 ? j.E : mem[p].E_work;
         h_sc[p].live = 1;
         commit = true;
       } else if (j.cuts < prm.max_dt_cuts) {
+        prev_ok[p] = 0;
         j.h *= 0.1;
         j.cuts += 1;
       } else {
+        prev_ok[p] = 0;
         j.done = true;
         j.status = h_sc[p].status != ST_OK ? h_sc[p].status : ST_ENOCONV;
       }

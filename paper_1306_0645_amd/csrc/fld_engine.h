@@ -100,6 +100,10 @@ class Engine {
   bool fused = false;      // one-sweep fused V-cycle kernels
   int last_nu = 1;         // sweeps per side of the cycle used by the last solve
   bool switched = false;   // the adaptive switch moved the handle to V(2,2)
+  // per problem: x holds the dE of the last successful substep, of length
+  // prev_h (the warm start of the next step)
+  std::vector<char> prev_ok;
+  std::vector<double> prev_h;
 
   Tables T{};
   Tile *d_tiles = nullptr;

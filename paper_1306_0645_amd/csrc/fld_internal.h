@@ -61,7 +61,8 @@ struct StepDev {
   const double *E, *kappa, *eta;
   double *Eout;          // destination of E + dE (may equal E)
   double dt, adot_a;     // dt and adot/a
-  double idx, idy, idz;  // 1 / dx, 1 / dy, 1 / dz
+  double idx, idy, idz;  // 1 / (a dx), 1 / (a dy), 1 / (a dz)
+  double warm;           // > 0: start from warm * (previous dE); 0: from 0
 };
 
 // Per-problem PCG scalars (device resident, read back by the host).
@@ -113,7 +114,7 @@ enum : int {
   K_HALF_OUT, K_RESTRICT_F, K_RESTRICT_C, K_PROLONG_F, K_PROLONG_C,
   K_COARSE_SOLVE, K_SPMV_P, K_UPDATE, K_TRUE_RESID, K_APPLY, K_SET_R,
   K_UPDATE_E, K_VDOWN_F, K_VDOWN_C, K_VUP_F, K_VUP_C, K_CHEM_H, K_ION_SUM,
-  K_NUM
+  K_WARM_RESID, K_NUM
 };
 
 // Brackets one launch with hipEvents when its kernel id is selected.
@@ -153,6 +154,7 @@ void launch_coarse_solve(const Tables &T, int prec, hipStream_t s);
 void launch_spmv_p(const Tables &T, TileList L0, hipStream_t s);
 void launch_update(const Tables &T, TileList L0, hipStream_t s);
 void launch_true_resid(const Tables &T, TileList L0, hipStream_t s);
+void launch_warm_resid(const Tables &T, TileList L0, hipStream_t s);
 void launch_apply(const Tables &T, TileList L0, const double *u, double *out,
                   hipStream_t s);
 void launch_set_r(const Tables &T, TileList L0, const double *r, int prec,
@@ -172,7 +174,8 @@ enum : int {
   FIN_RR = 3,     // after the update: ||r||^2, convergence
   FIN_TRUE = 4,   // after the true residual: verify or restart
   FIN_STEP = 5,   // after E += dE: relative change and ||dE||^2
-  FIN_SETR = 6    // after loading an external r (preconditioner test)
+  FIN_SETR = 6,   // after loading an external r (preconditioner test)
+  FIN_WARM = 7    // after r = b - A x0 for a warm start
 };
 
 }  // namespace fld

@@ -117,7 +117,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
       }
       bv[cc] = b;
       rv[cc] = b;
-      xv[cc] = 0.0;
+      // initial guess: 0, or the previous step's dE scaled by the step ratio
+      xv[cc] = S.warm > 0.0 ? S.warm * xv[cc] : 0.0;
       bb += b * b;
       Em = Ec;
       Km = Kc;
@@ -548,6 +549,41 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Tables T, TileList TL) {
   write_partials(T, tid, rr, 0.0);
 }
 
+// r = b - A x0 for problems starting from a warm initial guess x0, partial
+// ||r||^2 (FIN_WARM then restarts their PCG from this residual)
+__global__ __launch_bounds__(kBlock) void k_warm_resid(Tables T, TileList TL) {
+  const int tid = get_tile_index(TL);
+  const Tile t = TL.base[tid];
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.live || !(T.sd[t.prob].warm > 0.0)) return;
+  const LevelDev L = T.lv[t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const Coef<double> C = coefs<double>(L);
+  const Col col = tile_col(t);
+  if (sc.phase == PH_DONE && sc.status == ST_OK) {
+    // b = 0: the solution is 0, whatever the guess
+    if (col.on)
+      for (int k = t.z0; k < t.z0 + t.tz; ++k)
+        for (int e = 0; e < t.cpt; ++e)
+          P.x[(k * L.ny + col.j) * L.nx + col.i + e] = 0.0;
+    return;
+  }
+  if (sc.phase != PH_ITER) return;
+  double rr = 0.0;
+  if (col.on) {
+    auto xv = [&](int q) { return P.x[q]; };
+    for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+      for (int e = 0; e < t.cpt; ++e) {
+        const Nb n = nbrs(col.i + e, col.j, k, L.nx, L.ny, L.nz);
+        const double r = P.b[n.c] - (C.d[n.c] * P.x[n.c] - offsum(C, n, xv));
+        P.r[n.c] = r;
+        rr += r * r;
+      }
+    }
+  }
+  write_partials(T, tid, rr, 0.0);
+}
+
 // out = A u (single problem, inspection entry point)
 __global__ __launch_bounds__(kBlock) void k_apply(Tables T, TileList TL,
                                                   const double *u, double *out) {
@@ -661,6 +697,9 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
     case FIN_STEP: part = sc.live != 0; break;
     case FIN_TRUE: part = sc.phase == PH_VERIFY; break;
     case FIN_SETR: part = true; break;
+    case FIN_WARM:
+      part = sc.live && T.sd[p].warm > 0.0 && sc.phase == PH_ITER;
+      break;
     default: part = sc.active != 0; break;
   }
   if (!part) return;
@@ -763,6 +802,13 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
       sc.phase = PH_ITER;
       set_scale(sc, P.n, mixed);
       break;
+    case FIN_WARM:
+      // PCG from the warm guess: same ||b||, a fresh search direction
+      sc.rr = a0;
+      sc.restart = 1;
+      if (!finite(a0)) fail(sc, ST_ENONFINITE);
+      set_scale(sc, P.n, mixed);
+      break;
   }
 }
 
@@ -775,7 +821,8 @@ static const char *kKernelNames[K_NUM] = {
     "half_coarse", "half_out", "resid_restrict_fine", "resid_restrict_coarse",
     "prolong_black_fine", "prolong_black_coarse", "coarse_solve", "spmv_p",
     "update", "true_resid", "apply", "set_r", "update_E", "vdown_fine",
-    "vdown_coarse", "vup_fine", "vup_coarse", "chem_h", "ionized_sum"};
+    "vdown_coarse", "vup_fine", "vup_coarse", "chem_h", "ionized_sum",
+    "warm_resid"};
 
 namespace prof {
 struct Rec {
@@ -927,6 +974,10 @@ void launch_set_r(const Tables &T, TileList L0, const double *r, int prec,
                   hipStream_t s) {
   (void)prec;
   if (L0.nblocks) LAUNCH(K_SET_R, k_set_r, L0.nblocks, kBlock, s, T, L0, r);
+}
+
+void launch_warm_resid(const Tables &T, TileList L0, hipStream_t s) {
+  if (L0.nblocks) LAUNCH(K_WARM_RESID, k_warm_resid, L0.nblocks, kBlock, s, T, L0);
 }
 
 void launch_update_E(const Tables &T, TileList L0, double floor, int copy_only,

@@ -239,8 +239,9 @@ def test_subcycling_matches_oracle_substeps(fld, oracle_mod):
         its.append(U.solve()[1]["iters"])
     print(f"[subcycle] iterations at dt, 0.1 dt: {its}", flush=True)
     assert its[1] < its[0]
+    # cold starts on both sides: the replay below solves each substep from 0
     cap = dict(max_iter=its[1], tau_tol=1e30, max_dt_cuts=60, mg_levels=1,
-               cycle_switch=0)
+               cycle_switch=0, warm_start=0)
     S, prm = _solver(fld, p, **cap)
     E = dev(p["E"])
     st = S.step(E, kap, eta, p["dt"])
@@ -389,3 +390,39 @@ def test_comoving_step_matches_oracle(fld, oracle_mod, theta, prec):
     print(f"[comoving] iters={st['iters']} err={err:.2e}", flush=True)
     assert st["status"] == 0
     assert err <= GATE[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_warm_start_steps_match_oracle(fld, oracle_mod, prec):
+    """fld_step seeds each step's PCG with the previous step's dE (scaled by
+    the step ratio).  Three successive steps (the last at half the step size)
+    must match the oracle's cold solves to the gates and need no more
+    iterations than cold starts; a following step with b = 0 (E = eta = 0)
+    must return exactly E = 0, not the seed."""
+    import torch
+    log_case("warm_start", prec=prec)
+    p = _problem((48, 40, 32), 31, dt_factor=0.2)
+    kap, eta = dev(p["kappa"]), dev(p["eta"])
+    W, prm = _solver(fld, p, precision=prec, warm_start=1)
+    C, _ = _solver(fld, p, precision=prec, warm_start=0)
+    Ew, Ec = dev(p["E"]), dev(p["E"])
+    En = p["E"].copy()
+    for k, f in enumerate((1.0, 1.0, 0.5)):
+        dt = f * p["dt"]
+        sw = W.step(Ew, kap, eta, dt)
+        sc = C.step(Ec, kap, eta, dt)
+        q = dict(p)
+        q["E"], q["dt"] = En, dt
+        dEo, _, _, _ = oracle_problem(oracle_mod, q, prm).solve(tol=1e-13)
+        En = En + dEo
+        err = rel_l2(host(Ew), En)
+        print(f"[warm] step {k}: iters warm {sw['iters']} cold {sc['iters']} "
+              f"err {err:.2e}", flush=True)
+        assert sw["status"] == 0 and sw["rel_resid"] <= prm.rtol
+        assert err <= GATE[prec]
+        if k > 0:
+            assert sw["iters"] <= sc["iters"]
+    zero = torch.zeros_like(Ew)
+    st = W.step(zero, kap, zero, p["dt"])
+    assert st["status"] == 0
+    assert torch.count_nonzero(zero).item() == 0
