@@ -159,6 +159,9 @@ def parse():
     ap.add_argument("--fused-tile-z", type=int, default=0)
     ap.add_argument("--warm-start", type=int, default=1,
                     help="start each step's PCG from the previous dE")
+    ap.add_argument("--tail-cells", type=int, default=0,
+                    help="coarse levels of at most this many cells run in "
+                         "one workgroup per V-cycle")
     ap.add_argument("--prolongation", type=int, default=2,
                     help="mixed cycle: 0 constant, 1 trilinear, 2 automatic")
     ap.add_argument("--workload", default="many_sources",
@@ -202,7 +205,8 @@ def run_form(fld, torch, p, prec, steps, warmup, args):
                                      tile_z=args.tile_z, use_graph=graph,
                                      fused_tile_z=args.fused_tile_z,
                                      warm_start=args.warm_start,
-                                     prolongation=args.prolongation)
+                                     prolongation=args.prolongation,
+                                     tail_cells=args.tail_cells)
         return fld.Solver(p["shape"], p["h"], prm)
 
     S = solver(args.graph)

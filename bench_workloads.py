@@ -385,7 +385,9 @@ def hii_test1(args, fld, torch, synth, log):
             d = synth.hii_test1(n_oct, t_end_myr=args.hii_t_end, n_out=50)
             prm = fld.fld_default_params(synth.C_LIGHT, d["L_unit"],
                                          precision=prec, tau_tol=tau,
-                                         e_floor=d["e_floor"])
+                                         e_floor=d["e_floor"],
+                                         tail_cells=args.tail_cells,
+                                         warm_start=args.warm_start)
             chem = fld.fld_chem_default_params()
             drv = IsothermalHII(d["shape"], d["h"], prm, chem)
             E, x = (torch.from_numpy(d[k]).cuda() for k in ("E", "x"))
@@ -521,7 +523,9 @@ def cosmo_test2(args, fld, torch, synth, log):
             d = synth.cosmo_test2(n_oct, z_end=0.0, n_out=50)
             prm = fld.fld_default_params(synth.C_LIGHT, d["L_unit"],
                                          precision=prec, tau_tol=tau,
-                                         e_floor=d["e_floor"])
+                                         e_floor=d["e_floor"],
+                                         tail_cells=args.tail_cells,
+                                         warm_start=args.warm_start)
             drv = IsothermalHII(d["shape"], d["h"], prm,
                                 fld.fld_chem_default_params(),
                                 expansion=eds_expansion(d["H0"]))

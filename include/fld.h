@@ -119,7 +119,13 @@ typedef struct fld_params {
                           scaled by the ratio of the step sizes (the residual
                           b - A dE0 is formed first, the stopping rule is
                           unchanged); 0 = start from dE = 0 */
-  int32_t reserved[3];
+  int32_t tail_cells;  /* the coarsest level is solved (Jacobi-CG in FP64) by
+                          one workgroup per problem; coarse levels of at most
+                          this many cells above it join that kernel (same
+                          sweeps, no per-level launches).  Default 0: only
+                          the coarsest level (measured no faster with more on
+                          gfx950) */
+  int32_t reserved[2];
 } fld_params;
 
 typedef struct fld_stats {
@@ -148,7 +154,7 @@ typedef struct fld_server fld_server;
  * max_iter = 50, nu_pre = nu_post = 1, theta = 1, tau_tol = 1e-4, FP64,
  * coarse_scale = 0.5, max_dt_cuts = 8, graph replay on, cycle_switch = 12,
  * prolongation = 2 (trilinear in the mixed cycle once it has switched to
- * V(2,2)), warm_start = 1. */
+ * V(2,2)), warm_start = 1, tail_cells = 0. */
 void fld_default_params(fld_params *p, double c, double L_unit);
 
 const char *fld_strerror(fld_status s);

@@ -55,7 +55,8 @@ class Params(ctypes.Structure):
                 ("tile_z", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("fused_tile_z", ctypes.c_int32),
                 ("cycle_switch", ctypes.c_int32), ("prolongation", ctypes.c_int32),
-                ("warm_start", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("warm_start", ctypes.c_int32), ("tail_cells", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):

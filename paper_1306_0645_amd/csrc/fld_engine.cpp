@@ -42,6 +42,7 @@ bool params_ok(const fld_params &p) {
   if (p.fused_tile_z < 0 || p.fused_tile_z > 256 || (p.fused_tile_z & 1)) return false;
   if (p.cycle_switch < 0) return false;
   if (p.warm_start < 0 || p.warm_start > 1) return false;
+  if (p.tail_cells < 0) return false;
   if (p.prolongation < 0 || p.prolongation > 2) return false;
   return true;
 }
@@ -67,6 +68,10 @@ Hier make_hier(const fld_grid &g, const fld_params &p) {
     h.tiles[l] = count_tiles(p, h.n[l][0], h.n[l][1], h.n[l][2]);
     h.ftiles[l] = count_fused_tiles(p, h.n[l][0], h.n[l][1], h.n[l][2]);
   }
+  // the tail: the coarsest level, and above it every level below the finest
+  // with at most tail_cells cells
+  h.tail = h.levels > 1 ? h.levels - 1 : 1;
+  while (h.tail > 1 && h.cells(h.tail - 1) <= (long long)p.tail_cells) --h.tail;
   return h;
 }
 
@@ -161,6 +166,7 @@ void carve_problem(Carver &cv, const Hier &h, const fld_params &p, ProbMem &m) {
     }
   }
   m.pd.levels = h.levels;
+  m.pd.tail = h.tail;
   m.pd.cs = cv.take<double>(4 * (size_t)h.cells(h.levels - 1));
   m.E_work = cv.take<double>((size_t)h.cells(0));
 }
@@ -334,11 +340,14 @@ int Engine::build_lists(const std::vector<char> &member, int slot, ListSet &out)
   auto make = [&](int level, auto pred) { return make_any(level, false, pred); };
   out.fine = make(0, [](int) { return true; });
   for (int l = 0; l < kMaxLevels; ++l) {
+    // per-level sweeps: every level above the tail (the single level of a
+    // one-level hierarchy)
     auto smoothed = [&](int i) {
-      return l < hier[i].levels - 1 || (hier[i].levels == 1 && l == 0);
+      return hier[i].levels == 1 ? l == 0 : l < hier[i].tail;
     };
     out.smooth[l] = make(l, smoothed);
     out.exist[l] = make(l, [&](int) { return l >= 1; });
+    out.down[l] = make(l, [&](int i) { return l >= 1 && l <= hier[i].tail; });
     out.fsm[l] = make_any(l, true, smoothed);
     out.fdn[l] = make_any(l, true, [&](int i) { return l < hier[i].levels - 1; });
   }
@@ -443,9 +452,9 @@ void Engine::enqueue_vcycle(const ListSet &ls) {
     for (int l = 1; l < Lmax; ++l) {
       if (ls.smooth[l].nblocks == 0) continue;
       launch_pre0(T, ls.smooth[l], l, prec, stream);
-      if (l + 1 < Lmax) launch_resid_restrict(T, ls.exist[l + 1], l + 1, prec, stream);
+      if (l + 1 < Lmax) launch_resid_restrict(T, ls.down[l + 1], l + 1, prec, stream);
     }
-    if (Lmax > 1) launch_coarse_solve(T, prec, stream);
+    if (Lmax > 1) launch_vtail(T, prec, 1, 1, tri, stream);
     for (int l = Lmax - 1; l >= 1; --l) {
       if (ls.smooth[l].nblocks == 0) continue;
       launch_prolong_black(T, ls.smooth[l], l, prec, tri, stream);
@@ -454,7 +463,7 @@ void Engine::enqueue_vcycle(const ListSet &ls) {
     launch_vup(T, ls.fsm[0], 0, prec, mixed, tri, stream);
     return;
   }
-  const TileList *smooth = ls.smooth, *exist = ls.exist;
+  const TileList *smooth = ls.smooth, *down = ls.down;
   for (int l = 0; l < Lmax; ++l) {
     if (smooth[l].nblocks == 0) continue;
     launch_pre0(T, smooth[l], l, prec, stream);
@@ -462,9 +471,9 @@ void Engine::enqueue_vcycle(const ListSet &ls) {
       launch_half(T, smooth[l], l, 0, prec, stream);
       launch_half(T, smooth[l], l, 1, prec, stream);
     }
-    if (l + 1 < Lmax) launch_resid_restrict(T, exist[l + 1], l + 1, prec, stream);
+    if (l + 1 < Lmax) launch_resid_restrict(T, down[l + 1], l + 1, prec, stream);
   }
-  if (Lmax > 1) launch_coarse_solve(T, prec, stream);
+  if (Lmax > 1) launch_vtail(T, prec, prm.nu_pre, prm.nu_post, tri, stream);
   for (int l = Lmax - 1; l >= 0; --l) {
     if (smooth[l].nblocks == 0) continue;
     launch_prolong_black(T, smooth[l], l, prec, tri, stream);
@@ -516,12 +525,13 @@ int Engine::run_solve() {
           HIP_TRY(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
           hipStream_t saved = stream;
           stream = cap_stream;
-          enqueue_iteration(all);
+          // one graph holds the K iterations between host checks
+          for (int k = 0; k < K; ++k) enqueue_iteration(all);
           stream = saved;
           HIP_TRY(hipStreamEndCapture(cap_stream, &graph));
           HIP_TRY(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
         }
-        for (int k = 0; k < K; ++k) HIP_TRY(hipGraphLaunch(gexec, stream));
+        HIP_TRY(hipGraphLaunch(gexec, stream));
       } else {
         for (int k = 0; k < K; ++k) enqueue_iteration(all);
       }
@@ -561,6 +571,7 @@ int Engine::run_steps(std::vector<Job> &jobs) {
     if (warm) {
       launch_warm_resid(T, all.fine, stream);
       launch_fin(T, FIN_WARM, mixed, stream);
+      launch_warm_revert(T, all.fine, stream);
       warm = false;
     }
     st = run_solve();

@@ -29,6 +29,7 @@ struct Carver {
 // multigrid hierarchy shape of one grid
 struct Hier {
   int levels = 0;
+  int tail = 1;                 // first level of the single-workgroup tail
   int n[kMaxLevels][3] = {};
   int tiles[kMaxLevels] = {};   // tiles per level
   int ftiles[kMaxLevels] = {};  // fused-cycle tiles per level
@@ -74,6 +75,7 @@ struct ListSet {
   TileList fine{}, smooth[kMaxLevels]{}, exist[kMaxLevels]{};
   TileList fsm[kMaxLevels]{};   // fused tiles of smoothed levels
   TileList fdn[kMaxLevels]{};   // fused tiles of smoothed levels with a coarser one
+  TileList down[kMaxLevels]{};  // levels restricted into from a per-level sweep
 };
 
 constexpr int kListSlots = 4;  // independent range regions (server phases)

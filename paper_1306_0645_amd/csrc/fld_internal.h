@@ -13,8 +13,8 @@
 namespace fld {
 
 constexpr int kBlock = 256;          // threads per tile block (4 wave64)
-constexpr int kCoarseBlock = 1024;   // threads of the coarsest-level solve
 constexpr int kFinBlock = 1024;      // threads of the per-problem finalize
+constexpr int kTailBlock = 1024;     // threads of the V-cycle tail kernel
 constexpr int kMaxLevels = 12;
 
 // Status values (same numbers as the public fld_status).
@@ -53,7 +53,7 @@ struct ProbDev {
   int levels;            // number of multigrid levels
   int t0, t1;            // range of this problem's tiles in the finest list
   int f0, f1;            // range of its fused-cycle finest tiles
-  int pad;
+  int tail;              // first level of the single-workgroup V-cycle tail
 };
 
 // Per-step inputs of one problem (uploaded by the host at each assembly).
@@ -75,7 +75,8 @@ struct Scal {
   int iter, max_iter, phase, status;
   int active, restart, pbuf, restarts;
   int live;              // takes part in the current assembly / update
-  int pad[3];
+  int cold;              // the warm guess did not reduce ||r||: start from 0
+  int pad[2];
 };
 
 // A tile: cells [x0, x0+tx) x [y0, y0+ty) x [z0, z0+tz) of one level of one
@@ -114,7 +115,7 @@ enum : int {
   K_HALF_OUT, K_RESTRICT_F, K_RESTRICT_C, K_PROLONG_F, K_PROLONG_C,
   K_COARSE_SOLVE, K_SPMV_P, K_UPDATE, K_TRUE_RESID, K_APPLY, K_SET_R,
   K_UPDATE_E, K_VDOWN_F, K_VDOWN_C, K_VUP_F, K_VUP_C, K_CHEM_H, K_ION_SUM,
-  K_WARM_RESID, K_NUM
+  K_WARM_RESID, K_WARM_REVERT, K_NUM
 };
 
 // Brackets one launch with hipEvents when its kernel id is selected.
@@ -150,11 +151,13 @@ void launch_resid_restrict(const Tables &T, TileList coarse, int lc, int prec,
                            hipStream_t s);
 void launch_prolong_black(const Tables &T, TileList L, int l, int prec,
                           int trilinear, hipStream_t s);
-void launch_coarse_solve(const Tables &T, int prec, hipStream_t s);
+void launch_vtail(const Tables &T, int prec, int nu_pre, int nu_post,
+                  int trilinear, hipStream_t s);
 void launch_spmv_p(const Tables &T, TileList L0, hipStream_t s);
 void launch_update(const Tables &T, TileList L0, hipStream_t s);
 void launch_true_resid(const Tables &T, TileList L0, hipStream_t s);
 void launch_warm_resid(const Tables &T, TileList L0, hipStream_t s);
+void launch_warm_revert(const Tables &T, TileList L0, hipStream_t s);
 void launch_apply(const Tables &T, TileList L0, const double *u, double *out,
                   hipStream_t s);
 void launch_set_r(const Tables &T, TileList L0, const double *r, int prec,

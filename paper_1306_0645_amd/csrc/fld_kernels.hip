@@ -366,42 +366,149 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(Tables T,
   }
 }
 
-// Coarsest level: Jacobi-preconditioned CG in FP64 by one workgroup per
-// problem, to a relative residual of 1e-12 (an effectively exact solve).
+// ---------------------------------------------------------------------------
+// Tail of the V-cycle, one workgroup per problem: the coarsest level's
+// Jacobi-CG solve and, above it, the levels from P.tail down (each small):
+// pre-smoothing and restriction down to the coarsest level, the solve, then
+// prolongation and post-smoothing back up to P.tail, in the order of the
+// per-level path (red/black, red = even i+j+k), separated by workgroup
+// barriers on data that stays in the L2.  (By default P.tail is the
+// coarsest level: on gfx950 one workgroup sweeping 16^3 or 32^3 levels is
+// no faster than the per-level launches it replaces.)
+// ---------------------------------------------------------------------------
+
 template <typename R>
-__global__ __launch_bounds__(kCoarseBlock) void k_coarse_solve(Tables T) {
-  const int p = blockIdx.x;
-  const Scal &sc = T.sc[p];
-  const ProbDev P = T.pd[p];
-  if (!sc.active || P.levels < 2) return;
+struct LvlView {
+  int nx, ny, nz, n;
+  Coef<R> C;
+  R *x, *f;
+  __device__ __forceinline__ void ijk(int c, int &i, int &j, int &k) const {
+    i = c % nx;
+    j = (c / nx) % ny;
+    k = c / (nx * ny);
+  }
+};
+
+template <typename R>
+__device__ __forceinline__ LvlView<R> lvl_view(const Tables &T, int l, int p) {
+  const LevelDev L = T.lv[l * T.nprob + p];
+  LvlView<R> v;
+  v.nx = L.nx;
+  v.ny = L.ny;
+  v.nz = L.nz;
+  v.n = L.n;
+  v.C = coefs<R>(L);
+  v.x = (R *)L.x;
+  v.f = (R *)L.f;
+  return v;
+}
+
+// first pre-sweep from x = 0 (red x = f/d, black from those red values)
+template <typename R>
+__device__ void tail_pre0(const LvlView<R> &V) {
+  for (int c = threadIdx.x; c < V.n; c += kTailBlock) {
+    int i, j, k;
+    V.ijk(c, i, j, k);
+    const Nb n = nbrs(i, j, k, V.nx, V.ny, V.nz);
+    R v;
+    if (((i + j + k) & 1) == 0) {
+      v = V.f[c] * recip(V.C.d[c]);
+    } else {
+      auto red = [&](int q) { return V.f[q] * recip(V.C.d[q]); };
+      v = (V.f[c] + offsum(V.C, n, red)) * recip(V.C.d[c]);
+    }
+    V.x[c] = v;
+  }
+}
+
+template <typename R>
+__device__ void tail_half(const LvlView<R> &V, int colour) {
+  auto xv = [&](int q) { return V.x[q]; };
+  for (int c = threadIdx.x; c < V.n; c += kTailBlock) {
+    int i, j, k;
+    V.ijk(c, i, j, k);
+    if (((i + j + k) & 1) != colour) continue;
+    const Nb n = nbrs(i, j, k, V.nx, V.ny, V.nz);
+    V.x[c] = (V.f[c] + offsum(V.C, n, xv)) * recip(V.C.d[c]);
+  }
+}
+
+// coarse right-hand side: fine residual summed over the 8 children
+template <typename R>
+__device__ void tail_restrict(const LvlView<R> &F, const LvlView<R> &Cv) {
+  auto xv = [&](int q) { return F.x[q]; };
+  for (int c = threadIdx.x; c < Cv.n; c += kTailBlock) {
+    int I, J, K;
+    Cv.ijk(c, I, J, K);
+    R acc = 0;
+    for (int cz = 0; cz < 2; ++cz)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          const Nb n = nbrs(2 * I + cx, 2 * J + cy, 2 * K + cz, F.nx, F.ny, F.nz);
+          acc += F.f[n.c] - (F.C.d[n.c] * F.x[n.c] - offsum(F.C, n, xv));
+        }
+    Cv.f[c] = acc;
+  }
+}
+
+// black half-sweep with the coarse-grid correction folded in (red
+// neighbours read as x + e(parent))
+template <typename R>
+__device__ void tail_prolong_black(const LvlView<R> &V, const LvlView<R> &Cv,
+                                   bool tri) {
+  for (int c = threadIdx.x; c < V.n; c += kTailBlock) {
+    int i, j, k;
+    V.ijk(c, i, j, k);
+    if (((i + j + k) & 1) != 1) continue;
+    const Nb n = nbrs(i, j, k, V.nx, V.ny, V.nz);
+    const int im = i == 0 ? V.nx - 1 : i - 1, ip = i == V.nx - 1 ? 0 : i + 1;
+    const int jm = j == 0 ? V.ny - 1 : j - 1, jp = j == V.ny - 1 ? 0 : j + 1;
+    const int km = k == 0 ? V.nz - 1 : k - 1, kp = k == V.nz - 1 ? 0 : k + 1;
+    auto par = [&](int a, int b2, int c2) {
+      return coarse_corr(Cv.x, a, b2, c2, Cv.nx, Cv.ny, Cv.nz, tri);
+    };
+    const R s = V.C.tx[c] * (V.x[n.xp] + par(ip, j, k)) +
+                V.C.tx[n.xm] * (V.x[n.xm] + par(im, j, k)) +
+                V.C.ty[c] * (V.x[n.yp] + par(i, jp, k)) +
+                V.C.ty[n.ym] * (V.x[n.ym] + par(i, jm, k)) +
+                V.C.tz[c] * (V.x[n.zp] + par(i, j, kp)) +
+                V.C.tz[n.zm] * (V.x[n.zm] + par(i, j, km));
+    V.x[c] = (V.f[c] + s) * recip(V.C.d[c]);
+  }
+}
+
+// coarsest level: Jacobi-preconditioned CG in FP64 to a relative residual of
+// 1e-12 (an effectively exact solve), scratch in P.cs
+template <typename R>
+__device__ void tail_coarse_solve(const Tables &T, const ProbDev &P, int p,
+                                  double *sh) {
   const int lc = P.levels - 1;
   const LevelDev L = T.lv[lc * T.nprob + p];
   const int n = L.n, nx = L.nx, ny = L.ny, nz = L.nz;
   double *xs = P.cs, *rs = P.cs + n, *ps = P.cs + 2 * n, *qs = P.cs + 3 * n;
   const R *f = (const R *)L.f;
   R *xo = (R *)L.x;
-  __shared__ double sh[kCoarseBlock / 64];
   double acc = 0.0;
-  for (int c = threadIdx.x; c < n; c += kCoarseBlock) {
+  for (int c = threadIdx.x; c < n; c += kTailBlock) {
     const double v = (double)f[c];
     rs[c] = v;
     xs[c] = 0.0;
     acc += v * v;
   }
-  const double bb = block_sum<kCoarseBlock / 64>(acc, sh);
+  const double bb = block_sum<kTailBlock / 64>(acc, sh);
   double rz_old = 1.0;
   if (bb > 0.0) {
     for (int it = 0; it < 1000; ++it) {
       acc = 0.0;
-      for (int c = threadIdx.x; c < n; c += kCoarseBlock) acc += rs[c] * rs[c] / L.diag[c];
-      const double rz = block_sum<kCoarseBlock / 64>(acc, sh);
+      for (int c = threadIdx.x; c < n; c += kTailBlock) acc += rs[c] * rs[c] / L.diag[c];
+      const double rz = block_sum<kTailBlock / 64>(acc, sh);
       const double beta = it == 0 ? 0.0 : rz / rz_old;
       rz_old = rz;
-      for (int c = threadIdx.x; c < n; c += kCoarseBlock)
+      for (int c = threadIdx.x; c < n; c += kTailBlock)
         ps[c] = rs[c] / L.diag[c] + (it == 0 ? 0.0 : beta * ps[c]);
       __syncthreads();
       acc = 0.0;
-      for (int c = threadIdx.x; c < n; c += kCoarseBlock) {
+      for (int c = threadIdx.x; c < n; c += kTailBlock) {
         const int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
         const Nb nb = nbrs(i, j, k, nx, ny, nz);
         const double q = L.diag[c] * ps[c] -
@@ -411,21 +518,61 @@ __global__ __launch_bounds__(kCoarseBlock) void k_coarse_solve(Tables T) {
         qs[c] = q;
         acc += ps[c] * q;
       }
-      const double pq = block_sum<kCoarseBlock / 64>(acc, sh);
+      const double pq = block_sum<kTailBlock / 64>(acc, sh);
       const double alpha = rz / pq;
       acc = 0.0;
-      for (int c = threadIdx.x; c < n; c += kCoarseBlock) {
+      for (int c = threadIdx.x; c < n; c += kTailBlock) {
         xs[c] += alpha * ps[c];
         const double r = rs[c] - alpha * qs[c];
         rs[c] = r;
         acc += r * r;
       }
-      const double rr = block_sum<kCoarseBlock / 64>(acc, sh);
+      const double rr = block_sum<kTailBlock / 64>(acc, sh);
       if (!(rr > 1e-24 * bb)) break;  // converged (or NaN: stop)
     }
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < n; c += kCoarseBlock) xo[c] = (R)xs[c];
+  for (int c = threadIdx.x; c < n; c += kTailBlock) xo[c] = (R)xs[c];
+}
+
+template <typename R>
+__global__ __launch_bounds__(kTailBlock) void k_vtail(Tables T, int nu_pre,
+                                                     int nu_post, int trilinear) {
+  const int p = blockIdx.x;
+  const Scal &sc = T.sc[p];
+  const ProbDev P = T.pd[p];
+  if (!sc.active || P.levels < 2) return;
+  __shared__ double sh[kTailBlock / 64];
+  const int lt = P.tail, lc = P.levels - 1;
+  const bool tri = trilinear != 0;
+  for (int l = lt; l < lc; ++l) {
+    const LvlView<R> V = lvl_view<R>(T, l, p);
+    tail_pre0(V);
+    __syncthreads();
+    for (int s2 = 1; s2 < nu_pre; ++s2) {
+      tail_half(V, 0);
+      __syncthreads();
+      tail_half(V, 1);
+      __syncthreads();
+    }
+    tail_restrict(V, lvl_view<R>(T, l + 1, p));
+    __syncthreads();
+  }
+  tail_coarse_solve<R>(T, P, p, sh);
+  __syncthreads();
+  for (int l = lc - 1; l >= lt; --l) {
+    const LvlView<R> V = lvl_view<R>(T, l, p);
+    tail_prolong_black(V, lvl_view<R>(T, l + 1, p), tri);
+    __syncthreads();
+    tail_half(V, 0);
+    __syncthreads();
+    for (int s2 = 1; s2 < nu_post; ++s2) {
+      tail_half(V, 1);
+      __syncthreads();
+      tail_half(V, 0);
+      __syncthreads();
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -582,6 +729,25 @@ __global__ __launch_bounds__(kBlock) void k_warm_resid(Tables T, TileList TL) {
     }
   }
   write_partials(T, tid, rr, 0.0);
+}
+
+// x = 0, r = b for problems whose warm guess was rejected by FIN_WARM
+__global__ __launch_bounds__(kBlock) void k_warm_revert(Tables T, TileList TL) {
+  const Tile t = get_tile(TL);
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.live || !(T.sd[t.prob].warm > 0.0) || sc.phase != PH_ITER || !sc.cold)
+    return;
+  const LevelDev L = T.lv[t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const Col col = tile_col(t);
+  if (!col.on) return;
+  for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+    const int c0 = (k * L.ny + col.j) * L.nx + col.i;
+    for (int e = 0; e < t.cpt; ++e) {
+      P.x[c0 + e] = 0.0;
+      P.r[c0 + e] = P.b[c0 + e];
+    }
+  }
 }
 
 // out = A u (single problem, inspection entry point)
@@ -803,10 +969,11 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
       set_scale(sc, P.n, mixed);
       break;
     case FIN_WARM:
-      // PCG from the warm guess: same ||b||, a fresh search direction
-      sc.rr = a0;
+      // PCG from the warm guess (same ||b||, a fresh search direction), or
+      // from 0 if the guess does not reduce the residual (k_warm_revert)
       sc.restart = 1;
-      if (!finite(a0)) fail(sc, ST_ENONFINITE);
+      sc.cold = !(a0 < sc.bb);
+      if (!sc.cold) sc.rr = a0;
       set_scale(sc, P.n, mixed);
       break;
   }
@@ -822,7 +989,7 @@ static const char *kKernelNames[K_NUM] = {
     "prolong_black_fine", "prolong_black_coarse", "coarse_solve", "spmv_p",
     "update", "true_resid", "apply", "set_r", "update_E", "vdown_fine",
     "vdown_coarse", "vup_fine", "vup_coarse", "chem_h", "ionized_sum",
-    "warm_resid"};
+    "warm_resid", "warm_revert"};
 
 namespace prof {
 struct Rec {
@@ -947,11 +1114,15 @@ void launch_prolong_black(const Tables &T, TileList L, int l, int prec,
   }
 }
 
-void launch_coarse_solve(const Tables &T, int prec, hipStream_t s) {
+void launch_vtail(const Tables &T, int prec, int nu_pre, int nu_post,
+                  int trilinear, hipStream_t s) {
   if (!T.nprob) return;
-  if (prec) LAUNCH(K_COARSE_SOLVE, (k_coarse_solve<float>), T.nprob, kCoarseBlock, s, T);
-  else LAUNCH(K_COARSE_SOLVE, (k_coarse_solve<double>), T.nprob, kCoarseBlock, s, T);
+  if (prec)
+    LAUNCH(K_COARSE_SOLVE, (k_vtail<float>), T.nprob, kTailBlock, s, T, nu_pre, nu_post, trilinear);
+  else
+    LAUNCH(K_COARSE_SOLVE, (k_vtail<double>), T.nprob, kTailBlock, s, T, nu_pre, nu_post, trilinear);
 }
+
 
 void launch_spmv_p(const Tables &T, TileList L0, hipStream_t s) {
   if (L0.nblocks) LAUNCH(K_SPMV_P, k_spmv_p, L0.nblocks, kBlock, s, T, L0);
@@ -978,6 +1149,10 @@ void launch_set_r(const Tables &T, TileList L0, const double *r, int prec,
 
 void launch_warm_resid(const Tables &T, TileList L0, hipStream_t s) {
   if (L0.nblocks) LAUNCH(K_WARM_RESID, k_warm_resid, L0.nblocks, kBlock, s, T, L0);
+}
+
+void launch_warm_revert(const Tables &T, TileList L0, hipStream_t s) {
+  if (L0.nblocks) LAUNCH(K_WARM_REVERT, k_warm_revert, L0.nblocks, kBlock, s, T, L0);
 }
 
 void launch_update_E(const Tables &T, TileList L0, double floor, int copy_only,
