@@ -142,6 +142,24 @@ def measured_traffic(kernel, form):
     return None
 
 
+def copy_bandwidth(torch, n=1 << 27, reps=5):
+    """Measured HBM bandwidth of a plain streaming kernel (y = x + 0 over n
+    doubles: n*8 bytes read and written), best of reps, for context beside
+    the vendor peak."""
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    best = float("inf")
+    for _ in range(reps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        torch.add(x, 0.0, out=y)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) * 1e-3)
+    del x, y
+    return 2 * n * 8 / best / 1e9
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -280,10 +298,20 @@ def cpu_baseline(p):
     t0 = time.perf_counter()
     _, st, it, rel = O.solve(tol=1e-8, max_iter=1000)
     sec = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": p["E"].size / sec / 1e6, "unit": "Mcell-updates/s",
             "cores": 1, "kind": "oracle",
             "sample": f"one {p['shape'][0]}^3 step (limiter assembly + Jacobi-PCG "
-                      f"to 1e-8, {it} iterations, {sec:.1f} s), single thread"}
+                      f"to 1e-8, {it} iterations, {sec:.1f} s), single thread",
+            "host_cpu": cpu, "host_threads": os.cpu_count()}
 
 
 def main():
@@ -317,6 +345,8 @@ def main():
         forms[name] = run_form(fld, torch, p, prec, args.steps, args.warmup, args)
         log(f"[bench] {name}: {json.dumps(forms[name])}")
     head = forms.get("mixed") or forms[list(forms)[0]]
+    copy_bw = copy_bandwidth(torch)
+    log(f"[bench] streaming copy: {copy_bw:.0f} GB/s")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on one step")
@@ -354,6 +384,7 @@ def main():
             "bytes_per_cell": round(head["step_bytes_per_cell"], 1),
             "achieved": round(head["step_GBps"], 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(head["step_GBps"] / HBM_PEAK_GBS, 4)},
+        "hbm_copy_GBps": round(copy_bw, 1),
         "cpu_baseline": cpu,
         "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                       for kk, vv in v.items()} for k, v in forms.items()},

@@ -165,6 +165,7 @@ void carve_problem(Carver &cv, const Hier &h, const fld_params &p, ProbMem &m) {
       }
     }
   }
+  m.pd.xh = cv.take<double>((size_t)h.cells(0));
   m.pd.levels = h.levels;
   m.pd.tail = h.tail;
   m.pd.cs = cv.take<double>(4 * (size_t)h.cells(h.levels - 1));
@@ -292,6 +293,7 @@ int Engine::setup(const fld_params &p, hipStream_t s,
   h_sc.assign(np, Scal{});
   prev_ok.assign(np, 0);
   prev_h.assign(np, 0.0);
+  prev_h2.assign(np, 0.0);
   for (int i = 0; i < np; ++i) {
     for (int l = 0; l < hier[i].levels; ++l) h_lv[(size_t)l * np + i] = mem[i].lv[l];
     h_pd[i] = mem[i].pd;
@@ -424,6 +426,7 @@ void Engine::fill_step(int p, const double *E, const double *kappa,
   S.idy = 1.0 / (a * grids[p].dy);
   S.idz = 1.0 / (a * grids[p].dz);
   S.warm = 0.0;
+  S.w1 = S.w2 = 0.0;
   Scal &sc = h_sc[p];
   sc.live = 1;
   sc.tol2 = prm.rtol * prm.rtol;
@@ -559,8 +562,20 @@ int Engine::run_steps(std::vector<Job> &jobs) {
       any = true;
       j.h = std::min(j.h, j.dt - j.t);
       fill_step(p, j.in_work ? mem[p].E_work : j.E, j.kappa, j.eta, j.h, j.a, j.adot);
-      if (prm.warm_start && prev_ok[p] && prev_h[p] > 0.0) {
-        h_sd[p].warm = j.h / prev_h[p];
+      if (prm.warm_start && prev_ok[p] >= 1 && prev_h[p] > 0.0) {
+        // dE is about h times the mean rate over the step: scale the last
+        // dE, or extrapolate the rate linearly from the last two
+        const double h1 = prev_h[p], r1 = j.h / h1;
+        StepDev &S = h_sd[p];
+        S.warm = 1.0;
+        S.w1 = r1;
+        S.w2 = 0.0;
+        if (prev_ok[p] >= 2 && prev_h2[p] > 0.0) {
+          const double h0 = prev_h2[p];
+          const double tau = (h1 + j.h) / (h0 + h1);
+          S.w1 = r1 * (1.0 + tau);
+          S.w2 = -(j.h / h0) * tau;
+        }
         warm = true;
       }
     }
@@ -592,7 +607,10 @@ int Engine::run_steps(std::vector<Job> &jobs) {
       j.iters += h_sc[p].iter;
       j.restarts += h_sc[p].restarts;
       if (h_sc[p].phase == PH_DONE && h_sc[p].status == ST_OK) {
-        prev_ok[p] = 1;  // dE of this substep seeds the next one
+        // dE of this substep seeds the next one; with a warm start the one
+        // before was moved into P.xh by the assembly
+        prev_ok[p] = h_sd[p].warm > 0.0 ? 2 : 1;
+        prev_h2[p] = prev_h[p];
         prev_h[p] = j.h;
         const bool last = j.dt - (j.t + j.h) <= 1e-12 * j.dt;
         target[p] = (!j.in_work && last) ? 1 : 2;

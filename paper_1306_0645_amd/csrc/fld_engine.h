@@ -102,10 +102,11 @@ class Engine {
   bool fused = false;      // one-sweep fused V-cycle kernels
   int last_nu = 1;         // sweeps per side of the cycle used by the last solve
   bool switched = false;   // the adaptive switch moved the handle to V(2,2)
-  // per problem: x holds the dE of the last successful substep, of length
-  // prev_h (the warm start of the next step)
+  // per problem warm-start history: prev_ok = 0 none, 1 x holds the dE of
+  // the last successful substep (length prev_h), 2 also P.xh the one
+  // before it (length prev_h2)
   std::vector<char> prev_ok;
-  std::vector<double> prev_h;
+  std::vector<double> prev_h, prev_h2;
 
   Tables T{};
   Tile *d_tiles = nullptr;

@@ -49,6 +49,7 @@ struct LevelDev {
 struct ProbDev {
   int nx, ny, nz, n;
   double *x, *r, *z, *p0, *p1, *q, *b;
+  double *xh;            // dE of the step before the last (warm-start history)
   double *cs;            // coarsest-level CG scratch: 4 * n_coarsest doubles
   int levels;            // number of multigrid levels
   int t0, t1;            // range of this problem's tiles in the finest list
@@ -62,7 +63,8 @@ struct StepDev {
   double *Eout;          // destination of E + dE (may equal E)
   double dt, adot_a;     // dt and adot/a
   double idx, idy, idz;  // 1 / (a dx), 1 / (a dy), 1 / (a dz)
-  double warm;           // > 0: start from warm * (previous dE); 0: from 0
+  double warm;           // 1: warm start x0 = w1 dE(n) + w2 dE(n-1); 0: x0 = 0
+  double w1, w2;
 };
 
 // Per-problem PCG scalars (device resident, read back by the host).

@@ -117,8 +117,15 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
       }
       bv[cc] = b;
       rv[cc] = b;
-      // initial guess: 0, or the previous step's dE scaled by the step ratio
-      xv[cc] = S.warm > 0.0 ? S.warm * xv[cc] : 0.0;
+      // initial guess: 0, or extrapolated from the last two steps' dE (x
+      // holds the last, P.xh the one before; the last moves into P.xh)
+      if (S.warm > 0.0) {
+        const double xl = xv[cc];
+        xv[cc] = S.w1 * xl + (S.w2 != 0.0 ? S.w2 * P.xh[cc] : 0.0);
+        P.xh[cc] = xl;
+      } else {
+        xv[cc] = 0.0;
+      }
       bb += b * b;
       Em = Ec;
       Km = Kc;
