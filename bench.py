@@ -29,7 +29,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # once; neighbours and 1/8-size coarse arrays included where they are read.
 # (FP64 V-cycle, FP32 V-cycle)
 BYTES_PER_CELL = {
-    "assemble": (80.0, 96.0),
+    # assembly with a warm start: the guess x and its history xh are read
+    # and written besides E, kappa, eta in and the system out
+    "assemble": (104.0, 120.0),
     "spmv_p": (64.0, 64.0),
     "update": (48.0, 48.0),
     "pre0_fine": (48.0, 28.0),
@@ -102,6 +104,8 @@ def model_step_bytes(cells, iters, nu, prec_idx, levels, steps=1, warm=False):
     fixed = B["assemble"] + coarsen + B["true_resid"] + B["update_E"]
     if warm:  # the residual of the seeded initial guess
         fixed += B["warm_resid"]
+    else:     # a cold assembly neither reads the guess nor keeps history
+        fixed -= 24.0
     return cells * (steps * fixed + iters * per_iter)
 
 
