@@ -6,7 +6,9 @@ file.
 
 Candidates: tile depth in {0 (automatic), 1, 2, 4, 8} x (nu_pre, nu_post) in
 {(1, 1), (2, 2)}.  (1, 1) runs the fused finest-level passes; (2, 2) the
-per-half-sweep kernels.
+per-half-sweep kernels.  Candidates are timed with cold starts: every timed
+run restarts from the same fields, where a warm start would be seeded with
+the very answer of the previous run.
 """
 from __future__ import annotations
 
@@ -69,11 +71,13 @@ def tune_batch(shapes, hs, base: "fld.Params", fields, dts, reps=2,
     key = _key(shapes, base)
     cache = _load(cache_path)
 
-    def make(c):
+    def make(c, warm=None):
         p = fld.Params()
         ctypes_copy(p, base)
         for k, v in c.items():
             setattr(p, k, v)
+        if warm is not None:
+            p.warm_start = warm
         return p
 
     if key in cache:
@@ -81,7 +85,7 @@ def tune_batch(shapes, hs, base: "fld.Params", fields, dts, reps=2,
         return make(c), {"cached": True, "best": c, "key": key}
     results = []
     for c in CANDIDATES:
-        t = _time_batch(shapes, hs, make(c), fields, dts, reps)
+        t = _time_batch(shapes, hs, make(c, warm=0), fields, dts, reps)
         results.append((t, c))
         if log:
             log(f"[autotune] {c} -> {t * 1e3:.2f} ms")
