@@ -106,7 +106,7 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it with "
-            "`python -m paper_1306_0645_amd.build` (hipcc, gfx950)")
+            "`python paper_1306_0645_amd/build.py` (hipcc, gfx950)")
     lib = ctypes.CDLL(LIB_PATH)
     P, vp, i32, u64 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64
     d, sz = ctypes.c_double, ctypes.c_size_t

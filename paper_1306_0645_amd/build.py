@@ -1,6 +1,6 @@
 """Build the HIP library ``libfld.so`` for gfx950 in-tree.
 
-Usage: ``python -m paper_1306_0645_amd.build`` (or ``__graft_entry__.build()``).
+Usage: ``python paper_1306_0645_amd/build.py`` (or ``__graft_entry__.build()``).
 Every source is compiled with hipcc for gfx950 only, without packed FP32
 instructions, then linked into one shared library beside this file.
 """
