@@ -454,3 +454,30 @@ def test_single_workgroup_tail_matches_oracle(fld, oracle_mod, prec, nu):
         Mv = S.fld_precondition(v)
         a, b = float((v * Mu).sum()), float((u * Mv).sum())
         assert abs(a - b) <= 1e-12 * max(abs(a), abs(b))
+
+
+def test_largest_grid_1024(fld, oracle_mod):
+    """1024^3 = 2^30 cells (the C-ABI takes up to 2^31 - 1; a 132 GiB mixed
+    workspace), one mixed step of the many-source recipe: the solver's
+    residual meets the tolerance and the oracle's residual at 100 000
+    sampled cells agrees."""
+    import torch
+    log_case("grid_1024", prec=1)
+    n = 1024
+    q = synth.t_problem((n, n, n), 1.5, 64, (1e47, 1e50), 7, 0, "cuda")
+    prm = fld.fld_default_params(q["c"], q["L_unit"], precision=1)
+    S = fld.Solver(q["shape"], q["h"], prm)
+    S.assemble(q["E"], q["kappa"], q["eta"], q["dt"])
+    dE, st = S.solve()
+    torch.cuda.synchronize()
+    print(f"[grid_1024] iters={st['iters']} rel={st['rel_resid']:.2e}", flush=True)
+    assert st["status"] == 0 and st["rel_resid"] <= prm.rtol
+    rng = np.random.default_rng(1024)
+    cells = rng.choice(n ** 3, size=100000, replace=False).astype(np.int64)
+    O = oracle_mod.Problem(host(q["E"]), host(q["kappa"]), host(q["eta"]), q["h"],
+                           q["c"], prm.d_max, prm.r_min, q["dt"])
+    res, rhs = O.residual_at(host(dE), cells)
+    ratio = np.linalg.norm(res) / np.linalg.norm(rhs)
+    print(f"[grid_1024] sampled_rel={ratio:.2e}", flush=True)
+    assert ratio <= 10 * prm.rtol
+    S.close()
