@@ -55,6 +55,31 @@ def test_batch_equals_single_and_oracle(fld, oracle_mod, prec):
         assert rel_l2(host(E), p["E"] + dEo) <= (1e-6 if prec == 0 else 1e-5)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_warm_steps_equal_single(fld, oracle_mod, prec):
+    """Three successive steps (the warm start keeps a per-problem history):
+    every problem of the batch stays bit-identical to its single-problem
+    handle and within the gates of the oracle's cold steps."""
+    log_case("batch_warm", prec=prec)
+    ps = _probs(seed0=80)
+    prm = params(fld, ps[0], precision=prec, cycle_switch=0, warm_start=1)
+    B = fld.Batch([p["shape"] for p in ps], [p["h"] for p in ps], prm)
+    Ks = [dev(p["kappa"]) for p in ps]
+    Hs = [dev(p["eta"]) for p in ps]
+    Es = [dev(p["E"]) for p in ps]
+    solos = [fld.Solver(p["shape"], p["h"], prm) for p in ps]
+    E1 = [dev(p["E"]) for p in ps]
+    for k in range(3):
+        sts = B.step(Es, Ks, Hs, [p["dt"] for p in ps])
+        for S, E, K, H, p, st in zip(solos, E1, Ks, Hs, ps, sts):
+            st1 = S.step(E, K, H, p["dt"])
+            assert st["status"] == 0 and st["iters"] == st1["iters"]
+    for p, E, Es1 in zip(ps, Es, E1):
+        assert np.array_equal(host(E), host(Es1))
+        Eo = _oracle_steps(oracle_mod, p, prm, 3)
+        assert rel_l2(host(E), Eo) <= (1e-6 if prec == 0 else 1e-5)
+
+
 def _oracle_steps(oracle_mod, p, prm, n):
     E = p["E"].copy()
     for _ in range(n):
