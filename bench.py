@@ -181,6 +181,9 @@ def parse():
     ap.add_argument("--fused-tile-z", type=int, default=0)
     ap.add_argument("--warm-start", type=int, default=1,
                     help="start each step's PCG from the previous dE")
+    ap.add_argument("--check-every", type=int, default=0,
+                    help="PCG iterations between host convergence reads "
+                         "(0: automatic)")
     ap.add_argument("--tail-cells", type=int, default=0,
                     help="coarse levels of at most this many cells run in "
                          "one workgroup per V-cycle")
@@ -228,7 +231,8 @@ def run_form(fld, torch, p, prec, steps, warmup, args):
                                      fused_tile_z=args.fused_tile_z,
                                      warm_start=args.warm_start,
                                      prolongation=args.prolongation,
-                                     tail_cells=args.tail_cells)
+                                     tail_cells=args.tail_cells,
+                                     check_every=args.check_every)
         return fld.Solver(p["shape"], p["h"], prm)
 
     S = solver(args.graph)
