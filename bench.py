@@ -322,6 +322,37 @@ def cpu_baseline(p):
             "host_cpu": cpu, "host_threads": os.cpu_count()}
 
 
+_CPU_PROBLEM = None
+
+
+def _oracle_step_seconds(_):
+    import oracle
+    p = _CPU_PROBLEM
+    dmax, rmin = oracle.limits(p["c"], p["L_unit"])
+    O = oracle.Problem(p["E"], p["kappa"], p["eta"], p["h"], p["c"], dmax, rmin,
+                       p["dt"], p["theta"], p["a"], p["adot"])
+    t0 = time.perf_counter()
+    O.solve(tol=1e-8, max_iter=1000)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_all_cores(p, procs):
+    """The same oracle step solved by `procs` single-threaded processes at
+    once, one per host core (the oracle itself is serial); forked before the
+    GPU is touched.  Throughput = procs x cells / the slowest process."""
+    import multiprocessing as mp
+    global _CPU_PROBLEM
+    _CPU_PROBLEM = p
+    with mp.get_context("fork").Pool(procs) as pool:
+        secs = pool.map(_oracle_step_seconds, range(procs))
+    _CPU_PROBLEM = None
+    return {"value": procs * p["E"].size / max(secs) / 1e6,
+            "unit": "Mcell-updates/s", "cores": procs, "kind": "oracle",
+            "sample": f"{procs} concurrent single-threaded solves of the same "
+                      f"{p['shape'][0]}^3 step to 1e-8 ({max(secs):.1f} s for "
+                      f"the slowest)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -346,6 +377,12 @@ def main():
         del x, y
     log(f"[bench] generating the {args.n}^3 many-source workload")
     p = synth.many_sources(args.n)
+    cpu_all = None
+    if not args.no_cpu_baseline and not args.copy_probe:
+        # the host share of one GPU is 16 cores, whatever os.cpu_count() says
+        procs = max(1, min(16, os.cpu_count() or 1))
+        log(f"[bench] timing the oracle on {procs} cores (before the GPU starts)")
+        cpu_all = cpu_baseline_all_cores(p, procs)
     forms = {}
     for name in args.forms.split(","):
         prec = fld.FLD_PREC_MIXED if name == "mixed" else fld.FLD_PREC_FP64
@@ -394,6 +431,7 @@ def main():
             "unit": "GB/s", "frac": round(head["step_GBps"] / HBM_PEAK_GBS, 4)},
         "hbm_copy_GBps": round(copy_bw, 1),
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_all,
         "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                       for kk, vv in v.items()} for k, v in forms.items()},
     }
