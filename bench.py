@@ -44,6 +44,14 @@ BYTES_PER_CELL = {
     "vdown_fine": (41.0, 24.5),
     "vup_fine": (49.0, 40.5),
     "warm_resid": (56.0, 56.0),
+    # weighted-Jacobi smoother: first sweep from zero (diag, f, x out), a
+    # sweep (4 coefficient arrays, x in, f, x out), the last finest sweep
+    # (writes z; the mixed form also reads the old z), x + P e (x, e at 1/8,
+    # out)
+    "jacobi0_fine": (24.0, 16.0),
+    "jacobi_fine": (56.0, 32.0),
+    "jacobi_out": (56.0, 44.0),
+    "prolong_add_fine": (17.0, 8.5),
 }
 
 
@@ -54,6 +62,9 @@ BYTES_PER_CELL = {
 # reads 4 FP64 arrays of level l-1 and writes 4 of level l (plus 4 FP32 copies
 # in mixed mode).
 COARSE_CYCLE_BYTES = (48.0 + 49.0 + 57.0 + 56.0, 28.0 + 28.5 + 32.5 + 32.0)
+# the same under the weighted-Jacobi smoother: first sweep, residual and
+# restriction, x + P e, one sweep
+COARSE_CYCLE_BYTES_JACOBI = (24.0 + 49.0 + 17.0 + 56.0, 12.0 + 28.5 + 8.5 + 28.0)
 
 
 def coarse_fraction(levels):
@@ -79,6 +90,7 @@ def step_bytes(counts, cells, prec_idx, levels):
     cf = coarse_fraction(levels)
     cycles = counts.get("vdown_fine", 0) or counts.get("pre0_fine", 0)
     it += cycles * cf * COARSE_CYCLE_BYTES[prec_idx] * cells
+    it += counts.get("jacobi0_fine", 0) * cf * COARSE_CYCLE_BYTES_JACOBI[prec_idx] * cells
     coarsen = 32.0 * (1.0 + cf - 8.0 ** -(levels - 1)) + (48.0 if prec_idx else 32.0) * cf
     fixed += counts.get("assemble", 0) * coarsen * cells
     return fixed, it
@@ -187,6 +199,9 @@ def parse():
     ap.add_argument("--tail-cells", type=int, default=0,
                     help="coarse levels of at most this many cells run in "
                          "one workgroup per V-cycle")
+    ap.add_argument("--smoother", type=int, default=0,
+                    help="multigrid smoother: 0 red/black Gauss-Seidel, "
+                         "1 weighted Jacobi")
     ap.add_argument("--prolongation", type=int, default=2,
                     help="mixed cycle: 0 constant, 1 trilinear, 2 automatic")
     ap.add_argument("--workload", default="many_sources",
@@ -232,6 +247,7 @@ def run_form(fld, torch, p, prec, steps, warmup, args):
                                      warm_start=args.warm_start,
                                      prolongation=args.prolongation,
                                      tail_cells=args.tail_cells,
+                                     smoother=args.smoother,
                                      check_every=args.check_every)
         return fld.Solver(p["shape"], p["h"], prm)
 
@@ -423,6 +439,7 @@ def main():
         "config": {"workload": f"many_sources_{args.n}^3", "grid": [args.n] * 3,
                    "sources": 64, "sigma_ln": 1.5, "rtol": 1e-8,
                    "precision": "mixed" if "mixed" in forms else "fp64",
+                   "smoother": ("red/black Gauss-Seidel", "weighted Jacobi")[args.smoother],
                    "steps_per_run": args.steps},
         "roofline": roof,
         "step_roofline": {

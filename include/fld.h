@@ -73,6 +73,16 @@ typedef enum fld_precision {
                          and coarsest solve; flexible (Polak-Ribiere) PCG */
 } fld_precision;
 
+/* Multigrid smoother (Sec. 3.3 names red/black Gauss-Seidel sweeps). */
+typedef enum fld_smoother {
+  FLD_SMOOTH_RBGS = 0,   /* red/black Gauss-Seidel (default); with nu_pre =
+                            nu_post = 1 the finest level runs fused passes */
+  FLD_SMOOTH_JACOBI = 1  /* weighted Jacobi, weight 6/7 (the optimum for the
+                            7-point Laplacian under full 2x coarsening); one
+                            kernel per sweep and level, an extra iterate
+                            buffer per level; requires tail_cells = 0 */
+} fld_smoother;
+
 /* Periodic 3-D mesh.  Every extent must be even and >= 4 (red/black
  * colouring of a periodic grid needs even extents); nx*ny*nz < 2^31. */
 typedef struct fld_grid {
@@ -92,7 +102,8 @@ typedef struct fld_params {
                           fine faces); 0.5 rediscretises the operator (default) */
   int32_t max_iter;    /* PCG iteration cap; paper 50 (Table 1) */
   int32_t mg_levels;   /* multigrid levels incl. the finest; 0 = automatic */
-  int32_t nu_pre;      /* red/black sweeps before restriction; paper 1 (Table 1) */
+  int32_t nu_pre;      /* smoothing sweeps before restriction (a red/black
+                          sweep is both half-sweeps); paper 1 (Table 1) */
   int32_t nu_post;     /* sweeps after prolongation; paper 1 (Table 1) */
   int32_t precision;   /* fld_precision */
   int32_t max_dt_cuts; /* fld_step: at most this many 10x cuts (Sec. 3.4) */
@@ -125,7 +136,8 @@ typedef struct fld_params {
                           sweeps, no per-level launches).  Default 0: only
                           the coarsest level (measured no faster with more on
                           gfx950) */
-  int32_t reserved[2];
+  int32_t smoother;    /* fld_smoother; default FLD_SMOOTH_RBGS */
+  int32_t reserved;
 } fld_params;
 
 typedef struct fld_stats {
@@ -154,7 +166,7 @@ typedef struct fld_server fld_server;
  * max_iter = 50, nu_pre = nu_post = 1, theta = 1, tau_tol = 1e-4, FP64,
  * coarse_scale = 0.5, max_dt_cuts = 8, graph replay on, cycle_switch = 12,
  * prolongation = 2 (trilinear in the mixed cycle once it has switched to
- * V(2,2)), warm_start = 1, tail_cells = 0. */
+ * V(2,2)), warm_start = 1, tail_cells = 0, smoother = FLD_SMOOTH_RBGS. */
 void fld_default_params(fld_params *p, double c, double L_unit);
 
 const char *fld_strerror(fld_status s);

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libfld.so")
 FLD_OK, FLD_EINVAL, FLD_ENOMEM, FLD_ENOCONV = 0, -1, -2, -3
 FLD_ENONFINITE, FLD_EDEVICE, FLD_EBUSY = -4, -5, -6
 FLD_PREC_FP64, FLD_PREC_MIXED = 0, 1
+FLD_SMOOTH_RBGS, FLD_SMOOTH_JACOBI = 0, 1
 
 EXPORTS = (
     "fld_default_params", "fld_strerror", "fld_workspace_bytes", "fld_create",
@@ -56,7 +57,7 @@ class Params(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("fused_tile_z", ctypes.c_int32),
                 ("cycle_switch", ctypes.c_int32), ("prolongation", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("tail_cells", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("smoother", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -78,6 +78,7 @@ void fld_default_params(fld_params *p, double c, double L_unit) {
   p->prolongation = 2;
   p->warm_start = 1;
   p->tail_cells = 0;
+  p->smoother = FLD_SMOOTH_RBGS;
 }
 
 const char *fld_strerror(fld_status s) {

@@ -44,6 +44,10 @@ bool params_ok(const fld_params &p) {
   if (p.warm_start < 0 || p.warm_start > 1) return false;
   if (p.tail_cells < 0) return false;
   if (p.prolongation < 0 || p.prolongation > 2) return false;
+  if (p.smoother != FLD_SMOOTH_RBGS && p.smoother != FLD_SMOOTH_JACOBI) return false;
+  // the single-workgroup tail smooths red/black: keep it to the coarsest
+  // level under the Jacobi smoother
+  if (p.smoother == FLD_SMOOTH_JACOBI && p.tail_cells > 0) return false;
   return true;
 }
 
@@ -94,7 +98,9 @@ int count_fused_tiles(const fld_params &p, int nx, int ny, int nz) {
   return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz);
 }
 
-bool fused_cycle(const fld_params &p) { return p.nu_pre == 1 && p.nu_post == 1; }
+bool fused_cycle(const fld_params &p) {
+  return p.smoother == FLD_SMOOTH_RBGS && p.nu_pre == 1 && p.nu_post == 1;
+}
 
 // Tiles are up to 64 cells wide in x (one wave per row, one cell per lane,
 // so each load instruction covers consecutive addresses) and 4+ rows.
@@ -122,6 +128,7 @@ int count_tiles(const fld_params &p, int nx, int ny, int nz) {
 
 void carve_problem(Carver &cv, const Hier &h, const fld_params &p, ProbMem &m) {
   const bool mixed = p.precision == FLD_PREC_MIXED;
+  const bool jacobi = p.smoother == FLD_SMOOTH_JACOBI;
   std::memset(&m, 0, sizeof(m));
   for (int l = 0; l < h.levels; ++l) {
     const size_t n = (size_t)h.cells(l);
@@ -155,6 +162,7 @@ void carve_problem(Carver &cv, const Hier &h, const fld_params &p, ProbMem &m) {
       P.b = cv.take<double>(n);
       L.x = mixed ? (void *)cv.take<float>(n) : (void *)P.z;
       L.f = nullptr;
+      if (jacobi) L.x2 = mixed ? (void *)cv.take<float>(n) : (void *)cv.take<double>(n);
     } else {
       if (mixed) {
         L.x = cv.take<float>(n);
@@ -163,6 +171,7 @@ void carve_problem(Carver &cv, const Hier &h, const fld_params &p, ProbMem &m) {
         L.x = cv.take<double>(n);
         L.f = cv.take<double>(n);
       }
+      if (jacobi) L.x2 = mixed ? (void *)cv.take<float>(n) : (void *)cv.take<double>(n);
     }
   }
   m.pd.xh = cv.take<double>((size_t)h.cells(0));
@@ -467,6 +476,35 @@ void Engine::enqueue_vcycle(const ListSet &ls) {
     return;
   }
   const TileList *smooth = ls.smooth, *down = ls.down;
+  if (prm.smoother == FLD_SMOOTH_JACOBI) {
+    // weighted Jacobi ping-pongs between x and x2.  Pre-smoothing ends in x
+    // (restriction and the parent's prolongation read x); the correction
+    // x + P e goes to the buffer that makes the last post-sweep read x2 and
+    // write x, or z on the finest level.
+    const int np = prm.nu_pre, nq = prm.nu_post;
+    for (int l = 0; l < Lmax; ++l) {
+      if (smooth[l].nblocks == 0) continue;
+      int in2 = np & 1;  // first sweep writes x when nu_pre is odd
+      launch_jacobi(T, smooth[l], l, prec, 0, in2, 0, stream);
+      for (int s = 1; s < np; ++s) {
+        in2 ^= 1;
+        launch_jacobi(T, smooth[l], l, prec, 1, in2, 0, stream);
+      }
+      if (l + 1 < Lmax) launch_resid_restrict(T, down[l + 1], l + 1, prec, stream);
+    }
+    if (Lmax > 1) launch_vtail(T, prec, np, nq, tri, stream);
+    for (int l = Lmax - 1; l >= 0; --l) {
+      if (smooth[l].nblocks == 0) continue;
+      int in2 = nq & 1;  // buffer the correction lands in
+      launch_prolong_add(T, smooth[l], l, prec, tri, in2, stream);
+      for (int s = 0; s < nq; ++s) {
+        const int last = l == 0 && s == nq - 1;
+        launch_jacobi(T, smooth[l], l, prec, last ? 2 : 1, in2, mixed, stream);
+        in2 ^= 1;
+      }
+    }
+    return;
+  }
   for (int l = 0; l < Lmax; ++l) {
     if (smooth[l].nblocks == 0) continue;
     launch_pre0(T, smooth[l], l, prec, stream);

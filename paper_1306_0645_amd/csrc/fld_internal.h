@@ -43,6 +43,7 @@ struct LevelDev {
   void *x;                           // V-cycle iterate (level precision);
                                      // finest level FP64 mode: aliases z
   void *f;                           // V-cycle right-hand side (levels >= 1)
+  void *x2;                          // second iterate buffer (Jacobi smoother)
 };
 
 // One problem's finest-level Krylov state.
@@ -117,7 +118,8 @@ enum : int {
   K_HALF_OUT, K_RESTRICT_F, K_RESTRICT_C, K_PROLONG_F, K_PROLONG_C,
   K_COARSE_SOLVE, K_SPMV_P, K_UPDATE, K_TRUE_RESID, K_APPLY, K_SET_R,
   K_UPDATE_E, K_VDOWN_F, K_VDOWN_C, K_VUP_F, K_VUP_C, K_CHEM_H, K_ION_SUM,
-  K_WARM_RESID, K_WARM_REVERT, K_NUM
+  K_WARM_RESID, K_WARM_REVERT, K_JACOBI0_F, K_JACOBI_F, K_JACOBI_OUT,
+  K_JACOBI_C, K_PROLONG_ADD_F, K_PROLONG_ADD_C, K_NUM
 };
 
 // Brackets one launch with hipEvents when its kernel id is selected.
@@ -155,6 +157,14 @@ void launch_prolong_black(const Tables &T, TileList L, int l, int prec,
                           int trilinear, hipStream_t s);
 void launch_vtail(const Tables &T, int prec, int nu_pre, int nu_post,
                   int trilinear, hipStream_t s);
+// weighted Jacobi smoother: mode 0 = first sweep from x = 0, 1 = sweep,
+// 2 = last finest-level sweep writing z and the r.z partials (in = x2);
+// in_x2 selects the input buffer, the output is the other one
+void launch_jacobi(const Tables &T, TileList L, int l, int prec, int mode,
+                   int in_x2, int flexible, hipStream_t s);
+// x (or x2) = x + P e: the coarse-grid correction of every cell
+void launch_prolong_add(const Tables &T, TileList L, int l, int prec,
+                        int trilinear, int to_x2, hipStream_t s);
 void launch_spmv_p(const Tables &T, TileList L0, hipStream_t s);
 void launch_update(const Tables &T, TileList L0, hipStream_t s);
 void launch_true_resid(const Tables &T, TileList L0, hipStream_t s);

@@ -374,6 +374,90 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(Tables T,
 }
 
 // ---------------------------------------------------------------------------
+// Weighted Jacobi smoother (the alternative to red/black Gauss-Seidel):
+//   x_new = x + w (f - A x) / d,  w = 6/7,
+// which updates every cell from the old iterate, so it ping-pongs between
+// LevelDev::x and LevelDev::x2.  Symmetric in both sweeps, so the FP64
+// V-cycle stays a symmetric preconditioner.
+// ---------------------------------------------------------------------------
+
+constexpr double kJacobiW = 6.0 / 7.0;
+
+template <typename R, bool L0>
+__global__ __launch_bounds__(kBlock) void k_jacobi(Tables T, TileList TL, int l,
+                                                   int mode, int in_x2,
+                                                   int flexible) {
+  const int tid = get_tile_index(TL);
+  const Tile t = TL.base[tid];
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.active) return;
+  const LevelDev L = T.lv[l * T.nprob + t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const Coef<R> C = coefs<R>(L);
+  const auto f = fsrc<R, L0>(L, P, sc);
+  const R w = (R)kJacobiW;
+  const R *xin = (const R *)(in_x2 ? L.x2 : L.x);
+  R *xout = (R *)(in_x2 ? L.x : L.x2);
+  const Col col = tile_col(t);
+  double rz = 0.0, rzo = 0.0;
+  if (col.on) {
+    auto xv = [&](int q) { return xin[q]; };
+    for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+      const Nb n = nbrs(col.i, col.j, k, L.nx, L.ny, L.nz);
+      R v;
+      if (mode == 0) {
+        v = w * f(n.c) * recip(C.d[n.c]);
+      } else {
+        const R xc = xin[n.c];
+        v = xc + w * (f(n.c) - (C.d[n.c] * xc - offsum(C, n, xv))) * recip(C.d[n.c]);
+      }
+      if constexpr (L0) {
+        if (mode == 2) {
+          // z = s x in FP64 (the FP64 finest iterate is z itself)
+          const double zv = (double)v * sc.s;
+          const double rv = P.r[n.c];
+          if (flexible) rzo += rv * P.z[n.c];
+          P.z[n.c] = zv;
+          rz += rv * zv;
+          continue;
+        }
+      }
+      xout[n.c] = v;
+    }
+  }
+  if constexpr (L0) {
+    if (mode == 2) write_partials(T, tid, rz, rzo);
+  }
+}
+
+// out = x + P e over every cell of level l (P from coarse_corr); out is x
+// itself or x2
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_prolong_add(Tables T, TileList TL,
+                                                        int l, int trilinear,
+                                                        int to_x2) {
+  const Tile t = get_tile(TL);
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.active) return;
+  const LevelDev L = T.lv[l * T.nprob + t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const bool has_coarse = l + 1 < P.levels;  // one-level problem: a copy
+  const LevelDev Cl = T.lv[(has_coarse ? l + 1 : l) * T.nprob + t.prob];
+  const R *e = (const R *)Cl.x;
+  const R *x = (const R *)L.x;
+  R *out = (R *)(to_x2 ? L.x2 : L.x);
+  const Col col = tile_col(t);
+  if (!col.on) return;
+  for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+    const int c = (k * L.ny + col.j) * L.nx + col.i;
+    const R ec = has_coarse ? coarse_corr(e, col.i, col.j, k, Cl.nx, Cl.ny,
+                                          Cl.nz, trilinear != 0)
+                            : (R)0;
+    out[c] = x[c] + ec;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Tail of the V-cycle, one workgroup per problem: the coarsest level's
 // Jacobi-CG solve and, above it, the levels from P.tail down (each small):
 // pre-smoothing and restriction down to the coarsest level, the solve, then
@@ -996,7 +1080,8 @@ static const char *kKernelNames[K_NUM] = {
     "prolong_black_fine", "prolong_black_coarse", "coarse_solve", "spmv_p",
     "update", "true_resid", "apply", "set_r", "update_E", "vdown_fine",
     "vdown_coarse", "vup_fine", "vup_coarse", "chem_h", "ionized_sum",
-    "warm_resid", "warm_revert"};
+    "warm_resid", "warm_revert", "jacobi0_fine", "jacobi_fine", "jacobi_out",
+    "jacobi_coarse", "prolong_add_fine", "prolong_add_coarse"};
 
 namespace prof {
 struct Rec {
@@ -1156,6 +1241,27 @@ void launch_set_r(const Tables &T, TileList L0, const double *r, int prec,
 
 void launch_warm_resid(const Tables &T, TileList L0, hipStream_t s) {
   if (L0.nblocks) LAUNCH(K_WARM_RESID, k_warm_resid, L0.nblocks, kBlock, s, T, L0);
+}
+
+void launch_jacobi(const Tables &T, TileList L, int l, int prec, int mode,
+                   int in_x2, int flexible, hipStream_t s) {
+  if (!L.nblocks) return;
+  const int id = l ? K_JACOBI_C : mode == 0 ? K_JACOBI0_F : mode == 1 ? K_JACOBI_F : K_JACOBI_OUT;
+  if (prec) {
+    if (l == 0) LAUNCH(id, (k_jacobi<float, true>), L.nblocks, kBlock, s, T, L, l, mode, in_x2, flexible);
+    else LAUNCH(id, (k_jacobi<float, false>), L.nblocks, kBlock, s, T, L, l, mode, in_x2, flexible);
+  } else {
+    if (l == 0) LAUNCH(id, (k_jacobi<double, true>), L.nblocks, kBlock, s, T, L, l, mode, in_x2, flexible);
+    else LAUNCH(id, (k_jacobi<double, false>), L.nblocks, kBlock, s, T, L, l, mode, in_x2, flexible);
+  }
+}
+
+void launch_prolong_add(const Tables &T, TileList L, int l, int prec,
+                        int trilinear, int to_x2, hipStream_t s) {
+  if (!L.nblocks) return;
+  const int id = l ? K_PROLONG_ADD_C : K_PROLONG_ADD_F;
+  if (prec) LAUNCH(id, k_prolong_add<float>, L.nblocks, kBlock, s, T, L, l, trilinear, to_x2);
+  else LAUNCH(id, k_prolong_add<double>, L.nblocks, kBlock, s, T, L, l, trilinear, to_x2);
 }
 
 void launch_warm_revert(const Tables &T, TileList L0, hipStream_t s) {

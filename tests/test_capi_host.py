@@ -70,9 +70,22 @@ def test_workspace_sizing_and_validation(fld):
         assert fld.fld_workspace_bytes(fld.make_grid(bad, (1, 1, 1)), p) == 0
     assert fld.fld_workspace_bytes(fld.make_grid((8, 8, 8), (1, -1, 1)), p) == 0
     for field, val in [("theta", 0.3), ("c", 0.0), ("nu_pre", 0),
-                       ("precision", 7), ("max_iter", 0)]:
+                       ("precision", 7), ("max_iter", 0), ("smoother", 2)]:
         q = fld.fld_default_params(1.0, 1.0, **{field: val})
         assert fld.fld_workspace_bytes(g, q) == 0, field
+    # the Jacobi smoother keeps the single-workgroup tail to the coarsest level
+    q = fld.fld_default_params(1.0, 1.0, smoother=fld.FLD_SMOOTH_JACOBI,
+                               tail_cells=64)
+    assert fld.fld_workspace_bytes(g, q) == 0
+    # and carves one more iterate buffer per level
+    for prec in (fld.FLD_PREC_FP64, fld.FLD_PREC_MIXED):
+        r = fld.fld_default_params(1.0, 1.0, precision=prec)
+        j = fld.fld_default_params(1.0, 1.0, precision=prec,
+                                   smoother=fld.FLD_SMOOTH_JACOBI)
+        assert p.smoother == fld.FLD_SMOOTH_RBGS
+        extra = fld.fld_workspace_bytes(g, j) - fld.fld_workspace_bytes(g, r)
+        w = 4 if prec == fld.FLD_PREC_MIXED else 8
+        assert w * 32 ** 3 <= extra <= w * 32 ** 3 * 8 / 7 + (1 << 16), prec
 
 
 def test_create_rejects_bad_arguments_before_any_launch(fld):

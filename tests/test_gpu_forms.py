@@ -29,13 +29,14 @@ def _probs(seed0=40, dtf=0.02):
     return ps
 
 
+@pytest.mark.parametrize("smoother", [0, 1])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_batch_equals_single_and_oracle(fld, oracle_mod, prec):
-    log_case("batch", prec=prec)
+def test_batch_equals_single_and_oracle(fld, oracle_mod, prec, smoother):
+    log_case("batch", prec=prec, smoother=smoother)
     ps = _probs()
     # fixed cycle: a batch adapts its cycle on its hardest problem, a single
     # handle on its own, so bit-equality needs the switch off
-    prm = params(fld, ps[0], precision=prec, cycle_switch=0)
+    prm = params(fld, ps[0], precision=prec, cycle_switch=0, smoother=smoother)
     # per-problem paper limits differ with the box size: use one set for all
     singles = []
     for p in ps:
