@@ -1,0 +1,154 @@
+"""GPU: one multigrid V-cycle (the PCG preconditioner, applied through
+fld_precondition) against the textbook cycle written out here with numpy on
+the oracle's operator.
+
+The cycle of Table 1: nu red/black Gauss-Seidel sweeps from x = 0 (red
+half-sweep, then black), the residual summed over the 8 children into the
+coarse right-hand side, the coarse level recursively (the coarsest one solved
+exactly here, by Jacobi-CG to 1e-12 on the device), piecewise-constant
+prolongation added to x, then nu sweeps in the opposite colour order (black,
+then red).  Coarse operators: each coarse face is 0.5 times the sum of the 4
+fine faces it covers, and the coarse cell keeps the sum of its 8 children's
+mass (diagonal minus faces).  The finest level of V(1,1) runs the fused
+kernels; V(2,2) and the middle levels run the per-half-sweep kernels, so both
+are pinned to the same definition.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import synth
+from gpu_util import dev, host, log_case, oracle_problem, params, rel_l2
+
+
+@pytest.fixture(scope="module")
+def fld():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1306_0645_amd as m
+    return m
+
+
+def _offsum(T, u):
+    """sum over the 6 neighbours of the face coefficient times u (arrays are
+    [z][y][x], periodic; T[d] is the face towards +d)."""
+    s = np.zeros_like(u)
+    for ax, Td in zip((2, 1, 0), T):
+        s += Td * np.roll(u, -1, axis=ax) + np.roll(Td, 1, axis=ax) * np.roll(u, 1, axis=ax)
+    return s
+
+
+def _apply(op, u):
+    D, T = op
+    return D * u - _offsum(T, u)
+
+
+def _colour(shape):
+    k, j, i = np.indices(shape)
+    return (i + j + k) & 1
+
+
+def _half_sweep(op, f, x, colour_mask):
+    D, T = op
+    new = (f + _offsum(T, x)) / D
+    return np.where(colour_mask, new, x)
+
+
+def _coarsen(op, scale):
+    D, (Tx, Ty, Tz) = op
+    nz, ny, nx = D.shape
+    Z, Y, X = nz // 2, ny // 2, nx // 2
+    mass = D - (Tx + np.roll(Tx, 1, 2) + Ty + np.roll(Ty, 1, 1) + Tz + np.roll(Tz, 1, 0))
+    Mc = mass.reshape(Z, 2, Y, 2, X, 2).sum(axis=(1, 3, 5))
+    # a coarse +x face covers the +x faces of the 4 children with odd x
+    Tcx = scale * Tx[:, :, 1::2].reshape(Z, 2, Y, 2, X).sum(axis=(1, 3))
+    Tcy = scale * Ty[:, 1::2, :].reshape(Z, 2, Y, X, 2).sum(axis=(1, 4))
+    Tcz = scale * Tz[1::2, :, :].reshape(Z, Y, 2, X, 2).sum(axis=(2, 4))
+    Dc = Mc + Tcx + np.roll(Tcx, 1, 2) + Tcy + np.roll(Tcy, 1, 1) + Tcz + np.roll(Tcz, 1, 0)
+    return Dc, (Tcx, Tcy, Tcz)
+
+
+def _solve_exact(op, f):
+    D, (Tx, Ty, Tz) = op
+    shape = D.shape
+    n = D.size
+    idx = np.arange(n).reshape(shape)
+    rows, cols, vals = [idx.ravel()], [idx.ravel()], [D.ravel()]
+    for ax, Td in zip((2, 1, 0), (Tx, Ty, Tz)):
+        nb = np.roll(idx, -1, axis=ax)
+        rows += [idx.ravel(), nb.ravel()]
+        cols += [nb.ravel(), idx.ravel()]
+        vals += [-Td.ravel(), -Td.ravel()]
+    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n, n))
+    return spla.spsolve(A.tocsc(), f.ravel()).reshape(shape)
+
+
+def _vcycle(ops, l, f, nu):
+    op = ops[l]
+    if l == len(ops) - 1:
+        return _solve_exact(op, f)
+    red = _colour(f.shape) == 0
+    x = np.zeros_like(f)
+    for _ in range(nu):
+        x = _half_sweep(op, f, x, red)
+        x = _half_sweep(op, f, x, ~red)
+    r = f - _apply(op, x)
+    nz, ny, nx = f.shape
+    fc = r.reshape(nz // 2, 2, ny // 2, 2, nx // 2, 2).sum(axis=(1, 3, 5))
+    e = _vcycle(ops, l + 1, fc, nu)
+    x = x + np.repeat(np.repeat(np.repeat(e, 2, 0), 2, 1), 2, 2)
+    for _ in range(nu):
+        x = _half_sweep(op, f, x, ~red)
+        x = _half_sweep(op, f, x, red)
+    return x
+
+
+def test_textbook_cycle_helpers():
+    """Self-checks of the helpers above (CPU): with no mass the coarse
+    operator annihilates constants, as the fine one does; each coarse face is
+    half the sum of the 4 fine faces it covers; a red/black sweep pair is one
+    Gauss-Seidel sweep, so repeated sweeps converge to the exact solve."""
+    rng = np.random.default_rng(1)
+    T = tuple(rng.uniform(0.5, 2.0, size=(4, 6, 8)) for _ in range(3))
+    D = T[0] + np.roll(T[0], 1, 2) + T[1] + np.roll(T[1], 1, 1) + T[2] + np.roll(T[2], 1, 0)
+    Dc, Tc = _coarsen((D, T), 0.5)
+    one = np.ones(Dc.shape)
+    assert np.abs(_apply((Dc, Tc), one)).max() <= 1e-12
+    # each coarse face is half the sum of the 4 fine faces it covers
+    assert Tc[0][0, 0, 0] == pytest.approx(0.5 * T[0][0:2, 0:2, 1].sum(), rel=1e-14)
+    assert Tc[1][1, 2, 3] == pytest.approx(0.5 * T[1][2:4, 5, 6:8].sum(), rel=1e-14)
+    assert Tc[2][1, 2, 3] == pytest.approx(0.5 * T[2][3, 4:6, 6:8].sum(), rel=1e-14)
+    op = (D + 0.3, T)
+    f = rng.normal(size=D.shape)
+    red = _colour(D.shape) == 0
+    x = np.zeros_like(f)
+    for _ in range(400):
+        x = _half_sweep(op, f, _half_sweep(op, f, x, red), ~red)
+    assert np.allclose(x, _solve_exact(op, f), rtol=0, atol=1e-10 * np.abs(x).max())
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("levels", [2, 3])
+@pytest.mark.parametrize("nu", [1, 2])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_vcycle_is_the_textbook_cycle(fld, oracle_mod, prec, nu, levels):
+    log_case("vcycle", prec=prec, nu=nu, levels=levels)
+    shape = (24, 40, 96)  # [z][y][x]: ragged 64 x 16 fused tiles in x and y
+    p = synth.random_problem(shape, 61, sigma_ln=1.5, n_src=3, dt_factor=0.5)
+    prm = params(fld, p, precision=prec, mg_levels=levels, nu_pre=nu,
+                 nu_post=nu, cycle_switch=0, fused_tile_z=8)
+    S = fld.Solver(p["shape"], p["h"], prm)
+    S.assemble(dev(p["E"]), dev(p["kappa"]), dev(p["eta"]), p["dt"], p["a"], 0.0)
+    f = np.random.default_rng(7).normal(size=shape)
+    z = host(S.fld_precondition(dev(f)))
+    O = oracle_problem(oracle_mod, p, prm)
+    D, Ax, Ay, Az, _ = O.system()
+    ops = [(D, (Ax, Ay, Az))]
+    for _ in range(levels - 1):
+        ops.append(_coarsen(ops[-1], prm.coarse_scale))
+    zr = _vcycle(ops, 0, f, nu)
+    err = rel_l2(z, zr)
+    print(f"[vcycle] prec={prec} nu={nu} levels={levels} err={err:.2e}", flush=True)
+    assert err <= (1e-9 if prec == 0 else 2e-5)
