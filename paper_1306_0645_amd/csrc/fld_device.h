@@ -49,9 +49,8 @@ __device__ __forceinline__ int get_tile_index(const TileList &L) {
   return L.ranges[2 * lo + 1] + (b - L.ranges[2 * lo]);
 }
 
-// Thread -> cells: a thread owns t.cpt consecutive x cells starting at
-// (i, j); on smoothed levels cpt = 2, so the thread's cells are one red and
-// one black cell and every lane of a colour sweep has exactly one cell.
+// Thread -> cells: a thread owns the column (i, j) of the tile and walks its
+// planes (the tables give every tile cpt = 1 cell per thread along x).
 struct Col {
   int i, j;
   bool on;

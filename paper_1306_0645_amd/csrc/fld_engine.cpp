@@ -82,13 +82,13 @@ Hier make_hier(const fld_grid &g, const fld_params &p) {
 // Tiles of the fused one-sweep V-cycle kernels: 64 x 16 cells in x, y (their
 // LDS buffers are sized for that) and fused_tile_z planes in z.  Deeper tiles
 // cut the z-halo but leave fewer tiles to hide latency: measured on gfx950 at
-// 256^3, 16 planes suit the FP32 cycle and 32 the FP64 one (whose LDS use
-// already limits it to two tiles per CU).
+// 256^3 (Mcell-updates/s for 8, 16, 32, 64 planes: FP32 cycle 2532, 2537,
+// 2608, 2451; FP64 2203, 2268, 2308, 2217), 32 planes suit both.
 void fused_shape(const fld_params &p, int nx, int ny, int nz, int &tx, int &ty,
                  int &tz) {
   tx = std::min(nx, 64);
   ty = std::min(ny, 16);
-  const int def = p.precision == FLD_PREC_MIXED ? 16 : 32;
+  const int def = 32;
   tz = std::min(nz, p.fused_tile_z > 0 ? p.fused_tile_z : def);
 }
 

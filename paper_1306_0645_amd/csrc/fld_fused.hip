@@ -17,9 +17,25 @@
 // plane z0 - 3 + m (m >= 2) and finishes plane z0 - 4 + m (m >= 4), so the
 // y, x_b and output planes run two and one plane behind the loads.
 // Three-plane rolling LDS buffers hold y (tile + 2 halo) and x_b (tile + 1
-// halo).  HBM traffic per finest cell: the
-// right-hand side and 4 coefficients in, 1/8 coarse out (vdown); the same plus
-// the 1/8 coarse correction in and z out (vup).
+// halo).
+//
+// Every face coefficient joins one red and one black cell, so both
+// half-sweeps of a plane read all of them, one z-step apart; between the two
+// reads a block streams more than its share of the XCD's L2, so re-reading
+// them from memory doubles the coefficient traffic.  Instead thread
+// (ci, cj) = (tid & 31, tid >> 5) owns the 2 x 2 columns
+// x = x0 + 2ci + a, y = y0 + 2cj + b (a, b in {0, 1}) of the tile: it loads
+// their right-hand side, diagonal and faces once per plane with 2-wide vector
+// loads (plus the -x faces of its a = 0 cells and the -y faces of its b = 0
+// cells, which share cache lines with its neighbours' loads, issued at the
+// same time) and keeps them in registers from the black pass of a plane to
+// its red pass.  The black cells of the ring just outside the tile, which the
+// red cells on the tile's edge need, are done by every third thread from
+// loads of their own, and the tile + 2 halo of the y plane by a linear map
+// over the halo cells.  HBM traffic per finest cell: the right-hand side and
+// 4 coefficients in, 1/8 coarse out (vdown); the same plus the 1/8 coarse
+// correction in, the right-hand side read again for the output, and z out
+// (vup).
 #include <type_traits>
 
 #include "fld_device.h"
@@ -36,100 +52,286 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return i < 0 ? i + n : (i >= n ? i - n : i);
 }
 
-// Per-thread share of one plane of the tile + 2: at most kU cells, whose
-// global loads are issued together (and one plane ahead of their use).
-constexpr int kU = (kE2 + kBlock - 1) / kBlock;
-// black cells of the tile + 1 per thread (each row of the tile + 1 has an
-// even number of cells, half of them black)
-constexpr int kB = (kE1 / 2 + kBlock - 1) / kBlock;
+template <typename R>
+using Vec2 = R __attribute__((ext_vector_type(2)));
 
-template <typename R, bool L0>
-struct PlaneRegs {
-  using FT = typename std::conditional<L0, double, R>::type;
-  FT f[kU];
-  R d[kU];
-  R e[kU];
+template <typename R>
+__device__ __forceinline__ void ld2(const R *p, R &u, R &v) {
+  const Vec2<R> w = *reinterpret_cast<const Vec2<R> *>(p);
+  u = w.x;
+  v = w.y;
+}
+
+template <typename R>
+__device__ __forceinline__ void st2(R *p, R u, R v) {
+  Vec2<R> w;
+  w.x = u;
+  w.y = v;
+  *reinterpret_cast<Vec2<R> *>(p) = w;
+}
+
+// in-plane faces of one quad: Tx, Ty at (a, b) (the + faces of each cell),
+// the -x faces of the a = 0 cells and the -y faces of the b = 0 cells
+template <typename R>
+struct QFace {
+  R x00, x10, x01, x11, xl0, xl1;
+  R y00, y10, y01, y11, yb0, yb1;
 };
 
-// Issue the loads of plane pz of the tile + 2 (right-hand side, diagonal and,
-// for the up pass, the coarse correction at red cells).
+// one plane's Tz, diagonal reciprocal, ... of a quad, cell (a, b) = vab
+template <typename R>
+struct Q4 {
+  R v00, v10, v01, v11;
+};
+
+// the 6 faces of cell (a, b) of the quad, a = a1 (run time), b = B
+template <typename R>
+struct Faces6 {
+  R xp, xm, yp, ym, zp, zm;
+};
+
+template <int B, typename R>
+__device__ __forceinline__ Faces6<R> cell_faces(const QFace<R> &F, const Q4<R> &Zp,
+                                               const Q4<R> &Zm, bool a1) {
+  Faces6<R> f;
+  if constexpr (B == 0) {
+    f.xp = a1 ? F.x10 : F.x00;
+    f.xm = a1 ? F.x00 : F.xl0;
+    f.yp = a1 ? F.y10 : F.y00;
+    f.ym = a1 ? F.yb1 : F.yb0;
+    f.zp = a1 ? Zp.v10 : Zp.v00;
+    f.zm = a1 ? Zm.v10 : Zm.v00;
+  } else {
+    f.xp = a1 ? F.x11 : F.x01;
+    f.xm = a1 ? F.x01 : F.xl1;
+    f.yp = a1 ? F.y11 : F.y01;
+    f.ym = a1 ? F.y10 : F.y00;
+    f.zp = a1 ? Zp.v11 : Zp.v01;
+    f.zm = a1 ? Zm.v11 : Zm.v01;
+  }
+  return f;
+}
+
+template <int B, typename R>
+__device__ __forceinline__ R pick(const Q4<R> &q, bool a1) {
+  if constexpr (B == 0) return a1 ? q.v10 : q.v00;
+  else return a1 ? q.v11 : q.v01;
+}
+
+template <typename R>
+__device__ __forceinline__ void load_faces(QFace<R> &F, Q4<R> &Z, const Coef<R> &C,
+                                           int kz, int qx, int qy, int qxl,
+                                           int qyb, int nx, int ny, bool inplane) {
+  const int r0 = (kz * ny + qy) * nx, r1 = r0 + nx;
+  if (inplane) {
+    ld2(C.tx + r0 + qx, F.x00, F.x10);
+    ld2(C.tx + r1 + qx, F.x01, F.x11);
+    F.xl0 = C.tx[r0 + qxl];
+    F.xl1 = C.tx[r1 + qxl];
+    ld2(C.ty + r0 + qx, F.y00, F.y10);
+    ld2(C.ty + r1 + qx, F.y01, F.y11);
+    ld2(C.ty + (kz * ny + qyb) * nx + qx, F.yb0, F.yb1);
+  }
+  ld2(C.tz + r0 + qx, Z.v00, Z.v10);
+  ld2(C.tz + r1 + qx, Z.v01, Z.v11);
+}
+
+// halo cell q of the tile + 2 frame (the cells outside the tile): LDS
+// coordinates (ex, ey)
+__device__ __forceinline__ void halo_cell(int q, int tx, int ty, int &ex, int &ey) {
+  const int e2x = tx + 4;
+  if (q < 2 * e2x) {
+    ey = q / e2x;
+    ex = q - ey * e2x;
+  } else if (q < 4 * e2x) {
+    const int r = q - 2 * e2x, ry = r / e2x;
+    ey = ty + 2 + ry;
+    ex = r - ry * e2x;
+  } else {
+    const int r = q - 4 * e2x, c = r & 3;
+    ey = 2 + (r >> 2);
+    ex = c < 2 ? c : tx + c;
+  }
+}
+
+// black cell q (of tx + ty) of the ring just outside the tile on a plane of
+// parity pp, in the tile + 1 frame: rows y0 - 1 and y0 + ty, then columns
+// x0 - 1 and x0 + tx (x0, y0 and the extents are even)
+__device__ __forceinline__ void ring_black(int q, int tx, int ty, int pp, int &ex,
+                                           int &ey) {
+  const int hx = tx >> 1, hy = ty >> 1;
+  if (q < hx) {
+    ey = 0;
+    ex = 1 + 2 * q + pp;
+  } else if (q < 2 * hx) {
+    ey = ty + 1;
+    ex = 2 + 2 * (q - hx) - pp;
+  } else if (q < 2 * hx + hy) {
+    ex = 0;
+    ey = 1 + 2 * (q - 2 * hx) + pp;
+  } else {
+    ex = tx + 1;
+    ey = 2 + 2 * (q - 2 * hx - hy) - pp;
+  }
+}
+
+// the 7 coefficients of one ring black cell
+template <typename R>
+struct RingCoef {
+  R d, xp, xm, yp, ym, zp, zm;
+  int ex, ey;
+};
+
+template <typename R>
+__device__ __forceinline__ void load_ring(RingCoef<R> &rc, const Coef<R> &C,
+                                          const Tile &t, int q, int pb, int nx,
+                                          int ny, int nz) {
+  ring_black(q, t.tx, t.ty, pb & 1, rc.ex, rc.ey);
+  const Nb n = nbrs(wrapi(t.x0 - 1 + rc.ex, nx), wrapi(t.y0 - 1 + rc.ey, ny),
+                    wrapi(pb, nz), nx, ny, nz);
+  rc.d = C.d[n.c];
+  rc.xp = C.tx[n.c];
+  rc.xm = C.tx[n.xm];
+  rc.yp = C.ty[n.c];
+  rc.ym = C.ty[n.ym];
+  rc.zp = C.tz[n.c];
+  rc.zm = C.tz[n.zm];
+}
+
+// x_b = v_b + (sum_nb T v_nb) / d_b at LDS offset s of the tile + 2 frame
+template <typename R>
+__device__ __forceinline__ R black_value(const Faces6<R> &f, R idv, const R *vm,
+                                         const R *v0, const R *vp, int s) {
+  const R sum = f.xp * v0[s + 1] + f.xm * v0[s - 1] + f.yp * v0[s + kE2X] +
+                f.ym * v0[s - kE2X] + f.zp * vp[s] + f.zm * vm[s];
+  return v0[s] + sum * idv;
+}
+
+// sum_nb T x_nb over the black neighbours at LDS offset s of the tile + 1 frame
+template <typename R>
+__device__ __forceinline__ R red_sum(const Faces6<R> &f, const R *xm, const R *x0,
+                                     const R *xp, int s) {
+  return f.xp * x0[s + 1] + f.xm * x0[s - 1] + f.yp * x0[s + kE1X] +
+         f.ym * x0[s - kE1X] + f.zp * xp[s] + f.zm * xm[s];
+}
+
+constexpr int kHalo = (4 * (kFX + 4) + 4 * kFY + kBlock - 1) / kBlock;
+
+// right-hand side, diagonal (and coarse correction) of one plane: the quad's
+// 4 cells and this thread's halo cells
 template <typename R, bool L0, bool UP>
-__device__ __forceinline__ void load_plane(PlaneRegs<R, L0> &pr, const Tile &t,
-                                           int pz, int nx, int ny, int nz,
-                                           const FSrc<R, L0> &f, const R *d,
-                                           const R *e, bool has_coarse, int cnx,
-                                           int cny, int cnz = 1,
-                                           bool trilinear = false) {
-  const int e2x = t.tx + 4, n2 = e2x * (t.ty + 4);
+struct QPlane {
+  using FT = typename std::conditional<L0, double, R>::type;
+  FT f00, f10, f01, f11;
+  R d00, d10, d01, d11;
+  R e0, e1;  // coarse correction at the red cells of rows 0 and 1
+  FT hf[kHalo];
+  R hd[kHalo], he[kHalo];
+};
+
+template <typename R, bool L0, bool UP, bool TRI>
+__device__ __forceinline__ void q_load_plane(
+    QPlane<R, L0, UP> &pl, const Tile &t, int pz, bool qon, int qx, int qy,
+    int nx, int ny, int nz, const FSrc<R, L0> &f, const R *d, const R *e,
+    bool has_coarse, int cnx, int cny, int cnz) {
   const int kz = wrapi(pz, nz);
+  if (qon) {
+    const int r0 = (kz * ny + qy) * nx + qx, r1 = r0 + nx;
+    if constexpr (L0) {
+      ld2(f.r + r0, pl.f00, pl.f10);
+      ld2(f.r + r1, pl.f01, pl.f11);
+    } else {
+      ld2(f.f + r0, pl.f00, pl.f10);
+      ld2(f.f + r1, pl.f01, pl.f11);
+    }
+    ld2(d + r0, pl.d00, pl.d10);
+    ld2(d + r1, pl.d01, pl.d11);
+    if constexpr (UP) {
+      pl.e0 = pl.e1 = (R)0;
+      if (has_coarse) {
+        if constexpr (TRI) {
+          const int pp = pz & 1;  // red cells: row 0 at a = pp, row 1 at 1 - pp
+          pl.e0 = coarse_corr(e, qx + pp, qy, kz, cnx, cny, cnz, true);
+          pl.e1 = coarse_corr(e, qx + 1 - pp, qy + 1, kz, cnx, cny, cnz, true);
+        } else {
+          pl.e0 = pl.e1 = coarse_corr(e, qx, qy, kz, cnx, cny, cnz, false);
+        }
+      }
+    }
+  }
+  const int e2x = t.tx + 4, nh = 4 * e2x + 4 * t.ty;
 #pragma unroll
-  for (int u = 0; u < kU; ++u) {
-    const int c = threadIdx.x + u * kBlock;
-    if (c < n2) {
-      const int ey = c / e2x, ex = c - ey * e2x;
+  for (int u = 0; u < kHalo; ++u) {
+    const int q = threadIdx.x + u * kBlock;
+    if (q < nh) {
+      int ex, ey;
+      halo_cell(q, t.tx, t.ty, ex, ey);
       const int ux = t.x0 - 2 + ex, uy = t.y0 - 2 + ey;
       const int gx = wrapi(ux, nx), gy = wrapi(uy, ny);
       const int g = (kz * ny + gy) * nx + gx;
-      if constexpr (L0) pr.f[u] = f.r[g];
-      else pr.f[u] = f.f[g];
-      pr.d[u] = d[g];
+      if constexpr (L0) pl.hf[u] = f.r[g];
+      else pl.hf[u] = f.f[g];
+      pl.hd[u] = d[g];
       if constexpr (UP) {
-        pr.e[u] = (has_coarse && ((ux + uy + pz) & 1) == 0)
-                      ? coarse_corr(e, gx, gy, kz, cnx, cny, cnz, trilinear)
-                      : (R)0;
+        pl.he[u] = (has_coarse && ((ux + uy + pz) & 1) == 0)
+                       ? coarse_corr(e, gx, gy, kz, cnx, cny, cnz, TRI)
+                       : (R)0;
       }
     }
   }
 }
 
-// y = f / d (+ e for the up pass) into the LDS plane
+template <typename R, bool L0>
+__device__ __forceinline__ R scaled(typename QPlane<R, L0, false>::FT v, double inv_s) {
+  if constexpr (L0) return (R)(v * inv_s);
+  else return v;
+}
+
+// y = f / d (+ e at red cells for the up pass) into the LDS plane; returns
+// the quad's diagonal reciprocals
 template <typename R, bool L0, bool UP>
-__device__ __forceinline__ void store_plane(const PlaneRegs<R, L0> &pr,
-                                            const Tile &t, R *out,
-                                            double inv_s) {
-  const int e2x = t.tx + 4, n2 = e2x * (t.ty + 4);
+__device__ __forceinline__ Q4<R> q_store_plane(const QPlane<R, L0, UP> &pl,
+                                               const Tile &t, int pz, bool qon,
+                                               int ci, int cj, R *out,
+                                               double inv_s) {
+  Q4<R> id;
+  if (qon) {
+    id.v00 = recip(pl.d00);
+    id.v10 = recip(pl.d10);
+    id.v01 = recip(pl.d01);
+    id.v11 = recip(pl.d11);
+    R y00 = scaled<R, L0>(pl.f00, inv_s) * id.v00;
+    R y10 = scaled<R, L0>(pl.f10, inv_s) * id.v10;
+    R y01 = scaled<R, L0>(pl.f01, inv_s) * id.v01;
+    R y11 = scaled<R, L0>(pl.f11, inv_s) * id.v11;
+    if constexpr (UP) {
+      if (pz & 1) {  // red: (1, 0) and (0, 1)
+        y10 += pl.e0;
+        y01 += pl.e1;
+      } else {       // red: (0, 0) and (1, 1)
+        y00 += pl.e0;
+        y11 += pl.e1;
+      }
+    }
+    const int s = (2 * cj + 2) * kE2X + 2 * ci + 2;
+    out[s] = y00;
+    out[s + 1] = y10;
+    out[s + kE2X] = y01;
+    out[s + kE2X + 1] = y11;
+  }
+  const int e2x = t.tx + 4, nh = 4 * e2x + 4 * t.ty;
 #pragma unroll
-  for (int u = 0; u < kU; ++u) {
-    const int c = threadIdx.x + u * kBlock;
-    if (c < n2) {
-      const int ey = c / e2x, ex = c - ey * e2x;
-      R fv;
-      if constexpr (L0) fv = (R)(pr.f[u] * inv_s);
-      else fv = pr.f[u];
-      R v = fv * recip(pr.d[u]);
-      if constexpr (UP) v += pr.e[u];
+  for (int u = 0; u < kHalo; ++u) {
+    const int q = threadIdx.x + u * kBlock;
+    if (q < nh) {
+      int ex, ey;
+      halo_cell(q, t.tx, t.ty, ex, ey);
+      R v = scaled<R, L0>(pl.hf[u], inv_s) * recip(pl.hd[u]);
+      if constexpr (UP) v += pl.he[u];
       out[ey * kE2X + ex] = v;
     }
   }
-}
-
-// Black cells of plane pb over the tile + 1:
-//   x_b = v_b + (sum_nb T v_nb) / d_b
-// from the LDS planes pb - 1, pb, pb + 1 of v (v = y, or y + e at red cells).
-template <typename R>
-__device__ __forceinline__ void black_plane(const Tile &t, int pb, int nx,
-                                            int ny, int nz, const Coef<R> &C,
-                                            const R *vm, const R *v0,
-                                            const R *vp, R *xo) {
-  const int e1x = t.tx + 2, half = e1x >> 1, nb1 = half * (t.ty + 2);
-  const int kb = wrapi(pb, nz);
-#pragma unroll
-  for (int u = 0; u < kB; ++u) {
-    const int c = threadIdx.x + u * kBlock;
-    if (c < nb1) {
-      const int ey = c / half, h = c - ey * half;
-      // the black cell of pair h in row ey: (x0-1+ex) + (y0-1+ey) + pb odd,
-      // i.e. ex = 1 + x0 + y0 + ey + pb (mod 2)
-      const int ex = 2 * h + ((1 + t.x0 + t.y0 + ey + pb) & 1);
-      const int gx = t.x0 - 1 + ex, gy = t.y0 - 1 + ey;
-      const Nb n = nbrs(wrapi(gx, nx), wrapi(gy, ny), kb, nx, ny, nz);
-      const int s = (ey + 1) * kE2X + (ex + 1);
-      const R sum = C.tx[n.c] * v0[s + 1] + C.tx[n.xm] * v0[s - 1] +
-                    C.ty[n.c] * v0[s + kE2X] + C.ty[n.ym] * v0[s - kE2X] +
-                    C.tz[n.c] * vp[s] + C.tz[n.zm] * vm[s];
-      xo[ey * kE1X + ex] = v0[s] + sum * recip(C.d[n.c]);
-    }
-  }
+  return id;
 }
 
 template <typename R, bool L0>
@@ -147,55 +349,63 @@ __global__ __launch_bounds__(kBlock) void k_vdown(Tables T, TileList TL, int l) 
   __shared__ R ys[3][kE2];
   __shared__ R xs[3][kE1];
   const int nx = L.nx, ny = L.ny, nz = L.nz;
-  // each thread owns one coarse cell (2 x 2 fine columns) of the tile
   const int ci = threadIdx.x & 31, cj = threadIdx.x >> 5;
-  const bool cown = 2 * ci < t.tx && 2 * cj < t.ty;
-  PlaneRegs<R, L0> pr;
-  load_plane<R, L0, false>(pr, t, t.z0 - 2, nx, ny, nz, f, C.d, nullptr, false, 0, 0);
+  const bool qon = 2 * ci < t.tx && 2 * cj < t.ty;
+  const int qx = t.x0 + 2 * ci, qy = t.y0 + 2 * cj;
+  const int qxl = wrapi(qx - 1, nx), qyb = wrapi(qy - 1, ny);
+  const int rq = threadIdx.x / 3;
+  const bool ron = threadIdx.x == 3 * rq && rq < t.tx + t.ty;
+  QPlane<R, L0, false> pl;
+  q_load_plane<R, L0, false, false>(pl, t, t.z0 - 2, qon, qx, qy, nx, ny, nz, f,
+                                    C.d, nullptr, false, 0, 0, 0);
+  QFace<R> Fb{}, Fr{};  // in-plane faces of planes pz - 1 (black), pz - 2 (red)
+  Q4<R> Zb{}, Zr{}, Zrm{};  // Tz of planes pz - 1, pz - 2, pz - 3
+  Q4<R> I0{}, I1{};  // diagonal reciprocals of planes pz, pz - 1
+  RingCoef<R> rc{};
   R acc = 0;
   for (int m = 0; m < t.tz + 4; ++m) {
-    const int pz = t.z0 - 2 + m;
+    const int pz = t.z0 - 2 + m, pb = pz - 1, pr2 = pz - 2;
+    Fr = Fb;
+    Zrm = Zr;
+    Zr = Zb;
+    // faces of plane pb (its Tz only at m = 1: the -z face of plane pb + 1)
+    if (m >= 1 && qon)
+      load_faces(Fb, Zb, C, wrapi(pb, nz), qx, qy, qxl, qyb, nx, ny, m >= 2);
+    if (m >= 2 && ron) load_ring(rc, C, t, rq, pb, nx, ny, nz);
     // (1) y = f / d on plane pz (loaded one iteration ahead)
-    store_plane<R, L0, false>(pr, t, ys[m % 3], inv_s);
+    I1 = I0;
+    I0 = q_store_plane<R, L0, false>(pl, t, pz, qon, ci, cj, ys[m % 3], inv_s);
     if (m + 1 < t.tz + 4)
-      load_plane<R, L0, false>(pr, t, pz + 1, nx, ny, nz, f, C.d, nullptr, false, 0, 0);
+      q_load_plane<R, L0, false, false>(pl, t, pz + 1, qon, qx, qy, nx, ny, nz, f,
+                                        C.d, nullptr, false, 0, 0, 0);
     __syncthreads();
-    // coefficients of the red cells of plane pz - 2, loaded before the black
-    // pass so their latency overlaps it
-    const int pr2 = pz - 2;
-    const bool out = m >= 4 && cown;
-    R ctx[2], ctxm[2], cty[2], ctym[2], ctz[2], ctzm[2];
-    int cs[2];
-    if (out) {
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int a = (b + pr2) & 1;  // the red cell of row b
-        const int lx = 2 * ci + a, ly = 2 * cj + b;
-        const Nb n = nbrs(t.x0 + lx, t.y0 + ly, pr2, nx, ny, nz);
-        cs[b] = (ly + 1) * kE1X + (lx + 1);
-        ctx[b] = C.tx[n.c];
-        ctxm[b] = C.tx[n.xm];
-        cty[b] = C.ty[n.c];
-        ctym[b] = C.ty[n.ym];
-        ctz[b] = C.tz[n.c];
-        ctzm[b] = C.tz[n.zm];
-      }
-    }
-    // (2) black cells of plane pz - 1 over the tile + 1
+    // (2) black cells of plane pb over the tile + 1
     if (m >= 2) {
-      black_plane<R>(t, pz - 1, nx, ny, nz, C, ys[(m + 1) % 3], ys[(m + 2) % 3],
-                     ys[m % 3], xs[m % 3]);
+      const R *vm = ys[(m + 1) % 3], *v0 = ys[(m + 2) % 3], *vp = ys[m % 3];
+      R *xo = xs[m % 3];
+      if (qon) {
+        const bool b0 = (pb & 1) == 0, b1 = !b0;  // a of the black cell of rows 0, 1
+        const int s = (2 * cj + 2) * kE2X + 2 * ci + 2;
+        const int o = (2 * cj + 1) * kE1X + 2 * ci + 1;
+        xo[o + b0] = black_value(cell_faces<0>(Fb, Zb, Zr, b0), pick<0>(I1, b0), vm,
+                                 v0, vp, s + b0);
+        xo[o + kE1X + b1] = black_value(cell_faces<1>(Fb, Zb, Zr, b1),
+                                        pick<1>(I1, b1), vm, v0, vp, s + kE2X + b1);
+      }
+      if (ron) {
+        const Faces6<R> fr{rc.xp, rc.xm, rc.yp, rc.ym, rc.zp, rc.zm};
+        xo[rc.ey * kE1X + rc.ex] = black_value(fr, recip(rc.d), vm, v0, vp,
+                                               (rc.ey + 1) * kE2X + rc.ex + 1);
+      }
       __syncthreads();
     }
-    // (3) red residuals of plane pz - 2, summed into the coarse cell
-    if (out) {
+    // (3) red residuals of plane pr2, summed into the coarse cell
+    if (m >= 4 && qon) {
       const R *xm = xs[(m + 1) % 3], *x0 = xs[(m + 2) % 3], *xp = xs[m % 3];
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int s = cs[b];
-        acc += ctx[b] * x0[s + 1] + ctxm[b] * x0[s - 1] + cty[b] * x0[s + kE1X] +
-               ctym[b] * x0[s - kE1X] + ctz[b] * xp[s] + ctzm[b] * xm[s];
-      }
+      const bool r0 = (pr2 & 1) != 0, r1 = !r0;  // a of the red cell of rows 0, 1
+      const int o = (2 * cj + 1) * kE1X + 2 * ci + 1;
+      acc += red_sum(cell_faces<0>(Fr, Zr, Zrm, r0), xm, x0, xp, o + r0);
+      acc += red_sum(cell_faces<1>(Fr, Zr, Zrm, r1), xm, x0, xp, o + kE1X + r1);
       if ((pr2 - t.z0) & 1) {
         fc[((pr2 >> 1) * Cv.ny + (t.y0 >> 1) + cj) * Cv.nx + (t.x0 >> 1) + ci] = acc;
         acc = 0;
@@ -204,11 +414,10 @@ __global__ __launch_bounds__(kBlock) void k_vdown(Tables T, TileList TL, int l) 
   }
 }
 
-// TRI selects trilinear prolongation of the coarse correction (at compile
-// time: the piecewise-constant variant keeps its lower register count).
 template <typename R, bool L0, bool TRI>
 __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
                                                 int flexible) {
+  using FT = typename QPlane<R, L0, true>::FT;
   const int tid = get_tile_index(TL);
   const Tile t = TL.base[tid];
   const Scal &sc = T.sc[t.prob];
@@ -227,56 +436,116 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
   __shared__ R xs[3][kE1];
   const int nx = L.nx, ny = L.ny, nz = L.nz;
   const int cnx = Cl.nx, cny = Cl.ny, cnz = Cl.nz;
-  constexpr bool tri = TRI;
   const int ci = threadIdx.x & 31, cj = threadIdx.x >> 5;
-  const bool cown = 2 * ci < t.tx && 2 * cj < t.ty;
-  PlaneRegs<R, L0> pr;
-  load_plane<R, L0, true>(pr, t, t.z0 - 2, nx, ny, nz, f, C.d, e, has_coarse, cnx,
-                          cny, cnz, tri);
+  const bool qon = 2 * ci < t.tx && 2 * cj < t.ty;
+  const int qx = t.x0 + 2 * ci, qy = t.y0 + 2 * cj;
+  const int qxl = wrapi(qx - 1, nx), qyb = wrapi(qy - 1, ny);
+  const int rq = threadIdx.x / 3;
+  const bool ron = threadIdx.x == 3 * rq && rq < t.tx + t.ty;
+  QPlane<R, L0, true> pl;
+  q_load_plane<R, L0, true, TRI>(pl, t, t.z0 - 2, qon, qx, qy, nx, ny, nz, f, C.d,
+                                 e, has_coarse, cnx, cny, cnz);
+  QFace<R> Fb{}, Fr{};
+  Q4<R> Zb{}, Zr{}, Zrm{};
+  Q4<R> I0{}, I1{}, I2{};   // diagonal reciprocals of planes pz, pz - 1, pz - 2
+  RingCoef<R> rc{};
   double rz = 0.0, rzo = 0.0;
   for (int m = 0; m < t.tz + 4; ++m) {
-    const int pz = t.z0 - 2 + m;
-    // (1) v = y at black cells, y + e(parent) at red cells (loaded ahead)
-    store_plane<R, L0, true>(pr, t, vs[m % 3], inv_s);
+    const int pz = t.z0 - 2 + m, pb = pz - 1, pr2 = pz - 2;
+    Fr = Fb;
+    Zrm = Zr;
+    Zr = Zb;
+    if (m >= 1 && qon)
+      load_faces(Fb, Zb, C, wrapi(pb, nz), qx, qy, qxl, qyb, nx, ny, m >= 2);
+    if (m >= 2 && ron) load_ring(rc, C, t, rq, pb, nx, ny, nz);
+    const bool out = m >= 4 && qon;
+    const int o0 = (pr2 * ny + qy) * nx + qx;  // row 0 of the quad on plane pr2
+    // right-hand side of plane pr2 (read again: keeping it for the three
+    // iterations since its first load would cost more registers than the
+    // read costs bytes) and, for the flexible dot, the old z
+    Q4<FT> H{};
+    double zo00 = 0.0, zo10 = 0.0, zo01 = 0.0, zo11 = 0.0;
+    if (out) {
+      const FT *src;
+      if constexpr (L0) src = f.r;
+      else src = f.f;
+      ld2(src + o0, H.v00, H.v10);
+      ld2(src + o0 + nx, H.v01, H.v11);
+      if constexpr (L0) {
+        if (flexible) {
+          ld2(P.z + o0, zo00, zo10);
+          ld2(P.z + o0 + nx, zo01, zo11);
+        }
+      }
+    }
+    // (1) v = y, + e(parent) at red cells, on plane pz
+    I2 = I1;
+    I1 = I0;
+    I0 = q_store_plane<R, L0, true>(pl, t, pz, qon, ci, cj, vs[m % 3], inv_s);
     if (m + 1 < t.tz + 4)
-      load_plane<R, L0, true>(pr, t, pz + 1, nx, ny, nz, f, C.d, e, has_coarse,
-                              cnx, cny, cnz, tri);
+      q_load_plane<R, L0, true, TRI>(pl, t, pz + 1, qon, qx, qy, nx, ny, nz, f, C.d,
+                                     e, has_coarse, cnx, cny, cnz);
     __syncthreads();
-    // (2) new black values of plane pz - 1 over the tile + 1
+    // (2) new black values of plane pb over the tile + 1
     if (m >= 2) {
-      black_plane<R>(t, pz - 1, nx, ny, nz, C, vs[(m + 1) % 3], vs[(m + 2) % 3],
-                     vs[m % 3], xs[m % 3]);
+      const R *vm = vs[(m + 1) % 3], *v0 = vs[(m + 2) % 3], *vp = vs[m % 3];
+      R *xo = xs[m % 3];
+      if (qon) {
+        const bool b0 = (pb & 1) == 0, b1 = !b0;
+        const int s = (2 * cj + 2) * kE2X + 2 * ci + 2;
+        const int o = (2 * cj + 1) * kE1X + 2 * ci + 1;
+        xo[o + b0] = black_value(cell_faces<0>(Fb, Zb, Zr, b0), pick<0>(I1, b0), vm,
+                                 v0, vp, s + b0);
+        xo[o + kE1X + b1] = black_value(cell_faces<1>(Fb, Zb, Zr, b1),
+                                        pick<1>(I1, b1), vm, v0, vp, s + kE2X + b1);
+      }
+      if (ron) {
+        const Faces6<R> fr{rc.xp, rc.xm, rc.yp, rc.ym, rc.zp, rc.zm};
+        xo[rc.ey * kE1X + rc.ex] = black_value(fr, recip(rc.d), vm, v0, vp,
+                                               (rc.ey + 1) * kE2X + rc.ex + 1);
+      }
       __syncthreads();
     }
-    // (3) plane pz - 2 on the tile: new red values from the new black ones;
-    //     every cell is written (finest level: z = s x in FP64 plus dots)
-    if (m >= 4 && cown) {
-      const int pr2 = pz - 2;
+    // (3) plane pr2 on the tile: new red values from the new black ones, every
+    //     cell written (finest level: z = s x in FP64 plus the dots)
+    if (out) {
       const R *xm = xs[(m + 1) % 3], *x0 = xs[(m + 2) % 3], *xp = xs[m % 3];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int a = u & 1, b = u >> 1;
-        const int lx = 2 * ci + a, ly = 2 * cj + b;
-        const int s = (ly + 1) * kE1X + (lx + 1);
-        const Nb n = nbrs(t.x0 + lx, t.y0 + ly, pr2, nx, ny, nz);
-        R v;
-        if (((a + b + pr2) & 1) == 0) {
-          const R sum = C.tx[n.c] * x0[s + 1] + C.tx[n.xm] * x0[s - 1] +
-                        C.ty[n.c] * x0[s + kE1X] + C.ty[n.ym] * x0[s - kE1X] +
-                        C.tz[n.c] * xp[s] + C.tz[n.zm] * xm[s];
-          v = (f(n.c) + sum) * recip(C.d[n.c]);
-        } else {
-          v = x0[s];
-        }
-        if constexpr (L0) {
-          const double z = (double)v * s_out;
-          const double r = P.r[n.c];
-          if (flexible) rzo += r * P.z[n.c];
-          P.z[n.c] = z;
-          rz += r * z;
-        } else {
-          xout[n.c] = v;
-        }
+      const bool red00 = (pr2 & 1) == 0;  // (0,0), (1,1) red; else (1,0), (0,1)
+      const int o = (2 * cj + 1) * kE1X + 2 * ci + 1;
+      R v00, v10, v01, v11;
+      if (red00) {
+        v00 = (scaled<R, L0>(H.v00, inv_s) +
+               red_sum(cell_faces<0>(Fr, Zr, Zrm, false), xm, x0, xp, o)) * I2.v00;
+        v10 = x0[o + 1];
+        v01 = x0[o + kE1X];
+        v11 = (scaled<R, L0>(H.v11, inv_s) +
+               red_sum(cell_faces<1>(Fr, Zr, Zrm, true), xm, x0, xp, o + kE1X + 1)) *
+              I2.v11;
+      } else {
+        v00 = x0[o];
+        v10 = (scaled<R, L0>(H.v10, inv_s) +
+               red_sum(cell_faces<0>(Fr, Zr, Zrm, true), xm, x0, xp, o + 1)) * I2.v10;
+        v01 = (scaled<R, L0>(H.v01, inv_s) +
+               red_sum(cell_faces<1>(Fr, Zr, Zrm, false), xm, x0, xp, o + kE1X)) *
+              I2.v01;
+        v11 = x0[o + kE1X + 1];
+      }
+      if constexpr (L0) {
+        const double z00 = (double)v00 * s_out, z10 = (double)v10 * s_out;
+        const double z01 = (double)v01 * s_out, z11 = (double)v11 * s_out;
+        if (flexible) rzo += H.v00 * zo00;
+        rz += H.v00 * z00;
+        if (flexible) rzo += H.v10 * zo10;
+        rz += H.v10 * z10;
+        if (flexible) rzo += H.v01 * zo01;
+        rz += H.v01 * z01;
+        if (flexible) rzo += H.v11 * zo11;
+        rz += H.v11 * z11;
+        st2(P.z + o0, z00, z10);
+        st2(P.z + o0 + nx, z01, z11);
+      } else {
+        st2(xout + o0, v00, v10);
+        st2(xout + o0 + nx, v01, v11);
       }
     }
   }
