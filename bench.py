@@ -199,6 +199,8 @@ def parse():
     ap.add_argument("--tail-cells", type=int, default=0,
                     help="coarse levels of at most this many cells run in "
                          "one workgroup per V-cycle")
+    ap.add_argument("--fused-levels", type=int, default=0,
+                    help="levels run by the fused V(1,1) passes (0: automatic)")
     ap.add_argument("--smoother", type=int, default=0,
                     help="multigrid smoother: 0 red/black Gauss-Seidel, "
                          "1 weighted Jacobi")
@@ -248,6 +250,7 @@ def run_form(fld, torch, p, prec, steps, warmup, args):
                                      prolongation=args.prolongation,
                                      tail_cells=args.tail_cells,
                                      smoother=args.smoother,
+                                     fused_levels=args.fused_levels,
                                      check_every=args.check_every)
         return fld.Solver(p["shape"], p["h"], prm)
 

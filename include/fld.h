@@ -137,7 +137,11 @@ typedef struct fld_params {
                           the coarsest level (measured no faster with more on
                           gfx950) */
   int32_t smoother;    /* fld_smoother; default FLD_SMOOTH_RBGS */
-  int32_t reserved;
+  int32_t fused_levels;/* under V(1,1) red/black: the finest fused_levels
+                          levels run the two fused passes (coarse ones with
+                          8-plane tiles); 0 = automatic (the finest level, and
+                          each coarser one that still holds at least 2^20
+                          cells over all problems) */
 } fld_params;
 
 typedef struct fld_stats {
@@ -166,7 +170,8 @@ typedef struct fld_server fld_server;
  * max_iter = 50, nu_pre = nu_post = 1, theta = 1, tau_tol = 1e-4, FP64,
  * coarse_scale = 0.5, max_dt_cuts = 8, graph replay on, cycle_switch = 12,
  * prolongation = 2 (trilinear in the mixed cycle once it has switched to
- * V(2,2)), warm_start = 1, tail_cells = 0, smoother = FLD_SMOOTH_RBGS. */
+ * V(2,2)), warm_start = 1, tail_cells = 0, smoother = FLD_SMOOTH_RBGS,
+ * fused_levels = 0. */
 void fld_default_params(fld_params *p, double c, double L_unit);
 
 const char *fld_strerror(fld_status s);

@@ -45,6 +45,7 @@ bool params_ok(const fld_params &p) {
   if (p.tail_cells < 0) return false;
   if (p.prolongation < 0 || p.prolongation > 2) return false;
   if (p.smoother != FLD_SMOOTH_RBGS && p.smoother != FLD_SMOOTH_JACOBI) return false;
+  if (p.fused_levels < 0 || p.fused_levels > kMaxLevels) return false;
   // the single-workgroup tail smooths red/black: keep it to the coarsest
   // level under the Jacobi smoother
   if (p.smoother == FLD_SMOOTH_JACOBI && p.tail_cells > 0) return false;
@@ -70,7 +71,7 @@ Hier make_hier(const fld_grid &g, const fld_params &p) {
   }
   for (int l = 0; l < h.levels; ++l) {
     h.tiles[l] = count_tiles(p, h.n[l][0], h.n[l][1], h.n[l][2]);
-    h.ftiles[l] = count_fused_tiles(p, h.n[l][0], h.n[l][1], h.n[l][2]);
+    h.ftiles[l] = count_fused_tiles(p, l, h.n[l][0], h.n[l][1], h.n[l][2]);
   }
   // the tail: the coarsest level, and above it every level below the finest
   // with at most tail_cells cells
@@ -80,21 +81,23 @@ Hier make_hier(const fld_grid &g, const fld_params &p) {
 }
 
 // Tiles of the fused one-sweep V-cycle kernels: 64 x 16 cells in x, y (their
-// LDS buffers are sized for that) and fused_tile_z planes in z.  Deeper tiles
-// cut the z-halo but leave fewer tiles to hide latency: measured on gfx950 at
-// 256^3 (Mcell-updates/s for 8, 16, 32, 64 planes: FP32 cycle 2532, 2537,
-// 2608, 2451; FP64 2203, 2268, 2308, 2217), 32 planes suit both.
-void fused_shape(const fld_params &p, int nx, int ny, int nz, int &tx, int &ty,
-                 int &tz) {
+// LDS buffers are sized for that) and fused_tile_z planes in z on the finest
+// level.  Deeper tiles cut the z-halo but leave fewer tiles to hide latency:
+// measured on gfx950 at 256^3 (Mcell-updates/s for 8, 16, 32, 64 planes: FP32
+// cycle 2532, 2537, 2608, 2451; FP64 2203, 2268, 2308, 2217), 32 planes suit
+// both.  Coarse levels that run the fused passes are 8x smaller and use 8
+// planes, so that they still give a tile per CU.
+void fused_shape(const fld_params &p, int l, int nx, int ny, int nz, int &tx,
+                 int &ty, int &tz) {
   tx = std::min(nx, 64);
   ty = std::min(ny, 16);
-  const int def = 32;
-  tz = std::min(nz, p.fused_tile_z > 0 ? p.fused_tile_z : def);
+  const int def = l == 0 ? (p.fused_tile_z > 0 ? p.fused_tile_z : 32) : 8;
+  tz = std::min(nz, def);
 }
 
-int count_fused_tiles(const fld_params &p, int nx, int ny, int nz) {
+int count_fused_tiles(const fld_params &p, int l, int nx, int ny, int nz) {
   int tx, ty, tz;
-  fused_shape(p, nx, ny, nz, tx, ty, tz);
+  fused_shape(p, l, nx, ny, nz, tx, ty, tz);
   return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz);
 }
 
@@ -259,6 +262,20 @@ int Engine::setup(const fld_params &p, hipStream_t s,
   // problem, then the fused-cycle tiles, so both finest tilings come first
   // (their indices are the partial-sum slots)
   fused = fused_cycle(p);
+  // levels run by the fused passes: the finest, then each coarser one while
+  // it still holds 2^20 cells over all problems (or fused_levels of them)
+  fused_top = 1;
+  if (p.fused_levels > 0) {
+    fused_top = std::min(p.fused_levels, Lmax);
+  } else {
+    for (int l = 1; l < Lmax; ++l) {
+      long long c = 0;
+      for (int i = 0; i < np; ++i)
+        if (l < hier[i].levels) c += hier[i].cells(l);
+      if (c < (1LL << 20)) break;
+      fused_top = l + 1;
+    }
+  }
   h_tiles.clear();
   tbeg.assign((size_t)np * kMaxLevels, 0);
   fbeg.assign((size_t)np * kMaxLevels, 0);
@@ -292,7 +309,7 @@ int Engine::setup(const fld_params &p, hipStream_t s,
       fbeg[(size_t)i * kMaxLevels + l] = (int)h_tiles.size();
       const int nx = hier[i].n[l][0], ny = hier[i].n[l][1], nz = hier[i].n[l][2];
       int tx, ty, tz;
-      fused_shape(prm, nx, ny, nz, tx, ty, tz);
+      fused_shape(prm, l, nx, ny, nz, tx, ty, tz);
       emit(i, nx, ny, nz, tx, ty, tz);
     }
   }
@@ -360,7 +377,9 @@ int Engine::build_lists(const std::vector<char> &member, int slot, ListSet &out)
     out.exist[l] = make(l, [&](int) { return l >= 1; });
     out.down[l] = make(l, [&](int i) { return l >= 1 && l <= hier[i].tail; });
     out.fsm[l] = make_any(l, true, smoothed);
-    out.fdn[l] = make_any(l, true, [&](int i) { return l < hier[i].levels - 1; });
+    out.fdn[l] = make_any(l, true, [&](int i) {
+      return smoothed(i) && l < hier[i].levels - 1;
+    });
   }
   if (h_ranges.size() > per_slot) return ST_EINVAL;
   if (!h_ranges.empty())
@@ -457,17 +476,25 @@ void Engine::enqueue_vcycle(const ListSet &ls) {
   const int tri = (mixed && (prm.prolongation == 1 ||
                              (prm.prolongation == 2 && switched))) ? 1 : 0;
   if (fused) {
-    // one sweep each way: the finest level runs the two fused passes (they
-    // never store the pre-smoothed x); coarse levels, latency-bound small
-    // grids, run the per-half-sweep kernels
-    launch_vdown(T, ls.fdn[0], 0, prec, stream);
-    for (int l = 1; l < Lmax; ++l) {
+    // one sweep each way: the finest level, and the coarse levels with enough
+    // cells to fill the GPU, run the two fused passes (they never store the
+    // pre-smoothed x); the smaller, latency-bound levels run the
+    // per-half-sweep kernels
+    for (int l = 0; l < Lmax; ++l) {
+      if (l < fused_top) {
+        launch_vdown(T, ls.fdn[l], l, prec, stream);
+        continue;
+      }
       if (ls.smooth[l].nblocks == 0) continue;
       launch_pre0(T, ls.smooth[l], l, prec, stream);
       if (l + 1 < Lmax) launch_resid_restrict(T, ls.down[l + 1], l + 1, prec, stream);
     }
     if (Lmax > 1) launch_vtail(T, prec, 1, 1, tri, stream);
     for (int l = Lmax - 1; l >= 1; --l) {
+      if (l < fused_top) {
+        launch_vup(T, ls.fsm[l], l, prec, 0, tri, stream);
+        continue;
+      }
       if (ls.smooth[l].nblocks == 0) continue;
       launch_prolong_black(T, ls.smooth[l], l, prec, tri, stream);
       launch_half(T, ls.smooth[l], l, 0, prec, stream);

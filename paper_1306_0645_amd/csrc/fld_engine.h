@@ -42,9 +42,9 @@ Hier make_hier(const fld_grid &g, const fld_params &p);
 void tile_shape(const fld_params &p, int nx, int ny, int nz, int &tx, int &ty,
                 int &tz);
 int count_tiles(const fld_params &p, int nx, int ny, int nz);
-void fused_shape(const fld_params &p, int nx, int ny, int nz, int &tx, int &ty,
-                 int &tz);
-int count_fused_tiles(const fld_params &p, int nx, int ny, int nz);
+void fused_shape(const fld_params &p, int l, int nx, int ny, int nz, int &tx,
+                 int &ty, int &tz);
+int count_fused_tiles(const fld_params &p, int l, int nx, int ny, int nz);
 bool fused_cycle(const fld_params &p);
 size_t problem_bytes(const Hier &h, const fld_params &p);
 size_t tables_bytes(const std::vector<Hier> &hs);
@@ -100,6 +100,7 @@ class Engine {
   std::vector<int> tbeg;   // [p * kMaxLevels + l] first tile of (p, l)
   std::vector<int> fbeg;   // [p * kMaxLevels + l] first fused tile of (p, l)
   bool fused = false;      // one-sweep fused V-cycle kernels
+  int fused_top = 1;       // levels 0 .. fused_top - 1 run the fused passes
   int last_nu = 1;         // sweeps per side of the cycle used by the last solve
   bool switched = false;   // the adaptive switch moved the handle to V(2,2)
   // per problem warm-start history: prev_ok = 0 none, 1 x holds the dE of

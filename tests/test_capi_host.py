@@ -70,7 +70,8 @@ def test_workspace_sizing_and_validation(fld):
         assert fld.fld_workspace_bytes(fld.make_grid(bad, (1, 1, 1)), p) == 0
     assert fld.fld_workspace_bytes(fld.make_grid((8, 8, 8), (1, -1, 1)), p) == 0
     for field, val in [("theta", 0.3), ("c", 0.0), ("nu_pre", 0),
-                       ("precision", 7), ("max_iter", 0), ("smoother", 2)]:
+                       ("precision", 7), ("max_iter", 0), ("smoother", 2),
+                       ("fused_levels", -1), ("fused_levels", 13)]:
         q = fld.fld_default_params(1.0, 1.0, **{field: val})
         assert fld.fld_workspace_bytes(g, q) == 0, field
     # the Jacobi smoother keeps the single-workgroup tail to the coarsest level

@@ -541,3 +541,16 @@ def test_jacobi_fp64_preconditioner_is_symmetric_positive(fld):
     ratio = math.sqrt(np.vdot(e2, Ae2) / np.vdot(u, Ae))
     print(f"[jacobi vcycle] A-norm contraction {ratio:.3f}", flush=True)
     assert ratio < 0.7
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fused_coarse_levels_match_oracle(fld, oracle_mod, prec):
+    """Every level above the coarsest of a 128 x 96 x 64 grid in the fused
+    passes (fused_levels = 4; the automatic rule fuses a coarse level only
+    from 2^20 cells): the solve meets the gates."""
+    log_case("fused_coarse", prec=prec)
+    p = _problem((64, 96, 128), 45, dt_factor=0.5)
+    S, prm = _solver(fld, p, precision=prec, fused_levels=4, cycle_switch=0)
+    _assemble(S, p)
+    dE, st = S.solve()
+    _check_solution(oracle_mod, p, prm, host(dE), st, prec, "fused_coarse")

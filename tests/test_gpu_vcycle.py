@@ -129,16 +129,22 @@ def test_textbook_cycle_helpers():
     assert np.allclose(x, _solve_exact(op, f), rtol=0, atol=1e-10 * np.abs(x).max())
 
 
+CYCLES = [(nu, levels, fl) for nu, fl in ((1, 0), (1, 9), (2, 0)) for levels in (2, 3)]
+
+
 @pytest.mark.gpu
-@pytest.mark.parametrize("levels", [2, 3])
-@pytest.mark.parametrize("nu", [1, 2])
+@pytest.mark.parametrize("nu,levels,fused_levels", CYCLES)
 @pytest.mark.parametrize("prec", [0, 1])
-def test_vcycle_is_the_textbook_cycle(fld, oracle_mod, prec, nu, levels):
-    log_case("vcycle", prec=prec, nu=nu, levels=levels)
+def test_vcycle_is_the_textbook_cycle(fld, oracle_mod, prec, nu, levels,
+                                      fused_levels):
+    """fused_levels = 9: every level above the coarsest runs the fused passes
+    (its coarse tiles ragged in y and z); 0: only the finest."""
+    log_case("vcycle", prec=prec, nu=nu, levels=levels, fused=fused_levels)
     shape = (24, 40, 96)  # [z][y][x]: ragged 64 x 16 fused tiles in x and y
     p = synth.random_problem(shape, 61, sigma_ln=1.5, n_src=3, dt_factor=0.5)
     prm = params(fld, p, precision=prec, mg_levels=levels, nu_pre=nu,
-                 nu_post=nu, cycle_switch=0, fused_tile_z=8)
+                 nu_post=nu, cycle_switch=0, fused_tile_z=8,
+                 fused_levels=fused_levels)
     S = fld.Solver(p["shape"], p["h"], prm)
     S.assemble(dev(p["E"]), dev(p["kappa"]), dev(p["eta"]), p["dt"], p["a"], 0.0)
     f = np.random.default_rng(7).normal(size=shape)
@@ -150,5 +156,6 @@ def test_vcycle_is_the_textbook_cycle(fld, oracle_mod, prec, nu, levels):
         ops.append(_coarsen(ops[-1], prm.coarse_scale))
     zr = _vcycle(ops, 0, f, nu)
     err = rel_l2(z, zr)
-    print(f"[vcycle] prec={prec} nu={nu} levels={levels} err={err:.2e}", flush=True)
+    print(f"[vcycle] prec={prec} nu={nu} levels={levels} fused={fused_levels} "
+          f"err={err:.2e}", flush=True)
     assert err <= (1e-9 if prec == 0 else 2e-5)
