@@ -33,6 +33,10 @@ BYTES_PER_CELL = {
     # and written besides E, kappa, eta in and the system out
     "assemble": (104.0, 120.0),
     "spmv_p": (64.0, 64.0),
+    # fused iteration's SpMV: also x += alpha p_old (x read and written)
+    "spmv_px": (80.0, 80.0),
+    # the deferred x += alpha p when a solve stops iterating
+    "xfix": (24.0, 24.0),
     "update": (48.0, 48.0),
     "pre0_fine": (48.0, 28.0),
     "half_fine": (56.0, 32.0),
@@ -41,7 +45,9 @@ BYTES_PER_CELL = {
     "prolong_black_fine": (57.0, 32.5),
     "true_resid": (56.0, 56.0),
     "update_E": (24.0, 24.0),
-    "vdown_fine": (41.0, 24.5),
+    # fused down pass; in the mixed form it also reads q and writes the
+    # updated residual r - alpha q (the first iteration of a solve skips both)
+    "vdown_fine": (41.0, 40.5),
     "vup_fine": (49.0, 40.5),
     "warm_resid": (56.0, 56.0),
     # weighted-Jacobi smoother: first sweep from zero (diag, f, x out), a
@@ -72,7 +78,7 @@ def coarse_fraction(levels):
     return sum(8.0 ** -l for l in range(1, levels))
 
 
-STEP_KERNELS = ("assemble", "true_resid", "update_E", "warm_resid")
+STEP_KERNELS = ("assemble", "true_resid", "update_E", "warm_resid", "xfix")
 
 
 def step_bytes(counts, cells, prec_idx, levels):
@@ -106,14 +112,21 @@ def model_step_bytes(cells, iters, nu, prec_idx, levels, steps=1, warm=False):
     cf = coarse_fraction(levels)
     coarse = (COARSE_CYCLE_BYTES[prec_idx]
               + (4 * (nu - 1)) * (56.0, 32.0)[prec_idx])
-    if nu == 1:
-        fine = B["vdown_fine"] + B["vup_fine"]
+    if nu == 1 and prec_idx == 1:
+        # fused mixed iteration: the residual update rides in the down pass
+        # and the x update in the SpMV
+        per_iter = B["vdown_fine"] + B["vup_fine"] + cf * coarse + B["spmv_px"]
+    elif nu == 1:
+        per_iter = (B["vdown_fine"] + B["vup_fine"] + cf * coarse + B["spmv_p"]
+                    + B["update"])
     else:
         fine = (B["pre0_fine"] + B["resid_restrict_fine"] + B["prolong_black_fine"]
                 + B["half_out"] + (4 * (nu - 1)) * B["half_fine"])
-    per_iter = fine + cf * coarse + B["spmv_p"] + B["update"]
+        per_iter = fine + cf * coarse + B["spmv_p"] + B["update"]
     coarsen = 32.0 * (1.0 + cf - 8.0 ** -(levels - 1)) + (48.0 if prec_idx else 32.0) * cf
     fixed = B["assemble"] + coarsen + B["true_resid"] + B["update_E"]
+    if nu == 1 and prec_idx == 1:
+        fixed += B["xfix"]
     if warm:  # the residual of the seeded initial guess
         fixed += B["warm_resid"]
     else:     # a cold assembly neither reads the guess nor keeps history

@@ -170,12 +170,20 @@ struct FSrc {
   }
 };
 
+// the current residual buffer, and the other one
+__device__ __forceinline__ double *rcur(const ProbDev &P, const Scal &sc) {
+  return sc.rbuf ? P.r2 : P.r;
+}
+__device__ __forceinline__ double *rnext(const ProbDev &P, const Scal &sc) {
+  return sc.rbuf ? P.r : P.r2;
+}
+
 template <typename R, bool L0>
 __device__ __forceinline__ FSrc<R, L0> fsrc(const LevelDev &L, const ProbDev &P,
                                              const Scal &sc) {
   FSrc<R, L0> s;
   s.f = (const R *)L.f;
-  s.r = P.r;
+  s.r = rcur(P, sc);
   s.inv_s = sc.inv_s;
   return s;
 }

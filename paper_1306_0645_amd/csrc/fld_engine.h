@@ -46,6 +46,7 @@ void fused_shape(const fld_params &p, int l, int nx, int ny, int nz, int &tx,
                  int &ty, int &tz);
 int count_fused_tiles(const fld_params &p, int l, int nx, int ny, int nz);
 bool fused_cycle(const fld_params &p);
+bool lazy_iteration(const fld_params &p);
 size_t problem_bytes(const Hier &h, const fld_params &p);
 size_t tables_bytes(const std::vector<Hier> &hs);
 
@@ -100,6 +101,7 @@ class Engine {
   std::vector<int> tbeg;   // [p * kMaxLevels + l] first tile of (p, l)
   std::vector<int> fbeg;   // [p * kMaxLevels + l] first fused tile of (p, l)
   bool fused = false;      // one-sweep fused V-cycle kernels
+  bool lazy = false;       // fused PCG iteration (residual update in the down pass)
   int fused_top = 1;       // levels 0 .. fused_top - 1 run the fused passes
   int last_nu = 1;         // sweeps per side of the cycle used by the last solve
   bool switched = false;   // the adaptive switch moved the handle to V(2,2)
@@ -140,8 +142,9 @@ class Engine {
   int adapt_cycle(int max_iters);
 
   void enqueue_assemble(const ListSet &ls);
-  void enqueue_vcycle(const ListSet &ls);
+  void enqueue_vcycle(const ListSet &ls, bool in_iteration = false);
   void enqueue_iteration(const ListSet &ls);
+  void finish_x(const ListSet &ls);
   int run_solve();
   int run_steps(std::vector<Job> &jobs);
   int check_every() const;

@@ -281,6 +281,31 @@ __device__ __forceinline__ void q_load_plane(
   }
 }
 
+// q of plane pz at the quad's cells and this thread's halo cells (same cells
+// as q_load_plane)
+__device__ __forceinline__ void q_load_q(double (&qq)[4], double (&hq)[kHalo],
+                                         const double *q, const Tile &t, int pz,
+                                         bool qon, int qx, int qy, int nx, int ny,
+                                         int nz) {
+  const int kz = wrapi(pz, nz);
+  if (qon) {
+    const int r0 = (kz * ny + qy) * nx + qx;
+    ld2(q + r0, qq[0], qq[1]);
+    ld2(q + r0 + nx, qq[2], qq[3]);
+  }
+  const int e2x = t.tx + 4, nh = 4 * e2x + 4 * t.ty;
+#pragma unroll
+  for (int u = 0; u < kHalo; ++u) {
+    const int c = threadIdx.x + u * kBlock;
+    if (c < nh) {
+      int ex, ey;
+      halo_cell(c, t.tx, t.ty, ex, ey);
+      const int gx = wrapi(t.x0 - 2 + ex, nx), gy = wrapi(t.y0 - 2 + ey, ny);
+      hq[u] = q[(kz * ny + gy) * nx + gx];
+    }
+  }
+}
+
 template <typename R, bool L0>
 __device__ __forceinline__ R scaled(typename QPlane<R, L0, false>::FT v, double inv_s) {
   if constexpr (L0) return (R)(v * inv_s);
@@ -336,12 +361,15 @@ __device__ __forceinline__ Q4<R> q_store_plane(const QPlane<R, L0, UP> &pl,
 
 template <typename R, bool L0>
 __global__ __launch_bounds__(kBlock) void k_vdown(Tables T, TileList TL, int l) {
-  const Tile t = get_tile(TL);
+  const int tid = get_tile_index(TL);
+  const Tile t = TL.base[tid];
   const Scal &sc = T.sc[t.prob];
   if (!sc.active) return;
   const LevelDev L = T.lv[l * T.nprob + t.prob];
-  const LevelDev Cv = T.lv[(l + 1) * T.nprob + t.prob];
   const ProbDev P = T.pd[t.prob];
+  // a one-level problem runs this pass only for the residual update
+  const bool has_coarse = l + 1 < P.levels;
+  const LevelDev Cv = T.lv[(has_coarse ? l + 1 : l) * T.nprob + t.prob];
   const Coef<R> C = coefs<R>(L);
   const auto f = fsrc<R, L0>(L, P, sc);
   const double inv_s = sc.inv_s;
@@ -355,9 +383,24 @@ __global__ __launch_bounds__(kBlock) void k_vdown(Tables T, TileList TL, int l) 
   const int qxl = wrapi(qx - 1, nx), qyb = wrapi(qy - 1, ny);
   const int rq = threadIdx.x / 3;
   const bool ron = threadIdx.x == 3 * rq && rq < t.tx + t.ty;
+  // finest level of the fused PCG iteration: this iteration's residual is
+  // r - alpha q (alpha, q of the previous iteration), formed on the fly for
+  // every y plane, halo included, and written to the other residual buffer
+  // for the tile's own cells, with its partial ||.||^2
+  // (mixed precision only: the FP64 iteration updates r in a pass of its own)
+  constexpr bool kUpd = L0 && sizeof(R) == 4;
+  const bool upd = kUpd && sc.has_dir;
+  const double alpha = sc.alpha;
+  const double *qv = P.q;
+  double *rn = rnext(P, sc);
+  double qq[4] = {0.0, 0.0, 0.0, 0.0}, hq[kHalo] = {};
+  double rr = 0.0;
   QPlane<R, L0, false> pl;
   q_load_plane<R, L0, false, false>(pl, t, t.z0 - 2, qon, qx, qy, nx, ny, nz, f,
                                     C.d, nullptr, false, 0, 0, 0);
+  if constexpr (kUpd) {
+    if (upd) q_load_q(qq, hq, qv, t, t.z0 - 2, qon, qx, qy, nx, ny, nz);
+  }
   QFace<R> Fb{}, Fr{};  // in-plane faces of planes pz - 1 (black), pz - 2 (red)
   Q4<R> Zb{}, Zr{}, Zrm{};  // Tz of planes pz - 1, pz - 2, pz - 3
   Q4<R> I0{}, I1{};  // diagonal reciprocals of planes pz, pz - 1
@@ -373,11 +416,34 @@ __global__ __launch_bounds__(kBlock) void k_vdown(Tables T, TileList TL, int l) 
       load_faces(Fb, Zb, C, wrapi(pb, nz), qx, qy, qxl, qyb, nx, ny, m >= 2);
     if (m >= 2 && ron) load_ring(rc, C, t, rq, pb, nx, ny, nz);
     // (1) y = f / d on plane pz (loaded one iteration ahead)
+    if constexpr (kUpd) {
+      if (upd) {
+        pl.f00 = __builtin_fma(-alpha, qq[0], pl.f00);
+        pl.f10 = __builtin_fma(-alpha, qq[1], pl.f10);
+        pl.f01 = __builtin_fma(-alpha, qq[2], pl.f01);
+        pl.f11 = __builtin_fma(-alpha, qq[3], pl.f11);
+#pragma unroll
+        for (int u = 0; u < kHalo; ++u) pl.hf[u] = __builtin_fma(-alpha, hq[u], pl.hf[u]);
+        if (qon && pz >= t.z0 && pz < t.z0 + t.tz) {
+          const int r0 = (pz * ny + qy) * nx + qx;
+          st2(rn + r0, pl.f00, pl.f10);
+          st2(rn + r0 + nx, pl.f01, pl.f11);
+          rr += pl.f00 * pl.f00;
+          rr += pl.f10 * pl.f10;
+          rr += pl.f01 * pl.f01;
+          rr += pl.f11 * pl.f11;
+        }
+      }
+    }
     I1 = I0;
     I0 = q_store_plane<R, L0, false>(pl, t, pz, qon, ci, cj, ys[m % 3], inv_s);
-    if (m + 1 < t.tz + 4)
+    if (m + 1 < t.tz + 4) {
       q_load_plane<R, L0, false, false>(pl, t, pz + 1, qon, qx, qy, nx, ny, nz, f,
                                         C.d, nullptr, false, 0, 0, 0);
+      if constexpr (kUpd) {
+        if (upd) q_load_q(qq, hq, qv, t, pz + 1, qon, qx, qy, nx, ny, nz);
+      }
+    }
     __syncthreads();
     // (2) black cells of plane pb over the tile + 1
     if (m >= 2) {
@@ -407,11 +473,13 @@ __global__ __launch_bounds__(kBlock) void k_vdown(Tables T, TileList TL, int l) 
       acc += red_sum(cell_faces<0>(Fr, Zr, Zrm, r0), xm, x0, xp, o + r0);
       acc += red_sum(cell_faces<1>(Fr, Zr, Zrm, r1), xm, x0, xp, o + kE1X + r1);
       if ((pr2 - t.z0) & 1) {
-        fc[((pr2 >> 1) * Cv.ny + (t.y0 >> 1) + cj) * Cv.nx + (t.x0 >> 1) + ci] = acc;
+        if (has_coarse)
+          fc[((pr2 >> 1) * Cv.ny + (t.y0 >> 1) + cj) * Cv.nx + (t.x0 >> 1) + ci] = acc;
         acc = 0;
       }
     }
   }
+  if constexpr (kUpd) write_partials(T, tid, rr, 0.0);
 }
 
 template <typename R, bool L0, bool TRI>

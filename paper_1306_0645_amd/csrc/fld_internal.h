@@ -50,6 +50,7 @@ struct LevelDev {
 struct ProbDev {
   int nx, ny, nz, n;
   double *x, *r, *z, *p0, *p1, *q, *b;
+  double *r2;            // second residual buffer (fused V(1,1) iteration)
   double *xh;            // dE of the step before the last (warm-start history)
   double *cs;            // coarsest-level CG scratch: 4 * n_coarsest doubles
   int levels;            // number of multigrid levels
@@ -75,11 +76,16 @@ struct Scal {
   double rr_true, tol2;  // true residual^2; rtol^2
   double change2;        // sum of (dE / max(|E|, floor))^2
   double dEdE;           // ||dE||^2
+  double s_next;         // residual scale for the next V-cycle (snew set)
   int iter, max_iter, phase, status;
   int active, restart, pbuf, restarts;
   int live;              // takes part in the current assembly / update
   int cold;              // the warm guess did not reduce ||r||: start from 0
-  int pad[2];
+  // fused iteration: the residual lives in r (rbuf = 0) or r2 (rbuf = 1);
+  // has_dir: alpha, p and q of a previous iteration exist, so the down pass
+  // forms r - alpha q; xlag: x still lacks alpha p (added by the next SpMV,
+  // or by k_xfix when the iteration stops)
+  int rbuf, has_dir, xlag, snew;
 };
 
 // A tile: cells [x0, x0+tx) x [y0, y0+ty) x [z0, z0+tz) of one level of one
@@ -119,7 +125,7 @@ enum : int {
   K_COARSE_SOLVE, K_SPMV_P, K_UPDATE, K_TRUE_RESID, K_APPLY, K_SET_R,
   K_UPDATE_E, K_VDOWN_F, K_VDOWN_C, K_VUP_F, K_VUP_C, K_CHEM_H, K_ION_SUM,
   K_WARM_RESID, K_WARM_REVERT, K_JACOBI0_F, K_JACOBI_F, K_JACOBI_OUT,
-  K_JACOBI_C, K_PROLONG_ADD_F, K_PROLONG_ADD_C, K_NUM
+  K_JACOBI_C, K_PROLONG_ADD_F, K_PROLONG_ADD_C, K_SPMV_PX, K_XFIX, K_NUM
 };
 
 // Brackets one launch with hipEvents when its kernel id is selected.
@@ -143,7 +149,8 @@ void launch_assemble(const Tables &T, TileList L0, double c, double theta,
                      double dmax, double rmin, int mixed, hipStream_t s);
 void launch_coarsen(const Tables &T, TileList coarse, int lc, double scale,
                     int mixed, hipStream_t s);
-// alt: FIN_RZ reads the partials of the fused finest tiles
+// alt: FIN_RZ and FIN_RR2 read the partials of the fused finest tiles; FIN_PQ
+// with alt marks the fused iteration's deferred updates
 void launch_fin(const Tables &T, int which, int mixed, hipStream_t s,
                 int alt = 0);
 void launch_pre0(const Tables &T, TileList L, int l, int prec, hipStream_t s);
@@ -165,7 +172,11 @@ void launch_jacobi(const Tables &T, TileList L, int l, int prec, int mode,
 // x (or x2) = x + P e: the coarse-grid correction of every cell
 void launch_prolong_add(const Tables &T, TileList L, int l, int prec,
                         int trilinear, int to_x2, hipStream_t s);
-void launch_spmv_p(const Tables &T, TileList L0, hipStream_t s);
+// lazy = 1 (fused iteration): also x += alpha p_old, the update deferred
+// from the previous iteration
+void launch_spmv_p(const Tables &T, TileList L0, int lazy, hipStream_t s);
+// x += alpha p for problems that stopped iterating with the update pending
+void launch_xfix(const Tables &T, TileList L0, hipStream_t s);
 void launch_update(const Tables &T, TileList L0, hipStream_t s);
 void launch_true_resid(const Tables &T, TileList L0, hipStream_t s);
 void launch_warm_resid(const Tables &T, TileList L0, hipStream_t s);
@@ -190,7 +201,10 @@ enum : int {
   FIN_TRUE = 4,   // after the true residual: verify or restart
   FIN_STEP = 5,   // after E += dE: relative change and ||dE||^2
   FIN_SETR = 6,   // after loading an external r (preconditioner test)
-  FIN_WARM = 7    // after r = b - A x0 for a warm start
+  FIN_WARM = 7,   // after r = b - A x0 for a warm start
+  FIN_RR2 = 8,    // fused iteration, after the down pass formed r - alpha q:
+                  // ||r||^2, convergence, switch the residual buffer
+  FIN_XFIX = 9    // after k_xfix: the deferred x update is done
 };
 
 }  // namespace fld

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
   double *__restrict__ Tz = L.Tz;
   double *__restrict__ Dg = L.diag;
   double *__restrict__ bv = P.b;
-  double *__restrict__ rv = P.r;
+  double *__restrict__ rv = rcur(P, sc);
   double *__restrict__ xv = P.x;
   double bb = 0.0;
   if (col.on) {
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_half_out(Tables T, TileList TL,
       const bool red = ((col.i + col.j + k) & 1) == 0;
       if (red) v = (f(n.c) + offsum(C, n, xv)) * recip(C.d[n.c]);
       else v = x[n.c];
-      const double rv = P.r[n.c];
+      const double rv = f.r[n.c];
       double zv;
       if constexpr (sizeof(R) == 8) {
         // FP64: the finest iterate is z itself
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(Tables T, TileList TL, int l,
         if (mode == 2) {
           // z = s x in FP64 (the FP64 finest iterate is z itself)
           const double zv = (double)v * sc.s;
-          const double rv = P.r[n.c];
+          const double rv = f.r[n.c];
           if (flexible) rzo += rv * P.z[n.c];
           P.z[n.c] = zv;
           rz += rv * zv;
@@ -675,13 +675,16 @@ __global__ __launch_bounds__(kTailBlock) void k_vtail(Tables T, int nu_pre,
 // the old direction while the new one is written.  Each thread walks its
 // column in z keeping p_new at planes k-1, k, k+1 and the -z face in
 // registers.
-template <bool BETA>
+// LAZY: also x += alpha_old p_old at the cell (the fused iteration defers
+// that update of the previous iteration to here, where p_old is read anyway).
+template <bool BETA, bool LAZY>
 __device__ __forceinline__ double spmv_column(
     const Tile &t, const Col &col, int nx, int ny, int nz, double beta,
     const double *__restrict__ z, const double *__restrict__ po,
     double *__restrict__ pn, double *__restrict__ q,
     const double *__restrict__ Tx, const double *__restrict__ Ty,
-    const double *__restrict__ Tz, const double *__restrict__ Dg) {
+    const double *__restrict__ Tz, const double *__restrict__ Dg,
+    double alpha_old, double *__restrict__ x) {
   auto pv = [&](int g) { return BETA ? z[g] + beta * po[g] : z[g]; };
   const int plane = nx * ny, i = col.i, j = col.j;
   const int dxm = (i == 0) ? nx - 1 : -1, dxp = (i == nx - 1) ? 1 - nx : 1;
@@ -698,6 +701,7 @@ __device__ __forceinline__ double spmv_column(
                      Ty[c] * pv(c + dyp) + Ty[c + dym] * pv(c + dym) +
                      Tz[c] * p_p + tz_m * p_m;
     const double qq = Dg[c] * p_c - s;
+    if constexpr (LAZY) x[c] = x[c] + alpha_old * po[c];
     pn[c] = p_c;
     q[c] = qq;
     acc += p_c * qq;
@@ -709,6 +713,7 @@ __device__ __forceinline__ double spmv_column(
   return acc;
 }
 
+template <bool LAZY>
 __global__ __launch_bounds__(kBlock) void k_spmv_p(Tables T, TileList TL) {
   const int tid = get_tile_index(TL);
   const Tile t = TL.base[tid];
@@ -716,20 +721,40 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(Tables T, TileList TL) {
   if (!sc.active) return;
   const LevelDev L = T.lv[t.prob];
   const ProbDev P = T.pd[t.prob];
-  const double beta = sc.beta;
+  const double beta = sc.beta, alpha = sc.alpha;
   const double *po = sc.pbuf ? P.p1 : P.p0;
   double *pn = sc.pbuf ? P.p0 : P.p1;
   const Col col = tile_col(t);
   double pq = 0.0;
   if (col.on) {
-    if (beta != 0.0)
-      pq = spmv_column<true>(t, col, L.nx, L.ny, L.nz, beta, P.z, po, pn, P.q,
-                             L.Tx, L.Ty, L.Tz, L.diag);
+    if (LAZY && sc.xlag)
+      pq = spmv_column<true, true>(t, col, L.nx, L.ny, L.nz, beta, P.z, po, pn,
+                                   P.q, L.Tx, L.Ty, L.Tz, L.diag, alpha, P.x);
+    else if (beta != 0.0)
+      pq = spmv_column<true, false>(t, col, L.nx, L.ny, L.nz, beta, P.z, po, pn,
+                                    P.q, L.Tx, L.Ty, L.Tz, L.diag, 0.0, P.x);
     else
-      pq = spmv_column<false>(t, col, L.nx, L.ny, L.nz, beta, P.z, po, pn, P.q,
-                              L.Tx, L.Ty, L.Tz, L.diag);
+      pq = spmv_column<false, false>(t, col, L.nx, L.ny, L.nz, beta, P.z, po, pn,
+                                     P.q, L.Tx, L.Ty, L.Tz, L.diag, 0.0, P.x);
   }
   write_partials(T, tid, pq, 0.0);
+}
+
+// x += alpha p (the newest direction) for problems that stopped iterating
+// while the fused iteration's x update was still pending
+__global__ __launch_bounds__(kBlock) void k_xfix(Tables T, TileList TL) {
+  const Tile t = get_tile(TL);
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.xlag || sc.phase == PH_ITER) return;
+  const LevelDev L = T.lv[t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const double alpha = sc.alpha;
+  const double *__restrict__ p = sc.pbuf ? P.p1 : P.p0;
+  const Col col = tile_col(t);
+  if (!col.on) return;
+  const int plane = L.nx * L.ny;
+  int c = t.z0 * plane + col.j * L.nx + col.i;
+  for (int k = 0; k < t.tz; ++k, c += plane) P.x[c] = P.x[c] + alpha * p[c];
 }
 
 // x += alpha p, r -= alpha q, partial ||r||^2
@@ -744,7 +769,7 @@ __global__ __launch_bounds__(kBlock) void k_update(Tables T, TileList TL) {
   const double *__restrict__ p = sc.pbuf ? P.p1 : P.p0;
   const double *__restrict__ q = P.q;
   double *__restrict__ x = P.x;
-  double *__restrict__ r = P.r;
+  double *__restrict__ r = rcur(P, sc);
   const Col col = tile_col(t);
   double rr = 0.0;
   if (col.on) {
@@ -779,7 +804,7 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Tables T, TileList TL) {
       for (int e = 0; e < t.cpt; ++e) {
         const Nb n = nbrs(col.i + e, col.j, k, L.nx, L.ny, L.nz);
         const double r = P.b[n.c] - (C.d[n.c] * P.x[n.c] - offsum(C, n, xv));
-        P.r[n.c] = r;
+        rcur(P, sc)[n.c] = r;
         rr += r * r;
       }
     }
@@ -814,7 +839,7 @@ __global__ __launch_bounds__(kBlock) void k_warm_resid(Tables T, TileList TL) {
       for (int e = 0; e < t.cpt; ++e) {
         const Nb n = nbrs(col.i + e, col.j, k, L.nx, L.ny, L.nz);
         const double r = P.b[n.c] - (C.d[n.c] * P.x[n.c] - offsum(C, n, xv));
-        P.r[n.c] = r;
+        rcur(P, sc)[n.c] = r;
         rr += r * r;
       }
     }
@@ -836,7 +861,7 @@ __global__ __launch_bounds__(kBlock) void k_warm_revert(Tables T, TileList TL) {
     const int c0 = (k * L.ny + col.j) * L.nx + col.i;
     for (int e = 0; e < t.cpt; ++e) {
       P.x[c0 + e] = 0.0;
-      P.r[c0 + e] = P.b[c0 + e];
+      rcur(P, sc)[c0 + e] = P.b[c0 + e];
     }
   }
 }
@@ -863,8 +888,10 @@ __global__ __launch_bounds__(kBlock) void k_set_r(Tables T, TileList TL,
                                                   const double *rin) {
   const int tid = get_tile_index(TL);
   const Tile t = TL.base[tid];
+  const Scal &sc = T.sc[t.prob];
   const LevelDev L = T.lv[t.prob];
   const ProbDev P = T.pd[t.prob];
+  double *rv = rcur(P, sc);
   const Col col = tile_col(t);
   double rr = 0.0;
   if (col.on) {
@@ -872,7 +899,7 @@ __global__ __launch_bounds__(kBlock) void k_set_r(Tables T, TileList TL,
       const int c0 = (k * L.ny + col.j) * L.nx + col.i;
       for (int e = 0; e < t.cpt; ++e) {
         const double r = rin[c0 + e];
-        P.r[c0 + e] = r;
+        rv[c0 + e] = r;
         rr += r * r;
       }
     }
@@ -946,8 +973,9 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
   const int p = blockIdx.x;
   Scal &sc = T.sc[p];
   const ProbDev P = T.pd[p];
-  const int t0 = (alt && which == FIN_RZ) ? P.f0 : P.t0;
-  const int t1 = (alt && which == FIN_RZ) ? P.f1 : P.t1;
+  const bool fz = (alt && which == FIN_RZ) || which == FIN_RR2;
+  const int t0 = fz ? P.f0 : P.t0;
+  const int t1 = which == FIN_XFIX ? t0 : (fz ? P.f1 : P.t1);
   bool part;
   switch (which) {
     case FIN_BB:
@@ -957,6 +985,8 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
     case FIN_WARM:
       part = sc.live && T.sd[p].warm > 0.0 && sc.phase == PH_ITER;
       break;
+    case FIN_RR2: part = sc.active && sc.has_dir; break;
+    case FIN_XFIX: part = sc.xlag && sc.phase != PH_ITER; break;
     default: part = sc.active != 0; break;
   }
   if (!part) return;
@@ -993,6 +1023,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
       sc.restart = 1;
       sc.restarts = 0;
       sc.pbuf = 0;
+      sc.has_dir = sc.xlag = sc.snew = 0;
       sc.status = ST_OK;
       sc.phase = PH_ITER;
       sc.active = 1;
@@ -1018,6 +1049,41 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
       if (!(a0 > 0.0)) { fail(sc, ST_ENOCONV); break; }
       sc.alpha = sc.rho / a0;
       sc.pbuf ^= 1;
+      if (alt) {
+        // fused iteration: r -= alpha q happens in the next down pass, x +=
+        // alpha p in the next SpMV; the V-cycle scale changes between cycles
+        sc.has_dir = 1;
+        sc.xlag = 1;
+        if (sc.snew) {
+          sc.s = sc.s_next;
+          sc.inv_s = 1.0 / sc.s_next;
+          sc.snew = 0;
+        }
+      }
+      break;
+    case FIN_RR2:
+      sc.rr = a0;
+      sc.iter += 1;
+      sc.rbuf ^= 1;  // the down pass wrote r - alpha q to the other buffer
+      if (!finite(a0)) { fail(sc, ST_ENONFINITE); break; }
+      if (a0 <= sc.tol2 * sc.bb) {
+        sc.phase = PH_VERIFY;
+        sc.active = 0;
+      } else if (sc.iter >= sc.max_iter) {
+        fail(sc, ST_ENOCONV);
+      }
+      {
+        // scale of the next V-cycle (this one already uses the current s)
+        const double s0 = sc.s, i0 = sc.inv_s;
+        set_scale(sc, P.n, mixed);
+        sc.s_next = sc.s;
+        sc.s = s0;
+        sc.inv_s = i0;
+        sc.snew = 1;
+      }
+      break;
+    case FIN_XFIX:
+      sc.xlag = 0;
       break;
     case FIN_RR:
       sc.rr = a0;
@@ -1044,6 +1110,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
         sc.active = 1;
         sc.restart = 1;
         sc.restarts += 1;
+        sc.has_dir = sc.snew = 0;
         set_scale(sc, P.n, mixed);
       } else {
         fail(sc, ST_ENOCONV);
@@ -1057,12 +1124,14 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
       sc.rr = a0;
       sc.active = 1;
       sc.phase = PH_ITER;
+      sc.has_dir = sc.xlag = sc.snew = 0;
       set_scale(sc, P.n, mixed);
       break;
     case FIN_WARM:
       // PCG from the warm guess (same ||b||, a fresh search direction), or
       // from 0 if the guess does not reduce the residual (k_warm_revert)
       sc.restart = 1;
+      sc.has_dir = sc.xlag = sc.snew = 0;
       sc.cold = !(a0 < sc.bb);
       if (!sc.cold) sc.rr = a0;
       set_scale(sc, P.n, mixed);
@@ -1081,7 +1150,8 @@ static const char *kKernelNames[K_NUM] = {
     "update", "true_resid", "apply", "set_r", "update_E", "vdown_fine",
     "vdown_coarse", "vup_fine", "vup_coarse", "chem_h", "ionized_sum",
     "warm_resid", "warm_revert", "jacobi0_fine", "jacobi_fine", "jacobi_out",
-    "jacobi_coarse", "prolong_add_fine", "prolong_add_coarse"};
+    "jacobi_coarse", "prolong_add_fine", "prolong_add_coarse", "spmv_px",
+    "xfix"};
 
 namespace prof {
 struct Rec {
@@ -1216,8 +1286,14 @@ void launch_vtail(const Tables &T, int prec, int nu_pre, int nu_post,
 }
 
 
-void launch_spmv_p(const Tables &T, TileList L0, hipStream_t s) {
-  if (L0.nblocks) LAUNCH(K_SPMV_P, k_spmv_p, L0.nblocks, kBlock, s, T, L0);
+void launch_spmv_p(const Tables &T, TileList L0, int lazy, hipStream_t s) {
+  if (!L0.nblocks) return;
+  if (lazy) LAUNCH(K_SPMV_PX, k_spmv_p<true>, L0.nblocks, kBlock, s, T, L0);
+  else LAUNCH(K_SPMV_P, k_spmv_p<false>, L0.nblocks, kBlock, s, T, L0);
+}
+
+void launch_xfix(const Tables &T, TileList L0, hipStream_t s) {
+  if (L0.nblocks) LAUNCH(K_XFIX, k_xfix, L0.nblocks, kBlock, s, T, L0);
 }
 
 void launch_update(const Tables &T, TileList L0, hipStream_t s) {

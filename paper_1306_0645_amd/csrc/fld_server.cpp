@@ -228,9 +228,13 @@ int fld_server::tick() {
   TRY(e.build_lists(mS, 2, lsS));
   e.enqueue_iteration(lsS);
   TRY(e.download_sc());
-  bool anyV = false;
-  for (int i = 0; i < n; ++i)
-    if (mS[i] && e.h_sc[i].phase == PH_VERIFY) anyV = true;
+  bool anyV = false, fix = false;
+  for (int i = 0; i < n; ++i) {
+    if (!mS[i]) continue;
+    if (e.h_sc[i].phase == PH_VERIFY) anyV = true;
+    if (e.h_sc[i].xlag && e.h_sc[i].phase != PH_ITER) fix = true;
+  }
+  if (fix) e.finish_x(lsS);
   if (anyV) {
     launch_true_resid(e.T, lsS.fine, stream);
     launch_fin(e.T, FIN_TRUE, e.mixed, stream);

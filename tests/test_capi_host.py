@@ -78,15 +78,23 @@ def test_workspace_sizing_and_validation(fld):
     q = fld.fld_default_params(1.0, 1.0, smoother=fld.FLD_SMOOTH_JACOBI,
                                tail_cells=64)
     assert fld.fld_workspace_bytes(g, q) == 0
-    # and carves one more iterate buffer per level
+    # and carves one more iterate buffer per level; the mixed-precision fused
+    # V(1,1) red/black iteration carves a second FP64 residual on the finest
+    # level instead
     for prec in (fld.FLD_PREC_FP64, fld.FLD_PREC_MIXED):
-        r = fld.fld_default_params(1.0, 1.0, precision=prec)
+        r = fld.fld_default_params(1.0, 1.0, precision=prec, nu_pre=2, nu_post=2)
         j = fld.fld_default_params(1.0, 1.0, precision=prec,
                                    smoother=fld.FLD_SMOOTH_JACOBI)
         assert p.smoother == fld.FLD_SMOOTH_RBGS
         extra = fld.fld_workspace_bytes(g, j) - fld.fld_workspace_bytes(g, r)
         w = 4 if prec == fld.FLD_PREC_MIXED else 8
         assert w * 32 ** 3 <= extra <= w * 32 ** 3 * 8 / 7 + (1 << 16), prec
+        f = fld.fld_default_params(1.0, 1.0, precision=prec)
+        extra = fld.fld_workspace_bytes(g, f) - fld.fld_workspace_bytes(g, r)
+        if prec == fld.FLD_PREC_MIXED:
+            assert 8 * 32 ** 3 <= extra <= 8 * 32 ** 3 + (1 << 12), prec
+        else:
+            assert extra == 0
 
 
 def test_create_rejects_bad_arguments_before_any_launch(fld):
