@@ -139,7 +139,7 @@ typedef struct fld_params {
   int32_t smoother;    /* fld_smoother; default FLD_SMOOTH_RBGS */
   int32_t fused_levels;/* under V(1,1) red/black: the finest fused_levels
                           levels run the two fused passes (coarse ones with
-                          8-plane tiles); 0 = automatic (the finest level, and
+                          4-plane tiles); 0 = automatic (the finest level, and
                           each coarser one that still holds at least 2^20
                           cells over all problems) */
 } fld_params;

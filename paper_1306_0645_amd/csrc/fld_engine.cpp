@@ -85,13 +85,15 @@ Hier make_hier(const fld_grid &g, const fld_params &p) {
 // level.  Deeper tiles cut the z-halo but leave fewer tiles to hide latency:
 // measured on gfx950 at 256^3 (Mcell-updates/s for 8, 16, 32, 64 planes: FP32
 // cycle 2532, 2537, 2608, 2451; FP64 2203, 2268, 2308, 2217), 32 planes suit
-// both.  Coarse levels that run the fused passes are 8x smaller and use 8
-// planes, so that they still give a tile per CU.
+// both.  Coarse levels that run the fused passes are 8x smaller and use 4
+// planes, so that they still give a few tiles per CU (128^3 level of 256^3,
+// Mcell-updates/s with 8 and 4 planes: FP32 cycle 2622, 2652; FP64 2367,
+// 2383).
 void fused_shape(const fld_params &p, int l, int nx, int ny, int nz, int &tx,
                  int &ty, int &tz) {
   tx = std::min(nx, 64);
   ty = std::min(ny, 16);
-  const int def = l == 0 ? (p.fused_tile_z > 0 ? p.fused_tile_z : 32) : 8;
+  const int def = l == 0 ? (p.fused_tile_z > 0 ? p.fused_tile_z : 32) : 4;
   tz = std::min(nz, def);
 }
 
