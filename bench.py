@@ -209,7 +209,7 @@ def parse():
     ap.add_argument("--check-every", type=int, default=0,
                     help="PCG iterations between host convergence reads "
                          "(0: automatic)")
-    ap.add_argument("--tail-cells", type=int, default=0,
+    ap.add_argument("--tail-cells", type=int, default=512,
                     help="coarse levels of at most this many cells run in "
                          "one workgroup per V-cycle")
     ap.add_argument("--fused-levels", type=int, default=0,

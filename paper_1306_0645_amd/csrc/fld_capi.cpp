@@ -77,7 +77,7 @@ void fld_default_params(fld_params *p, double c, double L_unit) {
   p->cycle_switch = 12;
   p->prolongation = 2;
   p->warm_start = 1;
-  p->tail_cells = 0;
+  p->tail_cells = 512;
   p->smoother = FLD_SMOOTH_RBGS;
 }
 

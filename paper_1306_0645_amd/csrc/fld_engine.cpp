@@ -46,9 +46,6 @@ bool params_ok(const fld_params &p) {
   if (p.prolongation < 0 || p.prolongation > 2) return false;
   if (p.smoother != FLD_SMOOTH_RBGS && p.smoother != FLD_SMOOTH_JACOBI) return false;
   if (p.fused_levels < 0 || p.fused_levels > kMaxLevels) return false;
-  // the single-workgroup tail smooths red/black: keep it to the coarsest
-  // level under the Jacobi smoother
-  if (p.smoother == FLD_SMOOTH_JACOBI && p.tail_cells > 0) return false;
   return true;
 }
 
@@ -76,7 +73,10 @@ Hier make_hier(const fld_grid &g, const fld_params &p) {
   // the tail: the coarsest level, and above it every level below the finest
   // with at most tail_cells cells
   h.tail = h.levels > 1 ? h.levels - 1 : 1;
-  while (h.tail > 1 && h.cells(h.tail - 1) <= (long long)p.tail_cells) --h.tail;
+  // (the single-workgroup tail smooths red/black: under the Jacobi smoother
+  // it keeps to the coarsest level)
+  const long long tc = p.smoother == FLD_SMOOTH_JACOBI ? 0 : p.tail_cells;
+  while (h.tail > 1 && h.cells(h.tail - 1) <= tc) --h.tail;
   return h;
 }
 

@@ -74,10 +74,6 @@ def test_workspace_sizing_and_validation(fld):
                        ("fused_levels", -1), ("fused_levels", 13)]:
         q = fld.fld_default_params(1.0, 1.0, **{field: val})
         assert fld.fld_workspace_bytes(g, q) == 0, field
-    # the Jacobi smoother keeps the single-workgroup tail to the coarsest level
-    q = fld.fld_default_params(1.0, 1.0, smoother=fld.FLD_SMOOTH_JACOBI,
-                               tail_cells=64)
-    assert fld.fld_workspace_bytes(g, q) == 0
     # and carves one more iterate buffer per level; the mixed-precision fused
     # V(1,1) red/black iteration carves a second FP64 residual on the finest
     # level instead
