@@ -29,9 +29,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # once; neighbours and 1/8-size coarse arrays included where they are read.
 # (FP64 V-cycle, FP32 V-cycle)
 BYTES_PER_CELL = {
-    # assembly with a warm start: the guess x and its history xh are read
-    # and written besides E, kappa, eta in and the system out
-    "assemble": (104.0, 120.0),
+    # assembly with a warm start: E, kappa, eta and the two dE history
+    # buffers in; the system, b, the guess x and its residual r = b - A x out
+    "assemble": (96.0, 112.0),
     "spmv_p": (64.0, 64.0),
     # fused iteration's SpMV: also x += alpha p_old (x read and written)
     "spmv_px": (80.0, 80.0),
@@ -49,7 +49,6 @@ BYTES_PER_CELL = {
     # updated residual r - alpha q (the first iteration of a solve skips both)
     "vdown_fine": (41.0, 40.5),
     "vup_fine": (49.0, 40.5),
-    "warm_resid": (56.0, 56.0),
     # weighted-Jacobi smoother: first sweep from zero (diag, f, x out), a
     # sweep (4 coefficient arrays, x in, f, x out), the last finest sweep
     # (writes z; the mixed form also reads the old z), x + P e (x, e at 1/8,
@@ -78,7 +77,7 @@ def coarse_fraction(levels):
     return sum(8.0 ** -l for l in range(1, levels))
 
 
-STEP_KERNELS = ("assemble", "true_resid", "update_E", "warm_resid", "xfix")
+STEP_KERNELS = ("assemble", "true_resid", "update_E", "xfix")
 
 
 def step_bytes(counts, cells, prec_idx, levels):
@@ -127,10 +126,8 @@ def model_step_bytes(cells, iters, nu, prec_idx, levels, steps=1, warm=False):
     fixed = B["assemble"] + coarsen + B["true_resid"] + B["update_E"]
     if nu == 1 and prec_idx == 1:
         fixed += B["xfix"]
-    if warm:  # the residual of the seeded initial guess
-        fixed += B["warm_resid"]
-    else:     # a cold assembly neither reads the guess nor keeps history
-        fixed -= 24.0
+    if not warm:  # a cold assembly reads no history
+        fixed -= 16.0
     return cells * (steps * fixed + iters * per_iter)
 
 

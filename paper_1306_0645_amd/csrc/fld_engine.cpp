@@ -186,7 +186,9 @@ void carve_problem(Carver &cv, const Hier &h, const fld_params &p, ProbMem &m) {
       if (jacobi) L.x2 = mixed ? (void *)cv.take<float>(n) : (void *)cv.take<double>(n);
     }
   }
-  m.pd.xh = cv.take<double>((size_t)h.cells(0));
+  m.xb[0] = m.pd.x;
+  m.xb[1] = cv.take<double>((size_t)h.cells(0));
+  m.xb[2] = cv.take<double>((size_t)h.cells(0));
   m.pd.levels = h.levels;
   m.pd.tail = h.tail;
   m.pd.cs = cv.take<double>(4 * (size_t)h.cells(h.levels - 1));
@@ -330,6 +332,8 @@ int Engine::setup(const fld_params &p, hipStream_t s,
   prev_ok.assign(np, 0);
   prev_h.assign(np, 0.0);
   prev_h2.assign(np, 0.0);
+  xcur.assign(np, 0);
+  xold.assign(np, -1);
   for (int i = 0; i < np; ++i) {
     for (int l = 0; l < hier[i].levels; ++l) h_lv[(size_t)l * np + i] = mem[i].lv[l];
     h_pd[i] = mem[i].pd;
@@ -468,6 +472,7 @@ void Engine::fill_step(int p, const double *E, const double *kappa,
   S.idz = 1.0 / (a * grids[p].dz);
   S.warm = 0.0;
   S.w1 = S.w2 = 0.0;
+  S.h1 = S.h2 = nullptr;
   Scal &sc = h_sc[p];
   sc.live = 1;
   sc.tol2 = prm.rtol * prm.rtol;
@@ -674,22 +679,35 @@ int Engine::run_steps(std::vector<Job> &jobs) {
         S.warm = 1.0;
         S.w1 = r1;
         S.w2 = 0.0;
-        if (prev_ok[p] >= 2 && prev_h2[p] > 0.0) {
+        const bool two = prev_ok[p] >= 2 && prev_h2[p] > 0.0 && xold[p] >= 0;
+        if (two) {
           const double h0 = prev_h2[p];
           const double tau = (h1 + j.h) / (h0 + h1);
           S.w1 = r1 * (1.0 + tau);
           S.w2 = -(j.h / h0) * tau;
         }
+        // the guess goes into the buffer that holds neither history entry
+        const int a = xcur[p], b = two ? xold[p] : -1;
+        int nxt = 0;
+        while (nxt == a || nxt == b) ++nxt;
+        S.h1 = mem[p].xb[a];
+        S.h2 = two ? mem[p].xb[b] : nullptr;
+        mem[p].pd.x = h_pd[p].x = mem[p].xb[nxt];
+        xold[p] = a;
+        xcur[p] = nxt;
         warm = true;
       }
     }
     if (!any) break;
     int st = upload_sd_sc();
     if (st) return st;
+    if (warm)
+      HIP_TRY(hipMemcpyAsync(T.pd, h_pd.data(), sizeof(ProbDev) * h_pd.size(),
+                             hipMemcpyHostToDevice, stream));
+    // (a warm guess's residual b - A x0 comes out of the assembly, FIN_BB
+    // keeps the guess only if it reduces the residual)
     enqueue_assemble(all);
     if (warm) {
-      launch_warm_resid(T, all.fine, stream);
-      launch_fin(T, FIN_WARM, mixed, stream);
       launch_warm_revert(T, all.fine, stream);
       warm = false;
     }
@@ -711,8 +729,8 @@ int Engine::run_steps(std::vector<Job> &jobs) {
       j.iters += h_sc[p].iter;
       j.restarts += h_sc[p].restarts;
       if (h_sc[p].phase == PH_DONE && h_sc[p].status == ST_OK) {
-        // dE of this substep seeds the next one; with a warm start the one
-        // before was moved into P.xh by the assembly
+        // dE of this substep seeds the next one; after a warm start the
+        // one before stays in xb[xold]
         prev_ok[p] = h_sd[p].warm > 0.0 ? 2 : 1;
         prev_h2[p] = prev_h[p];
         prev_h[p] = j.h;

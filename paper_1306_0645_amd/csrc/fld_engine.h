@@ -54,6 +54,7 @@ size_t tables_bytes(const std::vector<Hier> &hs);
 struct ProbMem {
   LevelDev lv[kMaxLevels];
   ProbDev pd;
+  double *xb[3] = {};  // dE buffers: the iterate (pd.x) and two of history
   double *E_work = nullptr;
 };
 void carve_problem(Carver &cv, const Hier &h, const fld_params &p, ProbMem &m);
@@ -105,11 +106,14 @@ class Engine {
   int fused_top = 1;       // levels 0 .. fused_top - 1 run the fused passes
   int last_nu = 1;         // sweeps per side of the cycle used by the last solve
   bool switched = false;   // the adaptive switch moved the handle to V(2,2)
-  // per problem warm-start history: prev_ok = 0 none, 1 x holds the dE of
-  // the last successful substep (length prev_h), 2 also P.xh the one
-  // before it (length prev_h2)
+  // per problem warm-start history: prev_ok = 0 none, 1 buffer xb[xcur]
+  // (the iterate P.x) holds the dE of the last successful substep (length
+  // prev_h), 2 also xb[xold] the one before it (length prev_h2).  A warm
+  // step reads both and writes its guess into the third buffer, which
+  // becomes P.x.
   std::vector<char> prev_ok;
   std::vector<double> prev_h, prev_h2;
+  std::vector<int> xcur, xold;
 
   Tables T{};
   Tile *d_tiles = nullptr;

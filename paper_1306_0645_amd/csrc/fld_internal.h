@@ -51,7 +51,6 @@ struct ProbDev {
   int nx, ny, nz, n;
   double *x, *r, *z, *p0, *p1, *q, *b;
   double *r2;            // second residual buffer (fused V(1,1) iteration)
-  double *xh;            // dE of the step before the last (warm-start history)
   double *cs;            // coarsest-level CG scratch: 4 * n_coarsest doubles
   int levels;            // number of multigrid levels
   int t0, t1;            // range of this problem's tiles in the finest list
@@ -67,6 +66,7 @@ struct StepDev {
   double idx, idy, idz;  // 1 / (a dx), 1 / (a dy), 1 / (a dz)
   double warm;           // 1: warm start x0 = w1 dE(n) + w2 dE(n-1); 0: x0 = 0
   double w1, w2;
+  const double *h1, *h2; // dE(n), dE(n-1) (h2 null when w2 = 0); never P.x
 };
 
 // Per-problem PCG scalars (device resident, read back by the host).
@@ -124,7 +124,7 @@ enum : int {
   K_HALF_OUT, K_RESTRICT_F, K_RESTRICT_C, K_PROLONG_F, K_PROLONG_C,
   K_COARSE_SOLVE, K_SPMV_P, K_UPDATE, K_TRUE_RESID, K_APPLY, K_SET_R,
   K_UPDATE_E, K_VDOWN_F, K_VDOWN_C, K_VUP_F, K_VUP_C, K_CHEM_H, K_ION_SUM,
-  K_WARM_RESID, K_WARM_REVERT, K_JACOBI0_F, K_JACOBI_F, K_JACOBI_OUT,
+  K_WARM_REVERT, K_JACOBI0_F, K_JACOBI_F, K_JACOBI_OUT,
   K_JACOBI_C, K_PROLONG_ADD_F, K_PROLONG_ADD_C, K_SPMV_PX, K_XFIX, K_NUM
 };
 
@@ -179,7 +179,6 @@ void launch_spmv_p(const Tables &T, TileList L0, int lazy, hipStream_t s);
 void launch_xfix(const Tables &T, TileList L0, hipStream_t s);
 void launch_update(const Tables &T, TileList L0, hipStream_t s);
 void launch_true_resid(const Tables &T, TileList L0, hipStream_t s);
-void launch_warm_resid(const Tables &T, TileList L0, hipStream_t s);
 void launch_warm_revert(const Tables &T, TileList L0, hipStream_t s);
 void launch_apply(const Tables &T, TileList L0, const double *u, double *out,
                   hipStream_t s);
@@ -194,14 +193,14 @@ void launch_vup(const Tables &T, TileList L, int l, int prec, int flexible,
 
 // finalize kernels (launch_fin 'which')
 enum : int {
-  FIN_BB = 0,     // after assembly: ||b||^2, start the solve
+  FIN_BB = 0,     // after assembly: ||b||^2 (and ||b - A x0||^2 of a warm
+                  // guess), start the solve
   FIN_RZ = 1,     // after the V-cycle: rho = r.z, beta
   FIN_PQ = 2,     // after the SpMV: alpha = rho / p.q
   FIN_RR = 3,     // after the update: ||r||^2, convergence
   FIN_TRUE = 4,   // after the true residual: verify or restart
   FIN_STEP = 5,   // after E += dE: relative change and ||dE||^2
   FIN_SETR = 6,   // after loading an external r (preconditioner test)
-  FIN_WARM = 7,   // after r = b - A x0 for a warm start
   FIN_RR2 = 8,    // fused iteration, after the down pass formed r - alpha q:
                   // ||r||^2, convergence, switch the residual buffer
   FIN_XFIX = 9    // after k_xfix: the deferred x update is done

@@ -74,7 +74,15 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
   double *__restrict__ bv = P.b;
   double *__restrict__ rv = rcur(P, sc);
   double *__restrict__ xv = P.x;
-  double bb = 0.0;
+  // warm start: x0 = w1 dE(n) + w2 dE(n-1) from two history buffers that
+  // nothing writes here, so the guess at a neighbour is formed on the fly
+  // and r = b - A x0 comes out of this pass (the thread holds all 6 faces)
+  const bool warm = S.warm > 0.0;
+  const double w1 = S.w1, w2 = S.w2;
+  const double *__restrict__ h1 = S.h1;
+  const double *__restrict__ h2 = S.h2;
+  auto guess = [&](int g) { return h2 ? w1 * h1[g] + w2 * h2[g] : w1 * h1[g]; };
+  double bb = 0.0, rr = 0.0;
   if (col.on) {
     const int nx = L.nx, ny = L.ny, nz = L.nz, plane = nx * ny;
     const int i = col.i, j = col.j;
@@ -86,6 +94,11 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
     double Em = E[cm], Km = K[cm];
     double Ec = E[cc], Kc = K[cc];
     double Dzm = face_D(Em, Ec, Km, Kc, S.idz, c, dmax, rmin);
+    double gm = 0.0, gc = 0.0;  // guess at planes k - 1, k
+    if (warm) {
+      gm = guess(cm);
+      gc = guess(cc);
+    }
     for (int k = t.z0; k < t.z0 + t.tz; ++k) {
       const int cp = (k == nz - 1) ? cc - (nz - 1) * plane : cc + plane;
       const double Ep = E[cp], Kp = K[cp];
@@ -116,17 +129,24 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
         L.diag32[cc] = (float)diag;
       }
       bv[cc] = b;
-      rv[cc] = b;
-      // initial guess: 0, or extrapolated from the last two steps' dE (x
-      // holds the last, P.xh the one before; the last moves into P.xh)
-      if (S.warm > 0.0) {
-        const double xl = xv[cc];
-        xv[cc] = S.w1 * xl + (S.w2 != 0.0 ? S.w2 * P.xh[cc] : 0.0);
-        P.xh[cc] = xl;
+      bb += b * b;
+      if (warm) {
+        const double gp = guess(cp);
+        const double txm = tdt * Dxm * ix2, tym = tdt * Dym * iy2,
+                     tzm = tdt * Dzm * iz2;
+        const double off = tx * guess(cc + dxp) + txm * guess(cc + dxm) +
+                           ty * guess(cc + dyp) + tym * guess(cc + dym) +
+                           tz * gp + tzm * gm;
+        const double r = b - (diag * gc - off);
+        xv[cc] = gc;
+        rv[cc] = r;
+        rr += r * r;
+        gm = gc;
+        gc = gp;
       } else {
         xv[cc] = 0.0;
+        rv[cc] = b;
       }
-      bb += b * b;
       Em = Ec;
       Km = Kc;
       Ec = Ep;
@@ -135,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
       cc = cp;
     }
   }
-  write_partials(T, tid, bb, 0.0);
+  write_partials(T, tid, bb, rr);
 }
 
 // Coarse operator of level lc from level lc-1 (one thread per coarse cell):
@@ -812,56 +832,24 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Tables T, TileList TL) {
   write_partials(T, tid, rr, 0.0);
 }
 
-// r = b - A x0 for problems starting from a warm initial guess x0, partial
-// ||r||^2 (FIN_WARM then restarts their PCG from this residual)
-__global__ __launch_bounds__(kBlock) void k_warm_resid(Tables T, TileList TL) {
-  const int tid = get_tile_index(TL);
-  const Tile t = TL.base[tid];
-  const Scal &sc = T.sc[t.prob];
-  if (!sc.live || !(T.sd[t.prob].warm > 0.0)) return;
-  const LevelDev L = T.lv[t.prob];
-  const ProbDev P = T.pd[t.prob];
-  const Coef<double> C = coefs<double>(L);
-  const Col col = tile_col(t);
-  if (sc.phase == PH_DONE && sc.status == ST_OK) {
-    // b = 0: the solution is 0, whatever the guess
-    if (col.on)
-      for (int k = t.z0; k < t.z0 + t.tz; ++k)
-        for (int e = 0; e < t.cpt; ++e)
-          P.x[(k * L.ny + col.j) * L.nx + col.i + e] = 0.0;
-    return;
-  }
-  if (sc.phase != PH_ITER) return;
-  double rr = 0.0;
-  if (col.on) {
-    auto xv = [&](int q) { return P.x[q]; };
-    for (int k = t.z0; k < t.z0 + t.tz; ++k) {
-      for (int e = 0; e < t.cpt; ++e) {
-        const Nb n = nbrs(col.i + e, col.j, k, L.nx, L.ny, L.nz);
-        const double r = P.b[n.c] - (C.d[n.c] * P.x[n.c] - offsum(C, n, xv));
-        rcur(P, sc)[n.c] = r;
-        rr += r * r;
-      }
-    }
-  }
-  write_partials(T, tid, rr, 0.0);
-}
-
-// x = 0, r = b for problems whose warm guess was rejected by FIN_WARM
+// Warm-started problems whose guess FIN_BB rejected (it did not reduce the
+// residual): x = 0, r = b.  And b = 0: the solution is 0 whatever the guess.
 __global__ __launch_bounds__(kBlock) void k_warm_revert(Tables T, TileList TL) {
   const Tile t = get_tile(TL);
   const Scal &sc = T.sc[t.prob];
-  if (!sc.live || !(T.sd[t.prob].warm > 0.0) || sc.phase != PH_ITER || !sc.cold)
-    return;
+  if (!sc.live || !(T.sd[t.prob].warm > 0.0)) return;
+  const bool zero_b = sc.phase == PH_DONE && sc.status == ST_OK;
+  if (!zero_b && !(sc.phase == PH_ITER && sc.cold)) return;
   const LevelDev L = T.lv[t.prob];
   const ProbDev P = T.pd[t.prob];
+  double *rv = rcur(P, sc);
   const Col col = tile_col(t);
   if (!col.on) return;
   for (int k = t.z0; k < t.z0 + t.tz; ++k) {
     const int c0 = (k * L.ny + col.j) * L.nx + col.i;
     for (int e = 0; e < t.cpt; ++e) {
       P.x[c0 + e] = 0.0;
-      rcur(P, sc)[c0 + e] = P.b[c0 + e];
+      rv[c0 + e] = P.b[c0 + e];
     }
   }
 }
@@ -982,9 +970,6 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
     case FIN_STEP: part = sc.live != 0; break;
     case FIN_TRUE: part = sc.phase == PH_VERIFY; break;
     case FIN_SETR: part = true; break;
-    case FIN_WARM:
-      part = sc.live && T.sd[p].warm > 0.0 && sc.phase == PH_ITER;
-      break;
     case FIN_RR2: part = sc.active && sc.has_dir; break;
     case FIN_XFIX: part = sc.xlag && sc.phase != PH_ITER; break;
     default: part = sc.active != 0; break;
@@ -1027,8 +1012,16 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
       sc.status = ST_OK;
       sc.phase = PH_ITER;
       sc.active = 1;
+      sc.cold = 0;
       if (!finite(a0)) fail(sc, ST_ENONFINITE);
       else if (a0 == 0.0) { sc.phase = PH_DONE; sc.active = 0; }
+      else if (T.sd[p].warm > 0.0) {
+        // PCG from the warm guess (same ||b||), or from 0 (k_warm_revert)
+        // if the guess does not reduce the residual
+        sc.cold = !(a1 < a0);
+        if (!sc.cold) sc.rr = a1;
+        if (!finite(a1)) fail(sc, ST_ENONFINITE);
+      }
       set_scale(sc, P.n, mixed);
       break;
     case FIN_RZ: {
@@ -1127,15 +1120,6 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
       sc.has_dir = sc.xlag = sc.snew = 0;
       set_scale(sc, P.n, mixed);
       break;
-    case FIN_WARM:
-      // PCG from the warm guess (same ||b||, a fresh search direction), or
-      // from 0 if the guess does not reduce the residual (k_warm_revert)
-      sc.restart = 1;
-      sc.has_dir = sc.xlag = sc.snew = 0;
-      sc.cold = !(a0 < sc.bb);
-      if (!sc.cold) sc.rr = a0;
-      set_scale(sc, P.n, mixed);
-      break;
   }
 }
 
@@ -1149,7 +1133,7 @@ static const char *kKernelNames[K_NUM] = {
     "prolong_black_fine", "prolong_black_coarse", "coarse_solve", "spmv_p",
     "update", "true_resid", "apply", "set_r", "update_E", "vdown_fine",
     "vdown_coarse", "vup_fine", "vup_coarse", "chem_h", "ionized_sum",
-    "warm_resid", "warm_revert", "jacobi0_fine", "jacobi_fine", "jacobi_out",
+    "warm_revert", "jacobi0_fine", "jacobi_fine", "jacobi_out",
     "jacobi_coarse", "prolong_add_fine", "prolong_add_coarse", "spmv_px",
     "xfix"};
 
@@ -1315,9 +1299,6 @@ void launch_set_r(const Tables &T, TileList L0, const double *r, int prec,
   if (L0.nblocks) LAUNCH(K_SET_R, k_set_r, L0.nblocks, kBlock, s, T, L0, r);
 }
 
-void launch_warm_resid(const Tables &T, TileList L0, hipStream_t s) {
-  if (L0.nblocks) LAUNCH(K_WARM_RESID, k_warm_resid, L0.nblocks, kBlock, s, T, L0);
-}
 
 void launch_jacobi(const Tables &T, TileList L, int l, int prec, int mode,
                    int in_x2, int flexible, hipStream_t s) {
