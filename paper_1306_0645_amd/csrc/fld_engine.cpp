@@ -484,42 +484,49 @@ void Engine::enqueue_assemble(const ListSet &ls) {
   for (int l = 1; l < Lmax; ++l)
     launch_coarsen(T, ls.exist[l], l, prm.coarse_scale, mixed, stream);
   launch_fin(T, FIN_BB, mixed, stream);
+  need_pro = true;
+}
+
+// The fused V(1,1) cycle after its finest down pass: one sweep each way; the
+// coarse levels with enough cells to fill the GPU run the two fused passes
+// too (they never store the pre-smoothed x), the smaller, latency-bound ones
+// the per-half-sweep kernels; last the finest up pass.
+void Engine::enqueue_fused_rest(const ListSet &ls) {
+  const int prec = mixed;
+  const int tri = (mixed && (prm.prolongation == 1 ||
+                             (prm.prolongation == 2 && switched))) ? 1 : 0;
+  for (int l = 1; l < Lmax; ++l) {
+    if (l < fused_top) {
+      launch_vdown(T, ls.fdn[l], l, prec, VD_ALL, stream);
+      continue;
+    }
+    if (ls.smooth[l].nblocks == 0) continue;
+    launch_pre0(T, ls.smooth[l], l, prec, stream);
+    if (l + 1 < Lmax) launch_resid_restrict(T, ls.down[l + 1], l + 1, prec, stream);
+  }
+  if (Lmax > 1) launch_vtail(T, prec, 1, 1, tri, stream);
+  for (int l = Lmax - 1; l >= 1; --l) {
+    if (l < fused_top) {
+      launch_vup(T, ls.fsm[l], l, prec, 0, tri, stream);
+      continue;
+    }
+    if (ls.smooth[l].nblocks == 0) continue;
+    launch_prolong_black(T, ls.smooth[l], l, prec, tri, stream);
+    launch_half(T, ls.smooth[l], l, 0, prec, stream);
+  }
+  launch_vup(T, ls.fsm[0], 0, prec, mixed, tri, stream);
 }
 
 // One V-cycle for every active problem.  Pre-smoothing: red then black
 // (nu_pre sweeps); post-smoothing: black then red (nu_post sweeps), the
 // adjoint order, so the FP64 cycle is a symmetric preconditioner.
-void Engine::enqueue_vcycle(const ListSet &ls, bool in_iteration) {
+void Engine::enqueue_vcycle(const ListSet &ls) {
   const int prec = mixed;
   const int tri = (mixed && (prm.prolongation == 1 ||
                              (prm.prolongation == 2 && switched))) ? 1 : 0;
   if (fused) {
-    // one sweep each way: the finest level, and the coarse levels with enough
-    // cells to fill the GPU, run the two fused passes (they never store the
-    // pre-smoothed x); the smaller, latency-bound levels run the
-    // per-half-sweep kernels
-    for (int l = 0; l < Lmax; ++l) {
-      if (l < fused_top) {
-        launch_vdown(T, ls.fdn[l], l, prec, stream);
-        // the finest down pass formed this iteration's residual r - alpha q
-        if (l == 0 && in_iteration && lazy) launch_fin(T, FIN_RR2, mixed, stream, 1);
-        continue;
-      }
-      if (ls.smooth[l].nblocks == 0) continue;
-      launch_pre0(T, ls.smooth[l], l, prec, stream);
-      if (l + 1 < Lmax) launch_resid_restrict(T, ls.down[l + 1], l + 1, prec, stream);
-    }
-    if (Lmax > 1) launch_vtail(T, prec, 1, 1, tri, stream);
-    for (int l = Lmax - 1; l >= 1; --l) {
-      if (l < fused_top) {
-        launch_vup(T, ls.fsm[l], l, prec, 0, tri, stream);
-        continue;
-      }
-      if (ls.smooth[l].nblocks == 0) continue;
-      launch_prolong_black(T, ls.smooth[l], l, prec, tri, stream);
-      launch_half(T, ls.smooth[l], l, 0, prec, stream);
-    }
-    launch_vup(T, ls.fsm[0], 0, prec, mixed, tri, stream);
+    launch_vdown(T, ls.fdn[0], 0, prec, VD_ALL, stream);
+    enqueue_fused_rest(ls);
     return;
   }
   const TileList *smooth = ls.smooth, *down = ls.down;
@@ -579,16 +586,36 @@ void Engine::enqueue_vcycle(const ListSet &ls, bool in_iteration) {
 // (which reads p anyway), so the update needs no pass of its own.  (In FP64
 // the extra loads push the down pass past its register budget: measured at
 // 256^3, 2306 against 2375 Mcell-updates/s with the separate update.)  The
+// unit enqueued here is rotated so that it ends with that test: it starts
+// after the finest down pass, which the previous unit (or, for a problem
+// starting or restarting, enqueue_prologue) has done, so the host sees a
+// converged problem at the end of a batch instead of one unit later.  The
 // other forms update x and r in a pass of their own.
 void Engine::enqueue_iteration(const ListSet &ls) {
-  enqueue_vcycle(ls, true);
-  launch_fin(T, FIN_RZ, mixed, stream, fused ? 1 : 0);
-  launch_spmv_p(T, ls.fine, lazy ? 1 : 0, stream);
-  launch_fin(T, FIN_PQ, mixed, stream, lazy ? 1 : 0);
-  if (!lazy) {
-    launch_update(T, ls.fine, stream);
-    launch_fin(T, FIN_RR, mixed, stream);
+  if (lazy) {
+    enqueue_fused_rest(ls);
+    launch_fin(T, FIN_RZ, mixed, stream, 1);
+    launch_spmv_p(T, ls.fine, 1, stream);
+    launch_fin(T, FIN_PQ, mixed, stream, 1);
+    launch_vdown(T, ls.fdn[0], 0, mixed, VD_CONT, stream);
+    launch_fin(T, FIN_RR2, mixed, stream, 1);
+    return;
   }
+  enqueue_vcycle(ls);
+  launch_fin(T, FIN_RZ, mixed, stream, fused ? 1 : 0);
+  launch_spmv_p(T, ls.fine, 0, stream);
+  launch_fin(T, FIN_PQ, mixed, stream, 0);
+  launch_update(T, ls.fine, stream);
+  launch_fin(T, FIN_RR, mixed, stream);
+}
+
+// The finest down pass for problems that start or restart their PCG (rotated
+// fused iteration); a no-op otherwise.
+void Engine::enqueue_prologue(const ListSet &ls) {
+  if (!lazy || !need_pro) return;
+  launch_vdown(T, ls.fdn[0], 0, mixed, VD_FRESH, stream);
+  launch_fin(T, FIN_FRESH, mixed, stream);
+  need_pro = false;
 }
 
 // x += alpha p for problems that stopped iterating with that update pending
@@ -629,7 +656,9 @@ int Engine::run_solve() {
     if (nver) {
       launch_true_resid(T, all.fine, stream);
       launch_fin(T, FIN_TRUE, mixed, stream);
+      need_pro = true;
     } else if (nact) {
+      enqueue_prologue(all);
       const int K = check_every();
       if (prm.use_graph) {
         if (!gexec) {

@@ -103,6 +103,7 @@ class Engine {
   std::vector<int> fbeg;   // [p * kMaxLevels + l] first fused tile of (p, l)
   bool fused = false;      // one-sweep fused V-cycle kernels
   bool lazy = false;       // fused PCG iteration (residual update in the down pass)
+  bool need_pro = false;   // some problem (re)starts: enqueue_prologue is due
   int fused_top = 1;       // levels 0 .. fused_top - 1 run the fused passes
   int last_nu = 1;         // sweeps per side of the cycle used by the last solve
   bool switched = false;   // the adaptive switch moved the handle to V(2,2)
@@ -146,8 +147,10 @@ class Engine {
   int adapt_cycle(int max_iters);
 
   void enqueue_assemble(const ListSet &ls);
-  void enqueue_vcycle(const ListSet &ls, bool in_iteration = false);
+  void enqueue_vcycle(const ListSet &ls);
+  void enqueue_fused_rest(const ListSet &ls);
   void enqueue_iteration(const ListSet &ls);
+  void enqueue_prologue(const ListSet &ls);
   void finish_x(const ListSet &ls);
   int run_solve();
   int run_steps(std::vector<Job> &jobs);

@@ -360,11 +360,13 @@ __device__ __forceinline__ Q4<R> q_store_plane(const QPlane<R, L0, UP> &pl,
 }
 
 template <typename R, bool L0>
-__global__ __launch_bounds__(kBlock) void k_vdown(Tables T, TileList TL, int l) {
+__global__ __launch_bounds__(kBlock) void k_vdown(Tables T, TileList TL, int l,
+                                                  int sel) {
   const int tid = get_tile_index(TL);
   const Tile t = TL.base[tid];
   const Scal &sc = T.sc[t.prob];
   if (!sc.active) return;
+  if ((sel == VD_FRESH && !sc.fresh) || (sel == VD_CONT && sc.fresh)) return;
   const LevelDev L = T.lv[l * T.nprob + t.prob];
   const ProbDev P = T.pd[t.prob];
   // a one-level problem runs this pass only for the residual update
@@ -622,15 +624,16 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
 
 // launchers ------------------------------------------------------------------
 
-void launch_vdown(const Tables &T, TileList L, int l, int prec, hipStream_t s) {
+void launch_vdown(const Tables &T, TileList L, int l, int prec, int sel,
+                  hipStream_t s) {
   if (!L.nblocks) return;
   const int id = l == 0 ? K_VDOWN_F : K_VDOWN_C;
   if (prec) {
-    if (l == 0) FLD_LAUNCH(id, (k_vdown<float, true>), L.nblocks, kBlock, s, T, L, l);
-    else FLD_LAUNCH(id, (k_vdown<float, false>), L.nblocks, kBlock, s, T, L, l);
+    if (l == 0) FLD_LAUNCH(id, (k_vdown<float, true>), L.nblocks, kBlock, s, T, L, l, sel);
+    else FLD_LAUNCH(id, (k_vdown<float, false>), L.nblocks, kBlock, s, T, L, l, sel);
   } else {
-    if (l == 0) FLD_LAUNCH(id, (k_vdown<double, true>), L.nblocks, kBlock, s, T, L, l);
-    else FLD_LAUNCH(id, (k_vdown<double, false>), L.nblocks, kBlock, s, T, L, l);
+    if (l == 0) FLD_LAUNCH(id, (k_vdown<double, true>), L.nblocks, kBlock, s, T, L, l, sel);
+    else FLD_LAUNCH(id, (k_vdown<double, false>), L.nblocks, kBlock, s, T, L, l, sel);
   }
 }
 

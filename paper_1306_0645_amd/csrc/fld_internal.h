@@ -86,6 +86,8 @@ struct Scal {
   // forms r - alpha q; xlag: x still lacks alpha p (added by the next SpMV,
   // or by k_xfix when the iteration stops)
   int rbuf, has_dir, xlag, snew;
+  int fresh;             // (re)started: the finest down pass is still due
+  int pad;
 };
 
 // A tile: cells [x0, x0+tx) x [y0, y0+ty) x [z0, z0+tz) of one level of one
@@ -187,7 +189,11 @@ void launch_set_r(const Tables &T, TileList L0, const double *r, int prec,
 void launch_update_E(const Tables &T, TileList L0, double floor, int copy_only,
                      hipStream_t s);
 // fused one-sweep V-cycle passes (fld_fused.hip)
-void launch_vdown(const Tables &T, TileList L, int l, int prec, hipStream_t s);
+// sel (finest level of the rotated fused iteration): VD_ALL every active
+// problem, VD_FRESH those starting or restarting, VD_CONT the others
+enum : int { VD_ALL = 0, VD_FRESH = 1, VD_CONT = 2 };
+void launch_vdown(const Tables &T, TileList L, int l, int prec, int sel,
+                  hipStream_t s);
 void launch_vup(const Tables &T, TileList L, int l, int prec, int flexible,
                 int trilinear, hipStream_t s);
 
@@ -203,7 +209,8 @@ enum : int {
   FIN_SETR = 6,   // after loading an external r (preconditioner test)
   FIN_RR2 = 8,    // fused iteration, after the down pass formed r - alpha q:
                   // ||r||^2, convergence, switch the residual buffer
-  FIN_XFIX = 9    // after k_xfix: the deferred x update is done
+  FIN_XFIX = 9,   // after k_xfix: the deferred x update is done
+  FIN_FRESH = 10  // after the prologue's down pass: the problems iterate on
 };
 
 }  // namespace fld

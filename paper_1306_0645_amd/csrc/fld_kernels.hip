@@ -963,7 +963,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
   const ProbDev P = T.pd[p];
   const bool fz = (alt && which == FIN_RZ) || which == FIN_RR2;
   const int t0 = fz ? P.f0 : P.t0;
-  const int t1 = which == FIN_XFIX ? t0 : (fz ? P.f1 : P.t1);
+  const int t1 = (which == FIN_XFIX || which == FIN_FRESH) ? t0 : (fz ? P.f1 : P.t1);
   bool part;
   switch (which) {
     case FIN_BB:
@@ -972,6 +972,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
     case FIN_SETR: part = true; break;
     case FIN_RR2: part = sc.active && sc.has_dir; break;
     case FIN_XFIX: part = sc.xlag && sc.phase != PH_ITER; break;
+    case FIN_FRESH: part = sc.active && sc.fresh; break;
     default: part = sc.active != 0; break;
   }
   if (!part) return;
@@ -1009,6 +1010,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
       sc.restarts = 0;
       sc.pbuf = 0;
       sc.has_dir = sc.xlag = sc.snew = 0;
+      sc.fresh = 1;
       sc.status = ST_OK;
       sc.phase = PH_ITER;
       sc.active = 1;
@@ -1078,6 +1080,9 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
     case FIN_XFIX:
       sc.xlag = 0;
       break;
+    case FIN_FRESH:
+      sc.fresh = 0;
+      break;
     case FIN_RR:
       sc.rr = a0;
       sc.iter += 1;
@@ -1104,6 +1109,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
         sc.restart = 1;
         sc.restarts += 1;
         sc.has_dir = sc.snew = 0;
+        sc.fresh = 1;
         set_scale(sc, P.n, mixed);
       } else {
         fail(sc, ST_ENOCONV);
@@ -1117,7 +1123,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
       sc.rr = a0;
       sc.active = 1;
       sc.phase = PH_ITER;
-      sc.has_dir = sc.xlag = sc.snew = 0;
+      sc.has_dir = sc.xlag = sc.snew = sc.fresh = 0;
       set_scale(sc, P.n, mixed);
       break;
   }

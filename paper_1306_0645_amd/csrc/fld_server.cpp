@@ -226,6 +226,7 @@ int fld_server::tick() {
   }
   // (2) one PCG iteration for every solving request (device flags decide)
   TRY(e.build_lists(mS, 2, lsS));
+  e.enqueue_prologue(lsS);
   e.enqueue_iteration(lsS);
   TRY(e.download_sc());
   bool anyV = false, fix = false;
@@ -238,6 +239,7 @@ int fld_server::tick() {
   if (anyV) {
     launch_true_resid(e.T, lsS.fine, stream);
     launch_fin(e.T, FIN_TRUE, e.mixed, stream);
+    e.need_pro = true;
     TRY(e.download_sc());
   }
   // (3) commit finished solves; cut failed ones
