@@ -554,3 +554,17 @@ def test_fused_coarse_levels_match_oracle(fld, oracle_mod, prec):
     _assemble(S, p)
     dE, st = S.solve()
     _check_solution(oracle_mod, p, prm, host(dE), st, prec, "fused_coarse")
+
+
+@pytest.mark.parametrize("prolongation", [0, 1])
+def test_v11_prolongation_matches_oracle(fld, oracle_mod, prolongation):
+    """Mixed V(1,1) with piecewise-constant (0) and trilinear (1) correction
+    through the fused finest passes, the per-half-sweep coarse kernels and
+    the single-workgroup tail: the solve meets the gates."""
+    log_case("v11_prolongation", prolongation=prolongation)
+    p = _problem((64, 64, 64), 46, dt_factor=0.5)
+    S, prm = _solver(fld, p, precision=1, prolongation=prolongation,
+                     cycle_switch=0)
+    _assemble(S, p)
+    dE, st = S.solve()
+    _check_solution(oracle_mod, p, prm, host(dE), st, 1, f"prolong{prolongation}")
