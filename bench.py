@@ -214,6 +214,8 @@ def parse():
     ap.add_argument("--smoother", type=int, default=0,
                     help="multigrid smoother: 0 red/black Gauss-Seidel, "
                          "1 weighted Jacobi")
+    ap.add_argument("--cycle-switch", type=int, default=12,
+                    help="iterations above which a V(1,1) handle switches cycle")
     ap.add_argument("--prolongation", type=int, default=2,
                     help="mixed cycle: 0 constant, 1 trilinear, 2 automatic")
     ap.add_argument("--workload", default="many_sources",

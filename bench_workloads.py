@@ -124,7 +124,9 @@ def reionization(args, fld, torch, synth, log):
     log(f"[bench]   generated in {time.perf_counter() - t0:.1f} s; "
         f"ionized fraction {float((p['kappa'] < 1e-22).double().mean()):.4f}")
     prm = fld.fld_default_params(p["c"], p["L_unit"], precision=fld.FLD_PREC_MIXED,
-                                 mg_levels=6, use_graph=args.graph)
+                                 mg_levels=6, use_graph=args.graph,
+                                 cycle_switch=args.cycle_switch,
+                                 prolongation=args.prolongation)
     S = fld.Solver(p["shape"], p["h"], prm)
     E, K, H = p["E"], p["kappa"], p["eta"]
     steps = args.steps if args.steps != 10 else 20
@@ -142,14 +144,15 @@ def reionization(args, fld, torch, synth, log):
             log(f"[bench]   step {k + 1}/{steps}: iters {st['iters']}")
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
-    cycle_nu = st["cycle_nu"]
+    cycle_nu, cycle_tri = st["cycle_nu"], st["trilinear"]
     S.close()
     # kernel pass on a handle without graph replay (a replayed graph hides
     # its kernels from the timing hook), in the cycle the timed steps ended
     # with: survey one step, then time the dominant kernel over two more
     P = fld.Solver(p["shape"], p["h"], fld.fld_default_params(
         p["c"], p["L_unit"], precision=fld.FLD_PREC_MIXED, mg_levels=6,
-        use_graph=0, nu_pre=cycle_nu, nu_post=cycle_nu))
+        use_graph=0, nu_pre=cycle_nu, nu_post=cycle_nu, cycle_switch=0,
+        prolongation=cycle_tri, check_every=1))
     names, totals = _survey(fld, lambda: P.step(E, K, H, p["dt"]))
     dom = _dominant(fld, names, totals, E.numel(), BYTES_PER_CELL, 1)
     dom_id = names.index(dom)
@@ -169,7 +172,8 @@ def reionization(args, fld, torch, synth, log):
         "f64+f32",
         {"workload": f"reionization_share_{n}^3", "grid": [n] * 3,
          "sources": 10000, "sigma_ln": 2.0, "levels": 6, "precision": "mixed",
-         "rtol": 1e-8, "steps_per_run": steps, "final_cycle_nu": cycle_nu},
+         "rtol": 1e-8, "steps_per_run": steps, "final_cycle_nu": cycle_nu,
+         "final_trilinear": cycle_tri},
         {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
          "traffic": None},

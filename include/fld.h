@@ -116,15 +116,17 @@ typedef struct fld_params {
                           0 = automatic */
   int32_t cycle_switch;/* > 0 and nu_pre = nu_post = 1: when a solve needs
                           more PCG iterations than this, later solves of the
-                          handle use V(2,2), until one needs at most a third
-                          of it and the handle returns to V(1,1).  0, or any
-                          other configured cycle: the cycle stays
-                          nu_pre/nu_post.  Default 12 */
+                          handle switch cycle, until one needs at most a
+                          third of it and the handle switches back.  The
+                          switched cycle is V(1,1) with trilinear correction
+                          in mixed precision with prolongation = 2, else
+                          V(2,2).  0, or any other configured cycle: the cycle
+                          stays as configured.  Default 12 */
   int32_t prolongation;/* coarse-grid correction of the FP32 (mixed) cycle:
                           0 = piecewise constant, 1 = cell-centred trilinear,
-                          2 = trilinear only while the handle runs V(2,2)
-                          after a cycle switch (default).  The FP64 cycle is
-                          always piecewise constant with restriction = its
+                          2 = trilinear only while the handle is switched by
+                          cycle_switch (default).  The FP64 cycle is always
+                          piecewise constant with restriction = its
                           transpose, so it stays a symmetric preconditioner */
   int32_t warm_start;  /* fld_step / fld_batch_step: 1 (default) = start each
                           step's PCG from the handle's previous successful dE
@@ -153,6 +155,7 @@ typedef struct fld_stats {
   int32_t levels;       /* multigrid levels used */
   int32_t restarts;     /* refinement restarts from the true FP64 residual */
   int32_t cycle_nu;     /* red/black sweeps per side of the V-cycle used last */
+  int32_t trilinear;    /* 1: that cycle used the trilinear correction */
   double rel_resid;     /* true ||b - A dE||_2 / ||b||_2 of the last solve */
   double err_bound;     /* ||b - A dE||_2 / ||dE||_2: bounds the relative 2-norm
                            error of dE because ||A^-1||_2 <= 1 when adot >= 0 */

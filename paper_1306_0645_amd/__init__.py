@@ -64,7 +64,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("subcycles", ctypes.c_int32), ("dt_cuts", ctypes.c_int32),
                 ("levels", ctypes.c_int32), ("restarts", ctypes.c_int32),
-                ("cycle_nu", ctypes.c_int32),
+                ("cycle_nu", ctypes.c_int32), ("trilinear", ctypes.c_int32),
                 ("rel_resid", ctypes.c_double), ("err_bound", ctypes.c_double),
                 ("rel_change_rms", ctypes.c_double), ("dt_next", ctypes.c_double),
                 ("bnorm", ctypes.c_double), ("dEnorm", ctypes.c_double)]

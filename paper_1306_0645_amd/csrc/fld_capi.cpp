@@ -31,10 +31,11 @@ bool step_args_ok(double dt, double a, double adot) {
          std::isfinite(adot);
 }
 
-void fill_stats(fld_stats *s, const Job &j, int levels, int nu) {
+void fill_stats(fld_stats *s, const Job &j, int levels, int nu, int tri) {
   if (!s) return;
   std::memset(s, 0, sizeof(*s));
   s->cycle_nu = nu;
+  s->trilinear = tri;
   s->status = j.status;
   s->iters = j.iters;
   s->subcycles = j.substeps;
@@ -171,7 +172,7 @@ fld_status fld_solve(fld_handle *h, double *dE, fld_stats *stats) {
   const double rr = sc.phase == PH_DONE && sc.status == ST_OK ? sc.rr_true : sc.rr;
   j.rel_resid = sc.bb > 0.0 ? std::sqrt(rr / sc.bb) : 0.0;
   j.err_bound = j.dEnorm > 0.0 ? std::sqrt(rr) / j.dEnorm : 0.0;
-  fill_stats(stats, j, e.hier[0].levels, e.last_nu);
+  fill_stats(stats, j, e.hier[0].levels, e.last_nu, e.last_tri);
   e.h_sc[0].live = 1;  // the assembled system stays available
   return (fld_status)sc.status;
 }
@@ -195,7 +196,7 @@ fld_status fld_step(fld_handle *h, double *E, const double *kappa,
   const int st = e.run_steps(jobs);
   if (st) return (fld_status)st;
   e.assembled = true;
-  fill_stats(stats, j, e.hier[0].levels, e.last_nu);
+  fill_stats(stats, j, e.hier[0].levels, e.last_nu, e.last_tri);
   return (fld_status)j.status;
 }
 
@@ -331,7 +332,7 @@ fld_status fld_batch_step(fld_batch *b, double *const *E,
   e.assembled = true;
   int first = FLD_OK;
   for (int i = 0; i < n; ++i) {
-    if (per_problem) fill_stats(&per_problem[i], jobs[i], e.hier[i].levels, e.last_nu);
+    if (per_problem) fill_stats(&per_problem[i], jobs[i], e.hier[i].levels, e.last_nu, e.last_tri);
     if (jobs[i].status != FLD_OK && first == FLD_OK) first = jobs[i].status;
   }
   return (fld_status)first;

@@ -106,7 +106,8 @@ class Engine {
   bool need_pro = false;   // some problem (re)starts: enqueue_prologue is due
   int fused_top = 1;       // levels 0 .. fused_top - 1 run the fused passes
   int last_nu = 1;         // sweeps per side of the cycle used by the last solve
-  bool switched = false;   // the adaptive switch moved the handle to V(2,2)
+  int last_tri = 0;        // the last solve's cycle used trilinear correction
+  bool switched = false;   // the adaptive switch changed the handle's cycle
   // per problem warm-start history: prev_ok = 0 none, 1 buffer xb[xcur]
   // (the iterate P.x) holds the dE of the last successful substep (length
   // prev_h), 2 also xb[xold] the one before it (length prev_h2).  A warm
@@ -142,7 +143,8 @@ class Engine {
   int release_graph();
 
   // switch the V-cycle sweep counts (re-captures the graph next solve)
-  int set_cycle(int nu);
+  int set_switched(bool on);
+  int trilinear() const;
   // adaptive cycle choice after a solve that took max_iters iterations
   int adapt_cycle(int max_iters);
 
