@@ -293,7 +293,8 @@ def served(args, fld, torch, synth, log):
     torch.cuda.synchronize()
     ref = pool[max(sizes)]
     prm = fld.fld_default_params(ref["c"], ref["L_unit"],
-                                 precision=fld.FLD_PREC_MIXED)
+                                 precision=fld.FLD_PREC_MIXED,
+                                 prolongation=args.prolongation)
     free, total = torch.cuda.mem_get_info()
     arena = int(0.6 * free) // 256 * 256
     stream = torch.cuda.Stream()

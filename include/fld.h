@@ -144,7 +144,8 @@ typedef struct fld_params {
                           levels run the two fused passes (coarse ones with
                           4-plane tiles); 0 = automatic (the finest level, and
                           each coarser one that still holds at least 2^20
-                          cells over all problems) */
+                          cells; decided per problem, so that a problem's
+                          result does not depend on its batch) */
 } fld_params;
 
 typedef struct fld_stats {

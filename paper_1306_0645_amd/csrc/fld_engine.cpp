@@ -210,9 +210,9 @@ static size_t tables_layout(Carver &cv, const std::vector<Hier> &hs,
     for (int l = 0; l < h.levels; ++l) ntiles += h.tiles[l] + h.ftiles[l];
     nfine += h.tiles[0] + h.ftiles[0];  // partial slots: both finest tilings
   }
-  // fine + smooth/exist/fsm/fdn per level: at most (4 kMaxLevels + 1) ranges
-  // per problem and list set, 2 ints each, kListSlots sets
-  nranges = (size_t)(4 * kMaxLevels + 1) * np * 2 * kListSlots;
+  // fine + kListsPerLevel lists per level: at most one range per problem
+  // and list, 2 ints each, kListSlots sets
+  nranges = (size_t)(kListsPerLevel * kMaxLevels + 1) * np * 2 * kListSlots;
   LevelDev *lv = cv.take<LevelDev>((size_t)kMaxLevels * np);
   ProbDev *pd = cv.take<ProbDev>(np);
   StepDev *sd = cv.take<StepDev>(np);
@@ -274,18 +274,17 @@ int Engine::setup(const fld_params &p, hipStream_t s,
   // (their indices are the partial-sum slots)
   fused = fused_cycle(p);
   lazy = lazy_iteration(p);
-  // levels run by the fused passes: the finest, then each coarser one while
-  // it still holds 2^20 cells over all problems (or fused_levels of them)
-  fused_top = 1;
-  if (p.fused_levels > 0) {
-    fused_top = std::min(p.fused_levels, Lmax);
-  } else {
-    for (int l = 1; l < Lmax; ++l) {
-      long long c = 0;
-      for (int i = 0; i < np; ++i)
-        if (l < hier[i].levels) c += hier[i].cells(l);
-      if (c < (1LL << 20)) break;
-      fused_top = l + 1;
+  // levels of each problem run by the fused passes: the finest, then each
+  // coarser one of the problem that still holds 2^20 cells (or fused_levels
+  // of them); a property of the problem alone, so that its result does not
+  // depend on the company it is solved in
+  ftop.assign(np, 1);
+  for (int i = 0; i < np; ++i) {
+    if (p.fused_levels > 0) {
+      ftop[i] = std::min(p.fused_levels, hier[i].levels);
+    } else {
+      for (int l = 1; l < hier[i].levels && hier[i].cells(l) >= (1LL << 20); ++l)
+        ftop[i] = l + 1;
     }
   }
   h_tiles.clear();
@@ -334,6 +333,7 @@ int Engine::setup(const fld_params &p, hipStream_t s,
   prev_h2.assign(np, 0.0);
   xcur.assign(np, 0);
   xold.assign(np, -1);
+  warm_now.assign(np, 0);
   for (int i = 0; i < np; ++i) {
     for (int l = 0; l < hier[i].levels; ++l) h_lv[(size_t)l * np + i] = mem[i].lv[l];
     h_pd[i] = mem[i].pd;
@@ -390,11 +390,17 @@ int Engine::build_lists(const std::vector<char> &member, int slot, ListSet &out)
     out.smooth[l] = make(l, smoothed);
     out.exist[l] = make(l, [&](int) { return l >= 1; });
     out.down[l] = make(l, [&](int i) { return l >= 1 && l <= hier[i].tail; });
-    out.fsm[l] = make_any(l, true, smoothed);
+    out.fsm[l] = make_any(l, true, [&](int i) { return smoothed(i) && l < ftop[i]; });
     // (a one-level problem runs the finest down pass too: in the fused PCG
     // iteration it forms the residual)
     out.fdn[l] = make_any(l, true, [&](int i) {
-      return smoothed(i) && (l < hier[i].levels - 1 || l == 0);
+      return smoothed(i) && l < ftop[i] && (l < hier[i].levels - 1 || l == 0);
+    });
+    // the fused cycle's per-half-sweep levels, and the levels restricted into
+    // from one of them
+    out.gsm[l] = make(l, [&](int i) { return smoothed(i) && l >= ftop[i]; });
+    out.gdn[l] = make(l, [&](int i) {
+      return l >= 1 && l <= hier[i].tail && l - 1 >= ftop[i];
     });
   }
   if (h_ranges.size() > per_slot) return ST_EINVAL;
@@ -508,23 +514,15 @@ void Engine::enqueue_fused_rest(const ListSet &ls) {
   const int prec = mixed;
   const int tri = trilinear();
   for (int l = 1; l < Lmax; ++l) {
-    if (l < fused_top) {
-      launch_vdown(T, ls.fdn[l], l, prec, VD_ALL, stream);
-      continue;
-    }
-    if (ls.smooth[l].nblocks == 0) continue;
-    launch_pre0(T, ls.smooth[l], l, prec, stream);
-    if (l + 1 < Lmax) launch_resid_restrict(T, ls.down[l + 1], l + 1, prec, stream);
+    launch_vdown(T, ls.fdn[l], l, prec, VD_ALL, stream);
+    launch_pre0(T, ls.gsm[l], l, prec, stream);
+    if (l + 1 < Lmax) launch_resid_restrict(T, ls.gdn[l + 1], l + 1, prec, stream);
   }
   if (Lmax > 1) launch_vtail(T, prec, 1, 1, tri, stream);
   for (int l = Lmax - 1; l >= 1; --l) {
-    if (l < fused_top) {
-      launch_vup(T, ls.fsm[l], l, prec, 0, tri, stream);
-      continue;
-    }
-    if (ls.smooth[l].nblocks == 0) continue;
-    launch_prolong_black(T, ls.smooth[l], l, prec, tri, stream);
-    launch_half(T, ls.smooth[l], l, 0, prec, stream);
+    launch_vup(T, ls.fsm[l], l, prec, 0, tri, stream);
+    launch_prolong_black(T, ls.gsm[l], l, prec, tri, stream);
+    launch_half(T, ls.gsm[l], l, 0, prec, stream);
   }
   launch_vup(T, ls.fsm[0], 0, prec, mixed, tri, stream);
 }
@@ -697,6 +695,52 @@ int Engine::run_solve() {
   return ST_OK;
 }
 
+// Warm start of problem p's next solve over a step h, when its history
+// allows: dE is about h times the mean rate over the step, so scale the last
+// dE, or extrapolate the rate linearly from the last two.  The guess goes
+// into the dE buffer that holds neither history entry, which becomes P.x
+// (the caller uploads the problem table before the assembly).
+bool Engine::set_warm(int p, double h) {
+  warm_now[p] = 0;
+  if (!prm.warm_start || prev_ok[p] < 1 || !(prev_h[p] > 0.0)) return false;
+  warm_now[p] = 1;
+  const double h1 = prev_h[p], r1 = h / h1;
+  StepDev &S = h_sd[p];
+  S.warm = 1.0;
+  S.w1 = r1;
+  S.w2 = 0.0;
+  const bool two = prev_ok[p] >= 2 && prev_h2[p] > 0.0 && xold[p] >= 0;
+  if (two) {
+    const double h0 = prev_h2[p];
+    const double tau = (h1 + h) / (h0 + h1);
+    S.w1 = r1 * (1.0 + tau);
+    S.w2 = -(h / h0) * tau;
+  }
+  const int a = xcur[p], b = two ? xold[p] : -1;
+  int nxt = 0;
+  while (nxt == a || nxt == b) ++nxt;
+  S.h1 = mem[p].xb[a];
+  S.h2 = two ? mem[p].xb[b] : nullptr;
+  mem[p].pd.x = h_pd[p].x = mem[p].xb[nxt];
+  xold[p] = a;
+  xcur[p] = nxt;
+  return true;
+}
+
+// dE of a successful substep of length h seeds the next one; after a warm
+// start the one before stays in xb[xold]
+void Engine::note_success(int p, double h) {
+  prev_ok[p] = warm_now[p] ? 2 : 1;
+  prev_h2[p] = prev_h[p];
+  prev_h[p] = h;
+}
+
+int Engine::upload_pd() {
+  HIP_TRY(hipMemcpyAsync(T.pd, h_pd.data(), sizeof(ProbDev) * h_pd.size(),
+                         hipMemcpyHostToDevice, stream));
+  return ST_OK;
+}
+
 // Steps for every job not done: assemble, solve, and on success E += dE;
 // on failure cut the job's radiation step by 10x and subcycle (Sec. 3.4).
 int Engine::run_steps(std::vector<Job> &jobs) {
@@ -712,39 +756,15 @@ int Engine::run_steps(std::vector<Job> &jobs) {
       any = true;
       j.h = std::min(j.h, j.dt - j.t);
       fill_step(p, j.in_work ? mem[p].E_work : j.E, j.kappa, j.eta, j.h, j.a, j.adot);
-      if (prm.warm_start && prev_ok[p] >= 1 && prev_h[p] > 0.0) {
-        // dE is about h times the mean rate over the step: scale the last
-        // dE, or extrapolate the rate linearly from the last two
-        const double h1 = prev_h[p], r1 = j.h / h1;
-        StepDev &S = h_sd[p];
-        S.warm = 1.0;
-        S.w1 = r1;
-        S.w2 = 0.0;
-        const bool two = prev_ok[p] >= 2 && prev_h2[p] > 0.0 && xold[p] >= 0;
-        if (two) {
-          const double h0 = prev_h2[p];
-          const double tau = (h1 + j.h) / (h0 + h1);
-          S.w1 = r1 * (1.0 + tau);
-          S.w2 = -(j.h / h0) * tau;
-        }
-        // the guess goes into the buffer that holds neither history entry
-        const int a = xcur[p], b = two ? xold[p] : -1;
-        int nxt = 0;
-        while (nxt == a || nxt == b) ++nxt;
-        S.h1 = mem[p].xb[a];
-        S.h2 = two ? mem[p].xb[b] : nullptr;
-        mem[p].pd.x = h_pd[p].x = mem[p].xb[nxt];
-        xold[p] = a;
-        xcur[p] = nxt;
-        warm = true;
-      }
+      if (set_warm(p, j.h)) warm = true;
     }
     if (!any) break;
     int st = upload_sd_sc();
     if (st) return st;
-    if (warm)
-      HIP_TRY(hipMemcpyAsync(T.pd, h_pd.data(), sizeof(ProbDev) * h_pd.size(),
-                             hipMemcpyHostToDevice, stream));
+    if (warm) {
+      st = upload_pd();
+      if (st) return st;
+    }
     // (a warm guess's residual b - A x0 comes out of the assembly, FIN_BB
     // keeps the guess only if it reduces the residual)
     enqueue_assemble(all);
@@ -770,11 +790,7 @@ int Engine::run_steps(std::vector<Job> &jobs) {
       j.iters += h_sc[p].iter;
       j.restarts += h_sc[p].restarts;
       if (h_sc[p].phase == PH_DONE && h_sc[p].status == ST_OK) {
-        // dE of this substep seeds the next one; after a warm start the
-        // one before stays in xb[xold]
-        prev_ok[p] = h_sd[p].warm > 0.0 ? 2 : 1;
-        prev_h2[p] = prev_h[p];
-        prev_h[p] = j.h;
+        note_success(p, j.h);
         const bool last = j.dt - (j.t + j.h) <= 1e-12 * j.dt;
         target[p] = (!j.in_work && last) ? 1 : 2;
         h_sd[p].Eout = target[p] == 1 ? j.E : mem[p].E_work;

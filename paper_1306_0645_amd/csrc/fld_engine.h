@@ -78,7 +78,10 @@ struct ListSet {
   TileList fsm[kMaxLevels]{};   // fused tiles of smoothed levels
   TileList fdn[kMaxLevels]{};   // fused tiles of smoothed levels with a coarser one
   TileList down[kMaxLevels]{};  // levels restricted into from a per-level sweep
+  TileList gsm[kMaxLevels]{};   // fused cycle: per-half-sweep smoothed levels
+  TileList gdn[kMaxLevels]{};   // fused cycle: levels restricted into from one
 };
+constexpr int kListsPerLevel = 7;  // smooth, exist, down, fsm, fdn, gsm, gdn
 
 constexpr int kListSlots = 4;  // independent range regions (server phases)
 
@@ -104,7 +107,7 @@ class Engine {
   bool fused = false;      // one-sweep fused V-cycle kernels
   bool lazy = false;       // fused PCG iteration (residual update in the down pass)
   bool need_pro = false;   // some problem (re)starts: enqueue_prologue is due
-  int fused_top = 1;       // levels 0 .. fused_top - 1 run the fused passes
+  std::vector<int> ftop;   // per problem: levels 0 .. ftop - 1 run the fused passes
   int last_nu = 1;         // sweeps per side of the cycle used by the last solve
   int last_tri = 0;        // the last solve's cycle used trilinear correction
   bool switched = false;   // the adaptive switch changed the handle's cycle
@@ -116,6 +119,7 @@ class Engine {
   std::vector<char> prev_ok;
   std::vector<double> prev_h, prev_h2;
   std::vector<int> xcur, xold;
+  std::vector<char> warm_now;  // the current substep started from a warm guess
 
   Tables T{};
   Tile *d_tiles = nullptr;
@@ -144,6 +148,9 @@ class Engine {
 
   // switch the V-cycle sweep counts (re-captures the graph next solve)
   int set_switched(bool on);
+  bool set_warm(int p, double h);
+  void note_success(int p, double h);
+  int upload_pd();
   int trilinear() const;
   // adaptive cycle choice after a solve that took max_iters iterations
   int adapt_cycle(int max_iters);

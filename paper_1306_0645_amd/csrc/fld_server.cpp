@@ -100,6 +100,10 @@ struct Req {
   int step = 0;
   Job job;
   Scal sc{};
+  // warm-start history across engine rebuilds (Engine::set_warm)
+  char prev_ok = 0, warm_now = 0;
+  double prev_h = 0, prev_h2 = 0;
+  int xcur = 0, xold = -1;
   double t_submit = 0, t_admit = 0, t_done = 0;
   fld_result res{};
 };
@@ -183,7 +187,17 @@ int fld_server::rebuild() {
     eng->fill_step((int)i, eng->mem[i].E_work, q->r.kappa, q->r.eta, j.h, j.a, j.adot);
     eng->h_sc[i] = q->sc;
     eng->h_sc[i].live = 0;
+    // a request's dE buffers keep their place in its workspace
+    eng->prev_ok[i] = q->prev_ok;
+    eng->prev_h[i] = q->prev_h;
+    eng->prev_h2[i] = q->prev_h2;
+    eng->xcur[i] = q->xcur;
+    eng->xold[i] = q->xold;
+    eng->warm_now[i] = q->warm_now;
+    eng->mem[i].pd.x = eng->h_pd[i].x = eng->mem[i].xb[q->xcur];
   }
+  st = eng->upload_pd();
+  if (st) return st;
   return eng->upload_sd_sc();
 }
 
@@ -199,7 +213,9 @@ int fld_server::tick() {
   const int n = (int)resident.size();
   std::vector<char> mA(n, 0), mS(n, 0), mC(n, 0);
   bool anyA = false, anyS = false;
-  // (1) assembly for requests starting a substep
+  // (1) assembly for requests starting a substep (warm-started from the
+  // request's previous substeps, as fld_step does)
+  bool anyW = false;
   for (int i = 0; i < n; ++i) {
     Req *q = resident[i];
     e.h_sc[i].live = 0;
@@ -208,6 +224,7 @@ int fld_server::tick() {
       Job &j = q->job;
       j.h = std::min(j.h, j.dt - j.t);
       e.fill_step(i, e.mem[i].E_work, q->r.kappa, q->r.eta, j.h, j.a, j.adot);
+      if (e.set_warm(i, j.h)) anyW = true;
       mA[i] = 1;
       anyA = true;
       q->state = RQ_SOLVING;
@@ -219,10 +236,12 @@ int fld_server::tick() {
   }
   if (!anyS) return ST_OK;
   TRY(e.upload_sd_sc());
+  if (anyW) TRY(e.upload_pd());
   ListSet lsA, lsS, lsC;
   if (anyA) {
     TRY(e.build_lists(mA, 1, lsA));
     e.enqueue_assemble(lsA);
+    if (anyW) launch_warm_revert(e.T, lsA.fine, stream);
   }
   // (2) one PCG iteration for every solving request (device flags decide)
   TRY(e.build_lists(mS, 2, lsS));
@@ -254,12 +273,14 @@ int fld_server::tick() {
     j.iters += sc.iter;
     j.restarts += sc.restarts;
     if (sc.status == ST_OK) {
+      e.note_success(i, j.h);
       mC[i] = 1;
       anyC = true;
       e.h_sd[i].E = e.mem[i].E_work;
       e.h_sd[i].Eout = e.mem[i].E_work;
       e.h_sc[i].live = 1;
     } else if (j.cuts < prm.max_dt_cuts) {
+      e.prev_ok[i] = 0;
       j.h *= 0.1;
       j.cuts += 1;
       q->state = RQ_ASSEMBLE;
@@ -310,7 +331,16 @@ int fld_server::tick() {
     }
     for (int i = 0; i < n; ++i) e.h_sc[i].live = 0;
   }
-  for (int i = 0; i < n; ++i) resident[i]->sc = e.h_sc[i];
+  for (int i = 0; i < n; ++i) {
+    Req *q = resident[i];
+    q->sc = e.h_sc[i];
+    q->prev_ok = e.prev_ok[i];
+    q->prev_h = e.prev_h[i];
+    q->prev_h2 = e.prev_h2[i];
+    q->xcur = e.xcur[i];
+    q->xold = e.xold[i];
+    q->warm_now = e.warm_now[i];
+  }
   return ST_OK;
 }
 
