@@ -119,8 +119,8 @@ typedef struct fld_params {
                           handle switch cycle, until one needs at most a
                           third of it and the handle switches back.  The
                           switched cycle is V(1,1) with trilinear correction
-                          in mixed precision with prolongation = 2, else
-                          V(2,2).  0, or any other configured cycle: the cycle
+                          in mixed precision with prolongation = 2 when the
+                          largest grid has at least 2^23 cells, else V(2,2).  0, or any other configured cycle: the cycle
                           stays as configured.  Default 12 */
   int32_t prolongation;/* coarse-grid correction of the FP32 (mixed) cycle:
                           0 = piecewise constant, 1 = cell-centred trilinear,

@@ -442,15 +442,20 @@ int Engine::download_sc() {
   return ST_OK;
 }
 
-// The switched cycle.  In mixed precision with automatic prolongation it is
-// V(1,1) with trilinear correction: the fused passes make a V(1,1) iteration
-// less than half the cost of a per-half-sweep V(2,2) one (640^3 reionization
-// share, mixed: 776 Mcell-updates/s at 26.8 iterations per step against 564
-// at 17.1 with V(2,2)).  Otherwise V(2,2).
+// The switched cycle.  In mixed precision with automatic prolongation, on a
+// problem of at least 2^23 cells, it is V(1,1) with trilinear correction: the
+// fused passes make such a V(1,1) iteration less than half the cost of a
+// per-half-sweep V(2,2) one (640^3 reionization share, mixed: 776
+// Mcell-updates/s at 26.8 iterations per step against 564 at 17.1 with
+// V(2,2)).  Smaller grids are launch-bound, so the iterations V(2,2) saves
+// count for more (Test-1 and Test-2 octants of 32^3 to 128^3: V(2,2) 10-25 %
+// faster).  Otherwise, and in FP64, V(2,2).
 int Engine::set_switched(bool on) {
   if (on == switched) return ST_OK;
   switched = on;
-  const bool tri_only = mixed && prm.prolongation == 2;
+  long long big = 0;
+  for (const Hier &h : hier) big = std::max(big, h.cells(0));
+  const bool tri_only = mixed && prm.prolongation == 2 && big >= (1LL << 23);
   const int nu = (on && !tri_only) ? 2 : 1;
   prm.nu_pre = prm.nu_post = nu;
   fused = fused_cycle(prm);
