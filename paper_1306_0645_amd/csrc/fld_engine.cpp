@@ -85,16 +85,28 @@ Hier make_hier(const fld_grid &g, const fld_params &p) {
 // level.  Deeper tiles cut the z-halo but leave fewer tiles to hide latency:
 // measured on gfx950 at 256^3 (Mcell-updates/s for 8, 16, 32, 64 planes: FP32
 // cycle 2532, 2537, 2608, 2451; FP64 2203, 2268, 2308, 2217), 32 planes suit
-// both.  Coarse levels that run the fused passes are 8x smaller and use 4
-// planes, so that they still give a few tiles per CU (128^3 level of 256^3,
-// Mcell-updates/s with 8 and 4 planes: FP32 cycle 2622, 2652; FP64 2367,
-// 2383).
+// a grid that still gives 512 tiles with them; smaller grids halve the depth
+// (down to 2 planes) until they do, since a handful of tiles marching 32
+// planes each leaves the GPU idle (64^3: 8 tiles).  Coarse levels that run
+// the fused passes are 8x smaller and use 4 planes, so that they still give a
+// few tiles per CU (128^3 level of 256^3, Mcell-updates/s with 8 and 4
+// planes: FP32 cycle 2622, 2652; FP64 2367, 2383).
 void fused_shape(const fld_params &p, int l, int nx, int ny, int nz, int &tx,
                  int &ty, int &tz) {
   tx = std::min(nx, 64);
   ty = std::min(ny, 16);
-  const int def = l == 0 ? (p.fused_tile_z > 0 ? p.fused_tile_z : 32) : 4;
-  tz = std::min(nz, def);
+  if (l > 0) {
+    tz = std::min(nz, 4);
+    return;
+  }
+  if (p.fused_tile_z > 0) {
+    tz = std::min(nz, p.fused_tile_z);
+    return;
+  }
+  const long long xy = (long long)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
+  tz = 32;
+  while (tz > 2 && xy * ((nz + tz - 1) / tz) < 512) tz >>= 1;
+  tz = std::min(tz, nz);
 }
 
 int count_fused_tiles(const fld_params &p, int l, int nx, int ny, int nz) {
@@ -654,10 +666,14 @@ int Engine::check_every() const {
 // Iterate every problem in PH_ITER until each one is decided.  Problems whose
 // recursive residual meets the tolerance are verified with the true FP64
 // residual b - A x and restarted from it if it does not (refinement).
-int Engine::run_solve() {
+// predicted: the caller set the host mirror of every problem it just
+// assembled to "iterating", so the first batch goes out without waiting to
+// read the state back (a problem the assembly finished, b = 0, or failed,
+// skips the batch's kernels on the device and shows up at the first read)
+int Engine::run_solve(bool predicted) {
   last_nu = prm.nu_pre;
   last_tri = trilinear();
-  int st = download_sc();
+  int st = predicted ? ST_OK : download_sc();
   if (st) return st;
   for (;;) {
     int nact = 0, nver = 0;
@@ -777,7 +793,13 @@ int Engine::run_steps(std::vector<Job> &jobs) {
       launch_warm_revert(T, all.fine, stream);
       warm = false;
     }
-    st = run_solve();
+    for (int p = 0; p < np; ++p) {
+      if (jobs[p].done) continue;
+      h_sc[p].phase = PH_ITER;
+      h_sc[p].active = 1;
+      h_sc[p].xlag = 0;
+    }
+    st = run_solve(true);
     if (st) return st;
     {
       int mx = 0;
