@@ -254,10 +254,11 @@ size_t tables_bytes(const std::vector<Hier> &hs) {
 Engine::~Engine() { release_graph(); }
 
 int Engine::release_graph() {
-  if (gexec) hipGraphExecDestroy(gexec);
-  if (graph) hipGraphDestroy(graph);
-  gexec = nullptr;
-  graph = nullptr;
+  for (auto &g : graphs) {
+    if (g.second.exec) hipGraphExecDestroy(g.second.exec);
+    if (g.second.graph) hipGraphDestroy(g.second.graph);
+  }
+  graphs.clear();
   if (cap_stream) hipStreamDestroy(cap_stream);
   cap_stream = nullptr;
   return ST_OK;
@@ -657,9 +658,9 @@ int Engine::check_every() const {
   if (prm.check_every > 0) return prm.check_every;
   long long cells = 0;
   for (const Hier &h : hier) cells += h.cells(0);
-  // large grids: a host read every 2 iterations (measured ~1 % faster than
-  // every iteration at 256^3; a converged problem then idles through at most
-  // one iteration of early-returning kernels)
+  // (the batch size of a handle's first solve, before run_solve has an
+  // iteration count to go by) large grids: a host read every 2 iterations;
+  // small grids, where reads cost more than iterations, every 4
   return cells >= (1LL << 22) ? 2 : 4;
 }
 
@@ -675,6 +676,7 @@ int Engine::run_solve(bool predicted) {
   last_tri = trilinear();
   int st = predicted ? ST_OK : download_sc();
   if (st) return st;
+  first_batch = true;
   for (;;) {
     int nact = 0, nver = 0;
     bool fix = false;
@@ -690,20 +692,30 @@ int Engine::run_solve(bool predicted) {
       need_pro = true;
     } else if (nact) {
       enqueue_prologue(all);
-      const int K = check_every();
+      // iterations before the next host read: automatic mode sizes the
+      // solve's first batch to one less than the last solve took and reads
+      // after every iteration from there on, so a solve like the last costs
+      // two reads and no iteration of a converged problem (one of
+      // early-returning kernels, otherwise)
+      int K = check_every();
+      if (prm.check_every <= 0 && last_iters > 1)
+        K = first_batch ? std::min(last_iters - 1, 16) : 1;
+      first_batch = false;
       if (prm.use_graph) {
-        if (!gexec) {
-          HIP_TRY(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+        Captured &g = graphs[K];
+        if (!g.exec) {
+          if (!cap_stream)
+            HIP_TRY(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
           HIP_TRY(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
           hipStream_t saved = stream;
           stream = cap_stream;
           // one graph holds the K iterations between host checks
           for (int k = 0; k < K; ++k) enqueue_iteration(all);
           stream = saved;
-          HIP_TRY(hipStreamEndCapture(cap_stream, &graph));
-          HIP_TRY(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+          HIP_TRY(hipStreamEndCapture(cap_stream, &g.graph));
+          HIP_TRY(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
         }
-        HIP_TRY(hipGraphLaunch(gexec, stream));
+        HIP_TRY(hipGraphLaunch(g.exec, stream));
       } else {
         for (int k = 0; k < K; ++k) enqueue_iteration(all);
       }
@@ -713,6 +725,10 @@ int Engine::run_solve(bool predicted) {
     st = download_sc();
     if (st) return st;
   }
+  int mx = 0;
+  for (const Scal &sc : h_sc)
+    if (sc.live) mx = std::max(mx, sc.iter);
+  last_iters = mx;
   return ST_OK;
 }
 

@@ -4,6 +4,7 @@
 // and tile lists, and drives assembly, the PCG iteration and the step logic.
 #pragma once
 
+#include <map>
 #include <vector>
 
 #include "fld.h"
@@ -127,9 +128,15 @@ class Engine {
   size_t ranges_cap = 0;   // ints available at d_ranges (all slots)
   ListSet all;             // every problem (slot 0)
 
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  // captured K-iteration batches, by K
+  struct Captured {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::map<int, Captured> graphs;
   hipStream_t cap_stream = nullptr;
+  int last_iters = 0;       // iterations of the last solve (its slowest problem)
+  bool first_batch = true;  // the next batch is a solve's first
   bool assembled = false;
   int last_status = ST_OK;
 
