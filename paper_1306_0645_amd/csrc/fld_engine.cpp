@@ -671,7 +671,10 @@ int Engine::check_every() const {
 // assembled to "iterating", so the first batch goes out without waiting to
 // read the state back (a problem the assembly finished, b = 0, or failed,
 // skips the batch's kernels on the device and shows up at the first read)
-int Engine::run_solve(bool predicted) {
+// commit: right after each verification, E += dE for the problems it
+// decided (their Eout already set), so a converged step needs no further
+// round trip.
+int Engine::run_solve(bool predicted, bool commit) {
   last_nu = prm.nu_pre;
   last_tri = trilinear();
   int st = predicted ? ST_OK : download_sc();
@@ -690,6 +693,10 @@ int Engine::run_solve(bool predicted) {
       launch_true_resid(T, all.fine, stream);
       launch_fin(T, FIN_TRUE, mixed, stream);
       need_pro = true;
+      if (commit) {
+        launch_update_E(T, all.fine, prm.e_floor, 0, stream, 1);
+        launch_fin(T, FIN_STEP, mixed, stream, 1);
+      }
     } else if (nact) {
       enqueue_prologue(all);
       // iterations before the next host read: automatic mode sizes the
@@ -794,6 +801,11 @@ int Engine::run_steps(std::vector<Job> &jobs) {
       j.h = std::min(j.h, j.dt - j.t);
       fill_step(p, j.in_work ? mem[p].E_work : j.E, j.kappa, j.eta, j.h, j.a, j.adot);
       if (set_warm(p, j.h)) warm = true;
+      // where E + dE goes if this substep succeeds: the caller's E after
+      // the last substep of a step that never left it, else the work copy
+      const bool last = j.dt - (j.t + j.h) <= 1e-12 * j.dt;
+      target[p] = (!j.in_work && last) ? 1 : 2;
+      h_sd[p].Eout = target[p] == 1 ? j.E : mem[p].E_work;
     }
     if (!any) break;
     int st = upload_sd_sc();
@@ -815,7 +827,7 @@ int Engine::run_steps(std::vector<Job> &jobs) {
       h_sc[p].active = 1;
       h_sc[p].xlag = 0;
     }
-    st = run_solve(true);
+    st = run_solve(true, true);
     if (st) return st;
     {
       int mx = 0;
@@ -824,21 +836,27 @@ int Engine::run_steps(std::vector<Job> &jobs) {
       st = adapt_cycle(mx);
       if (st) return st;
     }
+    // problems the solve decided without a verification (b = 0) still need
+    // their E update
     bool commit = false;
+    std::vector<char> ok(np, 0);
     for (int p = 0; p < np; ++p) {
       Job &j = jobs[p];
-      target[p] = 0;
-      if (!h_sc[p].live) continue;
+      const bool live = h_sc[p].live;
       h_sc[p].live = 0;
+      if (!live) {
+        target[p] = 0;
+        continue;
+      }
       j.iters += h_sc[p].iter;
       j.restarts += h_sc[p].restarts;
       if (h_sc[p].phase == PH_DONE && h_sc[p].status == ST_OK) {
         note_success(p, j.h);
-        const bool last = j.dt - (j.t + j.h) <= 1e-12 * j.dt;
-        target[p] = (!j.in_work && last) ? 1 : 2;
-        h_sd[p].Eout = target[p] == 1 ? j.E : mem[p].E_work;
-        h_sc[p].live = 1;
-        commit = true;
+        ok[p] = 1;
+        if (!h_sc[p].committed) {
+          h_sc[p].live = 1;
+          commit = true;
+        }
       } else if (j.cuts < prm.max_dt_cuts) {
         prev_ok[p] = 0;
         j.h *= 0.1;
@@ -856,8 +874,10 @@ int Engine::run_steps(std::vector<Job> &jobs) {
       launch_fin(T, FIN_STEP, mixed, stream);
       st = download_sc();
       if (st) return st;
+    }
+    {
       for (int p = 0; p < np; ++p) {
-        if (!target[p]) continue;
+        if (!ok[p]) continue;
         Job &j = jobs[p];
         const Scal &sc = h_sc[p];
         const double n = (double)hier[p].cells(0);

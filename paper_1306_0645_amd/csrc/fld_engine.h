@@ -168,7 +168,7 @@ class Engine {
   void enqueue_iteration(const ListSet &ls);
   void enqueue_prologue(const ListSet &ls);
   void finish_x(const ListSet &ls);
-  int run_solve(bool predicted = false);
+  int run_solve(bool predicted = false, bool commit = false);
   int run_steps(std::vector<Job> &jobs);
   int check_every() const;
   void fill_step(int p, const double *E, const double *kappa, const double *eta,

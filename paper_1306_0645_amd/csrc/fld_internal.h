@@ -87,7 +87,7 @@ struct Scal {
   // or by k_xfix when the iteration stops)
   int rbuf, has_dir, xlag, snew;
   int fresh;             // (re)started: the finest down pass is still due
-  int pad;
+  int committed;         // E += dE of this solve is done (FIN_STEP)
 };
 
 // A tile: cells [x0, x0+tx) x [y0, y0+ty) x [z0, z0+tz) of one level of one
@@ -186,8 +186,10 @@ void launch_apply(const Tables &T, TileList L0, const double *u, double *out,
                   hipStream_t s);
 void launch_set_r(const Tables &T, TileList L0, const double *r, int prec,
                   hipStream_t s);
+// in_solve: right after a verification, for the problems it just decided
+// (FIN_STEP then takes alt = 1)
 void launch_update_E(const Tables &T, TileList L0, double floor, int copy_only,
-                     hipStream_t s);
+                     hipStream_t s, int in_solve = 0);
 // fused one-sweep V-cycle passes (fld_fused.hip)
 // sel (finest level of the rotated fused iteration): VD_ALL every active
 // problem, VD_FRESH those starting or restarting, VD_CONT the others

@@ -897,13 +897,19 @@ __global__ __launch_bounds__(kBlock) void k_set_r(Tables T, TileList TL,
 
 // E_out = E + dE with the relative-change sum (dE / max(|E_out|, floor))^2
 // and ||dE||^2; copy_only: E_out = dE (solve entry point).
+// in_solve: launched right after the verification; acts only on problems it
+// just decided (done, ok, not yet committed)
+__device__ __forceinline__ bool commit_now(const Scal &sc) {
+  return sc.live && sc.phase == PH_DONE && sc.status == ST_OK && !sc.committed;
+}
+
 __global__ __launch_bounds__(kBlock) void k_update_E(Tables T, TileList TL,
                                                      double floor,
-                                                     int copy_only) {
+                                                     int copy_only, int in_solve) {
   const int tid = get_tile_index(TL);
   const Tile t = TL.base[tid];
   const Scal &sc = T.sc[t.prob];
-  if (!sc.live) return;
+  if (in_solve ? !commit_now(sc) : !sc.live) return;
   const LevelDev L = T.lv[t.prob];
   const ProbDev P = T.pd[t.prob];
   const StepDev S = T.sd[t.prob];
@@ -967,7 +973,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
   bool part;
   switch (which) {
     case FIN_BB:
-    case FIN_STEP: part = sc.live != 0; break;
+    case FIN_STEP: part = alt ? commit_now(sc) : sc.live != 0; break;
     case FIN_TRUE: part = sc.phase == PH_VERIFY; break;
     case FIN_SETR: part = true; break;
     case FIN_RR2: part = sc.active && sc.has_dir; break;
@@ -1011,6 +1017,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
       sc.pbuf = 0;
       sc.has_dir = sc.xlag = sc.snew = 0;
       sc.fresh = 1;
+      sc.committed = 0;
       sc.status = ST_OK;
       sc.phase = PH_ITER;
       sc.active = 1;
@@ -1118,6 +1125,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
     case FIN_STEP:
       sc.change2 = a0;
       sc.dEdE = a1;
+      sc.committed = 1;
       break;
     case FIN_SETR:
       sc.rr = a0;
@@ -1332,8 +1340,10 @@ void launch_warm_revert(const Tables &T, TileList L0, hipStream_t s) {
 }
 
 void launch_update_E(const Tables &T, TileList L0, double floor, int copy_only,
-                     hipStream_t s) {
-  if (L0.nblocks) LAUNCH(K_UPDATE_E, k_update_E, L0.nblocks, kBlock, s, T, L0, floor, copy_only);
+                     hipStream_t s, int in_solve) {
+  if (L0.nblocks)
+    LAUNCH(K_UPDATE_E, k_update_E, L0.nblocks, kBlock, s, T, L0, floor, copy_only,
+           in_solve);
 }
 
 }  // namespace fld
