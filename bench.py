@@ -32,15 +32,17 @@ BYTES_PER_CELL = {
     # assembly with a warm start: E, kappa, eta and the two dE history
     # buffers in; the system, b, the guess x and its residual r = b - A x out
     "assemble": (96.0, 112.0),
-    "spmv_p": (64.0, 64.0),
+    # mixed form: z is read as the FP32 cycle output (4 B instead of 8)
+    "spmv_p": (64.0, 60.0),
     # fused iteration's SpMV: also x += alpha p_old (x read and written)
-    "spmv_px": (80.0, 80.0),
+    "spmv_px": (80.0, 76.0),
     # the deferred x += alpha p when a solve stops iterating
     "xfix": (24.0, 24.0),
     "update": (48.0, 48.0),
     "pre0_fine": (48.0, 28.0),
     "half_fine": (56.0, 32.0),
-    "half_out": (56.0, 44.0),
+    # mixed: reads the old FP32 z (flexible PCG) and writes the new one
+    "half_out": (56.0, 36.0),
     "resid_restrict_fine": (49.0, 28.5),
     "prolong_black_fine": (57.0, 32.5),
     "true_resid": (56.0, 56.0),
@@ -48,14 +50,14 @@ BYTES_PER_CELL = {
     # fused down pass; in the mixed form it also reads q and writes the
     # updated residual r - alpha q (the first iteration of a solve skips both)
     "vdown_fine": (41.0, 40.5),
-    "vup_fine": (49.0, 40.5),
+    "vup_fine": (49.0, 32.5),
     # weighted-Jacobi smoother: first sweep from zero (diag, f, x out), a
     # sweep (4 coefficient arrays, x in, f, x out), the last finest sweep
-    # (writes z; the mixed form also reads the old z), x + P e (x, e at 1/8,
-    # out)
+    # (writes z; the mixed form also reads the old z, both FP32), x + P e (x,
+    # e at 1/8, out)
     "jacobi0_fine": (24.0, 16.0),
     "jacobi_fine": (56.0, 32.0),
-    "jacobi_out": (56.0, 44.0),
+    "jacobi_out": (56.0, 36.0),
     "prolong_add_fine": (17.0, 8.5),
 }
 
@@ -78,6 +80,8 @@ def coarse_fraction(levels):
 
 
 STEP_KERNELS = ("assemble", "true_resid", "update_E", "xfix")
+# the old FP32 z that the mixed form's finest up pass reads for flexible PCG
+OLD_Z_BYTES = 4.0
 
 
 def step_bytes(counts, cells, prec_idx, levels):
@@ -98,6 +102,9 @@ def step_bytes(counts, cells, prec_idx, levels):
     it += counts.get("jacobi0_fine", 0) * cf * COARSE_CYCLE_BYTES_JACOBI[prec_idx] * cells
     coarsen = 32.0 * (1.0 + cf - 8.0 ** -(levels - 1)) + (48.0 if prec_idx else 32.0) * cf
     fixed += counts.get("assemble", 0) * coarsen * cells
+    if prec_idx:
+        # the first cycle of each solve reads no old z (beta = 0 there)
+        fixed -= counts.get("assemble", 0) * OLD_Z_BYTES * cells
     return fixed, it
 
 
@@ -126,6 +133,8 @@ def model_step_bytes(cells, iters, nu, prec_idx, levels, steps=1, warm=False):
     fixed = B["assemble"] + coarsen + B["true_resid"] + B["update_E"]
     if nu == 1 and prec_idx == 1:
         fixed += B["xfix"]
+    if prec_idx == 1:
+        fixed -= OLD_Z_BYTES  # no old z in the first cycle of the solve
     if not warm:  # a cold assembly reads no history
         fixed -= 16.0
     return cells * (steps * fixed + iters * per_iter)

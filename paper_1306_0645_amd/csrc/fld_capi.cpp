@@ -244,8 +244,12 @@ fld_status fld_precondition(fld_handle *h, const double *r, double *z) {
   launch_fin(e.T, FIN_SETR, e.mixed, e.stream);
   e.enqueue_vcycle(e.all);
   const ProbDev &P = e.mem[0].pd;
-  if (hipMemcpyAsync(z, P.z, nb, hipMemcpyDeviceToDevice, e.stream) != hipSuccess)
+  if (e.mixed) {
+    launch_z_out(e.T, e.all.fine, z, e.stream);
+    if (hipGetLastError() != hipSuccess) return FLD_EDEVICE;
+  } else if (hipMemcpyAsync(z, P.z, nb, hipMemcpyDeviceToDevice, e.stream) != hipSuccess) {
     return FLD_EDEVICE;
+  }
   int st = e.download_sc();  // also syncs
   if (st) return (fld_status)st;
   // the solve state was overwritten: a new fld_assemble is needed to solve

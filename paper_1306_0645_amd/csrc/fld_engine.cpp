@@ -178,7 +178,8 @@ void carve_problem(Carver &cv, const Hier &h, const fld_params &p, ProbMem &m) {
       P.n = L.n;
       P.x = cv.take<double>(n);
       P.r = cv.take<double>(n);
-      P.z = cv.take<double>(n);
+      if (mixed) P.z32 = cv.take<float>(n);
+      else P.z = cv.take<double>(n);
       P.p0 = cv.take<double>(n);
       P.p1 = cv.take<double>(n);
       P.q = cv.take<double>(n);
@@ -622,7 +623,7 @@ void Engine::enqueue_iteration(const ListSet &ls) {
   if (lazy) {
     enqueue_fused_rest(ls);
     launch_fin(T, FIN_RZ, mixed, stream, 1);
-    launch_spmv_p(T, ls.fine, 1, stream);
+    launch_spmv_p(T, ls.fine, 1, mixed, stream);
     launch_fin(T, FIN_PQ, mixed, stream, 1);
     launch_vdown(T, ls.fdn[0], 0, mixed, VD_CONT, stream);
     launch_fin(T, FIN_RR2, mixed, stream, 1);
@@ -630,7 +631,7 @@ void Engine::enqueue_iteration(const ListSet &ls) {
   }
   enqueue_vcycle(ls);
   launch_fin(T, FIN_RZ, mixed, stream, fused ? 1 : 0);
-  launch_spmv_p(T, ls.fine, 0, stream);
+  launch_spmv_p(T, ls.fine, 0, mixed, stream);
   launch_fin(T, FIN_PQ, mixed, stream, 0);
   launch_update(T, ls.fine, stream);
   launch_fin(T, FIN_RR, mixed, stream);

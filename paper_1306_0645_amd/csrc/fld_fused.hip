@@ -502,6 +502,10 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
   const R *e = (const R *)Cl.x;
   R *xout = (R *)L.x;
   const double s_out = sc.s;
+  // flexible PCG needs r.z_old, except where the PCG (re)starts (beta = 0);
+  // the mixed form keeps z as the cycle's FP32 output, z = zscale z32
+  const bool rd_old = flexible && !sc.restart;
+  const double zs_old = sc.zscale;
   __shared__ R vs[3][kE2];
   __shared__ R xs[3][kE1];
   const int nx = L.nx, ny = L.ny, nz = L.nz;
@@ -534,17 +538,17 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
     // iterations since its first load would cost more registers than the
     // read costs bytes) and, for the flexible dot, the old z
     Q4<FT> H{};
-    double zo00 = 0.0, zo10 = 0.0, zo01 = 0.0, zo11 = 0.0;
+    R zo00 = 0, zo10 = 0, zo01 = 0, zo11 = 0;
     if (out) {
       const FT *src;
       if constexpr (L0) src = f.r;
       else src = f.f;
       ld2(src + o0, H.v00, H.v10);
       ld2(src + o0 + nx, H.v01, H.v11);
-      if constexpr (L0) {
-        if (flexible) {
-          ld2(P.z + o0, zo00, zo10);
-          ld2(P.z + o0 + nx, zo01, zo11);
+      if constexpr (L0 && sizeof(R) == 4) {
+        if (rd_old) {
+          ld2(P.z32 + o0, zo00, zo10);
+          ld2(P.z32 + o0 + nx, zo01, zo11);
         }
       }
     }
@@ -577,7 +581,8 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
       __syncthreads();
     }
     // (3) plane pr2 on the tile: new red values from the new black ones, every
-    //     cell written (finest level: z = s x in FP64 plus the dots)
+    //     cell written (finest level: z = s x and the dots; the mixed form
+    //     stores x itself, FP32, as z32)
     if (out) {
       const R *xm = xs[(m + 1) % 3], *x0 = xs[(m + 2) % 3], *xp = xs[m % 3];
       const bool red00 = (pr2 & 1) == 0;  // (0,0), (1,1) red; else (1,0), (0,1)
@@ -603,16 +608,21 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
       if constexpr (L0) {
         const double z00 = (double)v00 * s_out, z10 = (double)v10 * s_out;
         const double z01 = (double)v01 * s_out, z11 = (double)v11 * s_out;
-        if (flexible) rzo += H.v00 * zo00;
+        if (rd_old) rzo += H.v00 * ((double)zo00 * zs_old);
         rz += H.v00 * z00;
-        if (flexible) rzo += H.v10 * zo10;
+        if (rd_old) rzo += H.v10 * ((double)zo10 * zs_old);
         rz += H.v10 * z10;
-        if (flexible) rzo += H.v01 * zo01;
+        if (rd_old) rzo += H.v01 * ((double)zo01 * zs_old);
         rz += H.v01 * z01;
-        if (flexible) rzo += H.v11 * zo11;
+        if (rd_old) rzo += H.v11 * ((double)zo11 * zs_old);
         rz += H.v11 * z11;
-        st2(P.z + o0, z00, z10);
-        st2(P.z + o0 + nx, z01, z11);
+        if constexpr (sizeof(R) == 4) {
+          st2(P.z32 + o0, v00, v10);
+          st2(P.z32 + o0 + nx, v01, v11);
+        } else {
+          st2(P.z + o0, z00, z10);
+          st2(P.z + o0 + nx, z01, z11);
+        }
       } else {
         st2(xout + o0, v00, v10);
         st2(xout + o0 + nx, v01, v11);

@@ -312,8 +312,9 @@ __global__ __launch_bounds__(kBlock) void k_prolong_black(Tables T, TileList TL,
   }
 }
 
-// Last red half-sweep on the finest level, producing z = s * x in FP64 and
-// the partial sums r.z and (flexible PCG) r.z_old.
+// Last red half-sweep on the finest level, producing z = s * x (FP64 form: in
+// place; mixed form: x itself as z32, z = zscale z32) and the partial sums r.z
+// and (flexible PCG, except at a (re)start) r.z_old.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_half_out(Tables T, TileList TL,
                                                      int flexible) {
@@ -326,7 +327,8 @@ __global__ __launch_bounds__(kBlock) void k_half_out(Tables T, TileList TL,
   const Coef<R> C = coefs<R>(L);
   const auto f = fsrc<R, true>(L, P, sc);
   R *x = (R *)L.x;
-  const double s = sc.s;
+  const double s = sc.s, zs_old = sc.zscale;
+  const bool rd_old = flexible && !sc.restart;
   const Col col = tile_col(t);
   double rz = 0.0, rzo = 0.0;
   if (col.on) {
@@ -338,15 +340,13 @@ __global__ __launch_bounds__(kBlock) void k_half_out(Tables T, TileList TL,
       if (red) v = (f(n.c) + offsum(C, n, xv)) * recip(C.d[n.c]);
       else v = x[n.c];
       const double rv = f.r[n.c];
-      double zv;
+      const double zv = (double)v * s;
       if constexpr (sizeof(R) == 8) {
         // FP64: the finest iterate is z itself
-        zv = (double)v * s;
         if (red) x[n.c] = (R)zv;
       } else {
-        zv = (double)v * s;
-        if (flexible) rzo += rv * P.z[n.c];
-        P.z[n.c] = zv;
+        if (rd_old) rzo += rv * ((double)P.z32[n.c] * zs_old);
+        P.z32[n.c] = v;
       }
       rz += rv * zv;
     }
@@ -433,11 +433,16 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(Tables T, TileList TL, int l,
       }
       if constexpr (L0) {
         if (mode == 2) {
-          // z = s x in FP64 (the FP64 finest iterate is z itself)
+          // z = s x (FP64 form: into z; mixed form: x itself into z32)
           const double zv = (double)v * sc.s;
           const double rv = f.r[n.c];
-          if (flexible) rzo += rv * P.z[n.c];
-          P.z[n.c] = zv;
+          if constexpr (sizeof(R) == 8) {
+            if (flexible) rzo += rv * P.z[n.c];
+            P.z[n.c] = zv;
+          } else {
+            if (flexible && !sc.restart) rzo += rv * ((double)P.z32[n.c] * sc.zscale);
+            P.z32[n.c] = v;
+          }
           rz += rv * zv;
           continue;
         }
@@ -697,15 +702,20 @@ __global__ __launch_bounds__(kTailBlock) void k_vtail(Tables T, int nu_pre,
 // registers.
 // LAZY: also x += alpha_old p_old at the cell (the fused iteration defers
 // that update of the previous iteration to here, where p_old is read anyway).
-template <bool BETA, bool LAZY>
+// ZT = float (mixed form): z is the FP32 cycle output, scaled by zs on load.
+template <bool BETA, bool LAZY, typename ZT>
 __device__ __forceinline__ double spmv_column(
     const Tile &t, const Col &col, int nx, int ny, int nz, double beta,
-    const double *__restrict__ z, const double *__restrict__ po,
+    const ZT *__restrict__ z, double zs, const double *__restrict__ po,
     double *__restrict__ pn, double *__restrict__ q,
     const double *__restrict__ Tx, const double *__restrict__ Ty,
     const double *__restrict__ Tz, const double *__restrict__ Dg,
     double alpha_old, double *__restrict__ x) {
-  auto pv = [&](int g) { return BETA ? z[g] + beta * po[g] : z[g]; };
+  auto zv = [&](int g) {
+    if constexpr (sizeof(ZT) == 4) return (double)z[g] * zs;
+    else return z[g];
+  };
+  auto pv = [&](int g) { return BETA ? zv(g) + beta * po[g] : zv(g); };
   const int plane = nx * ny, i = col.i, j = col.j;
   const int dxm = (i == 0) ? nx - 1 : -1, dxp = (i == nx - 1) ? 1 - nx : 1;
   const int dym = (j == 0) ? (ny - 1) * nx : -nx;
@@ -733,7 +743,7 @@ __device__ __forceinline__ double spmv_column(
   return acc;
 }
 
-template <bool LAZY>
+template <bool LAZY, typename ZT>
 __global__ __launch_bounds__(kBlock) void k_spmv_p(Tables T, TileList TL) {
   const int tid = get_tile_index(TL);
   const Tile t = TL.base[tid];
@@ -741,23 +751,40 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(Tables T, TileList TL) {
   if (!sc.active) return;
   const LevelDev L = T.lv[t.prob];
   const ProbDev P = T.pd[t.prob];
-  const double beta = sc.beta, alpha = sc.alpha;
+  const double beta = sc.beta, alpha = sc.alpha, zs = sc.zscale;
   const double *po = sc.pbuf ? P.p1 : P.p0;
   double *pn = sc.pbuf ? P.p0 : P.p1;
+  const ZT *z;
+  if constexpr (sizeof(ZT) == 4) z = P.z32;
+  else z = P.z;
   const Col col = tile_col(t);
   double pq = 0.0;
   if (col.on) {
     if (LAZY && sc.xlag)
-      pq = spmv_column<true, true>(t, col, L.nx, L.ny, L.nz, beta, P.z, po, pn,
+      pq = spmv_column<true, true>(t, col, L.nx, L.ny, L.nz, beta, z, zs, po, pn,
                                    P.q, L.Tx, L.Ty, L.Tz, L.diag, alpha, P.x);
     else if (beta != 0.0)
-      pq = spmv_column<true, false>(t, col, L.nx, L.ny, L.nz, beta, P.z, po, pn,
+      pq = spmv_column<true, false>(t, col, L.nx, L.ny, L.nz, beta, z, zs, po, pn,
                                     P.q, L.Tx, L.Ty, L.Tz, L.diag, 0.0, P.x);
     else
-      pq = spmv_column<false, false>(t, col, L.nx, L.ny, L.nz, beta, P.z, po, pn,
+      pq = spmv_column<false, false>(t, col, L.nx, L.ny, L.nz, beta, z, zs, po, pn,
                                      P.q, L.Tx, L.Ty, L.Tz, L.diag, 0.0, P.x);
   }
   write_partials(T, tid, pq, 0.0);
+}
+
+// out = s z32 right after a mixed-form cycle (s: the scale it ran at)
+__global__ __launch_bounds__(kBlock) void k_z_out(Tables T, TileList TL,
+                                                  double *__restrict__ out) {
+  const Tile t = get_tile(TL);
+  const LevelDev L = T.lv[t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const double zs = T.sc[t.prob].s;
+  const Col col = tile_col(t);
+  if (!col.on) return;
+  const int plane = L.nx * L.ny;
+  int c = t.z0 * plane + col.j * L.nx + col.i;
+  for (int k = 0; k < t.tz; ++k, c += plane) out[c] = (double)P.z32[c] * zs;
 }
 
 // x += alpha p (the newest direction) for problems that stopped iterating
@@ -1034,6 +1061,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
       set_scale(sc, P.n, mixed);
       break;
     case FIN_RZ: {
+      sc.zscale = sc.s;  // the scale z was just formed with
       sc.rho = a0;
       sc.rzo = a1;
       if (!finite(a0) || !finite(a1)) { fail(sc, ST_ENONFINITE); break; }
@@ -1284,10 +1312,15 @@ void launch_vtail(const Tables &T, int prec, int nu_pre, int nu_post,
 }
 
 
-void launch_spmv_p(const Tables &T, TileList L0, int lazy, hipStream_t s) {
+void launch_spmv_p(const Tables &T, TileList L0, int lazy, int prec, hipStream_t s) {
   if (!L0.nblocks) return;
-  if (lazy) LAUNCH(K_SPMV_PX, k_spmv_p<true>, L0.nblocks, kBlock, s, T, L0);
-  else LAUNCH(K_SPMV_P, k_spmv_p<false>, L0.nblocks, kBlock, s, T, L0);
+  if (lazy) LAUNCH(K_SPMV_PX, (k_spmv_p<true, float>), L0.nblocks, kBlock, s, T, L0);
+  else if (prec) LAUNCH(K_SPMV_P, (k_spmv_p<false, float>), L0.nblocks, kBlock, s, T, L0);
+  else LAUNCH(K_SPMV_P, (k_spmv_p<false, double>), L0.nblocks, kBlock, s, T, L0);
+}
+
+void launch_z_out(const Tables &T, TileList L0, double *out, hipStream_t s) {
+  if (L0.nblocks) LAUNCH(K_APPLY, k_z_out, L0.nblocks, kBlock, s, T, L0, out);
 }
 
 void launch_xfix(const Tables &T, TileList L0, hipStream_t s) {
