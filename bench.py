@@ -32,13 +32,13 @@ BYTES_PER_CELL = {
     # assembly with a warm start: E, kappa, eta and the two dE history
     # buffers in; the system, b, the guess x and its residual r = b - A x out
     "assemble": (96.0, 112.0),
-    # mixed form: z is read as the FP32 cycle output (4 B instead of 8)
-    "spmv_p": (64.0, 60.0),
+    # mixed form: z and p are FP32 (z in, p_old in, p_new out: 4 B each)
+    "spmv_p": (64.0, 52.0),
     # fused iteration's SpMV: also x += alpha p_old (x read and written)
-    "spmv_px": (80.0, 76.0),
+    "spmv_px": (80.0, 68.0),
     # the deferred x += alpha p when a solve stops iterating
-    "xfix": (24.0, 24.0),
-    "update": (48.0, 48.0),
+    "xfix": (24.0, 20.0),
+    "update": (48.0, 44.0),
     "pre0_fine": (48.0, 28.0),
     "half_fine": (56.0, 32.0),
     # mixed: reads the old FP32 z (flexible PCG) and writes the new one

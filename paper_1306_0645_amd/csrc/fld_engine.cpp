@@ -180,8 +180,13 @@ void carve_problem(Carver &cv, const Hier &h, const fld_params &p, ProbMem &m) {
       P.r = cv.take<double>(n);
       if (mixed) P.z32 = cv.take<float>(n);
       else P.z = cv.take<double>(n);
-      P.p0 = cv.take<double>(n);
-      P.p1 = cv.take<double>(n);
+      if (mixed) {
+        P.pf0 = cv.take<float>(n);
+        P.pf1 = cv.take<float>(n);
+      } else {
+        P.p0 = cv.take<double>(n);
+        P.p1 = cv.take<double>(n);
+      }
       P.q = cv.take<double>(n);
       P.b = cv.take<double>(n);
       P.r2 = lazy_iteration(p) ? cv.take<double>(n) : nullptr;
@@ -633,7 +638,7 @@ void Engine::enqueue_iteration(const ListSet &ls) {
   launch_fin(T, FIN_RZ, mixed, stream, fused ? 1 : 0);
   launch_spmv_p(T, ls.fine, 0, mixed, stream);
   launch_fin(T, FIN_PQ, mixed, stream, 0);
-  launch_update(T, ls.fine, stream);
+  launch_update(T, ls.fine, mixed, stream);
   launch_fin(T, FIN_RR, mixed, stream);
 }
 
@@ -649,7 +654,7 @@ void Engine::enqueue_prologue(const ListSet &ls) {
 // x += alpha p for problems that stopped iterating with that update pending
 // (fused form); keeps the host mirror in step
 void Engine::finish_x(const ListSet &ls) {
-  launch_xfix(T, ls.fine, stream);
+  launch_xfix(T, ls.fine, mixed, stream);
   launch_fin(T, FIN_XFIX, mixed, stream);
   for (Scal &sc : h_sc)
     if (sc.xlag && sc.phase != PH_ITER) sc.xlag = 0;

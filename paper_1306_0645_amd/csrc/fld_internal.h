@@ -49,9 +49,12 @@ struct LevelDev {
 // One problem's finest-level Krylov state.
 struct ProbDev {
   int nx, ny, nz, n;
-  double *x, *r, *z, *p0, *p1, *q, *b;  // z: FP64 form only (null in mixed)
-  // mixed form: the V-cycle's FP32 output as it is, z = zscale * z32
-  float *z32;
+  double *x, *r, *q, *b;
+  double *z, *p0, *p1;   // FP64 form (null in the mixed form)
+  // mixed form: the V-cycle's FP32 output as it is, z = zscale * z32, and
+  // the search direction in FP32 at the scale of the z it was formed from,
+  // p = pscale * pf0 (or pf1)
+  float *z32, *pf0, *pf1;
   double *r2;            // second residual buffer (fused V(1,1) iteration)
   double *cs;            // coarsest-level CG scratch: 4 * n_coarsest doubles
   int levels;            // number of multigrid levels
@@ -80,6 +83,7 @@ struct Scal {
   double dEdE;           // ||dE||^2
   double s_next;         // residual scale for the next V-cycle (snew set)
   double zscale;         // mixed form: z = zscale * z32 (the s its cycle ran at)
+  double pscale;         // mixed form: newest p = pscale * pf (its z's zscale)
   int iter, max_iter, phase, status;
   int active, restart, pbuf, restarts;
   int live;              // takes part in the current assembly / update
@@ -178,13 +182,13 @@ void launch_jacobi(const Tables &T, TileList L, int l, int prec, int mode,
 void launch_prolong_add(const Tables &T, TileList L, int l, int prec,
                         int trilinear, int to_x2, hipStream_t s);
 // lazy = 1 (fused iteration): also x += alpha p_old, the update deferred
-// from the previous iteration; prec = 1: z is read from z32 (mixed form)
+// from the previous iteration; prec = 1: mixed form (FP32 z and p)
 void launch_spmv_p(const Tables &T, TileList L0, int lazy, int prec, hipStream_t s);
 // out = s * z32 right after a mixed-form V-cycle (the preconditioner alone)
 void launch_z_out(const Tables &T, TileList L0, double *out, hipStream_t s);
 // x += alpha p for problems that stopped iterating with the update pending
-void launch_xfix(const Tables &T, TileList L0, hipStream_t s);
-void launch_update(const Tables &T, TileList L0, hipStream_t s);
+void launch_xfix(const Tables &T, TileList L0, int prec, hipStream_t s);
+void launch_update(const Tables &T, TileList L0, int prec, hipStream_t s);
 void launch_true_resid(const Tables &T, TileList L0, hipStream_t s);
 void launch_warm_revert(const Tables &T, TileList L0, hipStream_t s);
 void launch_apply(const Tables &T, TileList L0, const double *u, double *out,

@@ -23,6 +23,7 @@
 
 #include <math.h>
 
+#include <type_traits>
 #include <vector>
 
 namespace fld {
@@ -702,73 +703,95 @@ __global__ __launch_bounds__(kTailBlock) void k_vtail(Tables T, int nu_pre,
 // registers.
 // LAZY: also x += alpha_old p_old at the cell (the fused iteration defers
 // that update of the previous iteration to here, where p_old is read anyway).
-// ZT = float (mixed form): z is the FP32 cycle output, scaled by zs on load.
-template <bool BETA, bool LAZY, typename ZT>
+// MX (mixed form): z, p_old and p_new are FP32 at a scale each (zs for z and
+// p_new, ps for p_old); p_new is rounded to FP32 before it is used, so q, the
+// dot and the later x update all see the direction that is stored.
+template <bool MX>
+using DirT = std::conditional_t<MX, float, double>;
+
+template <bool BETA, bool LAZY, bool MX>
 __device__ __forceinline__ double spmv_column(
     const Tile &t, const Col &col, int nx, int ny, int nz, double beta,
-    const ZT *__restrict__ z, double zs, const double *__restrict__ po,
-    double *__restrict__ pn, double *__restrict__ q,
+    const DirT<MX> *__restrict__ z, double zs, const DirT<MX> *__restrict__ po,
+    double ps, DirT<MX> *__restrict__ pn, double *__restrict__ q,
     const double *__restrict__ Tx, const double *__restrict__ Ty,
     const double *__restrict__ Tz, const double *__restrict__ Dg,
     double alpha_old, double *__restrict__ x) {
-  auto zv = [&](int g) {
-    if constexpr (sizeof(ZT) == 4) return (double)z[g] * zs;
-    else return z[g];
+  using D = DirT<MX>;
+  const double cb = MX ? beta * ps / zs : beta;  // p_old's share, in z's scale
+  auto raw = [&](int g) -> D {  // p_new as stored
+    if constexpr (MX) return BETA ? (float)((double)z[g] + cb * (double)po[g]) : z[g];
+    else return BETA ? z[g] + beta * po[g] : z[g];
   };
-  auto pv = [&](int g) { return BETA ? zv(g) + beta * po[g] : zv(g); };
+  auto val = [&](D v) -> double {  // its value
+    if constexpr (MX) return zs * (double)v;
+    else return v;
+  };
   const int plane = nx * ny, i = col.i, j = col.j;
   const int dxm = (i == 0) ? nx - 1 : -1, dxp = (i == nx - 1) ? 1 - nx : 1;
   const int dym = (j == 0) ? (ny - 1) * nx : -nx;
   const int dyp = (j == ny - 1) ? -(ny - 1) * nx : nx;
   int c = t.z0 * plane + j * nx + i;
   const int cm0 = (t.z0 == 0) ? c + (nz - 1) * plane : c - plane;
-  double p_m = pv(cm0), p_c = pv(c), tz_m = Tz[cm0];
+  D r_m = raw(cm0), r_c = raw(c);
+  double tz_m = Tz[cm0];
   double acc = 0.0;
   for (int k = t.z0; k < t.z0 + t.tz; ++k) {
     const int cp = (k == nz - 1) ? c - (nz - 1) * plane : c + plane;
-    const double p_p = pv(cp);
-    const double s = Tx[c] * pv(c + dxp) + Tx[c + dxm] * pv(c + dxm) +
-                     Ty[c] * pv(c + dyp) + Ty[c + dym] * pv(c + dym) +
-                     Tz[c] * p_p + tz_m * p_m;
+    const D r_p = raw(cp);
+    const double s = Tx[c] * val(raw(c + dxp)) + Tx[c + dxm] * val(raw(c + dxm)) +
+                     Ty[c] * val(raw(c + dyp)) + Ty[c + dym] * val(raw(c + dym)) +
+                     Tz[c] * val(r_p) + tz_m * val(r_m);
+    const double p_c = val(r_c);
     const double qq = Dg[c] * p_c - s;
-    if constexpr (LAZY) x[c] = x[c] + alpha_old * po[c];
-    pn[c] = p_c;
+    if constexpr (LAZY) {
+      if constexpr (MX) x[c] = x[c] + alpha_old * (ps * (double)po[c]);
+      else x[c] = x[c] + alpha_old * po[c];
+    }
+    pn[c] = r_c;
     q[c] = qq;
     acc += p_c * qq;
     tz_m = Tz[c];
-    p_m = p_c;
-    p_c = p_p;
+    r_m = r_c;
+    r_c = r_p;
     c = cp;
   }
   return acc;
 }
 
-template <bool LAZY, typename ZT>
+template <bool LAZY, bool MX>
 __global__ __launch_bounds__(kBlock) void k_spmv_p(Tables T, TileList TL) {
+  using D = DirT<MX>;
   const int tid = get_tile_index(TL);
   const Tile t = TL.base[tid];
   const Scal &sc = T.sc[t.prob];
   if (!sc.active) return;
   const LevelDev L = T.lv[t.prob];
   const ProbDev P = T.pd[t.prob];
-  const double beta = sc.beta, alpha = sc.alpha, zs = sc.zscale;
-  const double *po = sc.pbuf ? P.p1 : P.p0;
-  double *pn = sc.pbuf ? P.p0 : P.p1;
-  const ZT *z;
-  if constexpr (sizeof(ZT) == 4) z = P.z32;
-  else z = P.z;
+  const double beta = sc.beta, alpha = sc.alpha, zs = sc.zscale, ps = sc.pscale;
+  const D *z, *po;
+  D *pn;
+  if constexpr (MX) {
+    z = P.z32;
+    po = sc.pbuf ? P.pf1 : P.pf0;
+    pn = sc.pbuf ? P.pf0 : P.pf1;
+  } else {
+    z = P.z;
+    po = sc.pbuf ? P.p1 : P.p0;
+    pn = sc.pbuf ? P.p0 : P.p1;
+  }
   const Col col = tile_col(t);
   double pq = 0.0;
   if (col.on) {
     if (LAZY && sc.xlag)
-      pq = spmv_column<true, true>(t, col, L.nx, L.ny, L.nz, beta, z, zs, po, pn,
-                                   P.q, L.Tx, L.Ty, L.Tz, L.diag, alpha, P.x);
+      pq = spmv_column<true, true, MX>(t, col, L.nx, L.ny, L.nz, beta, z, zs, po, ps,
+                                       pn, P.q, L.Tx, L.Ty, L.Tz, L.diag, alpha, P.x);
     else if (beta != 0.0)
-      pq = spmv_column<true, false>(t, col, L.nx, L.ny, L.nz, beta, z, zs, po, pn,
-                                    P.q, L.Tx, L.Ty, L.Tz, L.diag, 0.0, P.x);
+      pq = spmv_column<true, false, MX>(t, col, L.nx, L.ny, L.nz, beta, z, zs, po, ps,
+                                        pn, P.q, L.Tx, L.Ty, L.Tz, L.diag, 0.0, P.x);
     else
-      pq = spmv_column<false, false>(t, col, L.nx, L.ny, L.nz, beta, z, zs, po, pn,
-                                     P.q, L.Tx, L.Ty, L.Tz, L.diag, 0.0, P.x);
+      pq = spmv_column<false, false, MX>(t, col, L.nx, L.ny, L.nz, beta, z, zs, po,
+                                         ps, pn, P.q, L.Tx, L.Ty, L.Tz, L.diag, 0.0, P.x);
   }
   write_partials(T, tid, pq, 0.0);
 }
@@ -787,8 +810,16 @@ __global__ __launch_bounds__(kBlock) void k_z_out(Tables T, TileList TL,
   for (int k = 0; k < t.tz; ++k, c += plane) out[c] = (double)P.z32[c] * zs;
 }
 
+// the newest direction p at cell c (after FIN_PQ has swapped the buffers)
+template <bool MX>
+__device__ __forceinline__ double newest_p(const ProbDev &P, const Scal &sc, int c) {
+  if constexpr (MX) return sc.pscale * (double)(sc.pbuf ? P.pf1 : P.pf0)[c];
+  else return (sc.pbuf ? P.p1 : P.p0)[c];
+}
+
 // x += alpha p (the newest direction) for problems that stopped iterating
 // while the fused iteration's x update was still pending
+template <bool MX>
 __global__ __launch_bounds__(kBlock) void k_xfix(Tables T, TileList TL) {
   const Tile t = get_tile(TL);
   const Scal &sc = T.sc[t.prob];
@@ -796,15 +827,16 @@ __global__ __launch_bounds__(kBlock) void k_xfix(Tables T, TileList TL) {
   const LevelDev L = T.lv[t.prob];
   const ProbDev P = T.pd[t.prob];
   const double alpha = sc.alpha;
-  const double *__restrict__ p = sc.pbuf ? P.p1 : P.p0;
   const Col col = tile_col(t);
   if (!col.on) return;
   const int plane = L.nx * L.ny;
   int c = t.z0 * plane + col.j * L.nx + col.i;
-  for (int k = 0; k < t.tz; ++k, c += plane) P.x[c] = P.x[c] + alpha * p[c];
+  for (int k = 0; k < t.tz; ++k, c += plane)
+    P.x[c] = P.x[c] + alpha * newest_p<MX>(P, sc, c);
 }
 
 // x += alpha p, r -= alpha q, partial ||r||^2
+template <bool MX>
 __global__ __launch_bounds__(kBlock) void k_update(Tables T, TileList TL) {
   const int tid = get_tile_index(TL);
   const Tile t = TL.base[tid];
@@ -813,7 +845,6 @@ __global__ __launch_bounds__(kBlock) void k_update(Tables T, TileList TL) {
   const LevelDev L = T.lv[t.prob];
   const ProbDev P = T.pd[t.prob];
   const double alpha = sc.alpha;
-  const double *__restrict__ p = sc.pbuf ? P.p1 : P.p0;
   const double *__restrict__ q = P.q;
   double *__restrict__ x = P.x;
   double *__restrict__ r = rcur(P, sc);
@@ -823,7 +854,7 @@ __global__ __launch_bounds__(kBlock) void k_update(Tables T, TileList TL) {
     const int plane = L.nx * L.ny;
     int c = t.z0 * plane + col.j * L.nx + col.i;
     for (int k = 0; k < t.tz; ++k, c += plane) {
-      const double pc = p[c], qc = q[c], xc = x[c], rc = r[c];
+      const double pc = newest_p<MX>(P, sc, c), qc = q[c], xc = x[c], rc = r[c];
       x[c] = xc + alpha * pc;
       const double rn = rc - alpha * qc;
       r[c] = rn;
@@ -1074,6 +1105,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
       break;
     }
     case FIN_PQ:
+      sc.pscale = sc.zscale;  // the direction just formed has z's scale
       sc.pq = a0;
       if (!finite(a0)) { fail(sc, ST_ENONFINITE); break; }
       if (!(a0 > 0.0)) { fail(sc, ST_ENOCONV); break; }
@@ -1314,21 +1346,25 @@ void launch_vtail(const Tables &T, int prec, int nu_pre, int nu_post,
 
 void launch_spmv_p(const Tables &T, TileList L0, int lazy, int prec, hipStream_t s) {
   if (!L0.nblocks) return;
-  if (lazy) LAUNCH(K_SPMV_PX, (k_spmv_p<true, float>), L0.nblocks, kBlock, s, T, L0);
-  else if (prec) LAUNCH(K_SPMV_P, (k_spmv_p<false, float>), L0.nblocks, kBlock, s, T, L0);
-  else LAUNCH(K_SPMV_P, (k_spmv_p<false, double>), L0.nblocks, kBlock, s, T, L0);
+  if (lazy) LAUNCH(K_SPMV_PX, (k_spmv_p<true, true>), L0.nblocks, kBlock, s, T, L0);
+  else if (prec) LAUNCH(K_SPMV_P, (k_spmv_p<false, true>), L0.nblocks, kBlock, s, T, L0);
+  else LAUNCH(K_SPMV_P, (k_spmv_p<false, false>), L0.nblocks, kBlock, s, T, L0);
 }
 
 void launch_z_out(const Tables &T, TileList L0, double *out, hipStream_t s) {
   if (L0.nblocks) LAUNCH(K_APPLY, k_z_out, L0.nblocks, kBlock, s, T, L0, out);
 }
 
-void launch_xfix(const Tables &T, TileList L0, hipStream_t s) {
-  if (L0.nblocks) LAUNCH(K_XFIX, k_xfix, L0.nblocks, kBlock, s, T, L0);
+void launch_xfix(const Tables &T, TileList L0, int prec, hipStream_t s) {
+  if (!L0.nblocks) return;
+  if (prec) LAUNCH(K_XFIX, k_xfix<true>, L0.nblocks, kBlock, s, T, L0);
+  else LAUNCH(K_XFIX, k_xfix<false>, L0.nblocks, kBlock, s, T, L0);
 }
 
-void launch_update(const Tables &T, TileList L0, hipStream_t s) {
-  if (L0.nblocks) LAUNCH(K_UPDATE, k_update, L0.nblocks, kBlock, s, T, L0);
+void launch_update(const Tables &T, TileList L0, int prec, hipStream_t s) {
+  if (!L0.nblocks) return;
+  if (prec) LAUNCH(K_UPDATE, k_update<true>, L0.nblocks, kBlock, s, T, L0);
+  else LAUNCH(K_UPDATE, k_update<false>, L0.nblocks, kBlock, s, T, L0);
 }
 
 void launch_true_resid(const Tables &T, TileList L0, hipStream_t s) {
