@@ -38,6 +38,9 @@ BYTES_PER_CELL = {
     "spmv_px": (80.0, 68.0),
     # the deferred x += alpha p when a solve stops iterating
     "xfix": (24.0, 20.0),
+    # Galerkin warm guess: x0 and r = b - A x0 from the operator, b and the
+    # two dE (72 B), less the x and r the assembly then leaves to it (16 B)
+    "warm_x": (56.0, 56.0),
     "update": (48.0, 44.0),
     "pre0_fine": (48.0, 28.0),
     "half_fine": (56.0, 32.0),
@@ -79,7 +82,7 @@ def coarse_fraction(levels):
     return sum(8.0 ** -l for l in range(1, levels))
 
 
-STEP_KERNELS = ("assemble", "true_resid", "update_E", "xfix")
+STEP_KERNELS = ("assemble", "true_resid", "update_E", "xfix", "warm_x")
 # the old FP32 z that the mixed form's finest up pass reads for flexible PCG
 OLD_Z_BYTES = 4.0
 
@@ -109,6 +112,8 @@ def step_bytes(counts, cells, prec_idx, levels):
 
 
 def model_step_bytes(cells, iters, nu, prec_idx, levels, steps=1, warm=False):
+    # warm: 0/False cold, 1 extrapolated guess, 2 or True Galerkin guess (the
+    # library default)
     """Algorithmic bytes of `steps` steps of one problem taking `iters` PCG
     iterations in all, from the cycle structure:
     assembly and coarse operators, the true-residual check and E += dE once,
@@ -135,8 +140,11 @@ def model_step_bytes(cells, iters, nu, prec_idx, levels, steps=1, warm=False):
         fixed += B["xfix"]
     if prec_idx == 1:
         fixed -= OLD_Z_BYTES  # no old z in the first cycle of the solve
+    warm = 2 if warm is True else int(warm)
     if not warm:  # a cold assembly reads no history
         fixed -= 16.0
+    elif warm == 2:
+        fixed += B["warm_x"]
     return cells * (steps * fixed + iters * per_iter)
 
 
@@ -210,8 +218,9 @@ def parse():
     ap.add_argument("--tile-z", type=int, default=0)
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--fused-tile-z", type=int, default=0)
-    ap.add_argument("--warm-start", type=int, default=1,
-                    help="start each step's PCG from the previous dE")
+    ap.add_argument("--warm-start", type=int, default=2,
+                    help="start each step's PCG from the previous dEs: 1 "
+                         "extrapolated, 2 Galerkin projection (default), 0 off")
     ap.add_argument("--check-every", type=int, default=0,
                     help="PCG iterations between host convergence reads "
                          "(0: automatic)")
@@ -467,6 +476,7 @@ def main():
                    "sources": 64, "sigma_ln": 1.5, "rtol": 1e-8,
                    "precision": "mixed" if "mixed" in forms else "fp64",
                    "smoother": ("red/black Gauss-Seidel", "weighted Jacobi")[args.smoother],
+                   "warm_start": ("off", "extrapolated", "galerkin")[args.warm_start],
                    "steps_per_run": args.steps},
         "roofline": roof,
         "step_roofline": {

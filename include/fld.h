@@ -128,11 +128,17 @@ typedef struct fld_params {
                           cycle_switch (default).  The FP64 cycle is always
                           piecewise constant with restriction = its
                           transpose, so it stays a symmetric preconditioner */
-  int32_t warm_start;  /* fld_step / fld_batch_step: 1 (default) = start each
-                          step's PCG from the handle's previous successful dE
-                          scaled by the ratio of the step sizes (the residual
-                          b - A dE0 is formed first, the stopping rule is
-                          unchanged); 0 = start from dE = 0 */
+  int32_t warm_start;  /* fld_step / fld_batch_step (and each request of a
+                          server): start each step's PCG from the handle's
+                          previous successful dEs.  2 (default) = the
+                          combination c1 dE(n) + c2 dE(n-1) that is closest
+                          to the new solution in the new operator's A-norm
+                          (Galerkin: (dE(i), A dE(j)) c_j = (dE(i), b)); 1 =
+                          their extrapolation by the ratios of the step
+                          sizes; 0 = start from dE = 0.  The residual
+                          b - A dE0 is formed first, the guess is dropped if
+                          it does not reduce ||b - A dE0|| below ||b||, and
+                          the stopping rule is unchanged */
   int32_t tail_cells;  /* the coarsest level is solved (Jacobi-CG in FP64) by
                           one workgroup per problem; coarse levels of at most
                           this many cells above it join that kernel (same
@@ -175,7 +181,7 @@ typedef struct fld_server fld_server;
  * max_iter = 50, nu_pre = nu_post = 1, theta = 1, tau_tol = 1e-4, FP64,
  * coarse_scale = 0.5, max_dt_cuts = 8, graph replay on, cycle_switch = 12,
  * prolongation = 2 (trilinear in the mixed cycle once it has switched to
- * V(2,2)), warm_start = 1, tail_cells = 512, smoother = FLD_SMOOTH_RBGS,
+ * V(2,2)), warm_start = 2, tail_cells = 512, smoother = FLD_SMOOTH_RBGS,
  * fused_levels = 0. */
 void fld_default_params(fld_params *p, double c, double L_unit);
 

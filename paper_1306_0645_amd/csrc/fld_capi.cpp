@@ -77,7 +77,7 @@ void fld_default_params(fld_params *p, double c, double L_unit) {
   p->fused_tile_z = 0;
   p->cycle_switch = 12;
   p->prolongation = 2;
-  p->warm_start = 1;
+  p->warm_start = 2;
   p->tail_cells = 512;
   p->smoother = FLD_SMOOTH_RBGS;
 }

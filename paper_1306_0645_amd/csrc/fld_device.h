@@ -109,6 +109,27 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return s;
 }
 
+// N sums of a tile into out[N * tile + i] (one LDS round for all of them)
+template <int N>
+__device__ __forceinline__ void write_sums(double *out, int tile, const double (&v)[N]) {
+  constexpr int NW = kBlock / 64;
+  __shared__ double sh[N][NW];
+  double w[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) w[i] = wave_sum(v[i]);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) sh[i][threadIdx.x >> 6] = w[i];
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) s += sh[threadIdx.x][k];
+    out[N * tile + threadIdx.x] = s;
+  }
+}
+
 __device__ __forceinline__ void write_partials(const Tables &T, int tile,
                                                double a0, double a1) {
   __shared__ double sh[kBlock / 64];

@@ -41,7 +41,7 @@ bool params_ok(const fld_params &p) {
     return false;
   if (p.fused_tile_z < 0 || p.fused_tile_z > 256 || (p.fused_tile_z & 1)) return false;
   if (p.cycle_switch < 0) return false;
-  if (p.warm_start < 0 || p.warm_start > 1) return false;
+  if (p.warm_start < 0 || p.warm_start > 2) return false;
   if (p.tail_cells < 0) return false;
   if (p.prolongation < 0 || p.prolongation > 2) return false;
   if (p.smoother != FLD_SMOOTH_RBGS && p.smoother != FLD_SMOOTH_JACOBI) return false;
@@ -236,6 +236,7 @@ static size_t tables_layout(Carver &cv, const std::vector<Hier> &hs,
   StepDev *sd = cv.take<StepDev>(np);
   Scal *sc = cv.take<Scal>(np);
   double *part = cv.take<double>(2 * std::max<size_t>(nfine, 1));
+  double *gpart = cv.take<double>(kAsmSums * std::max<size_t>(nfine, 1));
   Tile *tiles = cv.take<Tile>(std::max<size_t>(ntiles, 1));
   int *ranges = cv.take<int>(nranges);
   if (e) {
@@ -244,6 +245,7 @@ static size_t tables_layout(Carver &cv, const std::vector<Hier> &hs,
     e->T.sd = sd;
     e->T.sc = sc;
     e->T.part = part;
+    e->T.gpart = gpart;
     e->T.nprob = np;
     e->d_tiles = tiles;
     e->d_ranges = ranges;
@@ -756,7 +758,7 @@ bool Engine::set_warm(int p, double h) {
   warm_now[p] = 1;
   const double h1 = prev_h[p], r1 = h / h1;
   StepDev &S = h_sd[p];
-  S.warm = 1.0;
+  S.warm = prm.warm_start;
   S.w1 = r1;
   S.w2 = 0.0;
   const bool two = prev_ok[p] >= 2 && prev_h2[p] > 0.0 && xold[p] >= 0;
@@ -775,6 +777,17 @@ bool Engine::set_warm(int p, double h) {
   xold[p] = a;
   xcur[p] = nxt;
   return true;
+}
+
+// After the assembly of warm-started problems: the Galerkin guess and its
+// residual (its coefficients come from FIN_BB), then x = 0, r = b wherever
+// the guess was not kept (or b = 0).
+void Engine::enqueue_warm(const ListSet &ls) {
+  if (prm.warm_start > 1) {
+    launch_warm_x(T, ls.fine, stream);
+    launch_fin(T, FIN_WARM, mixed, stream);
+  }
+  launch_warm_revert(T, ls.fine, stream);
 }
 
 // dE of a successful substep of length h seeds the next one; after a warm
@@ -824,7 +837,7 @@ int Engine::run_steps(std::vector<Job> &jobs) {
     // keeps the guess only if it reduces the residual)
     enqueue_assemble(all);
     if (warm) {
-      launch_warm_revert(T, all.fine, stream);
+      enqueue_warm(all);
       warm = false;
     }
     for (int p = 0; p < np; ++p) {

@@ -163,6 +163,7 @@ class Engine {
   int adapt_cycle(int max_iters);
 
   void enqueue_assemble(const ListSet &ls);
+  void enqueue_warm(const ListSet &ls);
   void enqueue_vcycle(const ListSet &ls);
   void enqueue_fused_rest(const ListSet &ls);
   void enqueue_iteration(const ListSet &ls);

@@ -69,7 +69,10 @@ struct StepDev {
   double *Eout;          // destination of E + dE (may equal E)
   double dt, adot_a;     // dt and adot/a
   double idx, idy, idz;  // 1 / (a dx), 1 / (a dy), 1 / (a dz)
-  double warm;           // 1: warm start x0 = w1 dE(n) + w2 dE(n-1); 0: x0 = 0
+  // warm start: 0: x0 = 0; 1: x0 = w1 dE(n) + w2 dE(n-1) (extrapolation);
+  // 2: x0 = c1 dE(n) + c2 dE(n-1) with c from the Galerkin condition in the
+  // new operator, (dE(i), A dE(j)) c_j = (dE(i), b)
+  double warm;
   double w1, w2;
   const double *h1, *h2; // dE(n), dE(n-1) (h2 null when w2 = 0); never P.x
 };
@@ -84,6 +87,7 @@ struct Scal {
   double s_next;         // residual scale for the next V-cycle (snew set)
   double zscale;         // mixed form: z = zscale * z32 (the s its cycle ran at)
   double pscale;         // mixed form: newest p = pscale * pf (its z's zscale)
+  double c1, c2;         // Galerkin warm guess x0 = c1 dE(n) + c2 dE(n-1)
   int iter, max_iter, phase, status;
   int active, restart, pbuf, restarts;
   int live;              // takes part in the current assembly / update
@@ -108,12 +112,18 @@ struct Tile {
 };
 
 // Launch context: the tables live in device memory.
+// per-tile sums of the assembly: ||b||^2, ||b - A x0||^2 (extrapolated
+// guess), and for the Galerkin guess (h_i, A h_j) and (h_i, b), h = dE(n),
+// dE(n-1)
+enum : int { AS_BB, AS_RR, AS_G11, AS_G12, AS_G22, AS_B1, AS_B2, kAsmSums };
+
 struct Tables {
   LevelDev *lv;     // [kMaxLevels][nprob]
   ProbDev *pd;      // [nprob]
   StepDev *sd;      // [nprob]
   Scal *sc;         // [nprob]
   double *part;     // [n finest tiles][2] block partial sums
+  double *gpart;    // [n finest tiles][kAsmSums] sums of the assembly
   int nprob;
 };
 
@@ -134,7 +144,8 @@ enum : int {
   K_COARSE_SOLVE, K_SPMV_P, K_UPDATE, K_TRUE_RESID, K_APPLY, K_SET_R,
   K_UPDATE_E, K_VDOWN_F, K_VDOWN_C, K_VUP_F, K_VUP_C, K_CHEM_H, K_ION_SUM,
   K_WARM_REVERT, K_JACOBI0_F, K_JACOBI_F, K_JACOBI_OUT,
-  K_JACOBI_C, K_PROLONG_ADD_F, K_PROLONG_ADD_C, K_SPMV_PX, K_XFIX, K_NUM
+  K_JACOBI_C, K_PROLONG_ADD_F, K_PROLONG_ADD_C, K_SPMV_PX, K_XFIX, K_WARM_X,
+  K_NUM
 };
 
 // Brackets one launch with hipEvents when its kernel id is selected.
@@ -191,6 +202,8 @@ void launch_xfix(const Tables &T, TileList L0, int prec, hipStream_t s);
 void launch_update(const Tables &T, TileList L0, int prec, hipStream_t s);
 void launch_true_resid(const Tables &T, TileList L0, hipStream_t s);
 void launch_warm_revert(const Tables &T, TileList L0, hipStream_t s);
+// x0 = c1 dE(n) + c2 dE(n-1), r = b - A x0 (Galerkin warm guesses)
+void launch_warm_x(const Tables &T, TileList L0, hipStream_t s);
 void launch_apply(const Tables &T, TileList L0, const double *u, double *out,
                   hipStream_t s);
 void launch_set_r(const Tables &T, TileList L0, const double *r, int prec,
@@ -221,7 +234,9 @@ enum : int {
   FIN_RR2 = 8,    // fused iteration, after the down pass formed r - alpha q:
                   // ||r||^2, convergence, switch the residual buffer
   FIN_XFIX = 9,   // after k_xfix: the deferred x update is done
-  FIN_FRESH = 10  // after the prologue's down pass: the problems iterate on
+  FIN_FRESH = 10, // after the prologue's down pass: the problems iterate on
+  FIN_WARM = 11   // after k_warm_x: keep the projected guess if it reduces
+                  // the residual
 };
 
 }  // namespace fld

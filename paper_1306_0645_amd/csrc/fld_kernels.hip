@@ -75,15 +75,18 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
   double *__restrict__ bv = P.b;
   double *__restrict__ rv = rcur(P, sc);
   double *__restrict__ xv = P.x;
-  // warm start: x0 = w1 dE(n) + w2 dE(n-1) from two history buffers that
-  // nothing writes here, so the guess at a neighbour is formed on the fly
-  // and r = b - A x0 comes out of this pass (the thread holds all 6 faces)
-  const bool warm = S.warm > 0.0;
+  // warm start from two history buffers that nothing writes here, so their
+  // values at a neighbour are read on the fly (the thread holds all 6 faces):
+  // extrapolated guess x0 = w1 dE(n) + w2 dE(n-1): r = b - A x0 comes out of
+  // this pass; Galerkin guess: this pass sums (h_i, A h_j) and (h_i, b) for
+  // the new operator, and k_warm_x forms x0 and r once c is known
+  const bool warm = S.warm > 0.0, gal = S.warm > 1.0;
   const double w1 = S.w1, w2 = S.w2;
   const double *__restrict__ h1 = S.h1;
   const double *__restrict__ h2 = S.h2;
   auto guess = [&](int g) { return h2 ? w1 * h1[g] + w2 * h2[g] : w1 * h1[g]; };
-  double bb = 0.0, rr = 0.0;
+  double bb = 0.0, rr = 0.0, g11 = 0.0, g12 = 0.0, g22 = 0.0, gb1 = 0.0,
+         gb2 = 0.0;
   if (col.on) {
     const int nx = L.nx, ny = L.ny, nz = L.nz, plane = nx * ny;
     const int i = col.i, j = col.j;
@@ -95,8 +98,16 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
     double Em = E[cm], Km = K[cm];
     double Ec = E[cc], Kc = K[cc];
     double Dzm = face_D(Em, Ec, Km, Kc, S.idz, c, dmax, rmin);
-    double gm = 0.0, gc = 0.0;  // guess at planes k - 1, k
-    if (warm) {
+    double gm = 0.0, gc = 0.0;  // guess (Galerkin: dE(n)) at planes k - 1, k
+    double um = 0.0, uc = 0.0;  // Galerkin: dE(n-1) at planes k - 1, k
+    if (gal) {
+      gm = h1[cm];
+      gc = h1[cc];
+      if (h2) {
+        um = h2[cm];
+        uc = h2[cc];
+      }
+    } else if (warm) {
       gm = guess(cm);
       gc = guess(cc);
     }
@@ -131,7 +142,30 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
       }
       bv[cc] = b;
       bb += b * b;
-      if (warm) {
+      if (gal) {
+        // A h at the cell for h = dE(n) and dE(n-1); x and r are k_warm_x's
+        const double txm = tdt * Dxm * ix2, tym = tdt * Dym * iy2,
+                     tzm = tdt * Dzm * iz2;
+        const double gp = h1[cp];
+        const double a1 = diag * gc - (tx * h1[cc + dxp] + txm * h1[cc + dxm] +
+                                       ty * h1[cc + dyp] + tym * h1[cc + dym] +
+                                       tz * gp + tzm * gm);
+        g11 += gc * a1;
+        gb1 += gc * b;
+        gm = gc;
+        gc = gp;
+        if (h2) {
+          const double up = h2[cp];
+          const double a2 = diag * uc - (tx * h2[cc + dxp] + txm * h2[cc + dxm] +
+                                         ty * h2[cc + dyp] + tym * h2[cc + dym] +
+                                         tz * up + tzm * um);
+          g12 += uc * a1;  // (dE(n-1), A dE(n)): A is symmetric
+          g22 += uc * a2;
+          gb2 += uc * b;
+          um = uc;
+          uc = up;
+        }
+      } else if (warm) {
         const double gp = guess(cp);
         const double txm = tdt * Dxm * ix2, tym = tdt * Dym * iy2,
                      tzm = tdt * Dzm * iz2;
@@ -156,7 +190,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
       cc = cp;
     }
   }
-  write_partials(T, tid, bb, rr);
+  const double sums[kAsmSums] = {bb, rr, g11, g12, g22, gb1, gb2};
+  write_sums(T.gpart, tid, sums);
 }
 
 // Coarse operator of level lc from level lc-1 (one thread per coarse cell):
@@ -892,6 +927,55 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Tables T, TileList TL) {
 
 // Warm-started problems whose guess FIN_BB rejected (it did not reduce the
 // residual): x = 0, r = b.  And b = 0: the solution is 0 whatever the guess.
+// Galerkin warm guess, once FIN_BB has solved for c: x0 = c1 dE(n) + c2
+// dE(n-1), formed at the cell and its neighbours on the fly, and r = b - A x0
+// with the assembled FP64 operator; partial ||r||^2 for FIN_WARM.
+__global__ __launch_bounds__(kBlock) void k_warm_x(Tables T, TileList TL) {
+  const int tid = get_tile_index(TL);
+  const Tile t = TL.base[tid];
+  const Scal &sc = T.sc[t.prob];
+  const StepDev S = T.sd[t.prob];
+  if (!sc.live || !(S.warm > 1.0) || sc.phase != PH_ITER || sc.cold) return;
+  const LevelDev L = T.lv[t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const double c1 = sc.c1, c2 = sc.c2;
+  const double *__restrict__ h1 = S.h1;
+  const double *__restrict__ h2 = S.h2;
+  auto g = [&](int q) { return h2 ? c1 * h1[q] + c2 * h2[q] : c1 * h1[q]; };
+  const double *__restrict__ Tx = L.Tx;
+  const double *__restrict__ Ty = L.Ty;
+  const double *__restrict__ Tz = L.Tz;
+  double *__restrict__ rv = rcur(P, sc);
+  const Col col = tile_col(t);
+  double rr = 0.0;
+  if (col.on) {
+    const int nx = L.nx, ny = L.ny, nz = L.nz, plane = nx * ny;
+    const int i = col.i, j = col.j;
+    const int dxm = (i == 0) ? nx - 1 : -1, dxp = (i == nx - 1) ? 1 - nx : 1;
+    const int dym = (j == 0) ? (ny - 1) * nx : -nx;
+    const int dyp = (j == ny - 1) ? -(ny - 1) * nx : nx;
+    int c = t.z0 * plane + j * nx + i;
+    const int cm0 = (t.z0 == 0) ? c + (nz - 1) * plane : c - plane;
+    double x_m = g(cm0), x_c = g(c), tz_m = Tz[cm0];
+    for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+      const int cp = (k == nz - 1) ? c - (nz - 1) * plane : c + plane;
+      const double x_p = g(cp);
+      const double off = Tx[c] * g(c + dxp) + Tx[c + dxm] * g(c + dxm) +
+                         Ty[c] * g(c + dyp) + Ty[c + dym] * g(c + dym) +
+                         Tz[c] * x_p + tz_m * x_m;
+      const double r = P.b[c] - (L.diag[c] * x_c - off);
+      P.x[c] = x_c;
+      rv[c] = r;
+      rr += r * r;
+      tz_m = Tz[c];
+      x_m = x_c;
+      x_c = x_p;
+      c = cp;
+    }
+  }
+  write_partials(T, tid, rr, 0.0);
+}
+
 __global__ __launch_bounds__(kBlock) void k_warm_revert(Tables T, TileList TL) {
   const Tile t = get_tile(TL);
   const Scal &sc = T.sc[t.prob];
@@ -1020,6 +1104,87 @@ __device__ __forceinline__ void fail(Scal &sc, int status) {
   sc.active = 0;
 }
 
+// FIN_BB: the assembly's sums (in tile order), the start of the solve and,
+// for a warm start, the guess: the extrapolated one is kept if it reduces
+// the residual; the Galerkin one gets its coefficients here (k_warm_x then
+// forms it and FIN_WARM applies the same test)
+__global__ __launch_bounds__(kFinBlock) void k_fin_bb(Tables T, int mixed) {
+  const int p = blockIdx.x;
+  Scal &sc = T.sc[p];
+  if (!sc.live) return;
+  const ProbDev &P = T.pd[p];
+  double a[kAsmSums];
+#pragma unroll
+  for (int i = 0; i < kAsmSums; ++i) a[i] = 0.0;
+  for (int t = P.t0 + (int)threadIdx.x; t < P.t1; t += kFinBlock) {
+#pragma unroll
+    for (int i = 0; i < kAsmSums; ++i) a[i] += T.gpart[kAsmSums * t + i];
+  }
+  constexpr int NW = kFinBlock / 64;
+  __shared__ double sh[kAsmSums][NW];
+#pragma unroll
+  for (int i = 0; i < kAsmSums; ++i) {
+    const double w = wave_sum(a[i]);
+    if ((threadIdx.x & 63) == 0) sh[i][threadIdx.x >> 6] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < kAsmSums; ++i) {
+    double v = 0.0;
+    for (int k = 0; k < NW; ++k) v += sh[i][k];
+    a[i] = v;
+  }
+  const double bb = a[AS_BB];
+  sc.bb = bb;
+  sc.rr = bb;
+  sc.rr_true = bb;
+  sc.iter = 0;
+  sc.restart = 1;
+  sc.restarts = 0;
+  sc.pbuf = 0;
+  sc.has_dir = sc.xlag = sc.snew = 0;
+  sc.fresh = 1;
+  sc.committed = 0;
+  sc.status = ST_OK;
+  sc.phase = PH_ITER;
+  sc.active = 1;
+  sc.cold = 0;
+  const double warm = T.sd[p].warm;
+  if (!finite(bb)) {
+    fail(sc, ST_ENONFINITE);
+  } else if (bb == 0.0) {
+    sc.phase = PH_DONE;
+    sc.active = 0;
+  } else if (warm > 1.0) {
+    // (h_i, A h_j) c = (h_i, b): the A-norm-closest point of span{h} to the
+    // solution; one vector when the pair is (nearly) dependent or absent
+    const double g11 = a[AS_G11], g12 = a[AS_G12], g22 = a[AS_G22];
+    const double b1 = a[AS_B1], b2 = a[AS_B2];
+    const double det = g11 * g22 - g12 * g12;
+    double c1 = 0.0, c2 = 0.0;
+    bool ok = g11 > 0.0 && finite(g11) && finite(b1);
+    if (ok && T.sd[p].h2 && g22 > 0.0 && det > 1e-10 * g11 * g22 &&
+        finite(g12) && finite(g22) && finite(b2)) {
+      c1 = (b1 * g22 - b2 * g12) / det;
+      c2 = (b2 * g11 - b1 * g12) / det;
+    } else if (ok) {
+      c1 = b1 / g11;
+    }
+    ok = ok && finite(c1) && finite(c2);
+    sc.c1 = c1;
+    sc.c2 = c2;
+    sc.cold = !ok;
+  } else if (warm > 0.0) {
+    // PCG from the warm guess (same ||b||), or from 0 (k_warm_revert)
+    // if the guess does not reduce the residual
+    const double rr = a[AS_RR];
+    sc.cold = !(rr < bb);
+    if (!sc.cold) sc.rr = rr;
+    if (!finite(rr)) fail(sc, ST_ENONFINITE);
+  }
+  set_scale(sc, P.n, mixed);
+}
+
 __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixed,
                                                   int alt) {
   const int p = blockIdx.x;
@@ -1037,6 +1202,9 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
     case FIN_RR2: part = sc.active && sc.has_dir; break;
     case FIN_XFIX: part = sc.xlag && sc.phase != PH_ITER; break;
     case FIN_FRESH: part = sc.active && sc.fresh; break;
+    case FIN_WARM:
+      part = sc.live && T.sd[p].warm > 1.0 && sc.phase == PH_ITER && !sc.cold;
+      break;
     default: part = sc.active != 0; break;
   }
   if (!part) return;
@@ -1065,32 +1233,6 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
   a1 = block_sum<kFinBlock / 64>(a1, sh);
   if (threadIdx.x != 0) return;
   switch (which) {
-    case FIN_BB:
-      sc.bb = a0;
-      sc.rr = a0;
-      sc.rr_true = a0;
-      sc.iter = 0;
-      sc.restart = 1;
-      sc.restarts = 0;
-      sc.pbuf = 0;
-      sc.has_dir = sc.xlag = sc.snew = 0;
-      sc.fresh = 1;
-      sc.committed = 0;
-      sc.status = ST_OK;
-      sc.phase = PH_ITER;
-      sc.active = 1;
-      sc.cold = 0;
-      if (!finite(a0)) fail(sc, ST_ENONFINITE);
-      else if (a0 == 0.0) { sc.phase = PH_DONE; sc.active = 0; }
-      else if (T.sd[p].warm > 0.0) {
-        // PCG from the warm guess (same ||b||), or from 0 (k_warm_revert)
-        // if the guess does not reduce the residual
-        sc.cold = !(a1 < a0);
-        if (!sc.cold) sc.rr = a1;
-        if (!finite(a1)) fail(sc, ST_ENONFINITE);
-      }
-      set_scale(sc, P.n, mixed);
-      break;
     case FIN_RZ: {
       sc.zscale = sc.s;  // the scale z was just formed with
       sc.rho = a0;
@@ -1149,6 +1291,16 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
       break;
     case FIN_FRESH:
       sc.fresh = 0;
+      break;
+    case FIN_WARM:
+      // keep the projected guess only if it reduces the residual (else
+      // k_warm_revert starts from 0)
+      sc.cold = !(a0 < sc.bb);
+      if (!finite(a0)) { fail(sc, ST_ENONFINITE); break; }
+      if (!sc.cold) {
+        sc.rr = a0;
+        set_scale(sc, P.n, mixed);
+      }
       break;
     case FIN_RR:
       sc.rr = a0;
@@ -1209,7 +1361,7 @@ static const char *kKernelNames[K_NUM] = {
     "vdown_coarse", "vup_fine", "vup_coarse", "chem_h", "ionized_sum",
     "warm_revert", "jacobi0_fine", "jacobi_fine", "jacobi_out",
     "jacobi_coarse", "prolong_add_fine", "prolong_add_coarse", "spmv_px",
-    "xfix"};
+    "xfix", "warm_x"};
 
 namespace prof {
 struct Rec {
@@ -1273,7 +1425,9 @@ void launch_coarsen(const Tables &T, TileList LC, int lc, double scale,
 }
 
 void launch_fin(const Tables &T, int which, int mixed, hipStream_t s, int alt) {
-  if (T.nprob) LAUNCH(K_FIN, k_fin, T.nprob, kFinBlock, s, T, which, mixed, alt);
+  if (!T.nprob) return;
+  if (which == FIN_BB) LAUNCH(K_FIN, k_fin_bb, T.nprob, kFinBlock, s, T, mixed);
+  else LAUNCH(K_FIN, k_fin, T.nprob, kFinBlock, s, T, which, mixed, alt);
 }
 
 void launch_pre0(const Tables &T, TileList L, int l, int prec, hipStream_t s) {
@@ -1369,6 +1523,10 @@ void launch_update(const Tables &T, TileList L0, int prec, hipStream_t s) {
 
 void launch_true_resid(const Tables &T, TileList L0, hipStream_t s) {
   if (L0.nblocks) LAUNCH(K_TRUE_RESID, k_true_resid, L0.nblocks, kBlock, s, T, L0);
+}
+
+void launch_warm_x(const Tables &T, TileList L0, hipStream_t s) {
+  if (L0.nblocks) LAUNCH(K_WARM_X, k_warm_x, L0.nblocks, kBlock, s, T, L0);
 }
 
 void launch_apply(const Tables &T, TileList L0, const double *u, double *out,

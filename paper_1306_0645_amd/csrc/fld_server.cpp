@@ -241,7 +241,7 @@ int fld_server::tick() {
   if (anyA) {
     TRY(e.build_lists(mA, 1, lsA));
     e.enqueue_assemble(lsA);
-    if (anyW) launch_warm_revert(e.T, lsA.fine, stream);
+    if (anyW) e.enqueue_warm(lsA);
   }
   // (2) one PCG iteration for every solving request (device flags decide)
   TRY(e.build_lists(mS, 2, lsS));

@@ -56,14 +56,16 @@ def test_batch_equals_single_and_oracle(fld, oracle_mod, prec, smoother):
         assert rel_l2(host(E), p["E"] + dEo) <= (1e-6 if prec == 0 else 1e-5)
 
 
+@pytest.mark.parametrize("warm", [1, 2])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_batch_warm_steps_equal_single(fld, oracle_mod, prec):
-    """Three successive steps (the warm start keeps a per-problem history):
-    every problem of the batch stays bit-identical to its single-problem
-    handle and within the gates of the oracle's cold steps."""
-    log_case("batch_warm", prec=prec)
+def test_batch_warm_steps_equal_single(fld, oracle_mod, prec, warm):
+    """Three successive steps (the warm start keeps a per-problem history;
+    extrapolated or Galerkin guess): every problem of the batch stays
+    bit-identical to its single-problem handle and within the gates of the
+    oracle's cold steps."""
+    log_case("batch_warm", prec=prec, warm=warm)
     ps = _probs(seed0=80)
-    prm = params(fld, ps[0], precision=prec, cycle_switch=0, warm_start=1)
+    prm = params(fld, ps[0], precision=prec, cycle_switch=0, warm_start=warm)
     B = fld.Batch([p["shape"] for p in ps], [p["h"] for p in ps], prm)
     Ks = [dev(p["kappa"]) for p in ps]
     Hs = [dev(p["eta"]) for p in ps]

@@ -395,22 +395,27 @@ def test_comoving_step_matches_oracle(fld, oracle_mod, theta, prec):
     assert err <= GATE[prec]
 
 
+@pytest.mark.parametrize("warm", [1, 2])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_warm_start_steps_match_oracle(fld, oracle_mod, prec):
-    """fld_step seeds each step's PCG with the previous step's dE (scaled by
-    the step ratio), or starts from 0 when that guess does not reduce the
-    residual.  Three successive steps (the last at half the step size) must
-    match the oracle's cold solves to the gates (the seed changes iteration
-    counts, not the stopping rule); a following step with b = 0
+def test_warm_start_steps_match_oracle(fld, oracle_mod, prec, warm):
+    """fld_step seeds each step's PCG with a guess from the previous steps'
+    dE (warm = 1: extrapolated by the step ratios; warm = 2: the Galerkin
+    combination of the last two in the new operator), or starts from 0 when
+    that guess does not reduce the residual.  Three successive steps (the
+    last at half the step size) must match the oracle's cold solves to the
+    gates (the seed changes iteration counts, not the stopping rule), never
+    taking more iterations in all than the cold start (Galerkin); a following
+    step with b = 0
     (E = eta = 0) must return exactly E = 0, not the seed."""
     import torch
-    log_case("warm_start", prec=prec)
+    log_case("warm_start", prec=prec, warm=warm)
     p = _problem((48, 40, 32), 31, dt_factor=0.2)
     kap, eta = dev(p["kappa"]), dev(p["eta"])
-    W, prm = _solver(fld, p, precision=prec, warm_start=1)
+    W, prm = _solver(fld, p, precision=prec, warm_start=warm)
     C, _ = _solver(fld, p, precision=prec, warm_start=0)
     Ew, Ec = dev(p["E"]), dev(p["E"])
     En = p["E"].copy()
+    its_w = its_c = 0
     for k, f in enumerate((1.0, 1.0, 0.5)):
         dt = f * p["dt"]
         sw = W.step(Ew, kap, eta, dt)
@@ -424,6 +429,12 @@ def test_warm_start_steps_match_oracle(fld, oracle_mod, prec):
               f"err {err:.2e}", flush=True)
         assert sw["status"] == 0 and sw["rel_resid"] <= prm.rtol
         assert err <= GATE[prec]
+        its_w += sw["iters"]
+        its_c += sc["iters"]
+    if warm == 2:
+        # the A-norm-closest combination of the history is never farther
+        # from the solution than the cold start's 0
+        assert its_w <= its_c
     zero, no_eta = torch.zeros_like(Ew), torch.zeros_like(Ew)
     st = W.step(zero, kap, no_eta, p["dt"])
     assert st["status"] == 0
