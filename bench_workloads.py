@@ -126,7 +126,8 @@ def reionization(args, fld, torch, synth, log):
     prm = fld.fld_default_params(p["c"], p["L_unit"], precision=fld.FLD_PREC_MIXED,
                                  mg_levels=6, use_graph=args.graph,
                                  cycle_switch=args.cycle_switch,
-                                 prolongation=args.prolongation)
+                                 prolongation=args.prolongation,
+                                 warm_start=args.warm_start)
     S = fld.Solver(p["shape"], p["h"], prm)
     E, K, H = p["E"], p["kappa"], p["eta"]
     steps = args.steps if args.steps != 10 else 20
@@ -208,7 +209,8 @@ def batch(args, fld, torch, synth, log):
     # one length unit for the batch parameters (limits from the largest box)
     ref = max(probs, key=lambda p: p["L_unit"])
     base = fld.fld_default_params(ref["c"], ref["L_unit"],
-                                  precision=fld.FLD_PREC_MIXED, use_graph=args.graph)
+                                  precision=fld.FLD_PREC_MIXED, use_graph=args.graph,
+                                  warm_start=args.warm_start)
     report = None
     if args.autotune:
         log("[bench] autotuning tile depth and sweep counts")
@@ -230,7 +232,7 @@ def batch(args, fld, torch, synth, log):
         assert all(s["status"] == 0 for s in sts)
         step_bytes += sum(model_step_bytes(int(np.prod(shp)), s["iters"],
                                            s["cycle_nu"], 1, s["levels"],
-                                           warm=True)
+                                           warm=args.warm_start)
                           for shp, s in zip(shapes, sts))
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
@@ -242,7 +244,8 @@ def batch(args, fld, torch, synth, log):
         solvers = []
         for p in probs:
             q = fld.fld_default_params(ref["c"], ref["L_unit"], precision=prec,
-                                       use_graph=args.graph)
+                                       use_graph=args.graph,
+                                       warm_start=args.warm_start)
             solvers.append(fld.Solver(p["shape"], p["h"], q))
         Es1 = [p["E"].clone() for p in probs]
         for S, E, k, h, dt in zip(solvers, Es1, K, H, dts):
@@ -294,7 +297,8 @@ def served(args, fld, torch, synth, log):
     ref = pool[max(sizes)]
     prm = fld.fld_default_params(ref["c"], ref["L_unit"],
                                  precision=fld.FLD_PREC_MIXED,
-                                 prolongation=args.prolongation)
+                                 prolongation=args.prolongation,
+                                 warm_start=args.warm_start)
     free, total = torch.cuda.mem_get_info()
     arena = int(0.6 * free) // 256 * 256
     stream = torch.cuda.Stream()
@@ -447,7 +451,7 @@ def multigroup(args, fld, torch, synth, log):
     log(f"[bench] multigroup {n}^3 x {G} groups: generating on the GPU")
     q = synth.t_multigroup(n, G, device="cuda")
     prm = fld.fld_default_params(q["c"], q["L_unit"], precision=fld.FLD_PREC_MIXED,
-                                 use_graph=args.graph)
+                                 use_graph=args.graph, warm_start=args.warm_start)
     mg = MultigroupFLD(q["shape"], q["h"], G, prm)
     E = q["E"].clone()
     for _ in range(args.warmup):
@@ -460,7 +464,7 @@ def multigroup(args, fld, torch, synth, log):
         assert all(s["status"] == 0 for s in sts)
         iters += [s["iters"] for s in sts]
         sbytes += sum(model_step_bytes(n ** 3, s["iters"], s["cycle_nu"], 1,
-                                       s["levels"], warm=True) for s in sts)
+                                       s["levels"], warm=args.warm_start) for s in sts)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     mg.close()

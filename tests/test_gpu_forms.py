@@ -60,7 +60,7 @@ def test_batch_equals_single_and_oracle(fld, oracle_mod, prec, smoother):
 @pytest.mark.parametrize("prec", [0, 1])
 def test_batch_warm_steps_equal_single(fld, oracle_mod, prec, warm):
     """Three successive steps (the warm start keeps a per-problem history;
-    extrapolated or Galerkin guess): every problem of the batch stays
+    extrapolated or projected guess): every problem of the batch stays
     bit-identical to its single-problem handle and within the gates of the
     oracle's cold steps."""
     log_case("batch_warm", prec=prec, warm=warm)
