@@ -437,6 +437,40 @@ def test_warm_start_steps_match_oracle(fld, oracle_mod, prec, warm):
     assert torch.count_nonzero(zero).item() == 0
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_galerkin_guess_recovers_a_combination(fld, oracle_mod, prec):
+    """With E^n, kappa and dt fixed, dE is affine in eta: for eta3 = 0.3 eta1
+    + 0.7 eta2 the solution is 0.3 dE(eta1) + 0.7 dE(eta2), a point of the
+    span of the two previous steps' dE.  The Galerkin guess (warm_start = 2)
+    is that point to the previous solves' tolerance, so the third step takes
+    at most 2 PCG iterations; the extrapolation (2 dE(n) - dE(n-1), warm_start
+    = 1) is not, and takes more.  Both results match the oracle's solve."""
+    import torch
+    log_case("galerkin_combination", prec=prec)
+    p = _problem((48, 40, 32), 35, dt_factor=0.2)
+    rng = np.random.default_rng(35)
+    eta1 = p["eta"]
+    eta2 = np.roll(p["eta"], (5, 7, 3), axis=(0, 1, 2)) * rng.uniform(0.5, 1.5)
+    eta3 = 0.3 * eta1 + 0.7 * eta2
+    kap = dev(p["kappa"])
+    its = {}
+    for warm in (1, 2):
+        S, prm = _solver(fld, p, precision=prec, warm_start=warm)
+        for k, eta in enumerate((eta1, eta2, eta3)):
+            E = dev(p["E"])
+            st = S.step(E, kap, dev(eta), p["dt"])
+            assert st["status"] == 0
+        its[warm] = st["iters"]
+        q = dict(p)
+        q["eta"] = eta3
+        dEo, _, _, _ = oracle_problem(oracle_mod, q, prm).solve(tol=1e-13)
+        assert rel_l2(host(E), p["E"] + dEo) <= GATE[prec]
+        S.close()
+    print(f"[galerkin] third-step iterations: extrapolated {its[1]}, "
+          f"Galerkin {its[2]}", flush=True)
+    assert its[2] <= 2 < its[1]
+
+
 @pytest.mark.parametrize("nu", [1, 2])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_single_workgroup_tail_matches_oracle(fld, oracle_mod, prec, nu):
