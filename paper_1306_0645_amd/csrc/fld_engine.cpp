@@ -749,9 +749,11 @@ int Engine::run_solve(bool predicted, bool commit) {
 
 // Warm start of problem p's next solve over a step h, when its history
 // allows: dE is about h times the mean rate over the step, so scale the last
-// dE, or extrapolate the rate linearly from the last two.  The guess goes
-// into the dE buffer that holds neither history entry, which becomes P.x
-// (the caller uploads the problem table before the assembly).
+// dE, or extrapolate the rate linearly from the last two (w1, w2; the
+// Galerkin guess combines the same two with coefficients the device solves
+// for).  The guess goes into the dE buffer that holds neither history entry,
+// which becomes P.x (the caller uploads the problem table before the
+// assembly).
 bool Engine::set_warm(int p, double h) {
   warm_now[p] = 0;
   if (!prm.warm_start || prev_ok[p] < 1 || !(prev_h[p] > 0.0)) return false;
@@ -833,8 +835,9 @@ int Engine::run_steps(std::vector<Job> &jobs) {
       st = upload_pd();
       if (st) return st;
     }
-    // (a warm guess's residual b - A x0 comes out of the assembly, FIN_BB
-    // keeps the guess only if it reduces the residual)
+    // (an extrapolated guess's residual b - A x0 comes out of the assembly,
+    // a Galerkin guess and its residual out of enqueue_warm; either is kept
+    // only if it reduces the residual)
     enqueue_assemble(all);
     if (warm) {
       enqueue_warm(all);

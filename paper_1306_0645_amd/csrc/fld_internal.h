@@ -223,8 +223,8 @@ void launch_vup(const Tables &T, TileList L, int l, int prec, int flexible,
 
 // finalize kernels (launch_fin 'which')
 enum : int {
-  FIN_BB = 0,     // after assembly: ||b||^2 (and ||b - A x0||^2 of a warm
-                  // guess), start the solve
+  FIN_BB = 0,     // after assembly (its own kernel): ||b||^2 and the warm
+                  // guess's sums, start the solve
   FIN_RZ = 1,     // after the V-cycle: rho = r.z, beta
   FIN_PQ = 2,     // after the SpMV: alpha = rho / p.q
   FIN_RR = 3,     // after the update: ||r||^2, convergence

@@ -925,8 +925,6 @@ __global__ __launch_bounds__(kBlock) void k_true_resid(Tables T, TileList TL) {
   write_partials(T, tid, rr, 0.0);
 }
 
-// Warm-started problems whose guess FIN_BB rejected (it did not reduce the
-// residual): x = 0, r = b.  And b = 0: the solution is 0 whatever the guess.
 // Galerkin warm guess, once FIN_BB has solved for c: x0 = c1 dE(n) + c2
 // dE(n-1), formed at the cell and its neighbours on the fly, and r = b - A x0
 // with the assembled FP64 operator; partial ||r||^2 for FIN_WARM.
@@ -976,6 +974,9 @@ __global__ __launch_bounds__(kBlock) void k_warm_x(Tables T, TileList TL) {
   write_partials(T, tid, rr, 0.0);
 }
 
+// Warm-started problems whose guess was dropped (by FIN_BB or FIN_WARM: it
+// did not reduce the residual): x = 0, r = b.  And b = 0: the solution is 0
+// whatever the guess.
 __global__ __launch_bounds__(kBlock) void k_warm_revert(Tables T, TileList TL) {
   const Tile t = get_tile(TL);
   const Scal &sc = T.sc[t.prob];
@@ -1195,7 +1196,6 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
   const int t1 = (which == FIN_XFIX || which == FIN_FRESH) ? t0 : (fz ? P.f1 : P.t1);
   bool part;
   switch (which) {
-    case FIN_BB:
     case FIN_STEP: part = alt ? commit_now(sc) : sc.live != 0; break;
     case FIN_TRUE: part = sc.phase == PH_VERIFY; break;
     case FIN_SETR: part = true; break;
