@@ -69,8 +69,11 @@ typedef enum fld_status {
 typedef enum fld_precision {
   FLD_PREC_FP64 = 0,  /* FP64 everywhere: PCG with a symmetric FP64 V-cycle */
   FLD_PREC_MIXED = 1  /* FP32 V-cycle (smoother, transfers, residuals);
-                         FP64 Krylov recurrences, outer residual, refinement
-                         and coarsest solve; flexible (Polak-Ribiere) PCG */
+                         its output z and the search direction p stored in
+                         FP32, each with a per-problem scale; x, r, q, the
+                         operator, the SpMV, the outer residual, refinement
+                         and the coarsest solve in FP64; flexible
+                         (Polak-Ribiere) PCG */
 } fld_precision;
 
 /* Multigrid smoother (Sec. 3.3 names red/black Gauss-Seidel sweeps). */
