@@ -410,11 +410,12 @@ def main():
     args = parse()
     if args.warm_start is None:
         # the Galerkin guess (the library default) where it measured faster;
-        # the extrapolation for the batch (about 1.45 iterations a step leave
-        # no room for the guess's extra pass) and for the Stromgren sweeps
-        # (slowly drifting fronts, where it took fewer iterations)
-        args.warm_start = 1 if args.workload in ("batch", "hii_test1",
-                                                 "cosmo_test2") else 2
+        # the extrapolation for the single source and the batch (1 and about
+        # 1.45 iterations a step leave no room for the guess's extra pass)
+        # and for the Stromgren sweeps (slowly drifting fronts, where it took
+        # fewer iterations)
+        args.warm_start = 1 if args.workload in ("single_source", "batch",
+                                                 "hii_test1", "cosmo_test2") else 2
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build "
               "has no multi-GPU path", file=sys.stderr)

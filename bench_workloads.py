@@ -75,7 +75,8 @@ def single_source(args, fld, torch, synth, log):
     from bench import BYTES_PER_CELL
     p = synth.single_source(32)
     prm = fld.fld_default_params(p["c"], p["L_unit"], mg_levels=4, nu_pre=2,
-                                 nu_post=2, use_graph=args.graph)
+                                 nu_post=2, use_graph=args.graph,
+                                 warm_start=args.warm_start)
     S = fld.Solver(p["shape"], p["h"], prm)
     E0 = torch.from_numpy(p["E"]).cuda()
     K = torch.from_numpy(p["kappa"]).cuda()
