@@ -158,13 +158,14 @@ def auto_levels(n):
     return lv
 
 
-def measured_traffic(kernel, form):
+def measured_traffic(kernel, form, root=ROOT):
     """HBM bytes per launch of `kernel` from the rocprofv3 byte-counter
-    records under profiles/, or None when there is no record or any source
-    the record names has changed since the counters were taken."""
+    records under root/profiles/, or None when there is no record or any
+    source the record names (relative to root) has changed since the
+    counters were taken."""
     import glob
     import hashlib
-    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+    for path in sorted(glob.glob(os.path.join(root, "profiles", "*.md"))):
         with open(path) as f:
             for line in f:
                 if not line.startswith("traffic-record:"):
@@ -175,7 +176,7 @@ def measured_traffic(kernel, form):
                 for item in kv.get("sources", "").split(","):
                     rel, want = item.rsplit(":", 1)
                     try:
-                        with open(os.path.join(ROOT, rel), "rb") as src:
+                        with open(os.path.join(root, rel), "rb") as src:
                             have = hashlib.sha256(src.read()).hexdigest()
                     except OSError:
                         return None
