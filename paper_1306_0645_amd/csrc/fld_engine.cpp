@@ -190,6 +190,8 @@ void carve_problem(Carver &cv, const Hier &h, const fld_params &p, ProbMem &m) {
       P.q = cv.take<double>(n);
       P.b = cv.take<double>(n);
       P.r2 = lazy_iteration(p) ? cv.take<double>(n) : nullptr;
+      P.ef = (mixed && fused_cycle(p) && p.prolongation != 0) ? cv.take<float>(n)
+                                                               : nullptr;
       L.x = mixed ? (void *)cv.take<float>(n) : (void *)P.z;
       L.f = nullptr;
       if (jacobi) L.x2 = mixed ? (void *)cv.take<float>(n) : (void *)cv.take<double>(n);
@@ -550,6 +552,7 @@ void Engine::enqueue_fused_rest(const ListSet &ls) {
     launch_prolong_black(T, ls.gsm[l], l, prec, tri, stream);
     launch_half(T, ls.gsm[l], l, 0, prec, stream);
   }
+  if (tri && mixed) launch_tri_fine(T, ls.fine, stream);
   launch_vup(T, ls.fsm[0], 0, prec, mixed, tri, stream);
 }
 

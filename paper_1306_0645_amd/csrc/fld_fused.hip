@@ -229,11 +229,13 @@ struct QPlane {
   R hd[kHalo], he[kHalo];
 };
 
-template <typename R, bool L0, bool UP, bool TRI>
+// EF (trilinear mixed finest level): ef holds the coarse correction already
+// interpolated to every fine cell (k_tri_fine), read in place of the gathers
+template <typename R, bool L0, bool UP, bool TRI, bool EF = false>
 __device__ __forceinline__ void q_load_plane(
     QPlane<R, L0, UP> &pl, const Tile &t, int pz, bool qon, int qx, int qy,
     int nx, int ny, int nz, const FSrc<R, L0> &f, const R *d, const R *e,
-    bool has_coarse, int cnx, int cny, int cnz) {
+    bool has_coarse, int cnx, int cny, int cnz, const R *ef = nullptr) {
   const int kz = wrapi(pz, nz);
   if (qon) {
     const int r0 = (kz * ny + qy) * nx + qx, r1 = r0 + nx;
@@ -251,8 +253,13 @@ __device__ __forceinline__ void q_load_plane(
       if (has_coarse) {
         if constexpr (TRI) {
           const int pp = pz & 1;  // red cells: row 0 at a = pp, row 1 at 1 - pp
-          pl.e0 = coarse_corr(e, qx + pp, qy, kz, cnx, cny, cnz, true);
-          pl.e1 = coarse_corr(e, qx + 1 - pp, qy + 1, kz, cnx, cny, cnz, true);
+          if constexpr (EF) {
+            pl.e0 = ef[r0 + pp];
+            pl.e1 = ef[r1 + 1 - pp];
+          } else {
+            pl.e0 = coarse_corr(e, qx + pp, qy, kz, cnx, cny, cnz, true);
+            pl.e1 = coarse_corr(e, qx + 1 - pp, qy + 1, kz, cnx, cny, cnz, true);
+          }
         } else {
           pl.e0 = pl.e1 = coarse_corr(e, qx, qy, kz, cnx, cny, cnz, false);
         }
@@ -274,7 +281,7 @@ __device__ __forceinline__ void q_load_plane(
       pl.hd[u] = d[g];
       if constexpr (UP) {
         pl.he[u] = (has_coarse && ((ux + uy + pz) & 1) == 0)
-                       ? coarse_corr(e, gx, gy, kz, cnx, cny, cnz, TRI)
+                       ? (EF ? ef[g] : coarse_corr(e, gx, gy, kz, cnx, cny, cnz, TRI))
                        : (R)0;
       }
     }
@@ -500,6 +507,11 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
   const auto f = fsrc<R, L0>(L, P, sc);
   const double inv_s = sc.inv_s;
   const R *e = (const R *)Cl.x;
+  // mixed trilinear finest level: the correction interpolated to the fine
+  // cells (allocated whenever a mixed fused cycle may go trilinear)
+  constexpr bool kEf = L0 && TRI && sizeof(R) == 4;
+  const R *ef = nullptr;
+  if constexpr (kEf) ef = P.ef;
   R *xout = (R *)L.x;
   const double s_out = sc.s;
   // flexible PCG needs r.z_old, except where the PCG (re)starts (beta = 0);
@@ -517,8 +529,8 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
   const int rq = threadIdx.x / 3;
   const bool ron = threadIdx.x == 3 * rq && rq < t.tx + t.ty;
   QPlane<R, L0, true> pl;
-  q_load_plane<R, L0, true, TRI>(pl, t, t.z0 - 2, qon, qx, qy, nx, ny, nz, f, C.d,
-                                 e, has_coarse, cnx, cny, cnz);
+  q_load_plane<R, L0, true, TRI, kEf>(pl, t, t.z0 - 2, qon, qx, qy, nx, ny, nz, f,
+                                      C.d, e, has_coarse, cnx, cny, cnz, ef);
   QFace<R> Fb{}, Fr{};
   Q4<R> Zb{}, Zr{}, Zrm{};
   Q4<R> I0{}, I1{}, I2{};   // diagonal reciprocals of planes pz, pz - 1, pz - 2
@@ -557,8 +569,8 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
     I1 = I0;
     I0 = q_store_plane<R, L0, true>(pl, t, pz, qon, ci, cj, vs[m % 3], inv_s);
     if (m + 1 < t.tz + 4)
-      q_load_plane<R, L0, true, TRI>(pl, t, pz + 1, qon, qx, qy, nx, ny, nz, f, C.d,
-                                     e, has_coarse, cnx, cny, cnz);
+      q_load_plane<R, L0, true, TRI, kEf>(pl, t, pz + 1, qon, qx, qy, nx, ny, nz, f,
+                                          C.d, e, has_coarse, cnx, cny, cnz, ef);
     __syncthreads();
     // (2) new black values of plane pb over the tile + 1
     if (m >= 2) {

@@ -55,6 +55,9 @@ struct ProbDev {
   // the search direction in FP32 at the scale of the z it was formed from,
   // p = pscale * pf0 (or pf1)
   float *z32, *pf0, *pf1;
+  // mixed form with trilinear prolongation possible: the finest level's
+  // coarse-grid correction interpolated to every cell (k_tri_fine)
+  float *ef;
   double *r2;            // second residual buffer (fused V(1,1) iteration)
   double *cs;            // coarsest-level CG scratch: 4 * n_coarsest doubles
   int levels;            // number of multigrid levels
@@ -145,7 +148,7 @@ enum : int {
   K_UPDATE_E, K_VDOWN_F, K_VDOWN_C, K_VUP_F, K_VUP_C, K_CHEM_H, K_ION_SUM,
   K_WARM_REVERT, K_JACOBI0_F, K_JACOBI_F, K_JACOBI_OUT,
   K_JACOBI_C, K_PROLONG_ADD_F, K_PROLONG_ADD_C, K_SPMV_PX, K_XFIX, K_WARM_X,
-  K_NUM
+  K_TRI_FINE, K_NUM
 };
 
 // Brackets one launch with hipEvents when its kernel id is selected.
@@ -204,6 +207,9 @@ void launch_true_resid(const Tables &T, TileList L0, hipStream_t s);
 void launch_warm_revert(const Tables &T, TileList L0, hipStream_t s);
 // x0 = c1 dE(n) + c2 dE(n-1), r = b - A x0 (Galerkin warm guesses)
 void launch_warm_x(const Tables &T, TileList L0, hipStream_t s);
+// ef = the trilinear interpolation of level 1's correction to every finest
+// cell (before the finest up pass of a trilinear mixed cycle)
+void launch_tri_fine(const Tables &T, TileList L0, hipStream_t s);
 void launch_apply(const Tables &T, TileList L0, const double *u, double *out,
                   hipStream_t s);
 void launch_set_r(const Tables &T, TileList L0, const double *r, int prec,

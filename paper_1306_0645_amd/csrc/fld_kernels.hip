@@ -974,6 +974,26 @@ __global__ __launch_bounds__(kBlock) void k_warm_x(Tables T, TileList TL) {
   write_partials(T, tid, rr, 0.0);
 }
 
+// The finest up pass of a trilinear mixed cycle reads the coarse-grid
+// correction from ef instead of gathering its 8 coarse values per cell: one
+// streaming pass interpolates it to every finest cell (the same arithmetic).
+__global__ __launch_bounds__(kBlock) void k_tri_fine(Tables T, TileList TL) {
+  const Tile t = get_tile(TL);
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.active) return;
+  const ProbDev P = T.pd[t.prob];
+  if (P.levels < 2 || !P.ef) return;
+  const LevelDev L = T.lv[t.prob];
+  const LevelDev C = T.lv[T.nprob + t.prob];
+  const float *e = (const float *)C.x;
+  const Col col = tile_col(t);
+  if (!col.on) return;
+  const int plane = L.nx * L.ny;
+  int c = t.z0 * plane + col.j * L.nx + col.i;
+  for (int k = t.z0; k < t.z0 + t.tz; ++k, c += plane)
+    P.ef[c] = coarse_corr(e, col.i, col.j, k, C.nx, C.ny, C.nz, true);
+}
+
 // Warm-started problems whose guess was dropped (by FIN_BB or FIN_WARM: it
 // did not reduce the residual): x = 0, r = b.  And b = 0: the solution is 0
 // whatever the guess.
@@ -1361,7 +1381,7 @@ static const char *kKernelNames[K_NUM] = {
     "vdown_coarse", "vup_fine", "vup_coarse", "chem_h", "ionized_sum",
     "warm_revert", "jacobi0_fine", "jacobi_fine", "jacobi_out",
     "jacobi_coarse", "prolong_add_fine", "prolong_add_coarse", "spmv_px",
-    "xfix", "warm_x"};
+    "xfix", "warm_x", "tri_fine"};
 
 namespace prof {
 struct Rec {
@@ -1523,6 +1543,10 @@ void launch_update(const Tables &T, TileList L0, int prec, hipStream_t s) {
 
 void launch_true_resid(const Tables &T, TileList L0, hipStream_t s) {
   if (L0.nblocks) LAUNCH(K_TRUE_RESID, k_true_resid, L0.nblocks, kBlock, s, T, L0);
+}
+
+void launch_tri_fine(const Tables &T, TileList L0, hipStream_t s) {
+  if (L0.nblocks) LAUNCH(K_TRI_FINE, k_tri_fine, L0.nblocks, kBlock, s, T, L0);
 }
 
 void launch_warm_x(const Tables &T, TileList L0, hipStream_t s) {
