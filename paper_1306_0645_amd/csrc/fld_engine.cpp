@@ -552,7 +552,7 @@ void Engine::enqueue_fused_rest(const ListSet &ls) {
     launch_prolong_black(T, ls.gsm[l], l, prec, tri, stream);
     launch_half(T, ls.gsm[l], l, 0, prec, stream);
   }
-  if (tri && mixed) launch_tri_fine(T, ls.fine, stream);
+  if (tri && mixed && Lmax > 1) launch_tri_fine(T, ls.exist[1], stream);
   launch_vup(T, ls.fsm[0], 0, prec, mixed, tri, stream);
 }
 

@@ -208,8 +208,9 @@ void launch_warm_revert(const Tables &T, TileList L0, hipStream_t s);
 // x0 = c1 dE(n) + c2 dE(n-1), r = b - A x0 (Galerkin warm guesses)
 void launch_warm_x(const Tables &T, TileList L0, hipStream_t s);
 // ef = the trilinear interpolation of level 1's correction to every finest
-// cell (before the finest up pass of a trilinear mixed cycle)
-void launch_tri_fine(const Tables &T, TileList L0, hipStream_t s);
+// cell (before the finest up pass of a trilinear mixed cycle); L1: level-1
+// tiles, one thread per level-1 cell
+void launch_tri_fine(const Tables &T, TileList L1, hipStream_t s);
 void launch_apply(const Tables &T, TileList L0, const double *u, double *out,
                   hipStream_t s);
 void launch_set_r(const Tables &T, TileList L0, const double *r, int prec,

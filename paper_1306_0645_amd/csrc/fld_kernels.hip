@@ -975,23 +975,61 @@ __global__ __launch_bounds__(kBlock) void k_warm_x(Tables T, TileList TL) {
 }
 
 // The finest up pass of a trilinear mixed cycle reads the coarse-grid
-// correction from ef instead of gathering its 8 coarse values per cell: one
-// streaming pass interpolates it to every finest cell (the same arithmetic).
+// correction from ef instead of gathering its 8 coarse values per cell: this
+// pass interpolates it to every finest cell.  One thread per level-1 cell
+// loads its 3 x 3 x 3 neighbourhood once and writes its 8 children, each
+// combined in the order coarse_corr uses (the same values).
 __global__ __launch_bounds__(kBlock) void k_tri_fine(Tables T, TileList TL) {
   const Tile t = get_tile(TL);
   const Scal &sc = T.sc[t.prob];
   if (!sc.active) return;
   const ProbDev P = T.pd[t.prob];
   if (P.levels < 2 || !P.ef) return;
-  const LevelDev L = T.lv[t.prob];
+  const LevelDev F = T.lv[t.prob];
   const LevelDev C = T.lv[T.nprob + t.prob];
-  const float *e = (const float *)C.x;
+  const float *__restrict__ e = (const float *)C.x;
+  float *__restrict__ ef = P.ef;
   const Col col = tile_col(t);
   if (!col.on) return;
-  const int plane = L.nx * L.ny;
-  int c = t.z0 * plane + col.j * L.nx + col.i;
-  for (int k = t.z0; k < t.z0 + t.tz; ++k, c += plane)
-    P.ef[c] = coarse_corr(e, col.i, col.j, k, C.nx, C.ny, C.nz, true);
+  const int cnx = C.nx, cny = C.ny, cnz = C.nz, fnx = F.nx, fny = F.ny;
+  const float A = 0.75f, B = 0.25f;
+  for (int K = t.z0; K < t.z0 + t.tz; ++K) {
+    for (int u = 0; u < t.cpt; ++u) {
+      const int I = col.i + u, J = col.j;
+      const int Im = I == 0 ? cnx - 1 : I - 1, Ip = I + 1 == cnx ? 0 : I + 1;
+      const int Jm = J == 0 ? cny - 1 : J - 1, Jp = J + 1 == cny ? 0 : J + 1;
+      const int Km = K == 0 ? cnz - 1 : K - 1, Kp = K + 1 == cnz ? 0 : K + 1;
+      const int ks[3] = {Km, K, Kp}, js[3] = {Jm, J, Jp};
+      float v[3][3][3];  // [z][y][x] offsets -1, 0, +1
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          const int row = (ks[dz] * cny + js[dy]) * cnx;
+          v[dz][dy][0] = e[row + Im];
+          v[dz][dy][1] = e[row + I];
+          v[dz][dy][2] = e[row + Ip];
+        }
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          float out[2];
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const int x2 = a ? 2 : 0, y2 = b ? 2 : 0, z2 = c ? 2 : 0;
+            const float zK = A * (A * v[1][1][1] + B * v[1][1][x2]) +
+                             B * (A * v[1][y2][1] + B * v[1][y2][x2]);
+            const float zK2 = A * (A * v[z2][1][1] + B * v[z2][1][x2]) +
+                              B * (A * v[z2][y2][1] + B * v[z2][y2][x2]);
+            out[a] = A * zK + B * zK2;
+          }
+          const int o = ((2 * K + c) * fny + 2 * J + b) * fnx + 2 * I;
+          ef[o] = out[0];
+          ef[o + 1] = out[1];
+        }
+    }
+  }
 }
 
 // Warm-started problems whose guess was dropped (by FIN_BB or FIN_WARM: it
