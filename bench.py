@@ -1,16 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the implicit grey FLD step on one MI355X.
 
-Default workload: 256^3 periodic grid, lognormal HI opacity (sigma_ln 1.5),
-64 point sources (Ndot log-uniform 1e47-1e50), smooth random E^n, dt = 1e-3
-light-crossing times, successive timesteps with the limiter recomputed from
-the new E each step, PCG + geometric multigrid to a 1e-8 relative residual.
+Default workload: one GPU's share of a large reionization box (Sec. 5: the
+3200^3 run on 125 GPU shares of 640^3 cells each), the 640^3 share with
+periodic self-wrapped halos, lognormal HI (sigma_ln 2.0) with ionized bubbles
+(x_HI = 1e-4) around 10^4 Poisson-placed sources (Ndot log-uniform
+1e46-1e49), E^0 = 1e-45 erg cm^-3, dt = 1e-3 light-crossing times of the
+3200-cell box, 6-level multigrid, PCG to a 1e-8 relative residual, 20
+successive steps from E^0 (the limiter recomputed from the new E each step).
 A "step" is one full timestep: assembly of the limiter system and every
 multigrid level, the preconditioned CG solve, and E += dE.
 
-Prints ONE JSON line: Mcell-updates/s of the mixed-precision form (the FP64
-form is reported beside it), the roofline of the dominant kernel timed live
-with hipEvents, and the oracle's CPU throughput on a bounded sample.
+Prints ONE JSON line: Mcell-updates/s of the mixed-precision form (the plain
+FP64 form is reported beside it), per-step latency quantiles, the roofline of
+the dominant kernel timed live with hipEvents, each form's residual and
+error bound evaluated by the oracle at every cell, and the oracle's CPU
+throughput on a bounded sample of the same step.  The 256^3 many-source
+workload and the 32^3 single-source latency run follow in "secondary".
 """
 import argparse
 import json
@@ -68,6 +74,19 @@ BYTES_PER_CELL = {
     "prolong_add_fine": (17.0, 8.5),
 }
 
+# The mixed form with an FP64 search direction (direction_fp64) reads and
+# writes p in 8 bytes instead of 4: p_old in and p_new out of the SpMV, p in
+# the update and the deferred x update.
+DIR64_EXTRA = {"spmv_p": 8.0, "spmv_px": 8.0, "xfix": 4.0, "update": 4.0}
+
+
+def bpc(name, prec_idx, dir64=False):
+    """Algorithmic bytes per finest cell of one launch of kernel `name`."""
+    v = BYTES_PER_CELL[name][prec_idx]
+    if prec_idx and dir64:
+        v += DIR64_EXTRA.get(name, 0.0)
+    return v
+
 
 # Coarse levels (every level below the finest).  One V-cycle's generic
 # kernels there (red+black pre-sweep from zero, residual and restriction,
@@ -91,14 +110,14 @@ STEP_KERNELS = ("assemble", "true_resid", "update_E", "xfix", "warm_x")
 OLD_Z_BYTES = 4.0
 
 
-def step_bytes(counts, cells, prec_idx, levels):
+def step_bytes(counts, cells, prec_idx, levels, dir64=False):
     """Algorithmic bytes of one step from the launches counted in a survey
     step, split into (per step, per PCG iteration x iterations): finest-level
     kernels exactly, coarse levels from their share of cells."""
     fixed = it = 0.0
     for name, count in counts.items():
         if name in BYTES_PER_CELL:
-            v = count * BYTES_PER_CELL[name][prec_idx] * cells
+            v = count * bpc(name, prec_idx, dir64) * cells
             if name in STEP_KERNELS:
                 fixed += v
             else:
@@ -115,7 +134,8 @@ def step_bytes(counts, cells, prec_idx, levels):
     return fixed, it
 
 
-def model_step_bytes(cells, iters, nu, prec_idx, levels, steps=1, warm=False):
+def model_step_bytes(cells, iters, nu, prec_idx, levels, steps=1, warm=False,
+                     dir64=False):
     # warm: 0/False cold, 1 extrapolated guess, 2 or True Galerkin guess (the
     # library default)
     """Algorithmic bytes of `steps` steps of one problem taking `iters` PCG
@@ -123,7 +143,7 @@ def model_step_bytes(cells, iters, nu, prec_idx, levels, steps=1, warm=False):
     assembly and coarse operators, the true-residual check and E += dE once,
     then per PCG iteration one V(nu,nu) cycle (fused finest-level passes for
     nu = 1), the SpMV and the vector update."""
-    B = {k: v[prec_idx] for k, v in BYTES_PER_CELL.items()}
+    B = {k: bpc(k, prec_idx, dir64) for k in BYTES_PER_CELL}
     cf = coarse_fraction(levels)
     coarse = (COARSE_CYCLE_BYTES[prec_idx]
               + (4 * (nu - 1)) * (56.0, 32.0)[prec_idx])
@@ -162,11 +182,11 @@ def auto_levels(n):
     return lv
 
 
-def measured_traffic(kernel, form, root=ROOT):
+def measured_traffic(kernel, form, workload=None, root=ROOT):
     """HBM bytes per launch of `kernel` from the rocprofv3 byte-counter
-    records under root/profiles/, or None when there is no record or any
-    source the record names (relative to root) has changed since the
-    counters were taken."""
+    records under root/profiles/ (for that workload, when one is named), or
+    None when there is no record or any source the record names (relative to
+    root) has changed since the counters were taken."""
     import glob
     import hashlib
     for path in sorted(glob.glob(os.path.join(root, "profiles", "*.md"))):
@@ -176,6 +196,8 @@ def measured_traffic(kernel, form, root=ROOT):
                     continue
                 kv = dict(t.split("=", 1) for t in line.split()[1:])
                 if kv.get("kernel") != kernel or kv.get("form") != form:
+                    continue
+                if workload is not None and kv.get("workload") != workload:
                     continue
                 for item in kv.get("sources", "").split(","):
                     rel, want = item.rsplit(":", 1)
@@ -215,11 +237,21 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=256, help="grid extent")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 20 for the reionization share, "
+                         "10 for the other step workloads)")
+    ap.add_argument("--warmup", type=int, default=2,
+                    help="untimed steps on a separate handle before the timed run")
+    ap.add_argument("--n", type=int, default=None, help="grid extent")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="reionization: skip the 256^3 and 32^3 secondary runs")
+    ap.add_argument("--no-parity", action="store_true",
+                    help="reionization: skip the oracle's residual of each form")
+    ap.add_argument("--forms", default="mixed,mixed_dir32,fp64")
+    ap.add_argument("--direction-fp64", type=int, default=1,
+                    help="mixed form: 1 keeps the PCG search direction in FP64, "
+                         "0 rounds it to FP32 at a per-problem scale")
     ap.add_argument("--tile-z", type=int, default=0)
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--fused-tile-z", type=int, default=0)
@@ -242,8 +274,10 @@ def parse():
                     help="iterations above which a V(1,1) handle switches cycle")
     ap.add_argument("--prolongation", type=int, default=2,
                     help="mixed cycle: 0 constant, 1 trilinear, 2 automatic")
-    ap.add_argument("--workload", default="many_sources",
-                    choices=["many_sources", "single_source", "reionization",
+    ap.add_argument("--coarse-op", type=int, default=0,
+                    help="coarse faces: 0 sum of the fine faces, 1 rows in series")
+    ap.add_argument("--workload", default="reionization",
+                    choices=["reionization", "many_sources", "single_source",
                              "batch", "served", "hii_test1", "multigroup",
                              "cosmo_test2"])
     ap.add_argument("--reps", type=int, default=300,
@@ -266,51 +300,80 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain copy kernel of 2 GiB read + 2 GiB "
                          "written, to calibrate the HBM byte counters")
+    ap.add_argument("--cpu-iters", type=int, default=3,
+                    help="oracle sample: Jacobi-PCG iterations timed on all "
+                         "cores (after a run of the assembly alone)")
     return ap.parse_args()
 
 
-def run_form(fld, torch, p, prec, steps, warmup, args):
-    """Timed steps with graph replay (the throughput), then the same number of
-    steps with per-kernel launches so hipEvents can time the dominant kernel
-    on its stream (a graph replay hides its kernels from the timing hook)."""
-    E = torch.from_numpy(p["E"]).cuda()
-    kap = torch.from_numpy(p["kappa"]).cuda()
-    eta = torch.from_numpy(p["eta"]).cuda()
-    names = fld.profile_kernels()
+def form_params(fld, p, prec, args, **kw):
+    """Library parameters of a form: the paper's defaults with the bench's
+    switches."""
+    base = dict(precision=prec, tile_z=args.tile_z, use_graph=args.graph,
+                fused_tile_z=args.fused_tile_z, warm_start=args.warm_start,
+                prolongation=args.prolongation, tail_cells=args.tail_cells,
+                smoother=args.smoother, fused_levels=args.fused_levels,
+                check_every=args.check_every, cycle_switch=args.cycle_switch,
+                coarse_op=args.coarse_op,
+                direction_fp64=args.direction_fp64 if prec else 0)
+    base.update(kw)
+    return fld.fld_default_params(p["c"], p["L_unit"], **base)
 
-    def solver(graph):
-        # the kernel-timing pass reads the convergence state after every
-        # iteration, so no launch of a converged problem (which returns at
-        # once) enters the per-launch average
-        prm = fld.fld_default_params(p["c"], p["L_unit"], precision=prec,
-                                     tile_z=args.tile_z, use_graph=graph,
-                                     fused_tile_z=args.fused_tile_z,
-                                     warm_start=args.warm_start,
-                                     prolongation=args.prolongation,
-                                     tail_cells=args.tail_cells,
-                                     smoother=args.smoother,
-                                     fused_levels=args.fused_levels,
-                                     check_every=args.check_every if graph else 1)
-        return fld.Solver(p["shape"], p["h"], prm)
 
-    S = solver(args.graph)
-    for w in range(max(1, warmup)):
-        S.step(E, kap, eta, p["dt"])
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def time_steps(fld, torch, p, prm, steps, warmup):
+    """`warmup` untimed steps on a handle of their own from E^0, then a
+    fresh handle times `steps` successive steps from E^0 (the limiter
+    recomputed each step).  Returns the handle (still open), E after the
+    timed steps, and the per-step records."""
+    E0 = p["E"]
+    K, H = p["kappa"], p["eta"]
+    if warmup > 0:
+        W = fld.Solver(p["shape"], p["h"], prm)
+        Ew = E0.clone()
+        for _ in range(warmup):
+            W.step(Ew, K, H, p["dt"])
+        W.close()
+        del W, Ew
+        torch.cuda.empty_cache()
+    S = fld.Solver(p["shape"], p["h"], prm)
+    E = E0.clone()
     torch.cuda.synchronize()
+    lat, recs = [], []
     t0 = time.perf_counter()
-    iters, rels = [], []
-    for _ in range(steps):
-        st = S.step(E, kap, eta, p["dt"])
-        iters.append(st["iters"])
-        rels.append(st["rel_resid"])
+    for k in range(steps):
+        ta = time.perf_counter()
+        st = S.step(E, K, H, p["dt"])  # returns once the step is decided
+        lat.append(time.perf_counter() - ta)
+        recs.append(st)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    S.close()
-    # kernel timing pass: survey one step, then time the dominant kernel
-    P = solver(0)
-    P.step(E, kap, eta, p["dt"])
+    sec = time.perf_counter() - t0
+    return S, E, recs, lat, sec
+
+
+def kernel_pass(fld, torch, p, prm, E, steps, prec_idx, dir64):
+    """Per-kernel timing on a handle without graph replay (a replayed graph
+    hides its kernels from the timing hook), reading the convergence state
+    after every iteration so that no launch of a converged problem enters
+    the averages: survey one step with every kernel timed, then time the
+    dominant kernel's launches over `steps` steps with hipEvents on the
+    handle's stream."""
+    names = fld.profile_kernels()
+    P = fld.Solver(p["shape"], p["h"], prm)
+    Ek = E.clone()
+    P.step(Ek, p["kappa"], p["eta"], p["dt"])
     fld.fld_profile_select(-2)
-    st_survey = P.step(E, kap, eta, p["dt"])
+    st_survey = P.step(Ek, p["kappa"], p["eta"], p["dt"])
     torch.cuda.synchronize()
     reads = {n: fld.fld_profile_read(k) for k, n in enumerate(names)}
     totals = {n: r[0] for n, r in reads.items()}
@@ -319,96 +382,324 @@ def run_form(fld, torch, p, prec, steps, warmup, args):
     dom_id = names.index(dom)
     fld.fld_profile_select(dom_id)
     torch.cuda.synchronize()
-    tp0 = time.perf_counter()
     for _ in range(steps):
-        P.step(E, kap, eta, p["dt"])
+        P.step(Ek, p["kappa"], p["eta"], p["dt"])
     torch.cuda.synchronize()
-    tp1 = time.perf_counter()
     ms_total, launches = fld.fld_profile_read(dom_id)
     fld.fld_profile_select(-1)
     P.close()
-    cells = p["E"].size
-    sec = t1 - t0
+    del Ek
+    cells = int(E.numel())
     avg_ms = ms_total / max(launches, 1)
-    bpc = BYTES_PER_CELL[dom][1 if prec == fld.FLD_PREC_MIXED else 0]
-    achieved = bpc * cells / (avg_ms * 1e-3) / 1e9
-    prec_idx = 1 if prec == fld.FLD_PREC_MIXED else 0
-    # whole-step algorithmic bytes, scaled from the survey step's iteration
-    # count to the timed steps' mean
-    fixed_b, iter_b = step_bytes(counts, cells, prec_idx, st_survey["levels"])
-    it_mean = sum(iters) / len(iters)
-    sb = fixed_b + iter_b / max(st_survey["iters"], 1) * it_mean
-    return {
-        "mcell_updates_per_s": cells * steps / sec / 1e6,
-        "ms_per_step": 1e3 * sec / steps,
-        "ms_per_step_unfused_launches": 1e3 * (tp1 - tp0) / steps,
-        "iters_per_step": sum(iters) / len(iters),
-        "max_rel_resid": max(rels),
-        "survey_ms": {k: round(v, 4) for k, v in sorted(
-            totals.items(), key=lambda kv: -kv[1]) if v > 0},
-        "dominant": dom,
-        "dominant_avg_ms": avg_ms,
-        "dominant_launches": launches,
-        "dominant_GBps": achieved,
-        "dominant_bytes_per_cell": bpc,
-        "step_bytes_per_cell": sb / cells,
-        "step_GBps": sb * steps / sec / 1e9,
-    }
+    b = bpc(dom, prec_idx, dir64)
+    fixed_b, iter_b = step_bytes(counts, cells, prec_idx, st_survey["levels"], dir64)
+    return {"dominant": dom, "dominant_avg_ms": avg_ms, "dominant_launches": launches,
+            "dominant_bytes_per_cell": b,
+            "dominant_GBps": b * cells / (avg_ms * 1e-3) / 1e9,
+            "survey_ms": {k: round(v, 4) for k, v in sorted(
+                totals.items(), key=lambda kv: -kv[1]) if v > 0},
+            "survey_iters": st_survey["iters"], "_fixed_b": fixed_b, "_iter_b": iter_b}
 
 
-def cpu_baseline(p):
+def oracle_residual(p, E_before, dE, parallel=True, chunk=1 << 24):
+    """The oracle's residual b - A dE at every cell, each computed on its own
+    from the oracle's limiter and operator, in chunks: returns the relative
+    residual ||b - A dE|| / ||b|| and the error bound ||b - A dE|| / ||dE||
+    (||A^-1||_2 <= 1 when adot >= 0, so this bounds the relative error
+    against the exact step).  The parallel build evaluates each cell with the
+    same arithmetic as the serial one."""
+    import numpy as np
+
     import oracle
+    En = E_before.detach().cpu().numpy()
+    Kh = p["kappa"].detach().cpu().numpy()
+    Hh = p["eta"].detach().cpu().numpy()
+    dEh = dE.detach().cpu().numpy()
     dmax, rmin = oracle.limits(p["c"], p["L_unit"])
-    O = oracle.Problem(p["E"], p["kappa"], p["eta"], p["h"], p["c"], dmax, rmin,
-                       p["dt"], p["theta"], p["a"], p["adot"])
+    O = oracle.Problem(En, Kh, Hh, p["h"], p["c"], dmax, rmin, p["dt"], parallel=parallel)
+    n = En.size
+    rr = bb = 0.0
+    for a in range(0, n, chunk):
+        cells = np.arange(a, min(n, a + chunk), dtype=np.int64)
+        res, rhs = O.residual_at(dEh, cells)
+        rr += float(np.dot(res, res))
+        bb += float(np.dot(rhs, rhs))
+    dd = float(np.dot(dEh.ravel(), dEh.ravel()))
+    return {"true_rel_resid": math.sqrt(rr / bb) if bb > 0 else 0.0,
+            "err_bound": math.sqrt(rr / dd) if dd > 0 else 0.0,
+            "cells_checked": int(n)}
+
+
+def run_form_headline(fld, torch, p, name, args, steps, levels=6):
+    prec = fld.FLD_PREC_MIXED if name.startswith("mixed") else fld.FLD_PREC_FP64
+    dir64 = bool(args.direction_fp64) if prec else False
+    if name == "mixed_dir32":
+        dir64 = False
+    elif name == "mixed_dir64":
+        dir64 = True
+    prm = form_params(fld, p, prec, args, mg_levels=levels,
+                      direction_fp64=int(dir64) if prec else 0)
+    log(f"[bench] form {name}: {args.warmup} warm-up + {steps} timed steps from E^0")
+    S, E, recs, lat, sec = time_steps(fld, torch, p, prm, steps, args.warmup)
+    for k in range(0, steps, 5):
+        log(f"[bench]   step {k + 1}: {recs[k]['iters']} iterations, "
+            f"{1e3 * lat[k]:.1f} ms")
+    import numpy as np
+    cells = int(E.numel())
+    iters = [r["iters"] for r in recs]
+    rels = [r["rel_resid"] for r in recs]
+    assert all(r["status"] == 0 for r in recs), [r["status"] for r in recs]
+    out = {"mcell_updates_per_s": cells * steps / sec / 1e6,
+           "ms_per_step": 1e3 * sec / steps,
+           "latency_ms": {"p50": float(np.percentile(np.array(lat) * 1e3, 50)),
+                          "p99": float(np.percentile(np.array(lat) * 1e3, 99)),
+                          "mean": float(np.mean(lat) * 1e3),
+                          "max": float(np.max(lat) * 1e3)},
+           "iters_per_step": float(np.mean(iters)), "iters": iters,
+           "max_rel_resid": float(max(rels)),
+           "max_err_bound": float(max(r["err_bound"] for r in recs)),
+           "restarts": int(sum(r["restarts"] for r in recs)),
+           "final_cycle": {"nu": recs[-1]["cycle_nu"], "trilinear": recs[-1]["trilinear"]},
+           "direction": "fp64" if (dir64 or not prec) else "fp32"}
+    if not args.no_parity:
+        # one more step of the same handle (its warm start and cycle), checked
+        # by the oracle at every cell
+        Eb = E.clone()
+        st = S.step(E, p["kappa"], p["eta"], p["dt"])
+        dE = E - Eb
+        torch.cuda.synchronize()
+        log(f"[bench]   oracle residual of step {steps + 1} at every cell")
+        par = oracle_residual(p, Eb, dE)
+        par["solver_rel_resid"] = st["rel_resid"]
+        par["step"] = steps + 1
+        out["parity"] = par
+        del Eb, dE
+    S.close()
+    del S
+    torch.cuda.empty_cache()
+    nu, tri = recs[-1]["cycle_nu"], recs[-1]["trilinear"]
+    kprm = form_params(fld, p, prec, args, mg_levels=levels, use_graph=0, check_every=1,
+                       cycle_switch=0, nu_pre=nu, nu_post=nu, prolongation=tri,
+                       direction_fp64=int(dir64) if prec else 0)
+    prec_idx = 1 if prec else 0
+    kp = kernel_pass(fld, torch, p, kprm, E, 2, prec_idx, dir64)
+    it_mean = out["iters_per_step"]
+    sb = kp.pop("_fixed_b") + kp.pop("_iter_b") / max(kp["survey_iters"], 1) * it_mean
+    out.update(kp)
+    out["step_bytes_per_cell"] = sb / cells
+    out["step_GBps"] = sb * steps / sec / 1e9
+    del E
+    torch.cuda.empty_cache()
+    return out
+
+
+def oracle_sample(p, threads, iters):
+    """The oracle on step 1 of the workload (its E^0): the assembly alone
+    (limiter, operator, b, diagonal: a Jacobi-PCG call with no iteration),
+    then the assembly and `iters` iterations, on `threads` host threads
+    (1: the serial build).  Returns the assembly time and the time per
+    iteration."""
+    import oracle
+    En = p["E"].detach().cpu().numpy()
+    Kh = p["kappa"].detach().cpu().numpy()
+    Hh = p["eta"].detach().cpu().numpy()
+    dmax, rmin = oracle.limits(p["c"], p["L_unit"])
+    par = threads > 1
+    used = oracle.threads(threads) if par else 1
+    O = oracle.Problem(En, Kh, Hh, p["h"], p["c"], dmax, rmin, p["dt"], parallel=par)
     t0 = time.perf_counter()
-    _, st, it, rel = O.solve(tol=1e-8, max_iter=1000)
-    sec = time.perf_counter() - t0
-    cpu = "unknown"
+    O.solve(tol=1e-8, max_iter=0)
+    t_asm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, _, it, _ = O.solve(tol=1e-8, max_iter=iters)
+    t_k = time.perf_counter() - t0
+    return t_asm, max(t_k - t_asm, 0.0) / max(it, 1), it, used
+
+
+def recorded_oracle_iterations(n):
+    path = os.path.join(ROOT, "oracle", f"reionization_{n}_iterations.txt")
     try:
-        with open("/proc/cpuinfo") as f:
+        with open(path) as f:
             for line in f:
-                if line.startswith("model name"):
-                    cpu = line.split(":", 1)[1].strip()
-                    break
+                if line.startswith("step1_iterations"):
+                    return int(line.split("=", 1)[1])
     except OSError:
         pass
-    return {"value": p["E"].size / sec / 1e6, "unit": "Mcell-updates/s",
-            "cores": 1, "kind": "oracle",
-            "sample": f"one {p['shape'][0]}^3 step (limiter assembly + Jacobi-PCG "
-                      f"to 1e-8, {it} iterations, {sec:.1f} s), single thread",
-            "host_cpu": cpu, "host_threads": os.cpu_count()}
+    return None
 
 
-_CPU_PROBLEM = None
+def cpu_baselines(p, args):
+    """The oracle timed on the host cores on a bounded sample of step 1 of the
+    workload: all cores (the host share of one GPU, 16, via the OpenMP build
+    of the same source) and one core (the serial build), each extrapolated
+    from its assembly and per-iteration times to the Jacobi-PCG iteration
+    count the oracle needs for 1e-8 on this step (recorded by
+    oracle/record_iterations.py)."""
+    n = p["shape"][0]
+    need = recorded_oracle_iterations(n)
+    cells = int(p["E"].numel())
+    cpu = host_cpu()
+    out = {}
+    for key, thr, k in (("all", min(16, os.cpu_count() or 1), args.cpu_iters),
+                        ("single", 1, 1)):
+        log(f"[bench] timing the oracle on {thr} thread(s): assembly + {k} iteration(s)")
+        t_asm, t_it, done, used = oracle_sample(p, thr, k)
+        rec = {"unit": "Mcell-updates/s", "cores": used, "kind": "oracle",
+               "host_cpu": cpu, "assembly_s": round(t_asm, 3),
+               "s_per_iteration": round(t_it, 4)}
+        if need:
+            t_step = t_asm + need * t_it
+            rec["value"] = round(cells / t_step / 1e6, 4)
+            rec["sample"] = (f"step 1 of the {n}^3 share: the oracle's assembly "
+                             f"({t_asm:.1f} s) and {done} of the {need} Jacobi-PCG "
+                             f"iterations its 1e-8 solve takes ({t_it:.2f} s each) "
+                             f"timed on {used} thread(s); the step time "
+                             f"{t_step:.0f} s is extrapolated from them")
+            rec["extrapolated"] = True
+        else:
+            rec["value"] = None
+            rec["sample"] = "no recorded oracle iteration count for this grid"
+        out[key] = rec
+    return out
 
 
-def _oracle_step_seconds(_):
-    import oracle
-    p = _CPU_PROBLEM
-    dmax, rmin = oracle.limits(p["c"], p["L_unit"])
-    O = oracle.Problem(p["E"], p["kappa"], p["eta"], p["h"], p["c"], dmax, rmin,
-                       p["dt"], p["theta"], p["a"], p["adot"])
+def secondary(fld, torch, synth, args):
+    """The 256^3 many-source workload (10 steps from its initial state, both
+    forms) and the 32^3 single-source latency (FP64 V(2,2), >= 200 reps)."""
+    import numpy as np
+    res = {}
+    p = synth.many_sources(256)
+    q = dict(p)
+    for k in ("E", "kappa", "eta"):
+        q[k] = torch.from_numpy(p[k]).cuda()
+    c2 = {}
+    for name, prec in (("mixed", fld.FLD_PREC_MIXED), ("fp64", fld.FLD_PREC_FP64)):
+        prm = form_params(fld, q, prec, args)
+        S, E, recs, lat, sec = time_steps(fld, torch, q, prm, 10, args.warmup)
+        S.close()
+        c2[name] = {"mcell_updates_per_s": round(256 ** 3 * 10 / sec / 1e6, 2),
+                    "ms_per_step": round(1e3 * sec / 10, 3),
+                    "latency_ms": {"p50": round(float(np.percentile(np.array(lat) * 1e3, 50)), 3),
+                                   "p99": round(float(np.percentile(np.array(lat) * 1e3, 99)), 3)},
+                    "iters_per_step": float(np.mean([r["iters"] for r in recs])),
+                    "max_rel_resid": float(max(r["rel_resid"] for r in recs))}
+        log(f"[bench] secondary many_sources_256^3 {name}: {c2[name]}")
+        del S, E
+    res["many_sources_256^3"] = c2
+    del q
+    torch.cuda.empty_cache()
+    p = synth.single_source(32)
+    prm = fld.fld_default_params(p["c"], p["L_unit"], mg_levels=4, nu_pre=2, nu_post=2,
+                                 use_graph=args.graph, warm_start=1)
+    S = fld.Solver(p["shape"], p["h"], prm)
+    E0 = torch.from_numpy(p["E"]).cuda()
+    K = torch.from_numpy(p["kappa"]).cuda()
+    H = torch.from_numpy(p["eta"]).cuda()
+    E = E0.clone()
+    lat, rel = [], []
+    for r in range(args.warmup + max(args.reps, 200)):
+        E.copy_(E0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = S.step(E, K, H, p["dt"])
+        t1 = time.perf_counter()
+        if r >= args.warmup:
+            lat.append(t1 - t0)
+            rel.append(st["rel_resid"])
+    S.close()
+    lat_ms = np.array(lat) * 1e3
+    res["single_source_32^3"] = {
+        "precision": "fp64", "cycle": "V(2,2)", "levels": 4, "reps": len(lat),
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 4)},
+        "mcell_updates_per_s": round(32 ** 3 / float(np.mean(lat)) / 1e6, 2),
+        "max_rel_resid": float(max(rel))}
+    log(f"[bench] secondary single_source_32^3: {res['single_source_32^3']}")
+    return res
+
+
+def headline(args, fld, torch, synth):
+    n = args.n or 640
+    steps = args.steps or 20
+    if args.copy_probe:
+        # y = x + 0 over 2^28 doubles: one kernel reading 2 GiB and writing 2 GiB
+        x = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+        y = x.add(0.0)
+        torch.cuda.synchronize()
+        del x, y
+    log(f"[bench] generating the {n}^3 reionization share on the GPU")
     t0 = time.perf_counter()
-    O.solve(tol=1e-8, max_iter=1000)
-    return time.perf_counter() - t0
-
-
-def cpu_baseline_all_cores(p, procs):
-    """The same oracle step solved by `procs` single-threaded processes at
-    once, one per host core (the oracle itself is serial); forked before the
-    GPU is touched.  Throughput = procs x cells / the slowest process."""
-    import multiprocessing as mp
-    global _CPU_PROBLEM
-    _CPU_PROBLEM = p
-    with mp.get_context("fork").Pool(procs) as pool:
-        secs = pool.map(_oracle_step_seconds, range(procs))
-    _CPU_PROBLEM = None
-    return {"value": procs * p["E"].size / max(secs) / 1e6,
-            "unit": "Mcell-updates/s", "cores": procs, "kind": "oracle",
-            "sample": f"{procs} concurrent single-threaded solves of the same "
-                      f"{p['shape'][0]}^3 step to 1e-8 ({max(secs):.1f} s for "
-                      f"the slowest)"}
+    p = synth.t_reionization_share(n=n, n_src=int(round(10000 * (n / 640) ** 3)),
+                                   device="cuda")
+    torch.cuda.synchronize()
+    log(f"[bench]   generated in {time.perf_counter() - t0:.1f} s; ionized "
+        f"(x_HI = 1e-4) volume {p['ionized_fraction']:.4f}")
+    cpu = None
+    if not args.no_cpu_baseline and not args.copy_probe:
+        cpu = cpu_baselines(p, args)
+    forms = {}
+    for name in args.forms.split(","):
+        forms[name] = run_form_headline(fld, torch, p, name, args, steps)
+        log(f"[bench] {name}: " + json.dumps(
+            {k: v for k, v in forms[name].items() if k not in ("survey_ms",)}))
+    head = forms.get("mixed") or forms[list(forms)[0]]
+    head_name = "mixed" if "mixed" in forms else list(forms)[0]
+    copy_bw = copy_bandwidth(torch)
+    log(f"[bench] streaming copy: {copy_bw:.0f} GB/s")
+    wl = f"reionization_share_{n}"
+    tform = "fp64" if head_name == "fp64" else (
+        "mixed_dir64" if head["direction"] == "fp64" else "mixed")
+    roof = {
+        "bound": "hbm",
+        "kernel": head["dominant"],
+        "achieved": round(head["dominant_GBps"], 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(head["dominant_GBps"] / HBM_PEAK_GBS, 4),
+        "traffic": measured_traffic(head["dominant"], tform, wl),
+        "bytes_per_cell": head["dominant_bytes_per_cell"],
+        "avg_launch_ms": round(head["dominant_avg_ms"], 4),
+    }
+    sec = None if args.no_secondary else secondary(fld, torch, synth, args)
+    fp64 = forms.get("fp64")
+    out = {
+        "metric": "FLD solve Mcell-updates/s + % HBM roofline at 1e-8 residual; "
+                  "p50/p99 solve latency",
+        "value": round(head["mcell_updates_per_s"], 2),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32" if head_name.startswith("mixed") else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"reionization_share_{n}^3", "grid": [n] * 3,
+                   "sources": int(round(10000 * (n / 640) ** 3)), "sigma_ln": 2.0,
+                   "levels": 6, "rtol": 1e-8, "precision": head_name,
+                   "direction": head["direction"],
+                   "start": "E^0 = 1e-45 erg/cm^3, all steps timed",
+                   "warm_start": ("off", "extrapolated", "galerkin")[args.warm_start],
+                   "steps_per_run": steps},
+        "latency_ms": {k: round(v, 3) for k, v in head["latency_ms"].items()},
+        "roofline": roof,
+        "step_roofline": {
+            "bytes_per_cell": round(head["step_bytes_per_cell"], 1),
+            "achieved": round(head["step_GBps"], 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(head["step_GBps"] / HBM_PEAK_GBS, 4)},
+        "hbm_copy_GBps": round(copy_bw, 1),
+        "cpu_baseline": cpu["all"] if cpu else None,
+        "cpu_baseline_single_core": cpu["single"] if cpu else None,
+        "speedup_vs_fp64": (round(head["mcell_updates_per_s"] / fp64["mcell_updates_per_s"], 3)
+                            if fp64 and head is not fp64 else None),
+        "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) and "resid" not in kk
+                           and "bound" not in kk else vv)
+                      for kk, vv in v.items()} for k, v in forms.items()},
+        "secondary": sec,
+    }
+    return out
 
 
 def main():
@@ -426,84 +717,19 @@ def main():
               "has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
+
     import paper_1306_0645_amd as fld
     import synth
 
-    if args.workload != "many_sources":
+    if args.workload == "reionization":
+        out = headline(args, fld, torch, synth)
+    else:
         import bench_workloads
+        if args.steps is None:
+            args.steps = 10
+        if args.n is None:
+            args.n = 256
         out = getattr(bench_workloads, args.workload)(args, fld, torch, synth, log)
-        print(json.dumps(out), flush=True)
-        return
-
-    if args.copy_probe:
-        # y = x + 0 over 2^28 doubles: one kernel reading 2 GiB and writing 2 GiB
-        x = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
-        y = x.add(0.0)
-        torch.cuda.synchronize()
-        del x, y
-    log(f"[bench] generating the {args.n}^3 many-source workload")
-    p = synth.many_sources(args.n)
-    cpu_all = None
-    if not args.no_cpu_baseline and not args.copy_probe:
-        # the host share of one GPU is 16 cores, whatever os.cpu_count() says
-        procs = max(1, min(16, os.cpu_count() or 1))
-        log(f"[bench] timing the oracle on {procs} cores (before the GPU starts)")
-        cpu_all = cpu_baseline_all_cores(p, procs)
-    forms = {}
-    for name in args.forms.split(","):
-        prec = fld.FLD_PREC_MIXED if name == "mixed" else fld.FLD_PREC_FP64
-        log(f"[bench] form {name}: {args.warmup} warmup + {args.steps} timed steps")
-        forms[name] = run_form(fld, torch, p, prec, args.steps, args.warmup, args)
-        log(f"[bench] {name}: {json.dumps(forms[name])}")
-    head = forms.get("mixed") or forms[list(forms)[0]]
-    copy_bw = copy_bandwidth(torch)
-    log(f"[bench] streaming copy: {copy_bw:.0f} GB/s")
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("[bench] timing the oracle on one step")
-        cpu = cpu_baseline(p)
-    roof = {
-        "bound": "hbm",
-        "kernel": head["dominant"],
-        "achieved": round(head["dominant_GBps"], 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(head["dominant_GBps"] / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(head["dominant"],
-                                    "mixed" if "mixed" in forms else "fp64"),
-    }
-    out = {
-        "metric": "FLD solve Mcell-updates/s + % HBM roofline at 1e-8 residual; "
-                  "p50/p99 solve latency",
-        "value": round(head["mcell_updates_per_s"], 2),
-        "unit": "Mcell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(head["ms_per_step"], 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64+f32" if "mixed" in forms else "f64",
-        "data": "synthetic",
-        "config": {"workload": f"many_sources_{args.n}^3", "grid": [args.n] * 3,
-                   "sources": 64, "sigma_ln": 1.5, "rtol": 1e-8,
-                   "precision": "mixed" if "mixed" in forms else "fp64",
-                   "smoother": ("red/black Gauss-Seidel", "weighted Jacobi")[args.smoother],
-                   "warm_start": ("off", "extrapolated",
-                                  "galerkin")[args.warm_start],
-                   "steps_per_run": args.steps},
-        "roofline": roof,
-        "step_roofline": {
-            "bytes_per_cell": round(head["step_bytes_per_cell"], 1),
-            "achieved": round(head["step_GBps"], 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(head["step_GBps"] / HBM_PEAK_GBS, 4)},
-        "hbm_copy_GBps": round(copy_bw, 1),
-        "cpu_baseline": cpu,
-        "cpu_baseline_all_cores": cpu_all,
-        "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
-                      for kk, vv in v.items()} for k, v in forms.items()},
-    }
     print(json.dumps(out), flush=True)
 
 

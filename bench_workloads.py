@@ -1,9 +1,9 @@
-"""Workloads of bench.py beyond the default 256^3 many-source run.
+"""Workloads of bench.py beyond the default 640^3 reionization share.
 
+many_sources   256^3, 64 sources, both forms, successive steps from the
+               initial state, each form checked by the oracle at every cell
 single_source  32^3, one source, FP64 V(2,2) 4 levels: latency p50/p99 of
                one step over many repetitions (fields cache-resident)
-reionization   one 640^3 share of a 3200^3 box with ionized bubbles around
-               10^4 sources, mixed precision, 6 levels, successive steps
 batch          96 independent problems of 32..128^3 in one batched step,
                autotuned, against the same problems solved one by one
 served         Poisson stream of 64..384^3 requests of 1-5 steps through the
@@ -115,73 +115,39 @@ def single_source(args, fld, torch, synth, log):
          "dominant": dom})
 
 
-def reionization(args, fld, torch, synth, log):
-    from bench import BYTES_PER_CELL
-    n = args.n if args.n != 256 else 640
-    log(f"[bench] generating the {n}^3 reionization share on the GPU")
-    t0 = time.perf_counter()
-    p = synth.t_reionization_share(n=n, device="cuda")
-    torch.cuda.synchronize()
-    log(f"[bench]   generated in {time.perf_counter() - t0:.1f} s; "
-        f"ionized fraction {float((p['kappa'] < 1e-22).double().mean()):.4f}")
-    prm = fld.fld_default_params(p["c"], p["L_unit"], precision=fld.FLD_PREC_MIXED,
-                                 mg_levels=6, use_graph=args.graph,
-                                 cycle_switch=args.cycle_switch,
-                                 prolongation=args.prolongation,
-                                 warm_start=args.warm_start)
-    S = fld.Solver(p["shape"], p["h"], prm)
-    E, K, H = p["E"], p["kappa"], p["eta"]
-    steps = args.steps if args.steps != 10 else 20
-    for w in range(args.warmup):
-        st = S.step(E, K, H, p["dt"])
-        log(f"[bench]   warmup step {w}: iters {st['iters']} rel {st['rel_resid']:.2e}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters, rel = [], []
-    for k in range(steps):
-        st = S.step(E, K, H, p["dt"])
-        iters.append(st["iters"])
-        rel.append(st["rel_resid"])
-        if k % 5 == 4:
-            log(f"[bench]   step {k + 1}/{steps}: iters {st['iters']}")
-    torch.cuda.synchronize()
-    sec = time.perf_counter() - t0
-    cycle_nu, cycle_tri = st["cycle_nu"], st["trilinear"]
-    S.close()
-    # kernel pass on a handle without graph replay (a replayed graph hides
-    # its kernels from the timing hook), in the cycle the timed steps ended
-    # with: survey one step, then time the dominant kernel over two more
-    P = fld.Solver(p["shape"], p["h"], fld.fld_default_params(
-        p["c"], p["L_unit"], precision=fld.FLD_PREC_MIXED, mg_levels=6,
-        use_graph=0, nu_pre=cycle_nu, nu_post=cycle_nu, cycle_switch=0,
-        prolongation=cycle_tri, check_every=1))
-    names, totals = _survey(fld, lambda: P.step(E, K, H, p["dt"]))
-    dom = _dominant(fld, names, totals, E.numel(), BYTES_PER_CELL, 1)
-    dom_id = names.index(dom)
-    fld.fld_profile_select(dom_id)
-    for _ in range(2):
-        P.step(E, K, H, p["dt"])
-    torch.cuda.synchronize()
-    ms_tot, launches = fld.fld_profile_read(dom_id)
-    fld.fld_profile_select(-1)
-    P.close()
-    cells = E.numel()
-    avg_ms = ms_tot / max(launches, 1)
-    achieved = BYTES_PER_CELL[dom][1] * cells / (avg_ms * 1e-3) / 1e9
+def many_sources(args, fld, torch, synth, log):
+    """The 256^3 many-source workload: 64 sources, sigma_ln 1.5, smooth E^n,
+    `steps` successive steps from the initial state in both forms, each
+    form's extra step checked by the oracle at every cell."""
+    import bench
+    n = args.n
+    log(f"[bench] generating the {n}^3 many-source workload")
+    p = synth.many_sources(n)
+    q = dict(p)
+    for k in ("E", "kappa", "eta"):
+        q[k] = torch.from_numpy(p[k]).cuda()
+    forms = {}
+    for name in args.forms.split(","):
+        forms[name] = bench.run_form_headline(fld, torch, q, name, args, args.steps,
+                                              levels=0)
+        log(f"[bench] {name}: " + json.dumps(
+            {k: v for k, v in forms[name].items() if k != "survey_ms"}))
+    head_name = "mixed" if "mixed" in forms else list(forms)[0]
+    head = forms[head_name]
+    tform = "fp64" if head_name == "fp64" else (
+        "mixed_dir64" if head["direction"] == "fp64" else "mixed")
     return _base(
-        "one 640^3 share of a 3200^3 box; inputs resident in HBM",
-        cells * steps / sec / 1e6, 1e3 * sec / steps, steps, args.warmup,
-        "f64+f32",
-        {"workload": f"reionization_share_{n}^3", "grid": [n] * 3,
-         "sources": 10000, "sigma_ln": 2.0, "levels": 6, "precision": "mixed",
-         "rtol": 1e-8, "steps_per_run": steps, "final_cycle_nu": cycle_nu,
-         "final_trilinear": cycle_tri},
-        {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-         "traffic": None},
-        {"iters_per_step": float(np.mean(iters)), "max_rel_resid": max(rel),
-         "survey_ms": {k: round(v, 3) for k, v in sorted(
-             totals.items(), key=lambda kv: -kv[1]) if v > 0}})
+        "256^3 many-source workload; inputs resident in HBM",
+        head["mcell_updates_per_s"], head["ms_per_step"], args.steps, args.warmup,
+        "f64+f32" if head_name.startswith("mixed") else "f64",
+        {"workload": f"many_sources_{n}^3", "grid": [n] * 3, "sources": 64,
+         "sigma_ln": 1.5, "rtol": 1e-8, "precision": head_name,
+         "direction": head["direction"], "steps_per_run": args.steps},
+        {"bound": "hbm", "kernel": head["dominant"],
+         "achieved": round(head["dominant_GBps"], 1), "peak": HBM_PEAK_GBS,
+         "unit": "GB/s", "frac": round(head["dominant_GBps"] / HBM_PEAK_GBS, 4),
+         "traffic": bench.measured_traffic(head["dominant"], tform, f"many_sources_{n}")},
+        {"latency_ms": head["latency_ms"], "forms": forms})
 
 
 def _batch_problems(synth, torch, nprob):

@@ -68,12 +68,12 @@ typedef enum fld_status {
 
 typedef enum fld_precision {
   FLD_PREC_FP64 = 0,  /* FP64 everywhere: PCG with a symmetric FP64 V-cycle */
-  FLD_PREC_MIXED = 1  /* FP32 V-cycle (smoother, transfers, residuals);
-                         its output z and the search direction p stored in
-                         FP32, each with a per-problem scale; x, r, q, the
-                         operator, the SpMV, the outer residual, refinement
-                         and the coarsest solve in FP64; flexible
-                         (Polak-Ribiere) PCG */
+  FLD_PREC_MIXED = 1  /* FP32 V-cycle (smoother, transfers, residuals)
+                         whose output z is kept in FP32 at a per-problem
+                         scale; x, r, q, the search direction p (unless
+                         direction_fp64 = 0), the operator, the SpMV, the
+                         outer residual, refinement and the coarsest solve in
+                         FP64; flexible (Polak-Ribiere) PCG */
 } fld_precision;
 
 /* Multigrid smoother (Sec. 3.3 names red/black Gauss-Seidel sweeps). */
@@ -123,8 +123,12 @@ typedef struct fld_params {
                           third of it and the handle switches back.  The
                           switched cycle is V(1,1) with trilinear correction
                           in mixed precision with prolongation = 2 when the
-                          largest grid has at least 2^23 cells, else V(2,2).  0, or any other configured cycle: the cycle
-                          stays as configured.  Default 12 */
+                          largest grid has at least 2^23 cells, else V(2,2);
+                          an FP64 handle whose largest grid has at least 2^23
+                          cells does not switch (its fused V(1,1) iteration
+                          costs less than half a V(2,2) one).  0, or any
+                          other configured cycle: the cycle stays as
+                          configured.  Default 12 */
   int32_t prolongation;/* coarse-grid correction of the FP32 (mixed) cycle:
                           0 = piecewise constant, 1 = cell-centred trilinear,
                           2 = trilinear only while the handle is switched by
@@ -155,6 +159,21 @@ typedef struct fld_params {
                           each coarser one that still holds at least 2^20
                           cells; decided per problem, so that a problem's
                           result does not depend on its batch) */
+  int32_t coarse_op;   /* coarse face coefficients: 0 = coarse_scale times the
+                          sum of the 4 fine faces the coarse face covers; 1 =
+                          2 coarse_scale times the sum over the 4 fine rows
+                          that cross it of the three fine faces between the
+                          two coarse centres taken in series, 1 / (0.5/T_in +
+                          1/T_face + 0.5/T_in'), which follows the flux
+                          through a coarse cell that straddles an opacity
+                          jump.  Both give coarse_scale times the fine sum
+                          in a uniform medium and keep the coarse operator
+                          7-point and symmetric */
+  int32_t direction_fp64; /* mixed precision: 1 (default) = the PCG search
+                          direction p in FP64, so only the V-cycle (whose
+                          output z is FP32 at a per-problem scale) runs in
+                          FP32; 0 = p rounded to FP32 at the scale of the z it
+                          was formed from (8 B less per cell and iteration) */
 } fld_params;
 
 typedef struct fld_stats {
@@ -185,7 +204,7 @@ typedef struct fld_server fld_server;
  * coarse_scale = 0.5, max_dt_cuts = 8, graph replay on, cycle_switch = 12,
  * prolongation = 2 (trilinear in the mixed cycle once it has switched to
  * V(2,2)), warm_start = 2, tail_cells = 512, smoother = FLD_SMOOTH_RBGS,
- * fused_levels = 0. */
+ * fused_levels = 0, coarse_op = 0, direction_fp64 = 1. */
 void fld_default_params(fld_params *p, double c, double L_unit);
 
 const char *fld_strerror(fld_status s);

@@ -35,6 +35,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fld_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same source with OpenMP over its cell loops: only for timing the oracle
+# on all host cores (its reductions sum in another order)
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 OK, NOCONV, NONFINITE, BADARG = 0, 1, 2, 3
 
@@ -43,28 +46,40 @@ DMAX_FACTOR = 0.006
 RMIN_FACTOR = 1e-20
 
 
+def _compile(out, extra):
+    tmp = out + ".tmp"
+    subprocess.check_call(
+        ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math", *extra,
+         "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math)."""
+    """Compile the oracle with gcc (plain -O2, no fast-math), serially and
+    with OpenMP."""
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(
-            ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math",
-             "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+        _compile(_LIB, [])
+    if force or not os.path.exists(_LIB_OMP):
+        _compile(_LIB_OMP, ["-fopenmp"])
     return _LIB
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+def _load(parallel: bool = False):
+    """The serial library (every parity check) or, with parallel, the OpenMP
+    build (timing only)."""
+    lib = _libs.get(parallel)
+    if lib is None:
+        path = _LIB_OMP if parallel else _LIB
+        if not os.path.exists(path):
             build(force=True)
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(path)
         d, i, p = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
         i64 = ctypes.c_int64
+        lib.oracle_threads.restype = i
+        lib.oracle_threads.argtypes = [i]
         lib.oracle_face_limiter.restype = d
         lib.oracle_face_limiter.argtypes = [d] * 8
         lib.oracle_faces.restype = None
@@ -89,8 +104,13 @@ def _load():
                                     d, d, d, i, d, d, i, p]
         lib.oracle_chem_h.restype = None
         lib.oracle_chem_h.argtypes = [i64, p, p, p, p, d, i, d, d, d, d, d]
-        _lib = lib
-    return _lib
+        _libs[parallel] = lib
+    return lib
+
+
+def threads(n: int = 0) -> int:
+    """Threads of the OpenMP build (n > 0 sets them); the serial build uses 1."""
+    return int(_load(True).oracle_threads(int(n)))
 
 
 def _arr(x, shape=None):
@@ -139,7 +159,10 @@ class Problem:
     """One step's frozen data: E^n, kappa, eta, dt, a, adot and the constants."""
 
     def __init__(self, E, kappa, eta, h, c, d_max, r_min, dt, theta=1.0, a=1.0,
-                 adot=0.0):
+                 adot=0.0, parallel=False):
+        # parallel: run on the OpenMP build (timing only; parity uses the
+        # serial build)
+        self._lib = _load(parallel)
         self.E = _arr(E)
         self.kappa = _arr(kappa, self.E.shape)
         self.eta = _arr(eta, self.E.shape)
@@ -159,7 +182,7 @@ class Problem:
     def system(self):
         """(diag, Ax, Ay, Az, b): A_pp, -A_{p,p+e_d}, and the right-hand side."""
         outs = [np.empty_like(self.E) for _ in range(5)]
-        _load().oracle_system(*self._common(), _ptr(self.E), _ptr(self.kappa),
+        self._lib.oracle_system(*self._common(), _ptr(self.E), _ptr(self.kappa),
                               _ptr(self.eta), self.c, self.d_max, self.r_min,
                               self.theta, self.dt, self.a, self.adot,
                               *[_ptr(o) for o in outs])
@@ -168,7 +191,7 @@ class Problem:
     def apply_A(self, u):
         u = _arr(u, self.E.shape)
         out = np.empty_like(u)
-        _load().oracle_apply_A(*self._common(), _ptr(self.E), _ptr(self.kappa),
+        self._lib.oracle_apply_A(*self._common(), _ptr(self.E), _ptr(self.kappa),
                                self.c, self.d_max, self.r_min, self.theta,
                                self.dt, self.a, self.adot, _ptr(u), _ptr(out))
         return out
@@ -178,7 +201,7 @@ class Problem:
         dE = np.empty_like(self.E)
         it = ctypes.c_int(0)
         rr = ctypes.c_double(0.0)
-        st = _load().oracle_solve(*self._common(), _ptr(self.E), _ptr(self.kappa),
+        st = self._lib.oracle_solve(*self._common(), _ptr(self.E), _ptr(self.kappa),
                                   _ptr(self.eta), self.c, self.d_max,
                                   self.r_min, self.theta, self.dt, self.a,
                                   self.adot, tol, max_iter, _ptr(dE),
@@ -191,7 +214,7 @@ class Problem:
         cells = np.ascontiguousarray(cells, dtype=np.int64)
         res = np.empty(cells.shape, dtype=np.float64)
         rhs = np.empty(cells.shape, dtype=np.float64)
-        _load().oracle_residual_at(*self._common(), _ptr(self.E),
+        self._lib.oracle_residual_at(*self._common(), _ptr(self.E),
                                    _ptr(self.kappa), _ptr(self.eta), self.c,
                                    self.d_max, self.r_min, self.theta, self.dt,
                                    self.a, self.adot, _ptr(x), _ptr(cells),

@@ -52,6 +52,30 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* The same source builds serially (liboracle.so, used for every parity check)
+ * and with OpenMP over the cell loops (liboracle_omp.so, used only to time
+ * the oracle on all host cores).  The parallel build sums its reductions in
+ * another order, so its results agree with the serial ones to rounding only. */
+#ifdef _OPENMP
+#include <omp.h>
+#define OR_FOR _Pragma("omp parallel for schedule(static)")
+#define OR_FOR_SUM_S _Pragma("omp parallel for schedule(static) reduction(+:s)")
+#else
+#define OR_FOR
+#define OR_FOR_SUM_S
+#endif
+
+/* Threads the cell loops run on (1 in the serial build); n > 0 sets it. */
+int oracle_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
 /* status codes returned by the oracle (its own numbering) */
 #define OR_OK 0
 #define OR_NOCONV 1
@@ -87,6 +111,7 @@ double oracle_face_limiter(double E1, double E2, double k1, double k2,
 void oracle_faces(int nx, int ny, int nz, double dx, double dy, double dz,
                   const double *E, const double *kappa, double c, double d_max,
                   double r_min, double *Dx, double *Dy, double *Dz) {
+  OR_FOR
   for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
@@ -110,6 +135,7 @@ void oracle_apply_L(int nx, int ny, int nz, double dx, double dy, double dz,
                     const double *kappa, double c, double adot_over_a,
                     const double *u, double *out) {
   double ix2 = 1.0 / (dx * dx), iy2 = 1.0 / (dy * dy), iz2 = 1.0 / (dz * dz);
+  OR_FOR
   for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
@@ -138,6 +164,7 @@ static void sys_apply_A(const or_system *s, const double *u, double *Lu,
   int64_t n = (int64_t)s->nx * s->ny * s->nz;
   oracle_apply_L(s->nx, s->ny, s->nz, s->dx, s->dy, s->dz, s->Dx, s->Dy, s->Dz,
                  s->kappa, s->c, s->adot_over_a, u, Lu);
+  OR_FOR
   for (int64_t p = 0; p < n; ++p) out[p] = u[p] - s->theta * s->dt * Lu[p];
 }
 
@@ -146,6 +173,7 @@ static void sys_diag(const or_system *s, double *d) {
   double ix2 = 1.0 / (s->dx * s->dx), iy2 = 1.0 / (s->dy * s->dy),
          iz2 = 1.0 / (s->dz * s->dz);
   int nx = s->nx, ny = s->ny, nz = s->nz;
+  OR_FOR
   for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
@@ -160,6 +188,7 @@ static void sys_diag(const or_system *s, double *d) {
 
 static double dot(const double *a, const double *b, int64_t n) {
   double s = 0.0;
+  OR_FOR_SUM_S
   for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
   return s;
 }
@@ -177,6 +206,7 @@ static int sys_pcg(const or_system *s, const double *b, double *x, double tol,
   double *Lw = malloc(n * sizeof(double)), *d = malloc(n * sizeof(double));
   int status = OR_NOCONV;
   sys_diag(s, d);
+  OR_FOR
   for (int64_t i = 0; i < n; ++i) { x[i] = 0.0; r[i] = b[i]; }
   double bb = dot(b, b, n);
   double rr = bb;
@@ -186,17 +216,21 @@ static int sys_pcg(const or_system *s, const double *b, double *x, double tol,
   if (bb == 0.0) { status = OR_OK; goto done; }
   double rz_old = 0.0;
   for (int it = 0; it < max_iter; ++it) {
+    OR_FOR
     for (int64_t i = 0; i < n; ++i) z[i] = r[i] / d[i];
     double rz = dot(r, z, n);
     if (it == 0) {
+      OR_FOR
       for (int64_t i = 0; i < n; ++i) p[i] = z[i];
     } else {
       double beta = rz / rz_old;
+      OR_FOR
       for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
     }
     rz_old = rz;
     sys_apply_A(s, p, Lw, q);
     double alpha = rz / dot(p, q, n);
+    OR_FOR
     for (int64_t i = 0; i < n; ++i) {
       x[i] += alpha * p[i];
       r[i] -= alpha * q[i];
@@ -239,6 +273,7 @@ static void sys_rhs(const or_system *s, const double *E, const double *eta,
   int64_t n = (int64_t)s->nx * s->ny * s->nz;
   oracle_apply_L(s->nx, s->ny, s->nz, s->dx, s->dy, s->dz, s->Dx, s->Dy, s->Dz,
                  s->kappa, s->c, s->adot_over_a, E, b);
+  OR_FOR
   for (int64_t p = 0; p < n; ++p) b[p] = s->dt * (b[p] + eta[p]);
 }
 
@@ -317,6 +352,7 @@ void oracle_residual_at(int nx, int ny, int nz, double dx, double dy, double dz,
   double hd[3] = {a * dx, a * dy, a * dz};
   double h2[3] = {hd[0] * hd[0], hd[1] * hd[1], hd[2] * hd[2]};
   double aa = adot / a;
+  OR_FOR
   for (int64_t t = 0; t < ncells; ++t) {
     int64_t p = cells[t];
     int i = (int)(p % nx), j = (int)((p / nx) % ny), k = (int)(p / ((int64_t)nx * ny));

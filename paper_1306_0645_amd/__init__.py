@@ -57,7 +57,8 @@ class Params(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("fused_tile_z", ctypes.c_int32),
                 ("cycle_switch", ctypes.c_int32), ("prolongation", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("tail_cells", ctypes.c_int32),
-                ("smoother", ctypes.c_int32), ("fused_levels", ctypes.c_int32)]
+                ("smoother", ctypes.c_int32), ("fused_levels", ctypes.c_int32),
+                ("coarse_op", ctypes.c_int32), ("direction_fp64", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

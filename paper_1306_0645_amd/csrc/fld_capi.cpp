@@ -80,6 +80,8 @@ void fld_default_params(fld_params *p, double c, double L_unit) {
   p->warm_start = 2;
   p->tail_cells = 512;
   p->smoother = FLD_SMOOTH_RBGS;
+  p->coarse_op = 0;
+  p->direction_fp64 = 1;
 }
 
 const char *fld_strerror(fld_status s) {

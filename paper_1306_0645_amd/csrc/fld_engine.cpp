@@ -46,6 +46,8 @@ bool params_ok(const fld_params &p) {
   if (p.prolongation < 0 || p.prolongation > 2) return false;
   if (p.smoother != FLD_SMOOTH_RBGS && p.smoother != FLD_SMOOTH_JACOBI) return false;
   if (p.fused_levels < 0 || p.fused_levels > kMaxLevels) return false;
+  if (p.coarse_op < 0 || p.coarse_op > 1) return false;
+  if (p.direction_fp64 < 0 || p.direction_fp64 > 1) return false;
   return true;
 }
 
@@ -180,7 +182,7 @@ void carve_problem(Carver &cv, const Hier &h, const fld_params &p, ProbMem &m) {
       P.r = cv.take<double>(n);
       if (mixed) P.z32 = cv.take<float>(n);
       else P.z = cv.take<double>(n);
-      if (mixed) {
+      if (mixed && !p.direction_fp64) {
         P.pf0 = cv.take<float>(n);
         P.pf1 = cv.take<float>(n);
       } else {
@@ -486,6 +488,18 @@ int Engine::set_switched(bool on) {
   return release_graph();
 }
 
+// In FP64 the switched cycle is V(2,2), whose per-half-sweep kernels cost
+// more than twice the fused V(1,1) passes on a grid that fills the GPU: on
+// the 640^3 reionization share (FP64) V(1,1) took 34.6 iterations per step
+// at 508 ms against 19.5 at 773 ms after switching.  So an FP64 handle whose
+// largest grid has at least 2^23 cells keeps V(1,1).
+bool Engine::switch_helps() const {
+  if (mixed) return true;
+  long long big = 0;
+  for (const Hier &h : hier) big = std::max(big, h.cells(0));
+  return big < (1LL << 23);
+}
+
 int Engine::trilinear() const {
   return (mixed && (prm.prolongation == 1 || (prm.prolongation == 2 && switched)))
              ? 1 : 0;
@@ -497,7 +511,7 @@ int Engine::trilinear() const {
 // is kept as is.
 int Engine::adapt_cycle(int max_iters) {
   const int thr = prm.cycle_switch;
-  if (thr <= 0) return ST_OK;
+  if (thr <= 0 || !switch_helps()) return ST_OK;
   if (!switched && prm.nu_pre == 1 && prm.nu_post == 1 && max_iters > thr)
     return set_switched(true);
   if (switched && max_iters * 3 <= thr) return set_switched(false);
@@ -529,7 +543,7 @@ void Engine::fill_step(int p, const double *E, const double *kappa,
 void Engine::enqueue_assemble(const ListSet &ls) {
   launch_assemble(T, ls.fine, prm.c, prm.theta, prm.d_max, prm.r_min, mixed, stream);
   for (int l = 1; l < Lmax; ++l)
-    launch_coarsen(T, ls.exist[l], l, prm.coarse_scale, mixed, stream);
+    launch_coarsen(T, ls.exist[l], l, prm.coarse_scale, mixed, prm.coarse_op, stream);
   launch_fin(T, FIN_BB, mixed, stream);
   need_pro = true;
 }
@@ -633,7 +647,7 @@ void Engine::enqueue_iteration(const ListSet &ls) {
   if (lazy) {
     enqueue_fused_rest(ls);
     launch_fin(T, FIN_RZ, mixed, stream, 1);
-    launch_spmv_p(T, ls.fine, 1, mixed, stream);
+    launch_spmv_p(T, ls.fine, 1, kmode(), stream);
     launch_fin(T, FIN_PQ, mixed, stream, 1);
     launch_vdown(T, ls.fdn[0], 0, mixed, VD_CONT, stream);
     launch_fin(T, FIN_RR2, mixed, stream, 1);
@@ -641,9 +655,9 @@ void Engine::enqueue_iteration(const ListSet &ls) {
   }
   enqueue_vcycle(ls);
   launch_fin(T, FIN_RZ, mixed, stream, fused ? 1 : 0);
-  launch_spmv_p(T, ls.fine, 0, mixed, stream);
+  launch_spmv_p(T, ls.fine, 0, kmode(), stream);
   launch_fin(T, FIN_PQ, mixed, stream, 0);
-  launch_update(T, ls.fine, mixed, stream);
+  launch_update(T, ls.fine, kmode(), stream);
   launch_fin(T, FIN_RR, mixed, stream);
 }
 
@@ -659,7 +673,7 @@ void Engine::enqueue_prologue(const ListSet &ls) {
 // x += alpha p for problems that stopped iterating with that update pending
 // (fused form); keeps the host mirror in step
 void Engine::finish_x(const ListSet &ls) {
-  launch_xfix(T, ls.fine, mixed, stream);
+  launch_xfix(T, ls.fine, kmode(), stream);
   launch_fin(T, FIN_XFIX, mixed, stream);
   for (Scal &sc : h_sc)
     if (sc.xlag && sc.phase != PH_ITER) sc.xlag = 0;

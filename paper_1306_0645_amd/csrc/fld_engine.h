@@ -159,6 +159,10 @@ class Engine {
   void note_success(int p, double h);
   int upload_pd();
   int trilinear() const;
+  // finest-level Krylov storage (launch_spmv_p): 0 FP64, 1 mixed with an
+  // FP32 direction, 2 mixed with an FP64 direction
+  int kmode() const { return mixed ? (prm.direction_fp64 ? 2 : 1) : 0; }
+  bool switch_helps() const;
   // adaptive cycle choice after a solve that took max_iters iterations
   int adapt_cycle(int max_iters);
 

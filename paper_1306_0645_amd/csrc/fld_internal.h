@@ -50,10 +50,11 @@ struct LevelDev {
 struct ProbDev {
   int nx, ny, nz, n;
   double *x, *r, *q, *b;
-  double *z, *p0, *p1;   // FP64 form (null in the mixed form)
+  double *z;             // FP64 form (null in the mixed form)
+  double *p0, *p1;       // FP64 direction (FP64 form; mixed with direction_fp64)
   // mixed form: the V-cycle's FP32 output as it is, z = zscale * z32, and
-  // the search direction in FP32 at the scale of the z it was formed from,
-  // p = pscale * pf0 (or pf1)
+  // the search direction either in FP32 at the scale of the z it was formed
+  // from, p = pscale * pf0 (or pf1), or in FP64 in p0 / p1
   float *z32, *pf0, *pf1;
   // mixed form with trilinear prolongation possible: the finest level's
   // coarse-grid correction interpolated to every cell (k_tri_fine)
@@ -170,8 +171,10 @@ struct ProfScope {
 // prec: 0 = FP64 V-cycle, 1 = FP32 V-cycle.
 void launch_assemble(const Tables &T, TileList L0, double c, double theta,
                      double dmax, double rmin, int mixed, hipStream_t s);
+// op: 0 = coarse faces from the 4 fine faces they cover, 1 = from the fine
+// rows through them, three faces in series (k_coarsen)
 void launch_coarsen(const Tables &T, TileList coarse, int lc, double scale,
-                    int mixed, hipStream_t s);
+                    int mixed, int op, hipStream_t s);
 // alt: FIN_RZ and FIN_RR2 read the partials of the fused finest tiles; FIN_PQ
 // with alt marks the fused iteration's deferred updates
 void launch_fin(const Tables &T, int which, int mixed, hipStream_t s,
@@ -195,14 +198,17 @@ void launch_jacobi(const Tables &T, TileList L, int l, int prec, int mode,
 // x (or x2) = x + P e: the coarse-grid correction of every cell
 void launch_prolong_add(const Tables &T, TileList L, int l, int prec,
                         int trilinear, int to_x2, hipStream_t s);
+// Krylov storage of the finest level (Engine::kmode): 0 = FP64 z and p,
+// 1 = mixed form with FP32 z and p (each at a per-problem scale), 2 = mixed
+// form with FP32 z and an FP64 search direction p
 // lazy = 1 (fused iteration): also x += alpha p_old, the update deferred
-// from the previous iteration; prec = 1: mixed form (FP32 z and p)
-void launch_spmv_p(const Tables &T, TileList L0, int lazy, int prec, hipStream_t s);
+// from the previous iteration (mixed forms only)
+void launch_spmv_p(const Tables &T, TileList L0, int lazy, int km, hipStream_t s);
 // out = s * z32 right after a mixed-form V-cycle (the preconditioner alone)
 void launch_z_out(const Tables &T, TileList L0, double *out, hipStream_t s);
 // x += alpha p for problems that stopped iterating with the update pending
-void launch_xfix(const Tables &T, TileList L0, int prec, hipStream_t s);
-void launch_update(const Tables &T, TileList L0, int prec, hipStream_t s);
+void launch_xfix(const Tables &T, TileList L0, int km, hipStream_t s);
+void launch_update(const Tables &T, TileList L0, int km, hipStream_t s);
 void launch_true_resid(const Tables &T, TileList L0, hipStream_t s);
 void launch_warm_revert(const Tables &T, TileList L0, hipStream_t s);
 // x0 = c1 dE(n) + c2 dE(n-1), r = b - A x0 (Galerkin warm guesses)

@@ -194,12 +194,24 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
   write_sums(T.gpart, tid, sums);
 }
 
-// Coarse operator of level lc from level lc-1 (one thread per coarse cell):
-// coarse faces are coarse_scale times the sum of the 4 fine faces they cover,
-// the coarse "mass" (diagonal minus faces) is the sum of the 8 children's.
+// Coarse operator of level lc from level lc-1 (one thread per coarse cell).
+// The coarse "mass" (diagonal minus faces) is the sum of the 8 children's.
+// Coarse faces, op = 0: coarse_scale times the sum of the 4 fine faces they
+// cover.  op = 1: each of the 4 fine rows that cross the coarse face joins
+// the two coarse centres through three fine faces in series, half of the
+// inner face of each coarse cell and the whole face between them, so the row
+// conducts 1 / (0.5 / T_in + 1 / T_mid + 0.5 / T_in'); the coarse face is
+// 2 coarse_scale times the sum over the rows (for a uniform medium both rules
+// give coarse_scale times the 4 fine faces).  Either way a coarse face is the
+// same sum of the same terms for both cells it joins, so the coarse operator
+// is exactly symmetric.
+__device__ __forceinline__ double series3(double a, double b, double c) {
+  return 1.0 / (0.5 / a + 1.0 / b + 0.5 / c);
+}
+
 __global__ __launch_bounds__(kBlock) void k_coarsen(Tables T, TileList LC,
                                                     int lc, double scale,
-                                                    int mixed) {
+                                                    int mixed, int op) {
   const Tile t = get_tile(LC);
   const Scal &sc = T.sc[t.prob];
   if (!sc.live) return;
@@ -224,12 +236,36 @@ __global__ __launch_bounds__(kBlock) void k_coarsen(Tables T, TileList LC,
             const double fyp = F.Ty[n.c], fym = F.Ty[n.ym];
             const double fzp = F.Tz[n.c], fzm = F.Tz[n.zm];
             mass += F.diag[n.c] - (fxp + fxm + fyp + fym + fzp + fzm);
-            if (cx == 1) txp += fxp; else txm += fxm;
-            if (cy == 1) typ += fyp; else tym += fym;
-            if (cz == 1) tzp += fzp; else tzm += fzm;
+            if (op == 0) {
+              if (cx == 1) txp += fxp; else txm += fxm;
+              if (cy == 1) typ += fyp; else tym += fym;
+              if (cz == 1) tzp += fzp; else tzm += fzm;
+            } else {
+              // a child on the + side: its -face (inner), its +face (the
+              // coarse face) and the neighbour's +face; on the - side: the
+              // -face of the cell two below, its own -face and +face
+              if (cx == 1) {
+                txp += series3(fxm, fxp, F.Tx[n.xp]);
+              } else {
+                const int i2 = 2 * I >= 2 ? 2 * I - 2 : 2 * I - 2 + fx;
+                txm += series3(F.Tx[n.c - 2 * I + i2], fxm, fxp);
+              }
+              if (cy == 1) {
+                typ += series3(fym, fyp, F.Ty[n.yp]);
+              } else {
+                const int j2 = 2 * J >= 2 ? 2 * J - 2 : 2 * J - 2 + fy;
+                tym += series3(F.Ty[n.c + (j2 - 2 * J) * fx], fym, fyp);
+              }
+              if (cz == 1) {
+                tzp += series3(fzm, fzp, F.Tz[n.zp]);
+              } else {
+                const int k2 = 2 * K >= 2 ? 2 * K - 2 : 2 * K - 2 + fz;
+                tzm += series3(F.Tz[n.c + (long long)(k2 - 2 * K) * fx * fy], fzm, fzp);
+              }
+            }
           }
-      txp *= scale; txm *= scale; typ *= scale; tym *= scale; tzp *= scale;
-      tzm *= scale;
+      const double s2 = op == 0 ? scale : 2.0 * scale;
+      txp *= s2; txm *= s2; typ *= s2; tym *= s2; tzp *= s2; tzm *= s2;
       const double diag = mass + txp + txm + typ + tym + tzp + tzm;
       const int o = (K * C.ny + J) * C.nx + I;
       C.Tx[o] = txp;
@@ -738,28 +774,38 @@ __global__ __launch_bounds__(kTailBlock) void k_vtail(Tables T, int nu_pre,
 // registers.
 // LAZY: also x += alpha_old p_old at the cell (the fused iteration defers
 // that update of the previous iteration to here, where p_old is read anyway).
-// MX (mixed form): z, p_old and p_new are FP32 at a scale each (zs for z and
-// p_new, ps for p_old); p_new is rounded to FP32 before it is used, so q, the
-// dot and the later x update all see the direction that is stored.
-template <bool MX>
-using DirT = std::conditional_t<MX, float, double>;
+// Krylov storage modes (KM): KM_FP64: z and p FP64.  KM_MIX32 (mixed form):
+// z, p_old and p_new FP32 at a scale each (zs for z and p_new, ps for
+// p_old); p_new is rounded to FP32 before it is used, so q, the dot and the
+// later x update all see the direction that is stored.  KM_MIX64 (mixed form
+// with an FP64 direction): z FP32 at the scale zs (the V-cycle's output as
+// it is), p_old and p_new FP64.
+enum : int { KM_FP64 = 0, KM_MIX32 = 1, KM_MIX64 = 2 };
 
-template <bool BETA, bool LAZY, bool MX>
+template <int KM>
+using ZT = std::conditional_t<KM == KM_FP64, double, float>;
+template <int KM>
+using DirT = std::conditional_t<KM == KM_MIX32, float, double>;
+
+template <bool BETA, bool LAZY, int KM>
 __device__ __forceinline__ double spmv_column(
     const Tile &t, const Col &col, int nx, int ny, int nz, double beta,
-    const DirT<MX> *__restrict__ z, double zs, const DirT<MX> *__restrict__ po,
-    double ps, DirT<MX> *__restrict__ pn, double *__restrict__ q,
+    const ZT<KM> *__restrict__ z, double zs, const DirT<KM> *__restrict__ po,
+    double ps, DirT<KM> *__restrict__ pn, double *__restrict__ q,
     const double *__restrict__ Tx, const double *__restrict__ Ty,
     const double *__restrict__ Tz, const double *__restrict__ Dg,
     double alpha_old, double *__restrict__ x) {
-  using D = DirT<MX>;
-  const double cb = MX ? beta * ps / zs : beta;  // p_old's share, in z's scale
+  using D = DirT<KM>;
+  const double cb = KM == KM_MIX32 ? beta * ps / zs : beta;  // p_old's share, in z's scale
   auto raw = [&](int g) -> D {  // p_new as stored
-    if constexpr (MX) return BETA ? (float)((double)z[g] + cb * (double)po[g]) : z[g];
+    if constexpr (KM == KM_MIX32)
+      return BETA ? (float)((double)z[g] + cb * (double)po[g]) : z[g];
+    else if constexpr (KM == KM_MIX64)
+      return BETA ? zs * (double)z[g] + beta * po[g] : zs * (double)z[g];
     else return BETA ? z[g] + beta * po[g] : z[g];
   };
   auto val = [&](D v) -> double {  // its value
-    if constexpr (MX) return zs * (double)v;
+    if constexpr (KM == KM_MIX32) return zs * (double)v;
     else return v;
   };
   const int plane = nx * ny, i = col.i, j = col.j;
@@ -780,7 +826,7 @@ __device__ __forceinline__ double spmv_column(
     const double p_c = val(r_c);
     const double qq = Dg[c] * p_c - s;
     if constexpr (LAZY) {
-      if constexpr (MX) x[c] = x[c] + alpha_old * (ps * (double)po[c]);
+      if constexpr (KM == KM_MIX32) x[c] = x[c] + alpha_old * (ps * (double)po[c]);
       else x[c] = x[c] + alpha_old * po[c];
     }
     pn[c] = r_c;
@@ -794,9 +840,9 @@ __device__ __forceinline__ double spmv_column(
   return acc;
 }
 
-template <bool LAZY, bool MX>
+template <bool LAZY, int KM>
 __global__ __launch_bounds__(kBlock) void k_spmv_p(Tables T, TileList TL) {
-  using D = DirT<MX>;
+  using D = DirT<KM>;
   const int tid = get_tile_index(TL);
   const Tile t = TL.base[tid];
   const Scal &sc = T.sc[t.prob];
@@ -804,14 +850,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(Tables T, TileList TL) {
   const LevelDev L = T.lv[t.prob];
   const ProbDev P = T.pd[t.prob];
   const double beta = sc.beta, alpha = sc.alpha, zs = sc.zscale, ps = sc.pscale;
-  const D *z, *po;
+  const ZT<KM> *z;
+  const D *po;
   D *pn;
-  if constexpr (MX) {
-    z = P.z32;
+  if constexpr (KM == KM_FP64) z = P.z;
+  else z = P.z32;
+  if constexpr (KM == KM_MIX32) {
     po = sc.pbuf ? P.pf1 : P.pf0;
     pn = sc.pbuf ? P.pf0 : P.pf1;
   } else {
-    z = P.z;
     po = sc.pbuf ? P.p1 : P.p0;
     pn = sc.pbuf ? P.p0 : P.p1;
   }
@@ -819,13 +866,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(Tables T, TileList TL) {
   double pq = 0.0;
   if (col.on) {
     if (LAZY && sc.xlag)
-      pq = spmv_column<true, true, MX>(t, col, L.nx, L.ny, L.nz, beta, z, zs, po, ps,
+      pq = spmv_column<true, true, KM>(t, col, L.nx, L.ny, L.nz, beta, z, zs, po, ps,
                                        pn, P.q, L.Tx, L.Ty, L.Tz, L.diag, alpha, P.x);
     else if (beta != 0.0)
-      pq = spmv_column<true, false, MX>(t, col, L.nx, L.ny, L.nz, beta, z, zs, po, ps,
+      pq = spmv_column<true, false, KM>(t, col, L.nx, L.ny, L.nz, beta, z, zs, po, ps,
                                         pn, P.q, L.Tx, L.Ty, L.Tz, L.diag, 0.0, P.x);
     else
-      pq = spmv_column<false, false, MX>(t, col, L.nx, L.ny, L.nz, beta, z, zs, po,
+      pq = spmv_column<false, false, KM>(t, col, L.nx, L.ny, L.nz, beta, z, zs, po,
                                          ps, pn, P.q, L.Tx, L.Ty, L.Tz, L.diag, 0.0, P.x);
   }
   write_partials(T, tid, pq, 0.0);
@@ -846,15 +893,15 @@ __global__ __launch_bounds__(kBlock) void k_z_out(Tables T, TileList TL,
 }
 
 // the newest direction p at cell c (after FIN_PQ has swapped the buffers)
-template <bool MX>
+template <int KM>
 __device__ __forceinline__ double newest_p(const ProbDev &P, const Scal &sc, int c) {
-  if constexpr (MX) return sc.pscale * (double)(sc.pbuf ? P.pf1 : P.pf0)[c];
+  if constexpr (KM == KM_MIX32) return sc.pscale * (double)(sc.pbuf ? P.pf1 : P.pf0)[c];
   else return (sc.pbuf ? P.p1 : P.p0)[c];
 }
 
 // x += alpha p (the newest direction) for problems that stopped iterating
 // while the fused iteration's x update was still pending
-template <bool MX>
+template <int KM>
 __global__ __launch_bounds__(kBlock) void k_xfix(Tables T, TileList TL) {
   const Tile t = get_tile(TL);
   const Scal &sc = T.sc[t.prob];
@@ -867,11 +914,11 @@ __global__ __launch_bounds__(kBlock) void k_xfix(Tables T, TileList TL) {
   const int plane = L.nx * L.ny;
   int c = t.z0 * plane + col.j * L.nx + col.i;
   for (int k = 0; k < t.tz; ++k, c += plane)
-    P.x[c] = P.x[c] + alpha * newest_p<MX>(P, sc, c);
+    P.x[c] = P.x[c] + alpha * newest_p<KM>(P, sc, c);
 }
 
 // x += alpha p, r -= alpha q, partial ||r||^2
-template <bool MX>
+template <int KM>
 __global__ __launch_bounds__(kBlock) void k_update(Tables T, TileList TL) {
   const int tid = get_tile_index(TL);
   const Tile t = TL.base[tid];
@@ -889,7 +936,7 @@ __global__ __launch_bounds__(kBlock) void k_update(Tables T, TileList TL) {
     const int plane = L.nx * L.ny;
     int c = t.z0 * plane + col.j * L.nx + col.i;
     for (int k = 0; k < t.tz; ++k, c += plane) {
-      const double pc = newest_p<MX>(P, sc, c), qc = q[c], xc = x[c], rc = r[c];
+      const double pc = newest_p<KM>(P, sc, c), qc = q[c], xc = x[c], rc = r[c];
       x[c] = xc + alpha * pc;
       const double rn = rc - alpha * qc;
       r[c] = rn;
@@ -1478,8 +1525,8 @@ void launch_assemble(const Tables &T, TileList L0, double c, double theta,
 }
 
 void launch_coarsen(const Tables &T, TileList LC, int lc, double scale,
-                    int mixed, hipStream_t s) {
-  if (LC.nblocks) LAUNCH(K_COARSEN, k_coarsen, LC.nblocks, kBlock, s, T, LC, lc, scale, mixed);
+                    int mixed, int op, hipStream_t s) {
+  if (LC.nblocks) LAUNCH(K_COARSEN, k_coarsen, LC.nblocks, kBlock, s, T, LC, lc, scale, mixed, op);
 }
 
 void launch_fin(const Tables &T, int which, int mixed, hipStream_t s, int alt) {
@@ -1556,27 +1603,31 @@ void launch_vtail(const Tables &T, int prec, int nu_pre, int nu_post,
 }
 
 
-void launch_spmv_p(const Tables &T, TileList L0, int lazy, int prec, hipStream_t s) {
+void launch_spmv_p(const Tables &T, TileList L0, int lazy, int km, hipStream_t s) {
   if (!L0.nblocks) return;
-  if (lazy) LAUNCH(K_SPMV_PX, (k_spmv_p<true, true>), L0.nblocks, kBlock, s, T, L0);
-  else if (prec) LAUNCH(K_SPMV_P, (k_spmv_p<false, true>), L0.nblocks, kBlock, s, T, L0);
-  else LAUNCH(K_SPMV_P, (k_spmv_p<false, false>), L0.nblocks, kBlock, s, T, L0);
+  if (lazy && km == KM_MIX64) LAUNCH(K_SPMV_PX, (k_spmv_p<true, KM_MIX64>), L0.nblocks, kBlock, s, T, L0);
+  else if (lazy) LAUNCH(K_SPMV_PX, (k_spmv_p<true, KM_MIX32>), L0.nblocks, kBlock, s, T, L0);
+  else if (km == KM_MIX64) LAUNCH(K_SPMV_P, (k_spmv_p<false, KM_MIX64>), L0.nblocks, kBlock, s, T, L0);
+  else if (km == KM_MIX32) LAUNCH(K_SPMV_P, (k_spmv_p<false, KM_MIX32>), L0.nblocks, kBlock, s, T, L0);
+  else LAUNCH(K_SPMV_P, (k_spmv_p<false, KM_FP64>), L0.nblocks, kBlock, s, T, L0);
 }
 
 void launch_z_out(const Tables &T, TileList L0, double *out, hipStream_t s) {
   if (L0.nblocks) LAUNCH(K_APPLY, k_z_out, L0.nblocks, kBlock, s, T, L0, out);
 }
 
-void launch_xfix(const Tables &T, TileList L0, int prec, hipStream_t s) {
+void launch_xfix(const Tables &T, TileList L0, int km, hipStream_t s) {
   if (!L0.nblocks) return;
-  if (prec) LAUNCH(K_XFIX, k_xfix<true>, L0.nblocks, kBlock, s, T, L0);
-  else LAUNCH(K_XFIX, k_xfix<false>, L0.nblocks, kBlock, s, T, L0);
+  if (km == KM_MIX32) LAUNCH(K_XFIX, k_xfix<KM_MIX32>, L0.nblocks, kBlock, s, T, L0);
+  else if (km == KM_MIX64) LAUNCH(K_XFIX, k_xfix<KM_MIX64>, L0.nblocks, kBlock, s, T, L0);
+  else LAUNCH(K_XFIX, k_xfix<KM_FP64>, L0.nblocks, kBlock, s, T, L0);
 }
 
-void launch_update(const Tables &T, TileList L0, int prec, hipStream_t s) {
+void launch_update(const Tables &T, TileList L0, int km, hipStream_t s) {
   if (!L0.nblocks) return;
-  if (prec) LAUNCH(K_UPDATE, k_update<true>, L0.nblocks, kBlock, s, T, L0);
-  else LAUNCH(K_UPDATE, k_update<false>, L0.nblocks, kBlock, s, T, L0);
+  if (km == KM_MIX32) LAUNCH(K_UPDATE, k_update<KM_MIX32>, L0.nblocks, kBlock, s, T, L0);
+  else if (km == KM_MIX64) LAUNCH(K_UPDATE, k_update<KM_MIX64>, L0.nblocks, kBlock, s, T, L0);
+  else LAUNCH(K_UPDATE, k_update<KM_FP64>, L0.nblocks, kBlock, s, T, L0);
 }
 
 void launch_true_resid(const Tables &T, TileList L0, hipStream_t s) {

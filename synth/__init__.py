@@ -398,6 +398,7 @@ def t_reionization_share(n=640, n_src=10000, sigma_ln=2.0, device="cuda",
         ionized[iz, iy, ix] |= d2 <= r * r
     # x_HI = 1e-4 inside the bubbles
     kappa = SIGMA_HI * nH * torch.where(ionized, 1e-4, 1.0)
+    ion_frac = float(ionized.double().mean())
     del nH, ionized
     eta = t_emissivity(shape, cells, ndot, dx ** 3, device)
     L = L_cells * dx
@@ -405,7 +406,8 @@ def t_reionization_share(n=640, n_src=10000, sigma_ln=2.0, device="cuda",
     E = torch.full(shape, 1e-45, dtype=torch.float64, device=device)
     return {"name": f"reionization_{n}", "shape": shape, "h": (dx, dx, dx),
             "E": E, "kappa": kappa, "eta": eta, "c": C_LIGHT, "L_unit": L,
-            "dt": dt, "theta": 1.0, "a": 1.0, "adot": 0.0}
+            "dt": dt, "theta": 1.0, "a": 1.0, "adot": 0.0,
+            "ionized_fraction": ion_frac}
 
 
 def group_structure(G: int, e_lo_ev: float = 13.6, e_hi_ev: float = 13.6 * 8.0,
