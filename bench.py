@@ -300,9 +300,6 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain copy kernel of 2 GiB read + 2 GiB "
                          "written, to calibrate the HBM byte counters")
-    ap.add_argument("--cpu-iters", type=int, default=3,
-                    help="oracle sample: Jacobi-PCG iterations timed on all "
-                         "cores (after a run of the assembly alone)")
     return ap.parse_args()
 
 
@@ -493,27 +490,14 @@ def run_form_headline(fld, torch, p, name, args, steps, levels=6):
     return out
 
 
-def oracle_sample(p, threads, iters):
-    """The oracle on step 1 of the workload (its E^0): the assembly alone
-    (limiter, operator, b, diagonal: a Jacobi-PCG call with no iteration),
-    then the assembly and `iters` iterations, on `threads` host threads
-    (1: the serial build).  Returns the assembly time and the time per
-    iteration."""
+def _oracle_problem(p, parallel):
     import oracle
     En = p["E"].detach().cpu().numpy()
     Kh = p["kappa"].detach().cpu().numpy()
     Hh = p["eta"].detach().cpu().numpy()
     dmax, rmin = oracle.limits(p["c"], p["L_unit"])
-    par = threads > 1
-    used = oracle.threads(threads) if par else 1
-    O = oracle.Problem(En, Kh, Hh, p["h"], p["c"], dmax, rmin, p["dt"], parallel=par)
-    t0 = time.perf_counter()
-    O.solve(tol=1e-8, max_iter=0)
-    t_asm = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    _, _, it, _ = O.solve(tol=1e-8, max_iter=iters)
-    t_k = time.perf_counter() - t0
-    return t_asm, max(t_k - t_asm, 0.0) / max(it, 1), it, used
+    return oracle.Problem(En, Kh, Hh, p["h"], p["c"], dmax, rmin, p["dt"],
+                          parallel=parallel)
 
 
 def recorded_oracle_iterations(n):
@@ -529,37 +513,60 @@ def recorded_oracle_iterations(n):
 
 
 def cpu_baselines(p, args):
-    """The oracle timed on the host cores on a bounded sample of step 1 of the
-    workload: all cores (the host share of one GPU, 16, via the OpenMP build
-    of the same source) and one core (the serial build), each extrapolated
-    from its assembly and per-iteration times to the Jacobi-PCG iteration
-    count the oracle needs for 1e-8 on this step (recorded by
-    oracle/record_iterations.py)."""
+    """The oracle on the host cores, on step 1 of the workload (its E^0).
+    All cores (the host share of one GPU, 16 threads, through the OpenMP
+    build of the same source): the whole step, limiter assembly and
+    Jacobi-PCG to the same 1e-8 rule.  One core (the serial build): the
+    assembly and the first one and two iterations are timed, and the step is
+    extrapolated to the iteration count of the all-cores solve (or, without
+    it, to the count recorded by oracle/record_iterations.py)."""
+    import oracle
     n = p["shape"][0]
-    need = recorded_oracle_iterations(n)
     cells = int(p["E"].numel())
     cpu = host_cpu()
     out = {}
-    for key, thr, k in (("all", min(16, os.cpu_count() or 1), args.cpu_iters),
-                        ("single", 1, 1)):
-        log(f"[bench] timing the oracle on {thr} thread(s): assembly + {k} iteration(s)")
-        t_asm, t_it, done, used = oracle_sample(p, thr, k)
-        rec = {"unit": "Mcell-updates/s", "cores": used, "kind": "oracle",
-               "host_cpu": cpu, "assembly_s": round(t_asm, 3),
-               "s_per_iteration": round(t_it, 4)}
-        if need:
-            t_step = t_asm + need * t_it
-            rec["value"] = round(cells / t_step / 1e6, 4)
-            rec["sample"] = (f"step 1 of the {n}^3 share: the oracle's assembly "
-                             f"({t_asm:.1f} s) and {done} of the {need} Jacobi-PCG "
-                             f"iterations its 1e-8 solve takes ({t_it:.2f} s each) "
-                             f"timed on {used} thread(s); the step time "
-                             f"{t_step:.0f} s is extrapolated from them")
-            rec["extrapolated"] = True
-        else:
-            rec["value"] = None
-            rec["sample"] = "no recorded oracle iteration count for this grid"
-        out[key] = rec
+    thr = min(16, os.cpu_count() or 1)
+    used = oracle.threads(thr)
+    log(f"[bench] the oracle's step 1 on {used} threads, to 1e-8")
+    O = _oracle_problem(p, True)
+    t0 = time.perf_counter()
+    _, st, it_all, rel = O.solve(tol=1e-8, max_iter=100000)
+    sec = time.perf_counter() - t0
+    del O
+    out["all"] = {"value": round(cells / sec / 1e6, 4), "unit": "Mcell-updates/s",
+                  "cores": used, "kind": "oracle", "host_cpu": cpu,
+                  "sample": (f"step 1 of the {n}^3 share (E^0): the oracle's limiter "
+                             f"assembly and Jacobi-PCG to 1e-8 ({it_all} iterations, "
+                             f"relative residual {rel:.2e}) in {sec:.1f} s on {used} "
+                             "threads (OpenMP build of the oracle)"),
+                  "status": int(st), "seconds": round(sec, 2), "iterations": int(it_all)}
+    need = it_all if st == oracle.OK else recorded_oracle_iterations(n)
+    log("[bench] the oracle's step 1 on one thread: assembly + 1 and 3 iterations")
+    O = _oracle_problem(p, False)
+    t0 = time.perf_counter()
+    O.solve(tol=1e-8, max_iter=1)
+    t1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.solve(tol=1e-8, max_iter=3)
+    t3 = time.perf_counter() - t0
+    del O
+    t_it = max(t3 - t1, 0.0) / 2.0
+    t_asm = max(t1 - t_it, 0.0)
+    rec = {"unit": "Mcell-updates/s", "cores": 1, "kind": "oracle", "host_cpu": cpu,
+           "assembly_s": round(t_asm, 3), "s_per_iteration": round(t_it, 4)}
+    if need:
+        t_step = t_asm + need * t_it
+        rec["value"] = round(cells / t_step / 1e6, 4)
+        rec["sample"] = (f"step 1 of the {n}^3 share on one thread (serial build): "
+                         f"the assembly ({t_asm:.1f} s) and the per-iteration time "
+                         f"({t_it:.2f} s, from runs of 1 and 3 Jacobi-PCG "
+                         f"iterations) timed, the step extrapolated to the {need} "
+                         f"iterations of its 1e-8 solve: {t_step:.0f} s")
+        rec["extrapolated"] = True
+    else:
+        rec["value"] = None
+        rec["sample"] = "no oracle iteration count for this grid"
+    out["single"] = rec
     return out
 
 

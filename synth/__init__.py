@@ -507,3 +507,20 @@ def cosmo_test2(n_oct: int = 16, ndot: float = 5e46, z_end: float = 0.0,
         "cell_volume": dx ** 3,
     }
 
+
+
+def thin_uniform_problem(n: int, nu: float, seed: int = 0, kappa_scale: float = 1e-12):
+    """An optically thin periodic n^3 box (the lognormal HI opacity scaled by
+    kappa_scale) with a smooth positive emissivity (a smoothed lognormal of
+    sigma 0.5 around 1e-25 erg cm^-3 s^-1) and a uniform E^n = 1e-20, over a
+    step long enough that the diffusion number dt D_max / dx^2 is nu
+    (D_max = 0.006 c L_unit with L_unit the box side)."""
+    rng = rng_for(11, seed)
+    shape = (int(n),) * 3
+    dx = DX_TEST1
+    L = n * dx
+    kappa = kappa_scale * SIGMA_HI * lognormal(shape, 1e-3, 1.0, rng)
+    eta = 1e-25 * np.exp(0.5 * smooth_gaussian(shape, 3.0, rng))
+    dt = nu * dx * dx / (0.006 * C_LIGHT * L)
+    E = np.full(shape, 1e-20)
+    return _problem(shape, dx, kappa, eta, E, L, dt, f"thin_{n}_{nu:g}_{seed}")

@@ -55,12 +55,28 @@ def _half_sweep(op, f, x, colour_mask):
     return np.where(colour_mask, new, x)
 
 
-def _coarsen(op, scale):
+def _coarsen(op, scale, series=False):
     D, (Tx, Ty, Tz) = op
     nz, ny, nx = D.shape
     Z, Y, X = nz // 2, ny // 2, nx // 2
     mass = D - (Tx + np.roll(Tx, 1, 2) + Ty + np.roll(Ty, 1, 1) + Tz + np.roll(Tz, 1, 0))
     Mc = mass.reshape(Z, 2, Y, 2, X, 2).sum(axis=(1, 3, 5))
+    if series:
+        # each fine row across a coarse face: the coarse cell's inner face
+        # (half of it), the face itself and the next cell's inner face (half)
+        # in series, then 2 x scale x the sum over the 4 rows
+        def rows(T, ax):
+            inner = np.take(T, np.arange(0, T.shape[ax], 2), axis=ax)
+            face = np.take(T, np.arange(1, T.shape[ax], 2), axis=ax)
+            nxt = np.roll(inner, -1, axis=ax)
+            with np.errstate(divide="ignore"):  # a zero face blocks its row
+                return 1.0 / (0.5 / inner + 1.0 / face + 0.5 / nxt)
+        Tx, Ty, Tz = rows(Tx, 2), rows(Ty, 1), rows(Tz, 0)
+        Tcx = 2 * scale * Tx.reshape(Z, 2, Y, 2, X).sum(axis=(1, 3))
+        Tcy = 2 * scale * Ty.reshape(Z, 2, Y, X, 2).sum(axis=(1, 4))
+        Tcz = 2 * scale * Tz.reshape(Z, Y, 2, X, 2).sum(axis=(2, 4))
+        Dc = Mc + Tcx + np.roll(Tcx, 1, 2) + Tcy + np.roll(Tcy, 1, 1) + Tcz + np.roll(Tcz, 1, 0)
+        return Dc, (Tcx, Tcy, Tcz)
     # a coarse +x face covers the +x faces of the 4 children with odd x
     Tcx = scale * Tx[:, :, 1::2].reshape(Z, 2, Y, 2, X).sum(axis=(1, 3))
     Tcy = scale * Ty[:, 1::2, :].reshape(Z, 2, Y, X, 2).sum(axis=(1, 4))
@@ -85,7 +101,29 @@ def _solve_exact(op, f):
     return spla.spsolve(A.tocsc(), f.ravel()).reshape(shape)
 
 
-def _vcycle(ops, l, f, nu):
+def _prolong(e, trilinear):
+    """Coarse-grid correction at every fine cell: the coarse value of the
+    parent (piecewise constant), or cell-centred trilinear interpolation,
+    per axis 3/4 of the parent and 1/4 of the coarse neighbour on the side of
+    the fine cell (periodic)."""
+    if not trilinear:
+        return np.repeat(np.repeat(np.repeat(e, 2, 0), 2, 1), 2, 2)
+    for ax in range(3):
+        lo = 0.75 * e + 0.25 * np.roll(e, 1, axis=ax)
+        hi = 0.75 * e + 0.25 * np.roll(e, -1, axis=ax)
+        shp = list(e.shape)
+        shp[ax] *= 2
+        out = np.empty(shp)
+        sl = [slice(None)] * 3
+        sl[ax] = slice(0, None, 2)
+        out[tuple(sl)] = lo
+        sl[ax] = slice(1, None, 2)
+        out[tuple(sl)] = hi
+        e = out
+    return e
+
+
+def _vcycle(ops, l, f, nu, trilinear=False):
     op = ops[l]
     if l == len(ops) - 1:
         return _solve_exact(op, f)
@@ -97,8 +135,8 @@ def _vcycle(ops, l, f, nu):
     r = f - _apply(op, x)
     nz, ny, nx = f.shape
     fc = r.reshape(nz // 2, 2, ny // 2, 2, nx // 2, 2).sum(axis=(1, 3, 5))
-    e = _vcycle(ops, l + 1, fc, nu)
-    x = x + np.repeat(np.repeat(np.repeat(e, 2, 0), 2, 1), 2, 2)
+    e = _vcycle(ops, l + 1, fc, nu, trilinear)
+    x = x + _prolong(e, trilinear)
     for _ in range(nu):
         x = _half_sweep(op, f, x, ~red)
         x = _half_sweep(op, f, x, red)
@@ -127,6 +165,35 @@ def test_textbook_cycle_helpers():
     for _ in range(400):
         x = _half_sweep(op, f, _half_sweep(op, f, x, red), ~red)
     assert np.allclose(x, _solve_exact(op, f), rtol=0, atol=1e-10 * np.abs(x).max())
+    # the series rule: equal to the sum rule for a uniform medium; a row
+    # with one blocked face contributes nothing; and the coarse operator
+    # still annihilates constants
+    U = tuple(np.full((4, 6, 8), 1.7) for _ in range(3))
+    DU = sum(2 * u for u in U)
+    a, b = _coarsen((DU, U), 0.5), _coarsen((DU, U), 0.5, series=True)
+    for ta, tb in zip(a[1], b[1]):
+        assert np.allclose(ta, tb, rtol=1e-14, atol=0)
+    Tb = tuple(t.copy() for t in T)
+    Tb[0][:, :, 2] = 0.0
+    Db = Tb[0] + np.roll(Tb[0], 1, 2) + Tb[1] + np.roll(Tb[1], 1, 1) + Tb[2] + np.roll(Tb[2], 1, 0)
+    Dc, Tc = _coarsen((Db, Tb), 0.5, series=True)
+    assert np.abs(_apply((Dc, Tc), one)).max() <= 1e-12
+    # fine x-faces at x = 2 closed: that is the inner face of coarse cell 1,
+    # so every row through it is cut and both coarse x-faces of coarse cell 1
+    # vanish, the others do not
+    assert np.all(Tc[0][:, :, 0] == 0.0) and np.all(Tc[0][:, :, 1] == 0.0)
+    assert np.all(Tc[0][:, :, 2:] > 0.0)
+    want = 1.0 / (0.5 / Tb[0][0:2, 0:2, 4] + 1.0 / Tb[0][0:2, 0:2, 5] + 0.5 / Tb[0][0:2, 0:2, 6])
+    assert Tc[0][0, 0, 2] == pytest.approx(2 * 0.5 * want.sum(), rel=1e-14)
+    # trilinear interpolation reproduces a constant and is 3/4 : 1/4
+    e = rng.normal(size=(2, 3, 4))
+    assert np.allclose(_prolong(np.ones((2, 3, 4)), True), 1.0, rtol=1e-15)
+    fe = _prolong(e, True)
+    want = 0.75 * (0.75 * (0.75 * e[1, 2, 3] + 0.25 * e[1, 2, 0])
+                   + 0.25 * (0.75 * e[1, 1, 3] + 0.25 * e[1, 1, 0]))
+    want += 0.25 * (0.75 * (0.75 * e[0, 2, 3] + 0.25 * e[0, 2, 0])
+                    + 0.25 * (0.75 * e[0, 1, 3] + 0.25 * e[0, 1, 0]))
+    assert fe[3, 4, 7] == pytest.approx(want, rel=1e-14)
 
 
 CYCLES = [(nu, levels, fl) for nu, fl in ((1, 0), (1, 9), (2, 0)) for levels in (2, 3)]
@@ -159,3 +226,46 @@ def test_vcycle_is_the_textbook_cycle(fld, oracle_mod, prec, nu, levels,
     print(f"[vcycle] prec={prec} nu={nu} levels={levels} fused={fused_levels} "
           f"err={err:.2e}", flush=True)
     assert err <= (1e-9 if prec == 0 else 2e-5)
+
+
+VARIANTS = [  # (prec, levels, fused_levels, prolongation, coarse_op)
+    (1, 2, 0, 1, 0), (1, 3, 0, 1, 0), (1, 3, 9, 1, 0),
+    (0, 3, 0, 0, 1), (1, 3, 0, 0, 1), (1, 3, 0, 1, 1),
+]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec,levels,fused_levels,prolongation,coarse_op", VARIANTS)
+def test_vcycle_variants_are_the_textbook_cycle(fld, oracle_mod, prec, levels,
+                                                fused_levels, prolongation,
+                                                coarse_op):
+    """The mixed V(1,1) cycle with the trilinear correction (the fused finest
+    passes with the interpolated correction of k_tri_fine, the coarse fused or
+    per-half-sweep kernels and the tail), and the series coarse-face rule:
+    the same textbook cycle with those two definitions."""
+    log_case("vcycle_variant", prec=prec, levels=levels, fused=fused_levels,
+             prolongation=prolongation, coarse_op=coarse_op)
+    shape = (24, 40, 96)
+    p = synth.random_problem(shape, 62, sigma_ln=1.5, n_src=3, dt_factor=0.5)
+    prm = params(fld, p, precision=prec, mg_levels=levels, nu_pre=1, nu_post=1,
+                 cycle_switch=0, fused_tile_z=8, fused_levels=fused_levels,
+                 prolongation=prolongation, coarse_op=coarse_op)
+    S = fld.Solver(p["shape"], p["h"], prm)
+    S.assemble(dev(p["E"]), dev(p["kappa"]), dev(p["eta"]), p["dt"], p["a"], 0.0)
+    f = np.random.default_rng(8).normal(size=shape)
+    z = host(S.fld_precondition(dev(f)))
+    O = oracle_problem(oracle_mod, p, prm)
+    D, Ax, Ay, Az, _ = O.system()
+    ops = [(D, (Ax, Ay, Az))]
+    for _ in range(levels - 1):
+        ops.append(_coarsen(ops[-1], prm.coarse_scale, series=bool(coarse_op)))
+    zr = _vcycle(ops, 0, f, 1, trilinear=bool(prolongation))
+    err = rel_l2(z, zr)
+    # the other definition is measurably different (the check has teeth)
+    ops2 = [ops[0]]
+    for _ in range(levels - 1):
+        ops2.append(_coarsen(ops2[-1], prm.coarse_scale, series=not coarse_op))
+    other = rel_l2(z, _vcycle(ops2, 0, f, 1, trilinear=not prolongation))
+    print(f"[vcycle variant] err={err:.2e} other definition={other:.2e}", flush=True)
+    assert err <= (1e-9 if prec == 0 else 2e-5)
+    assert other > 100 * max(err, 1e-9)
