@@ -253,6 +253,27 @@ fld_status fld_step(fld_handle *h, double *E, const double *kappa,
 /* Release the handle's host metadata (the workspace stays the caller's). */
 fld_status fld_destroy(fld_handle *h);
 
+/* --- One step without a caller workspace. --------------------------------
+ * For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * step as fld_create + fld_step + fld_destroy on the grid g, with kernels
+ * launched one by one (use_graph is ignored), but its workspace is a device
+ * array of FLD_STATIC_SCRATCH_BYTES that the library holds on every device it
+ * runs on until the process ends.  It calls no hipMalloc or hipFree and no
+ * routine that allocates device memory (host metadata is built and freed
+ * within the call).  E (in E^n, out E^{n+1}), kappa, eta, dt, a, adot, stats
+ * and the errors are those of fld_step; FLD_ENOMEM if
+ * fld_workspace_bytes(g, p) exceeds FLD_STATIC_SCRATCH_BYTES (a 64^3 mixed or
+ * an 80^3 FP64 grid fits).  Nothing carries over between calls.  Every call
+ * on one device uses that device's single array: calls that overlap on one
+ * device (two host threads, or two streams) race and must not be made. */
+#define FLD_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+size_t fld_static_scratch_bytes(void);
+fld_status fld_step_static(const fld_grid *g, const fld_params *p,
+                           void *hip_stream, double *E, const double *kappa,
+                           const double *eta, double dt, double a, double adot,
+                           fld_stats *stats);
+
 /* --- Components of the solve, exported for inspection and testing. ------ */
 
 /* Copy the assembled finest-level system to caller device buffers (any may

@@ -33,7 +33,7 @@ EXPORTS = (
     "fld_server_create", "fld_server_submit", "fld_server_poll",
     "fld_server_drain", "fld_server_destroy",
     "fld_profile_num_kernels", "fld_profile_kernel_name", "fld_profile_select",
-    "fld_profile_read",
+    "fld_profile_read", "fld_static_scratch_bytes", "fld_step_static",
     "fld_chem_default_params", "fld_chem_h_update", "fld_chem_ionized_sum",
 )
 
@@ -121,6 +121,9 @@ def _load():
         "fld_solve": (i32, [vp, vp, P(Stats)]),
         "fld_step": (i32, [vp, vp, vp, vp, d, d, d, P(Stats)]),
         "fld_destroy": (i32, [vp]),
+        "fld_static_scratch_bytes": (sz, []),
+        "fld_step_static": (i32, [P(Grid), P(Params), vp, vp, vp, vp, d, d, d,
+                                  P(Stats)]),
         "fld_get_system": (i32, [vp, vp, vp, vp, vp, vp]),
         "fld_apply": (i32, [vp, vp, vp]),
         "fld_precondition": (i32, [vp, vp, vp]),
@@ -306,6 +309,27 @@ class Solver:
 
     # short aliases
     assemble, solve, step = fld_assemble, fld_solve, fld_step
+
+
+def fld_static_scratch_bytes() -> int:
+    """Size of the library's own device workspace used by fld_step_static."""
+    return int(_lib.fld_static_scratch_bytes())
+
+
+def fld_step_static(shape, h, params: Params, E, kappa, eta, dt, a=1.0, adot=0.0,
+                    stream=None, check=True):
+    """One radiation step on the library's own device workspace (no caller
+    workspace and no device allocation): E is updated in place."""
+    grid = make_grid(shape, h)
+    n = grid.nx * grid.ny * grid.nz
+    st = Stats()
+    s = _lib.fld_step_static(ctypes.byref(grid), ctypes.byref(params),
+                             _stream_ptr(stream), _dptr(E, n, "E"),
+                             _dptr(kappa, n, "kappa"), _dptr(eta, n, "eta"),
+                             float(dt), float(a), float(adot), ctypes.byref(st))
+    if check:
+        _check(s, "fld_step_static")
+    return s, st.as_dict()
 
 
 class Batch:
