@@ -276,6 +276,11 @@ def parse():
                     help="mixed cycle: 0 constant, 1 trilinear, 2 automatic")
     ap.add_argument("--coarse-op", type=int, default=0,
                     help="coarse faces: 0 sum of the fine faces, 1 rows in series")
+    ap.add_argument("--local-sweeps", type=int, default=None,
+                    help="mixed fused cycle: extra sweeps over the strongly "
+                         "coupled finest cells (default: the library's)")
+    ap.add_argument("--local-coupling", type=float, default=None,
+                    help="threshold of the local-sweep mask (default: the library's)")
     ap.add_argument("--workload", default="reionization",
                     choices=["reionization", "many_sources", "single_source",
                              "batch", "served", "hii_test1", "multigroup",
@@ -313,6 +318,10 @@ def form_params(fld, p, prec, args, **kw):
                 check_every=args.check_every, cycle_switch=args.cycle_switch,
                 coarse_op=args.coarse_op,
                 direction_fp64=args.direction_fp64 if prec else 0)
+    if args.local_sweeps is not None:
+        base["local_sweeps"] = args.local_sweeps
+    if args.local_coupling is not None:
+        base["local_coupling"] = args.local_coupling
     base.update(kw)
     return fld.fld_default_params(p["c"], p["L_unit"], **base)
 

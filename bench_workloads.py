@@ -164,12 +164,20 @@ def _batch_problems(synth, torch, nprob):
 
 
 def batch(args, fld, torch, synth, log):
+    """96 independent problems of 32..128^3, one step each to 1e-8, in one
+    batched step (one launch per kernel and level for all problems, the PCG
+    iterations replayed from captured graphs), with the tile depth and sweep
+    counts the autotuner picks, timed as it is tuned: each timed step starts
+    cold from the problems' initial fields.  Beside it: the same cold step
+    problem by problem (mixed and plain FP64), and warm successive steps."""
     from paper_1306_0645_amd import autotune
+    from bench import model_step_bytes
     log(f"[bench] generating {args.batch} batch problems on the GPU")
     probs = _batch_problems(synth, torch, args.batch)
     shapes = [p["shape"] for p in probs]
     hs = [p["h"] for p in probs]
     cells = sum(int(np.prod(s)) for s in shapes)
+    E0 = [p["E"] for p in probs]
     K = [p["kappa"] for p in probs]
     H = [p["eta"] for p in probs]
     dts = [p["dt"] for p in probs]
@@ -177,108 +185,168 @@ def batch(args, fld, torch, synth, log):
     ref = max(probs, key=lambda p: p["L_unit"])
     base = fld.fld_default_params(ref["c"], ref["L_unit"],
                                   precision=fld.FLD_PREC_MIXED, use_graph=args.graph,
-                                  warm_start=args.warm_start)
+                                  warm_start=0)
     report = None
     if args.autotune:
-        log("[bench] autotuning tile depth and sweep counts")
-        base, report = autotune.tune_batch(shapes, hs, base,
-                                           ([p["E"] for p in probs], K, H), dts,
-                                           log=log)
-    B = fld.Batch(shapes, hs, base)
-    Es = [p["E"].clone() for p in probs]
-    for _ in range(args.warmup):
-        B.step(Es, K, H, dts)
-    from bench import model_step_bytes
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters = []
-    step_bytes = 0.0
-    for _ in range(args.steps):
-        sts = B.step(Es, K, H, dts)
-        iters += [s["iters"] for s in sts]
-        assert all(s["status"] == 0 for s in sts)
-        step_bytes += sum(model_step_bytes(int(np.prod(shp)), s["iters"],
-                                           s["cycle_nu"], 1, s["levels"],
-                                           warm=args.warm_start)
-                          for shp, s in zip(shapes, sts))
-    torch.cuda.synchronize()
-    sec = time.perf_counter() - t0
-    batched = cells * args.steps / sec / 1e6
-    step_gbps = step_bytes / sec / 1e9
-    B.close()
+        log("[bench] autotuning tile depth and sweep counts (cold steps)")
+        base, report = autotune.tune_batch(shapes, hs, base, (E0, K, H), dts, log=log)
 
-    def one_by_one(prec, steps):
-        solvers = []
-        for p in probs:
-            q = fld.fld_default_params(ref["c"], ref["L_unit"], precision=prec,
-                                       use_graph=args.graph,
-                                       warm_start=args.warm_start)
-            solvers.append(fld.Solver(p["shape"], p["h"], q))
-        Es1 = [p["E"].clone() for p in probs]
-        for S, E, k, h, dt in zip(solvers, Es1, K, H, dts):
-            S.step(E, k, h, dt)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
+    def cold_steps(B, reps):
+        """reps timed single steps, each from the initial fields (the handle
+        keeps no warm-start history: warm_start = 0)"""
+        times, iters, nbytes = [], [], 0.0
+        for r in range(reps + 1):
+            Es = [e.clone() for e in E0]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sts = B.step(Es, K, H, dts)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            assert all(s["status"] == 0 for s in sts)
+            if r == 0:
+                continue  # captures the graphs
+            times.append(dt)
+            iters += [s["iters"] for s in sts]
+            nbytes += sum(model_step_bytes(int(np.prod(shp)), s["iters"], s["cycle_nu"],
+                                           1, s["levels"], warm=0)
+                          for shp, s in zip(shapes, sts))
+        return times, iters, nbytes
+
+    reps = max(3, args.steps)
+    B = fld.Batch(shapes, hs, base)
+    times, iters, nbytes = cold_steps(B, reps)
+    B.close()
+    sec = float(np.median(times))
+    batched = cells / sec / 1e6
+    step_gbps = nbytes / sum(times) / 1e9
+
+    def one_by_one(prec):
+        q = fld.fld_default_params(ref["c"], ref["L_unit"], precision=prec,
+                                   use_graph=args.graph, warm_start=0,
+                                   tile_z=base.tile_z if prec else 0)
+        solvers = [fld.Solver(p["shape"], p["h"], q) for p in probs]
+        best = float("inf")
+        for r in range(3):
+            Es1 = [e.clone() for e in E0]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
             for S, E, k, h, dt in zip(solvers, Es1, K, H, dts):
                 S.step(E, k, h, dt)
-        torch.cuda.synchronize()
-        s = time.perf_counter() - t0
+            torch.cuda.synchronize()
+            if r:
+                best = min(best, time.perf_counter() - t0)
         for S in solvers:
             S.close()
-        return cells * steps / s / 1e6
+        return cells / best / 1e6
 
-    log("[bench] the same problems one by one (mixed, then FP64)")
-    single_mixed = one_by_one(fld.FLD_PREC_MIXED, max(1, args.steps // 2))
-    single_fp64 = one_by_one(fld.FLD_PREC_FP64, max(1, args.steps // 2))
+    log("[bench] the same cold step problem by problem (mixed, then FP64)")
+    single_mixed = one_by_one(fld.FLD_PREC_MIXED)
+    single_fp64 = one_by_one(fld.FLD_PREC_FP64)
+    # warm successive steps (each problem's PCG starts from its previous dEs)
+    wprm = fld.Params()
+    autotune.ctypes_copy(wprm, base)
+    wprm.warm_start = 1
+    B = fld.Batch(shapes, hs, wprm)
+    Es = [e.clone() for e in E0]
+    B.step(Es, K, H, dts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    witers = []
+    for _ in range(args.steps):
+        witers += [s["iters"] for s in B.step(Es, K, H, dts)]
+    torch.cuda.synchronize()
+    wsec = time.perf_counter() - t0
+    B.close()
+    warm = cells * args.steps / wsec / 1e6
     return _base(
-        "aggregate over the batch; per-problem working sets up to 128^3",
-        batched, 1e3 * sec / args.steps, args.steps, args.warmup, "f64+f32",
+        "aggregate over the batch, one cold step per problem (median of "
+        f"{reps}); per-problem working sets up to 128^3",
+        batched, 1e3 * sec, 1, 0, "f64+f32",
         {"workload": f"batch_{args.batch}x{{32..128}}^3", "problems": args.batch,
-         "cells": cells, "precision": "mixed", "rtol": 1e-8,
+         "cells": cells, "precision": "mixed", "rtol": 1e-8, "start": "cold",
          "tuned": {"tile_z": base.tile_z, "nu_pre": base.nu_pre,
                    "nu_post": base.nu_post}},
         None,
-        {"step_roofline": {"bytes_per_cell": round(step_bytes / (cells * args.steps), 1),
+        {"step_roofline": {"bytes_per_cell": round(nbytes / (cells * reps), 1),
                            "achieved": round(step_gbps, 1), "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": round(step_gbps / HBM_PEAK_GBS, 4),
                            "model": "algorithmic bytes of each problem's step "
                                     "from its iterations and cycle"},
-         "forms": {"batched_mixed": round(batched, 2),
-                   "one_by_one_mixed": round(single_mixed, 2),
-                   "one_by_one_fp64": round(single_fp64, 2)},
-         "iters_per_problem": float(np.mean(iters)), "autotune": report})
+         "latency_ms": {"p50": round(1e3 * float(np.percentile(times, 50)), 3),
+                        "p99": round(1e3 * float(np.percentile(times, 99)), 3)},
+         "forms": {"batched_mixed_cold": round(batched, 2),
+                   "one_by_one_mixed_cold": round(single_mixed, 2),
+                   "one_by_one_fp64_cold": round(single_fp64, 2),
+                   "batched_mixed_warm_successive": round(warm, 2)},
+         "iters_per_problem": float(np.mean(iters)),
+         "iters_per_problem_warm": float(np.mean(witers)),
+         "autotune": report})
+
+
+def _oracle_request_error(synth, req, E0, K, H, E_out, steps):
+    """The oracle's steps of one served request (its fields copied to the
+    host), each solved to 1e-13 from the previous one's result: relative L2
+    error of the served E against the oracle's (OpenMP build of the oracle,
+    which evaluates every cell as the serial one does; its reductions sum in
+    another order)."""
+    import oracle
+    dmax, rmin = oracle.limits(req["c"], req["L_unit"])
+    En = E0.detach().cpu().numpy()
+    Kh, Hh = K.detach().cpu().numpy(), H.detach().cpu().numpy()
+    for _ in range(steps):
+        O = oracle.Problem(En, Kh, Hh, req["h"], req["c"], dmax, rmin, req["dt"],
+                           parallel=True)
+        dE, st, _, _ = O.solve(tol=1e-13, max_iter=100000)
+        if st != oracle.OK:
+            return float("nan")
+        En = En + dE
+    got = E_out.detach().cpu().numpy()
+    return float(np.linalg.norm(got - En) / np.linalg.norm(En))
 
 
 def served(args, fld, torch, synth, log):
+    """Poisson stream of requests of 64..384^3 (log-uniform, multiples of 16)
+    with 1-5 steps each through the continuous-batching server: every request
+    has its own seeded opacity and sources (up to 1000); E^0 is one smooth
+    field per grid size.  The arena is 80 % of the free HBM once the request
+    fields are resident.  Reports p50/p99 latency (submit -> result) and
+    aggregate Mcell-updates/s, an oracle check of a sample of the results,
+    and the same requests through plain FP64 handles one after another."""
     nreq = args.requests
     shapes = [synth.serve_request_shape(i) for i in range(nreq)]
     sizes = sorted({s[0] for s in shapes})
     log(f"[bench] served: {nreq} requests over {len(sizes)} grid sizes; "
-        "generating one field set per size on the GPU")
-    pool = {}
-    for n in sizes:
-        p = synth.t_problem((n, n, n), 1.25, 500, (1e47, 1e50), 5, n, "cuda")
-        pool[n] = p
+        "generating each request's fields on the GPU")
+    t0 = time.perf_counter()
+    reqs, e0 = [], {}
+    for i, (n, steps, n_src, sigma) in enumerate(shapes):
+        q = synth.t_problem((n, n, n), sigma, n_src, (1e47, 1e50), 5, i, "cuda")
+        if n not in e0:
+            e0[n] = q["E"]
+        else:
+            del q["E"]
+        q["E"] = e0[n]
+        q["out"] = torch.empty_like(e0[n])
+        reqs.append(q)
+        if i % 100 == 99:
+            log(f"[bench]   generated {i + 1}/{nreq}")
     torch.cuda.synchronize()
-    ref = pool[max(sizes)]
+    log(f"[bench]   fields generated in {time.perf_counter() - t0:.1f} s")
+    ref = max(reqs, key=lambda q: q["L_unit"])
     prm = fld.fld_default_params(ref["c"], ref["L_unit"],
                                  precision=fld.FLD_PREC_MIXED,
                                  prolongation=args.prolongation,
                                  warm_start=args.warm_start)
     free, total = torch.cuda.mem_get_info()
-    arena = int(0.6 * free) // 256 * 256
+    arena = int(0.8 * free) // 256 * 256
     stream = torch.cuda.Stream()
     srv = fld.Server(prm, arena, stream=stream)
-    log(f"[bench]   arena {arena / 2**30:.1f} GiB")
+    log(f"[bench]   arena {arena / 2**30:.1f} GiB (80 % of {free / 2**30:.1f} GiB free)")
 
     def submit(i):
-        n, steps, _, _ = shapes[i]
-        p = pool[n]
-        out = torch.empty_like(p["E"])
-        t = srv.submit(p["shape"], p["h"], p["E"], p["kappa"], p["eta"], out,
-                       p["dt"], n_steps=steps)
-        return t, out
+        q = reqs[i]
+        return srv.submit(q["shape"], q["h"], q["E"], q["kappa"], q["eta"], q["out"],
+                          q["dt"], n_steps=shapes[i][1])
 
     def work(idx):
         return sum(shapes[i][0] ** 3 * shapes[i][1] for i in idx)
@@ -289,7 +357,7 @@ def served(args, fld, torch, synth, log):
     ts = [submit(i) for i in range(nsat)]
     srv.drain()
     sat_s = time.perf_counter() - t0
-    for t, _ in ts:
+    for t in ts:
         r = srv.poll(t)
         assert r is not None and r["status"] == 0, r
     sat_rate = nsat / sat_s
@@ -310,8 +378,10 @@ def served(args, fld, torch, synth, log):
             log(f"[bench]   submitted {i + 1}/{nreq}")
     srv.drain()
     wall = time.perf_counter() - t0
-    res = [srv.poll(t) for t, _ in tickets]
+    res = [srv.poll(t) for t in tickets]
     srv.close()
+    del srv
+    torch.cuda.empty_cache()
     assert all(r is not None and r["status"] == 0 for r in res)
     from bench import auto_levels, model_step_bytes
     sbytes = sum(model_step_bytes(shapes[i][0] ** 3, r["iters"], 1, 1,
@@ -322,12 +392,41 @@ def served(args, fld, torch, synth, log):
     que = np.array([r["queue_s"] for r in res]) * 1e3
     thr = work(range(nreq)) / wall / 1e6
     p50, p99 = np.percentile(lat, [50, 99])
+    # oracle check of a sample: 20 requests drawn (seeded) among those of at
+    # most 96^3, where the oracle's steps take about a second each
+    small = [i for i in range(nreq) if shapes[i][0] <= 96]
+    pick = sorted(np.random.default_rng(1312).choice(small, size=min(20, len(small)),
+                                                     replace=False).tolist())
+    log(f"[bench]   oracle check of {len(pick)} requests")
+    import oracle
+    oracle.threads(16)
+    errs = [_oracle_request_error(synth, reqs[i], reqs[i]["E"], reqs[i]["kappa"],
+                                  reqs[i]["eta"], reqs[i]["out"], shapes[i][1])
+            for i in pick]
+    # the same requests through plain FP64 handles, one after another (a
+    # handle per request: its workspace, its steps)
+    log("[bench]   the same requests through plain FP64 handles")
+    p64 = fld.fld_default_params(ref["c"], ref["L_unit"], precision=fld.FLD_PREC_FP64,
+                                 warm_start=args.warm_start)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, q in enumerate(reqs):
+        S = fld.Solver(q["shape"], q["h"], p64)
+        E = q["E"].clone()
+        for _ in range(shapes[i][1]):
+            S.step(E, q["kappa"], q["eta"], q["dt"])
+        S.close()
+        del S, E
+    torch.cuda.synchronize()
+    fp64_wall = time.perf_counter() - t0
+    fp64_thr = work(range(nreq)) / fp64_wall / 1e6
     return _base(
         "open-loop Poisson arrivals; latency = submit -> result",
         thr, 1e3 * wall / nreq, nreq, 0, "f64+f32",
         {"workload": f"served_{nreq}_requests_64..384^3", "requests": nreq,
          "load": args.load, "arrival_rate_per_s": round(lam, 2),
-         "precision": "mixed", "rtol": 1e-8, "arena_GiB": round(arena / 2**30, 1)},
+         "precision": "mixed", "rtol": 1e-8, "arena_GiB": round(arena / 2**30, 1),
+         "fields": "per request (seeded opacity and sources); E^0 per grid size"},
         None,
         {"latency_ms": {"p50": round(float(p50), 3), "p99": round(float(p99), 3),
                         "mean": round(float(lat.mean()), 3)},
@@ -337,6 +436,10 @@ def served(args, fld, torch, synth, log):
                         "mcell_updates_per_s": round(sat_mcells, 1)},
          "max_rel_resid": max(r["rel_resid"] for r in res),
          "iters_mean": float(np.mean([r["iters"] for r in res])),
+         "oracle_sample": {"requests": pick, "max_rel_l2": max(errs),
+                           "gate": 1e-5},
+         "forms": {"served_mixed": round(thr, 2),
+                   "plain_fp64_one_by_one": round(fp64_thr, 2)},
          "step_roofline": {"bytes_per_cell": round(sbytes / work(range(nreq)), 1),
                            "achieved": round(sgbps, 1), "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": round(sgbps / HBM_PEAK_GBS, 4),

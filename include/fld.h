@@ -174,6 +174,16 @@ typedef struct fld_params {
                           output z is FP32 at a per-problem scale) runs in
                           FP32; 0 = p rounded to FP32 at the scale of the z it
                           was formed from (8 B less per cell and iteration) */
+  int32_t local_sweeps; /* mixed precision, fused V(1,1) cycle: after the
+                          finest post-sweep, this many more red/black sweeps
+                          (black, then red) restricted to the finest cells
+                          whose coupling dominates their diagonal (sum of the
+                          6 faces > local_coupling x diagonal, marked at each
+                          assembly): in ionized bubbles, where absorption is
+                          weak and D reaches D_max, one sweep leaves the error
+                          that is smooth inside the bubble and the coarse
+                          levels miss it.  0 = none.  Default 1 */
+  double local_coupling; /* threshold of that mask, in [0, 1]; default 0.98 */
 } fld_params;
 
 typedef struct fld_stats {
@@ -204,7 +214,8 @@ typedef struct fld_server fld_server;
  * coarse_scale = 0.5, max_dt_cuts = 8, graph replay on, cycle_switch = 12,
  * prolongation = 2 (trilinear in the mixed cycle once it has switched to
  * V(2,2)), warm_start = 2, tail_cells = 512, smoother = FLD_SMOOTH_RBGS,
- * fused_levels = 0, coarse_op = 0, direction_fp64 = 1. */
+ * fused_levels = 0, coarse_op = 0, direction_fp64 = 1, local_sweeps = 1,
+ * local_coupling = 0.98. */
 void fld_default_params(fld_params *p, double c, double L_unit);
 
 const char *fld_strerror(fld_status s);
@@ -252,6 +263,28 @@ fld_status fld_step(fld_handle *h, double *E, const double *kappa,
 
 /* Release the handle's host metadata (the workspace stays the caller's). */
 fld_status fld_destroy(fld_handle *h);
+
+/* Several steps with the step control on the device (Sec. 3.4, the
+ * radiation subcycling loop): n_steps > 0 takes n_steps steps of dt, each
+ * exactly as fld_step takes it (a failed solve cuts the substep by 10x and
+ * the substeps then grow by the controller's factor until dt is covered);
+ * n_steps = 0 takes steps of the controller's suggestion, the first of dt
+ * and each next one of dt_next = h clamp(tau_tol / rho, 0.1, 2) (h the last
+ * substep), clipped to end at t_end.  The assembly, PCG, verification, E
+ * update and the controller run as captured graphs of `units` PCG iterations
+ * (0 = 8); the host reads the per-problem state once per graph, not per
+ * substep.  The cycle stays as configured (the adaptive switch of
+ * cycle_switch does not act inside a run).  The results equal those of the
+ * same steps through fld_step, bit for bit.  E: device FP64, in E^0, out E
+ * after the last completed step (a failed step leaves E as the step before
+ * it left it).  stats (host, nullable): iters, restarts, subcycles and
+ * dt_cuts summed over the run, the rest of the last substep; steps_done
+ * (host, nullable): steps completed.  Errors: those of fld_step, and
+ * FLD_EINVAL for n_steps < 0, units < 0, or n_steps = 0 without t_end > 0. */
+fld_status fld_advance(fld_handle *h, double *E, const double *kappa,
+                       const double *eta, int32_t n_steps, double dt, double t_end,
+                       double a, double adot, int32_t units, fld_stats *stats,
+                       int32_t *steps_done);
 
 /* --- One step without a caller workspace. --------------------------------
  * For callers that cannot allocate device memory (code under HIP stream
@@ -316,6 +349,17 @@ fld_status fld_batch_step(fld_batch *b, double *const *E,
                           const double *const *eta, const double *dt,
                           const double *a, const double *adot,
                           fld_stats *per_problem);
+
+/* fld_advance for every problem of the batch (their own dt, a, adot; the
+ * same n_steps or t_end); one unit covers all problems, each with its own
+ * substeps.  per_problem and steps_done: host arrays of n, nullable.
+ * Returns FLD_OK if every problem succeeded, else the first failing
+ * problem's status. */
+fld_status fld_batch_advance(fld_batch *b, double *const *E,
+                             const double *const *kappa, const double *const *eta,
+                             int32_t n_steps, const double *dt, double t_end,
+                             const double *a, const double *adot, int32_t units,
+                             fld_stats *per_problem, int32_t *steps_done);
 
 fld_status fld_batch_destroy(fld_batch *b);
 

@@ -34,6 +34,7 @@ EXPORTS = (
     "fld_server_drain", "fld_server_destroy",
     "fld_profile_num_kernels", "fld_profile_kernel_name", "fld_profile_select",
     "fld_profile_read", "fld_static_scratch_bytes", "fld_step_static",
+    "fld_advance", "fld_batch_advance",
     "fld_chem_default_params", "fld_chem_h_update", "fld_chem_ionized_sum",
 )
 
@@ -58,7 +59,8 @@ class Params(ctypes.Structure):
                 ("cycle_switch", ctypes.c_int32), ("prolongation", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("tail_cells", ctypes.c_int32),
                 ("smoother", ctypes.c_int32), ("fused_levels", ctypes.c_int32),
-                ("coarse_op", ctypes.c_int32), ("direction_fp64", ctypes.c_int32)]
+                ("coarse_op", ctypes.c_int32), ("direction_fp64", ctypes.c_int32),
+                ("local_sweeps", ctypes.c_int32), ("local_coupling", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -121,6 +123,10 @@ def _load():
         "fld_solve": (i32, [vp, vp, P(Stats)]),
         "fld_step": (i32, [vp, vp, vp, vp, d, d, d, P(Stats)]),
         "fld_destroy": (i32, [vp]),
+        "fld_advance": (i32, [vp, vp, vp, vp, i32, d, d, d, d, i32, P(Stats),
+                              P(i32)]),
+        "fld_batch_advance": (i32, [vp, P(vp), P(vp), P(vp), i32, P(d), d, P(d),
+                                    P(d), i32, P(Stats), P(i32)]),
         "fld_static_scratch_bytes": (sz, []),
         "fld_step_static": (i32, [P(Grid), P(Params), vp, vp, vp, vp, d, d, d,
                                   P(Stats)]),
@@ -287,6 +293,25 @@ class Solver:
             _check(s, "fld_step")
         return st.as_dict()
 
+    def fld_advance(self, E, kappa, eta, dt, n_steps=1, t_end=0.0, a=1.0,
+                    adot=0.0, units=0, check=True):
+        """Steps with the substep control on the device: n_steps steps of dt
+        (n_steps = 0: steps of the controller's dt_next from dt until t_end).
+        Returns the stats dict with 'steps' (steps completed) added."""
+        st = Stats()
+        done = ctypes.c_int32(0)
+        s = _lib.fld_advance(self.handle, _dptr(E, self.n, "E"),
+                             _dptr(kappa, self.n, "kappa"), _dptr(eta, self.n, "eta"),
+                             int(n_steps), float(dt), float(t_end), float(a),
+                             float(adot), int(units), ctypes.byref(st),
+                             ctypes.byref(done))
+        if check:
+            _check(s, "fld_advance")
+        out = st.as_dict()
+        out["steps"] = done.value
+        out["returned"] = s
+        return out
+
     def fld_get_system(self):
         out = {k: torch.empty(self.shape, dtype=torch.float64, device=self.device)
                for k in ("diag", "Tx", "Ty", "Tz", "b")}
@@ -308,7 +333,7 @@ class Solver:
         return z
 
     # short aliases
-    assemble, solve, step = fld_assemble, fld_solve, fld_step
+    assemble, solve, step, advance = fld_assemble, fld_solve, fld_step, fld_advance
 
 
 def fld_static_scratch_bytes() -> int:
@@ -382,7 +407,32 @@ class Batch:
             _check(s, "fld_batch_step")
         return [st.as_dict() for st in stats]
 
+    def fld_batch_advance(self, Es, kappas, etas, dts, n_steps=1, t_end=0.0,
+                          a=None, adot=None, units=0, check=True):
+        """fld_advance for every problem of the batch at once."""
+        n = self.n
+        cells = [s[0] * s[1] * s[2] for s in self.shapes]
+        VP = ctypes.c_void_p * n
+        E = VP(*[_dptr(t, c, "E") for t, c in zip(Es, cells)])
+        K = VP(*[_dptr(t, c, "kappa") for t, c in zip(kappas, cells)])
+        H = VP(*[_dptr(t, c, "eta") for t, c in zip(etas, cells)])
+        D = (ctypes.c_double * n)(*[float(v) for v in dts])
+        A = (ctypes.c_double * n)(*([1.0] * n if a is None else [float(v) for v in a]))
+        AD = (ctypes.c_double * n)(*([0.0] * n if adot is None else
+                                     [float(v) for v in adot]))
+        stats = (Stats * n)()
+        done = (ctypes.c_int32 * n)()
+        s = _lib.fld_batch_advance(self.handle, E, K, H, int(n_steps), D,
+                                   float(t_end), A, AD, int(units), stats, done)
+        if check:
+            _check(s, "fld_batch_advance")
+        out = [st.as_dict() for st in stats]
+        for o, d in zip(out, done):
+            o["steps"] = int(d)
+        return out
+
     step = fld_batch_step
+    advance = fld_batch_advance
 
 
 class Server:

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfld.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["fld_kernels.hip", "fld_fused.hip", "fld_chem.hip", "fld_static.hip",
+SOURCES = ["fld_kernels.hip", "fld_fused.hip", "fld_chem.hip", "fld_control.hip",
+           "fld_static.hip",
            "fld_engine.cpp", "fld_capi.cpp", "fld_server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -82,6 +82,8 @@ void fld_default_params(fld_params *p, double c, double L_unit) {
   p->smoother = FLD_SMOOTH_RBGS;
   p->coarse_op = 0;
   p->direction_fp64 = 1;
+  p->local_sweeps = 1;
+  p->local_coupling = 0.98;
 }
 
 const char *fld_strerror(fld_status s) {
@@ -199,6 +201,32 @@ fld_status fld_step(fld_handle *h, double *E, const double *kappa,
   if (st) return (fld_status)st;
   e.assembled = true;
   fill_stats(stats, j, e.hier[0].levels, e.last_nu, e.last_tri);
+  return (fld_status)j.status;
+}
+
+fld_status fld_advance(fld_handle *h, double *E, const double *kappa,
+                       const double *eta, int32_t n_steps, double dt, double t_end,
+                       double a, double adot, int32_t units, fld_stats *stats,
+                       int32_t *steps_done) {
+  if (!h || !E || !kappa || !eta || !step_args_ok(dt, a, adot)) return FLD_EINVAL;
+  if (n_steps < 0 || units < 0) return FLD_EINVAL;
+  if (n_steps == 0 && !(std::isfinite(t_end) && t_end > 0.0)) return FLD_EINVAL;
+  Engine &e = h->eng;
+  const size_t nb = h->n * sizeof(double);
+  if (overlaps(E, nb, kappa, nb) || overlaps(E, nb, eta, nb)) return FLD_EINVAL;
+  std::vector<Job> jobs(1);
+  Job &j = jobs[0];
+  j.E = E;
+  j.kappa = kappa;
+  j.eta = eta;
+  j.dt = dt;
+  j.a = a;
+  j.adot = adot;
+  const int st = e.run_advance(jobs, n_steps, n_steps == 0, t_end, units ? units : 8);
+  if (st) return (fld_status)st;
+  e.assembled = true;
+  fill_stats(stats, j, e.hier[0].levels, e.prm.nu_pre, e.trilinear());
+  if (steps_done) *steps_done = j.steps;
   return (fld_status)j.status;
 }
 
@@ -339,6 +367,44 @@ fld_status fld_batch_step(fld_batch *b, double *const *E,
   int first = FLD_OK;
   for (int i = 0; i < n; ++i) {
     if (per_problem) fill_stats(&per_problem[i], jobs[i], e.hier[i].levels, e.last_nu, e.last_tri);
+    if (jobs[i].status != FLD_OK && first == FLD_OK) first = jobs[i].status;
+  }
+  return (fld_status)first;
+}
+
+fld_status fld_batch_advance(fld_batch *b, double *const *E,
+                             const double *const *kappa, const double *const *eta,
+                             int32_t n_steps, const double *dt, double t_end,
+                             const double *a, const double *adot, int32_t units,
+                             fld_stats *per_problem, int32_t *steps_done) {
+  if (!b || !E || !kappa || !eta || !dt || !a || !adot) return FLD_EINVAL;
+  if (n_steps < 0 || units < 0) return FLD_EINVAL;
+  if (n_steps == 0 && !(std::isfinite(t_end) && t_end > 0.0)) return FLD_EINVAL;
+  Engine &e = b->eng;
+  const int n = (int)e.hier.size();
+  std::vector<Job> jobs(n);
+  for (int i = 0; i < n; ++i) {
+    if (!E[i] || !kappa[i] || !eta[i] || !step_args_ok(dt[i], a[i], adot[i]))
+      return FLD_EINVAL;
+    const size_t nb = (size_t)e.hier[i].cells(0) * sizeof(double);
+    if (overlaps(E[i], nb, kappa[i], nb) || overlaps(E[i], nb, eta[i], nb))
+      return FLD_EINVAL;
+    Job &j = jobs[i];
+    j.E = E[i];
+    j.kappa = kappa[i];
+    j.eta = eta[i];
+    j.dt = dt[i];
+    j.a = a[i];
+    j.adot = adot[i];
+  }
+  const int st = e.run_advance(jobs, n_steps, n_steps == 0, t_end, units ? units : 8);
+  if (st) return (fld_status)st;
+  e.assembled = true;
+  int first = FLD_OK;
+  for (int i = 0; i < n; ++i) {
+    if (per_problem)
+      fill_stats(&per_problem[i], jobs[i], e.hier[i].levels, e.prm.nu_pre, e.trilinear());
+    if (steps_done) steps_done[i] = jobs[i].steps;
     if (jobs[i].status != FLD_OK && first == FLD_OK) first = jobs[i].status;
   }
   return (fld_status)first;

@@ -191,6 +191,16 @@ struct FSrc {
   }
 };
 
+// Assembly and warm start of a problem are due: for the host-driven step
+// whenever the problem takes part (the host launches them when due); for
+// device-controlled stepping when its controller asked for them.
+__device__ __forceinline__ bool asm_due(const Scal &sc) {
+  return sc.live && (!sc.ctl || sc.stage == 1);
+}
+__device__ __forceinline__ bool warm_due(const Scal &sc) {
+  return sc.live && (!sc.ctl || sc.stage == 2);
+}
+
 // the current residual buffer, and the other one
 __device__ __forceinline__ double *rcur(const ProbDev &P, const Scal &sc) {
   return sc.rbuf ? P.r2 : P.r;

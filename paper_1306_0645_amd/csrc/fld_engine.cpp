@@ -48,6 +48,8 @@ bool params_ok(const fld_params &p) {
   if (p.fused_levels < 0 || p.fused_levels > kMaxLevels) return false;
   if (p.coarse_op < 0 || p.coarse_op > 1) return false;
   if (p.direction_fp64 < 0 || p.direction_fp64 > 1) return false;
+  if (p.local_sweeps < 0 || p.local_sweeps > 8) return false;
+  if (!(p.local_coupling >= 0.0 && p.local_coupling <= 1.0)) return false;
   return true;
 }
 
@@ -192,6 +194,7 @@ void carve_problem(Carver &cv, const Hier &h, const fld_params &p, ProbMem &m) {
       P.q = cv.take<double>(n);
       P.b = cv.take<double>(n);
       P.r2 = lazy_iteration(p) ? cv.take<double>(n) : nullptr;
+      P.lmask = (mixed && p.local_sweeps > 0) ? cv.take<unsigned char>(n) : nullptr;
       P.ef = (mixed && fused_cycle(p) && p.prolongation != 0) ? cv.take<float>(n)
                                                                : nullptr;
       L.x = mixed ? (void *)cv.take<float>(n) : (void *)P.z;
@@ -215,6 +218,8 @@ void carve_problem(Carver &cv, const Hier &h, const fld_params &p, ProbMem &m) {
   m.pd.tail = h.tail;
   m.pd.cs = cv.take<double>(4 * (size_t)h.cells(h.levels - 1));
   m.E_work = cv.take<double>((size_t)h.cells(0));
+  for (int k = 0; k < 3; ++k) m.pd.xb[k] = m.xb[k];
+  m.pd.Ework = m.E_work;
 }
 
 size_t problem_bytes(const Hier &h, const fld_params &p) {
@@ -240,6 +245,9 @@ static size_t tables_layout(Carver &cv, const std::vector<Hier> &hs,
   StepDev *sd = cv.take<StepDev>(np);
   Scal *sc = cv.take<Scal>(np);
   double *part = cv.take<double>(2 * std::max<size_t>(nfine, 1));
+  double *lpart = cv.take<double>(2 * std::max<size_t>(nfine, 1));
+  int *lcnt = cv.take<int>(std::max<size_t>(nfine, 1));
+  CtlDev *ctl = cv.take<CtlDev>(std::max(np, 1));
   double *gpart = cv.take<double>(kAsmSums * std::max<size_t>(nfine, 1));
   Tile *tiles = cv.take<Tile>(std::max<size_t>(ntiles, 1));
   int *ranges = cv.take<int>(nranges);
@@ -249,6 +257,9 @@ static size_t tables_layout(Carver &cv, const std::vector<Hier> &hs,
     e->T.sd = sd;
     e->T.sc = sc;
     e->T.part = part;
+    e->T.lpart = lpart;
+    e->T.lcnt = lcnt;
+    e->T.ctl = ctl;
     e->T.gpart = gpart;
     e->T.nprob = np;
     e->d_tiles = tiles;
@@ -271,6 +282,11 @@ int Engine::release_graph() {
     if (g.second.graph) hipGraphDestroy(g.second.graph);
   }
   graphs.clear();
+  for (auto &g : unit_graphs) {
+    if (g.second.exec) hipGraphExecDestroy(g.second.exec);
+    if (g.second.graph) hipGraphDestroy(g.second.graph);
+  }
+  unit_graphs.clear();
   if (cap_stream) hipStreamDestroy(cap_stream);
   cap_stream = nullptr;
   return ST_OK;
@@ -544,6 +560,8 @@ void Engine::enqueue_assemble(const ListSet &ls) {
   launch_assemble(T, ls.fine, prm.c, prm.theta, prm.d_max, prm.r_min, mixed, stream);
   for (int l = 1; l < Lmax; ++l)
     launch_coarsen(T, ls.exist[l], l, prm.coarse_scale, mixed, prm.coarse_op, stream);
+  if (mixed && prm.local_sweeps > 0)
+    launch_lmask(T, ls.fine, prm.local_coupling, stream);
   launch_fin(T, FIN_BB, mixed, stream);
   need_pro = true;
 }
@@ -568,6 +586,12 @@ void Engine::enqueue_fused_rest(const ListSet &ls) {
   }
   if (tri && mixed && Lmax > 1) launch_tri_fine(T, ls.exist[1], stream);
   launch_vup(T, ls.fsm[0], 0, prec, mixed, tri, stream);
+  if (local_on()) {
+    for (int k = 0; k < prm.local_sweeps; ++k) {
+      launch_local(T, ls.fine, 1, stream);
+      launch_local(T, ls.fine, 0, stream);
+    }
+  }
 }
 
 // One V-cycle for every active problem.  Pre-smoothing: red then black
@@ -646,7 +670,7 @@ void Engine::enqueue_vcycle(const ListSet &ls) {
 void Engine::enqueue_iteration(const ListSet &ls) {
   if (lazy) {
     enqueue_fused_rest(ls);
-    launch_fin(T, FIN_RZ, mixed, stream, 1);
+    launch_fin(T, FIN_RZ, mixed, stream, local_on() ? 2 : 1);
     launch_spmv_p(T, ls.fine, 1, kmode(), stream);
     launch_fin(T, FIN_PQ, mixed, stream, 1);
     launch_vdown(T, ls.fdn[0], 0, mixed, VD_CONT, stream);
@@ -944,6 +968,147 @@ int Engine::run_steps(std::vector<Job> &jobs) {
       for (int p = 0; p < np; ++p) h_sc[p].live = 0;
     }
   }
+  HIP_TRY(hipStreamSynchronize(stream));
+  return ST_OK;
+}
+
+// One unit of device-controlled stepping: for every problem whose state
+// asks for it, the next substep's assembly and warm start, the prologue of
+// the fused iteration, one PCG iteration, the true-residual verification,
+// E += dE, the controller and the copy of a finished run's E.
+void Engine::enqueue_unit(const ListSet &ls, const CtlParams &cp) {
+  launch_assemble(T, ls.fine, prm.c, prm.theta, prm.d_max, prm.r_min, mixed, stream);
+  for (int l = 1; l < Lmax; ++l)
+    launch_coarsen(T, ls.exist[l], l, prm.coarse_scale, mixed, prm.coarse_op, stream);
+  if (mixed && prm.local_sweeps > 0)
+    launch_lmask(T, ls.fine, prm.local_coupling, stream);
+  launch_fin(T, FIN_BB, mixed, stream);
+  if (prm.warm_start > 1) {
+    launch_warm_x(T, ls.fine, stream);
+    launch_fin(T, FIN_WARM, mixed, stream);
+  }
+  launch_warm_revert(T, ls.fine, stream);
+  launch_fin(T, FIN_STAGE, mixed, stream);
+  if (lazy) {
+    launch_vdown(T, ls.fdn[0], 0, mixed, VD_FRESH, stream);
+    launch_fin(T, FIN_FRESH, mixed, stream);
+  }
+  enqueue_iteration(ls);
+  launch_xfix(T, ls.fine, kmode(), stream);
+  launch_fin(T, FIN_XFIX, mixed, stream);
+  launch_true_resid(T, ls.fine, stream);
+  launch_fin(T, FIN_TRUE, mixed, stream);
+  launch_update_E(T, ls.fine, prm.e_floor, 0, stream, 1);
+  launch_fin(T, FIN_STEP, mixed, stream, 1);
+  launch_control(T, cp, stream);
+  launch_copy_E(T, ls.fine, stream);
+}
+
+// Steps of every job with the substep control on the device (Sec. 3.4, the
+// radiation subcycling loop): n_steps steps of j.dt (or, adaptive, steps of
+// the controller's dt_next from j.dt until t_end), each subcycled after a
+// failed solve.  The host sets up the first substep as run_steps does, then
+// replays a graph of `units` units and reads the state once per replay.  The
+// cycle stays as configured (no adaptive switch inside a run).
+int Engine::run_advance(std::vector<Job> &jobs, int n_steps, int adaptive,
+                        double t_end, int units) {
+  const int np = (int)jobs.size();
+  std::vector<CtlDev> hc(np);
+  for (int p = 0; p < np; ++p) {
+    Job &j = jobs[p];
+    const double h0 = adaptive ? std::min(j.dt, t_end) : j.dt;
+    fill_step(p, j.E, j.kappa, j.eta, h0, j.a, j.adot);
+    set_warm(p, h0);
+    h_sd[p].Eout = j.E;  // the first substep covers its step: it writes E
+    CtlDev &c = hc[p];
+    std::memset(&c, 0, sizeof(c));
+    c.E = j.E;
+    c.dt0 = j.dt;
+    c.t_end = t_end;
+    c.n_steps = n_steps;
+    c.adaptive = adaptive;
+    c.dt = c.h = h0;
+    c.target = 1;
+    c.prev_ok = prev_ok[p];
+    c.xcur = xcur[p];
+    c.xold = xold[p];
+    c.warm_now = warm_now[p];
+    c.prev_h = prev_h[p];
+    c.prev_h2 = prev_h2[p];
+    Scal &sc = h_sc[p];
+    sc.ctl = 1;
+    sc.stage = 1;
+    sc.live = 1;
+    sc.phase = PH_DONE;
+    sc.active = 0;
+    sc.xlag = 0;
+  }
+  HIP_TRY(hipMemcpyAsync(T.ctl, hc.data(), sizeof(CtlDev) * np, hipMemcpyHostToDevice,
+                         stream));
+  int st = upload_pd();
+  if (st) return st;
+  st = upload_sd_sc();
+  if (st) return st;
+  const CtlParams cp{prm.tau_tol, prm.max_dt_cuts, prm.warm_start};
+  Captured &g = unit_graphs[units];
+  if (!g.exec) {
+    if (!cap_stream)
+      HIP_TRY(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+    hipStream_t saved = stream;
+    stream = cap_stream;
+    for (int u = 0; u < units; ++u) enqueue_unit(all, cp);
+    stream = saved;
+    HIP_TRY(hipStreamEndCapture(cap_stream, &g.graph));
+    HIP_TRY(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+  }
+  for (;;) {
+    HIP_TRY(hipGraphLaunch(g.exec, stream));
+    HIP_TRY(hipMemcpyAsync(hc.data(), T.ctl, sizeof(CtlDev) * np, hipMemcpyDeviceToHost,
+                           stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    bool all_done = true;
+    for (const CtlDev &c : hc) all_done = all_done && c.done;
+    if (all_done) break;
+  }
+  // the host mirrors follow the device: tables, the iterate buffer in use,
+  // the warm-start history, and the problems leave device control
+  HIP_TRY(hipMemcpyAsync(h_pd.data(), T.pd, sizeof(ProbDev) * np, hipMemcpyDeviceToHost,
+                         stream));
+  HIP_TRY(hipMemcpyAsync(h_sd.data(), T.sd, sizeof(StepDev) * np, hipMemcpyDeviceToHost,
+                         stream));
+  st = download_sc();
+  if (st) return st;
+  for (int p = 0; p < np; ++p) {
+    const CtlDev &c = hc[p];
+    Job &j = jobs[p];
+    mem[p].pd.x = h_pd[p].x;
+    prev_ok[p] = (char)c.prev_ok;
+    xcur[p] = c.xcur;
+    xold[p] = c.xold;
+    warm_now[p] = (char)c.warm_now;
+    prev_h[p] = c.prev_h;
+    prev_h2[p] = c.prev_h2;
+    j.status = c.status;
+    j.iters = c.iters;
+    j.restarts = c.restarts;
+    j.substeps = c.substeps;
+    j.cuts = c.cuts_total;
+    j.rho = c.rho;
+    j.dt_next = c.dt_next;
+    j.rel_resid = c.rel_resid;
+    j.err_bound = c.err_bound;
+    j.bnorm = c.bnorm;
+    j.dEnorm = c.dEnorm;
+    j.steps = c.steps;
+    j.t = c.t_total;
+    j.done = true;
+    h_sc[p].ctl = 0;
+    h_sc[p].stage = 0;
+    h_sc[p].live = 0;
+  }
+  st = upload_sd_sc();
+  if (st) return st;
   HIP_TRY(hipStreamSynchronize(stream));
   return ST_OK;
 }

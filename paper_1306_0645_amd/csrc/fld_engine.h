@@ -66,7 +66,7 @@ struct Job {
   const double *kappa = nullptr, *eta = nullptr;
   double dt = 0, a = 1, adot = 0;
   double t = 0, h = 0;
-  int cuts = 0, substeps = 0, iters = 0, restarts = 0;
+  int cuts = 0, substeps = 0, iters = 0, restarts = 0, steps = 0;
   int status = ST_OK;
   bool done = false, in_work = false;
   double rho = 0, dt_next = 0, rel_resid = 0, err_bound = 0, bnorm = 0,
@@ -134,6 +134,7 @@ class Engine {
     hipGraphExec_t exec = nullptr;
   };
   std::map<int, Captured> graphs;
+  std::map<int, Captured> unit_graphs;  // device-controlled units, by count
   hipStream_t cap_stream = nullptr;
   int last_iters = 0;       // iterations of the last solve (its slowest problem)
   bool first_batch = true;  // the next batch is a solve's first
@@ -163,6 +164,9 @@ class Engine {
   // FP32 direction, 2 mixed with an FP64 direction
   int kmode() const { return mixed ? (prm.direction_fp64 ? 2 : 1) : 0; }
   bool switch_helps() const;
+  // extra red/black sweeps over the strongly coupled finest cells after the
+  // fused cycle's post-sweep (mixed precision)
+  bool local_on() const { return mixed && fused && prm.local_sweeps > 0; }
   // adaptive cycle choice after a solve that took max_iters iterations
   int adapt_cycle(int max_iters);
 
@@ -175,6 +179,9 @@ class Engine {
   void finish_x(const ListSet &ls);
   int run_solve(bool predicted = false, bool commit = false);
   int run_steps(std::vector<Job> &jobs);
+  void enqueue_unit(const ListSet &ls, const CtlParams &cp);
+  int run_advance(std::vector<Job> &jobs, int n_steps, int adaptive, double t_end,
+                  int units);
   int check_every() const;
   void fill_step(int p, const double *E, const double *kappa, const double *eta,
                  double dt, double a, double adot);

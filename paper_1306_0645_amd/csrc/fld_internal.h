@@ -60,11 +60,17 @@ struct ProbDev {
   // coarse-grid correction interpolated to every cell (k_tri_fine)
   float *ef;
   double *r2;            // second residual buffer (fused V(1,1) iteration)
+  // local smoothing (mixed fused cycle): 1 where the coupling to the
+  // neighbours dominates the cell's diagonal (sum of faces > local_coupling
+  // x diagonal), else 0
+  unsigned char *lmask;
   double *cs;            // coarsest-level CG scratch: 4 * n_coarsest doubles
   int levels;            // number of multigrid levels
   int t0, t1;            // range of this problem's tiles in the finest list
   int f0, f1;            // range of its fused-cycle finest tiles
   int tail;              // first level of the single-workgroup V-cycle tail
+  double *xb[3];         // the dE buffers (iterate and warm-start history)
+  double *Ework;         // working copy of E while a step is subcycled
 };
 
 // Per-step inputs of one problem (uploaded by the host at each assembly).
@@ -103,6 +109,29 @@ struct Scal {
   int rbuf, has_dir, xlag, snew;
   int fresh;             // (re)started: the finest down pass is still due
   int committed;         // E += dE of this solve is done (FIN_STEP)
+  // device-controlled stepping (fld_advance): ctl = 1 while the device runs
+  // the substeps; stage 1: the next substep's assembly is due, 2: its warm
+  // start is due, 0: neither (iterating, verifying, or done)
+  int ctl, stage;
+};
+
+// Device-side step control of one problem (fld_advance): the requested run,
+// its progress, and the warm-start history the host keeps otherwise.
+struct CtlDev {
+  double *E;             // the caller's E: E^0 in, E after the last step out
+  double dt0, t_end;     // step size (adaptive: the first step's); end time
+  int n_steps, adaptive; // fixed steps of dt0, or steps of the controller's
+                         // dt_next until t_end
+  int done, status;      // the run is over; its status
+  double t, h, dt;       // time reached in the current step, the substep
+                         // being taken, the current step's size
+  double t_total;        // time covered by the completed steps
+  int steps, substeps, cuts, cuts_total, iters, restarts;
+  int in_work, target;   // E lives in Ework; the substep writes E (1) or Ework (2)
+  int copy_due;          // the run's E is in Ework: copy it to E
+  int prev_ok, xcur, xold, warm_now;
+  double prev_h, prev_h2;
+  double rho, dt_next, rel_resid, err_bound, bnorm, dEnorm;
 };
 
 // A tile: cells [x0, x0+tx) x [y0, y0+ty) x [z0, z0+tz) of one level of one
@@ -127,6 +156,9 @@ struct Tables {
   StepDev *sd;      // [nprob]
   Scal *sc;         // [nprob]
   double *part;     // [n finest tiles][2] block partial sums
+  double *lpart;    // [n finest tiles][2] the local sweeps' r.z changes
+  int *lcnt;        // [n finest tiles] cells of the tile in the local mask
+  CtlDev *ctl;      // [nprob] device-side step control
   double *gpart;    // [n finest tiles][kAsmSums] sums of the assembly
   int nprob;
 };
@@ -149,7 +181,7 @@ enum : int {
   K_UPDATE_E, K_VDOWN_F, K_VDOWN_C, K_VUP_F, K_VUP_C, K_CHEM_H, K_ION_SUM,
   K_WARM_REVERT, K_JACOBI0_F, K_JACOBI_F, K_JACOBI_OUT,
   K_JACOBI_C, K_PROLONG_ADD_F, K_PROLONG_ADD_C, K_SPMV_PX, K_XFIX, K_WARM_X,
-  K_TRI_FINE, K_NUM
+  K_TRI_FINE, K_LMASK, K_LOCAL, K_CONTROL, K_COPY_E, K_NUM
 };
 
 // Brackets one launch with hipEvents when its kernel id is selected.
@@ -217,6 +249,22 @@ void launch_warm_x(const Tables &T, TileList L0, hipStream_t s);
 // cell (before the finest up pass of a trilinear mixed cycle); L1: level-1
 // tiles, one thread per level-1 cell
 void launch_tri_fine(const Tables &T, TileList L1, hipStream_t s);
+// local smoothing of the mixed fused cycle: the mask of strongly coupled
+// finest cells (after the assembly), and one red/black sweep over them
+// (colour 1 = black, then 0 = red) after the finest post-sweep, in z32,
+// with the change of r.z per tile in lpart[2 t + colour]
+void launch_lmask(const Tables &T, TileList L0, double coupling, hipStream_t s);
+void launch_local(const Tables &T, TileList L0, int colour, hipStream_t s);
+// device-controlled stepping (fld_control.hip): the controller after each
+// unit's verification and commit (one block per problem), and the copy of a
+// finished run's E from the working copy
+struct CtlParams {
+  double tau_tol;
+  int max_dt_cuts;
+  int warm_start;
+};
+void launch_control(const Tables &T, CtlParams cp, hipStream_t s);
+void launch_copy_E(const Tables &T, TileList L0, hipStream_t s);
 void launch_apply(const Tables &T, TileList L0, const double *u, double *out,
                   hipStream_t s);
 void launch_set_r(const Tables &T, TileList L0, const double *r, int prec,
@@ -248,8 +296,11 @@ enum : int {
                   // ||r||^2, convergence, switch the residual buffer
   FIN_XFIX = 9,   // after k_xfix: the deferred x update is done
   FIN_FRESH = 10, // after the prologue's down pass: the problems iterate on
-  FIN_WARM = 11   // after k_warm_x: keep the projected guess if it reduces
+  FIN_WARM = 11,  // after k_warm_x: keep the projected guess if it reduces
                   // the residual
+  FIN_STAGE = 12  // device-controlled stepping: the substep's warm start is
+                  // done, its PCG runs on
+  // (FIN_RZ with alt = 2: the fused cycle's partials plus the local sweeps')
 };
 
 }  // namespace fld

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Tables T, TileList L0,
   const int tid = get_tile_index(L0);
   const Tile t = L0.base[tid];
   const Scal &sc = T.sc[t.prob];
-  if (!sc.live) return;
+  if (!asm_due(sc)) return;
   const LevelDev L = T.lv[t.prob];
   const ProbDev P = T.pd[t.prob];
   const StepDev S = T.sd[t.prob];
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void k_coarsen(Tables T, TileList LC,
                                                     int mixed, int op) {
   const Tile t = get_tile(LC);
   const Scal &sc = T.sc[t.prob];
-  if (!sc.live) return;
+  if (!asm_due(sc)) return;
   const LevelDev F = T.lv[(lc - 1) * T.nprob + t.prob];
   const LevelDev C = T.lv[lc * T.nprob + t.prob];
   const Col col = tile_col(t);
@@ -980,7 +980,7 @@ __global__ __launch_bounds__(kBlock) void k_warm_x(Tables T, TileList TL) {
   const Tile t = TL.base[tid];
   const Scal &sc = T.sc[t.prob];
   const StepDev S = T.sd[t.prob];
-  if (!sc.live || !(S.warm > 1.0) || sc.phase != PH_ITER || sc.cold) return;
+  if (!warm_due(sc) || !(S.warm > 1.0) || sc.phase != PH_ITER || sc.cold) return;
   const LevelDev L = T.lv[t.prob];
   const ProbDev P = T.pd[t.prob];
   const double c1 = sc.c1, c2 = sc.c2;
@@ -1079,13 +1079,85 @@ __global__ __launch_bounds__(kBlock) void k_tri_fine(Tables T, TileList TL) {
   }
 }
 
+// Local smoothing.  Where a cell's coupling to its neighbours dominates its
+// diagonal (an ionized bubble: little absorption, D near D_max, so the cell
+// is almost a pure diffusion cell), one red/black sweep leaves the error that
+// is smooth inside the bubble nearly untouched and the coarse levels, whose
+// cells mix bubble and neutral children, do not represent it; extra sweeps
+// restricted to those cells act on it at a small fraction of a full sweep's
+// cost.  k_lmask marks them once per assembly from the FP64 finest operator
+// (and counts them per tile); k_local runs one half-sweep of colour `colour`
+// over the marked cells of a tile, in place in the cycle's FP32 output z32,
+// with the cycle's scaled right-hand side and FP32 coefficients, and records
+// the change of r.z that the update makes (r the FP64 residual the cycle ran
+// on, z = s z32).
+__global__ __launch_bounds__(kBlock) void k_lmask(Tables T, TileList TL,
+                                                  double coupling) {
+  const int tid = get_tile_index(TL);
+  const Tile t = TL.base[tid];
+  const Scal &sc = T.sc[t.prob];
+  if (!asm_due(sc)) return;
+  const LevelDev L = T.lv[t.prob];
+  const ProbDev P = T.pd[t.prob];
+  const Col col = tile_col(t);
+  double cnt = 0.0;
+  if (col.on) {
+    for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+      const Nb n = nbrs(col.i, col.j, k, L.nx, L.ny, L.nz);
+      const double faces = L.Tx[n.c] + L.Tx[n.xm] + L.Ty[n.c] + L.Ty[n.ym] +
+                           L.Tz[n.c] + L.Tz[n.zm];
+      const bool m = faces > coupling * L.diag[n.c];
+      P.lmask[n.c] = m ? 1 : 0;
+      cnt += m ? 1.0 : 0.0;
+    }
+  }
+  __shared__ double sh[kBlock / 64];
+  const double c = block_sum<kBlock / 64>(cnt, sh);
+  if (threadIdx.x == 0) T.lcnt[tid] = (int)c;
+}
+
+__global__ __launch_bounds__(kBlock) void k_local(Tables T, TileList TL, int colour) {
+  const int tid = get_tile_index(TL);
+  const Tile t = TL.base[tid];
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.active) return;
+  double dz = 0.0;
+  if (T.lcnt[tid] > 0) {
+    const LevelDev L = T.lv[t.prob];
+    const ProbDev P = T.pd[t.prob];
+    const Coef<float> C = coefs<float>(L);
+    const double *r = rcur(P, sc);
+    const double inv_s = sc.inv_s, s = sc.s;
+    float *z = P.z32;
+    const Col col = tile_col(t);
+    if (col.on) {
+      for (int k = t.z0; k < t.z0 + t.tz; ++k) {
+        if (((col.i + col.j + k) & 1) != colour) continue;
+        const Nb n = nbrs(col.i, col.j, k, L.nx, L.ny, L.nz);
+        if (!P.lmask[n.c]) continue;
+        const float f = (float)(r[n.c] * inv_s);
+        const float sum = C.tx[n.c] * z[n.xp] + C.tx[n.xm] * z[n.xm] +
+                          C.ty[n.c] * z[n.yp] + C.ty[n.ym] * z[n.ym] +
+                          C.tz[n.c] * z[n.zp] + C.tz[n.zm] * z[n.zm];
+        const float xn = (f + sum) * recip(C.d[n.c]);
+        const float xo = z[n.c];
+        z[n.c] = xn;
+        dz += r[n.c] * (s * ((double)xn - (double)xo));
+      }
+    }
+  }
+  __shared__ double sh[kBlock / 64];
+  const double v = block_sum<kBlock / 64>(dz, sh);
+  if (threadIdx.x == 0) T.lpart[2 * tid + colour] = v;
+}
+
 // Warm-started problems whose guess was dropped (by FIN_BB or FIN_WARM: it
 // did not reduce the residual): x = 0, r = b.  And b = 0: the solution is 0
 // whatever the guess.
 __global__ __launch_bounds__(kBlock) void k_warm_revert(Tables T, TileList TL) {
   const Tile t = get_tile(TL);
   const Scal &sc = T.sc[t.prob];
-  if (!sc.live || !(T.sd[t.prob].warm > 0.0)) return;
+  if (!warm_due(sc) || !(T.sd[t.prob].warm > 0.0)) return;
   const bool zero_b = sc.phase == PH_DONE && sc.status == ST_OK;
   if (!zero_b && !(sc.phase == PH_ITER && sc.cold)) return;
   const LevelDev L = T.lv[t.prob];
@@ -1217,7 +1289,7 @@ __device__ __forceinline__ void fail(Scal &sc, int status) {
 __global__ __launch_bounds__(kFinBlock) void k_fin_bb(Tables T, int mixed) {
   const int p = blockIdx.x;
   Scal &sc = T.sc[p];
-  if (!sc.live) return;
+  if (!asm_due(sc)) return;
   const ProbDev &P = T.pd[p];
   double a[kAsmSums];
 #pragma unroll
@@ -1289,6 +1361,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin_bb(Tables T, int mixed) {
     if (!finite(rr)) fail(sc, ST_ENONFINITE);
   }
   set_scale(sc, P.n, mixed);
+  if (sc.ctl) sc.stage = 2;  // device-controlled: the warm start is next
 }
 
 __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixed,
@@ -1308,13 +1381,21 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(Tables T, int which, int mixe
     case FIN_XFIX: part = sc.xlag && sc.phase != PH_ITER; break;
     case FIN_FRESH: part = sc.active && sc.fresh; break;
     case FIN_WARM:
-      part = sc.live && T.sd[p].warm > 1.0 && sc.phase == PH_ITER && !sc.cold;
+      part = warm_due(sc) && T.sd[p].warm > 1.0 && sc.phase == PH_ITER && !sc.cold;
       break;
+    case FIN_STAGE:
+      if (threadIdx.x == 0 && sc.ctl && sc.stage == 2) sc.stage = 0;
+      return;
     default: part = sc.active != 0; break;
   }
   if (!part) return;
   // independent loads in flight: 4 per thread per round, summed in order
   double a0 = 0.0, a1 = 0.0;
+  if (which == FIN_RZ && alt == 2) {
+    // r.z changes of the local sweeps (black, red), per finest tile
+    for (int t = P.t0 + (int)threadIdx.x; t < P.t1; t += kFinBlock)
+      a0 += T.lpart[2 * t] + T.lpart[2 * t + 1];
+  }
   int t = t0 + (int)threadIdx.x;
   for (; t + 3 * kFinBlock < t1; t += 4 * kFinBlock) {
     double v[8];
@@ -1466,7 +1547,7 @@ static const char *kKernelNames[K_NUM] = {
     "vdown_coarse", "vup_fine", "vup_coarse", "chem_h", "ionized_sum",
     "warm_revert", "jacobi0_fine", "jacobi_fine", "jacobi_out",
     "jacobi_coarse", "prolong_add_fine", "prolong_add_coarse", "spmv_px",
-    "xfix", "warm_x", "tri_fine"};
+    "xfix", "warm_x", "tri_fine", "lmask", "local", "control", "copy_E"};
 
 namespace prof {
 struct Rec {
@@ -1636,6 +1717,14 @@ void launch_true_resid(const Tables &T, TileList L0, hipStream_t s) {
 
 void launch_tri_fine(const Tables &T, TileList L0, hipStream_t s) {
   if (L0.nblocks) LAUNCH(K_TRI_FINE, k_tri_fine, L0.nblocks, kBlock, s, T, L0);
+}
+
+void launch_lmask(const Tables &T, TileList L0, double coupling, hipStream_t s) {
+  if (L0.nblocks) LAUNCH(K_LMASK, k_lmask, L0.nblocks, kBlock, s, T, L0, coupling);
+}
+
+void launch_local(const Tables &T, TileList L0, int colour, hipStream_t s) {
+  if (L0.nblocks) LAUNCH(K_LOCAL, k_local, L0.nblocks, kBlock, s, T, L0, colour);
 }
 
 void launch_warm_x(const Tables &T, TileList L0, hipStream_t s) {

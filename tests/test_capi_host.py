@@ -152,3 +152,30 @@ def test_chem_defaults_and_validation(fld):
     s = fld._lib.fld_chem_ionized_sum
     assert s(ctypes.byref(grid), None, None, x) == EINVAL
     assert s(ctypes.byref(grid), None, x, ctypes.c_void_p(x.value + 8)) == EINVAL
+
+
+def test_struct_layouts_match_the_header(fld, tmp_path):
+    """The ctypes mirrors of fld_grid, fld_params, fld_stats, fld_request and
+    fld_result have the size and field offsets the C compiler gives the
+    header's structs (a field added on one side only would shift every
+    field after it)."""
+    import subprocess
+    structs = {"fld_grid": fld.Grid, "fld_params": fld.Params, "fld_stats": fld.Stats,
+               "fld_request": fld.Request, "fld_result": fld.Result}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fld.h"',
+             'int main(void) {']
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)

@@ -123,7 +123,17 @@ def _prolong(e, trilinear):
     return e
 
 
-def _vcycle(ops, l, f, nu, trilinear=False):
+def _local_mask(op, coupling):
+    """Cells whose coupling to the neighbours dominates their diagonal."""
+    D, (Tx, Ty, Tz) = op
+    faces = Tx + np.roll(Tx, 1, 2) + Ty + np.roll(Ty, 1, 1) + Tz + np.roll(Tz, 1, 0)
+    return faces > coupling * D
+
+
+def _vcycle(ops, l, f, nu, trilinear=False, local=(0, 0.9)):
+    """local = (sweeps, coupling): after the finest post-sweep, `sweeps`
+    more black-then-red half-sweep pairs restricted to the cells of
+    _local_mask (the mixed fused cycle's local smoothing)."""
     op = ops[l]
     if l == len(ops) - 1:
         return _solve_exact(op, f)
@@ -140,6 +150,11 @@ def _vcycle(ops, l, f, nu, trilinear=False):
     for _ in range(nu):
         x = _half_sweep(op, f, x, ~red)
         x = _half_sweep(op, f, x, red)
+    if l == 0 and local[0] > 0:
+        m = _local_mask(op, local[1])
+        for _ in range(local[0]):
+            x = _half_sweep(op, f, x, ~red & m)
+            x = _half_sweep(op, f, x, red & m)
     return x
 
 
@@ -221,35 +236,44 @@ def test_vcycle_is_the_textbook_cycle(fld, oracle_mod, prec, nu, levels,
     ops = [(D, (Ax, Ay, Az))]
     for _ in range(levels - 1):
         ops.append(_coarsen(ops[-1], prm.coarse_scale))
-    zr = _vcycle(ops, 0, f, nu)
+    # the mixed fused V(1,1) cycle ends with the local sweeps
+    local = (prm.local_sweeps, prm.local_coupling) if (prec == 1 and nu == 1) else (0, 0.9)
+    zr = _vcycle(ops, 0, f, nu, local=local)
     err = rel_l2(z, zr)
     print(f"[vcycle] prec={prec} nu={nu} levels={levels} fused={fused_levels} "
+          f"local cells={_local_mask(ops[0], prm.local_coupling).mean():.3f} "
           f"err={err:.2e}", flush=True)
     assert err <= (1e-9 if prec == 0 else 2e-5)
 
 
-VARIANTS = [  # (prec, levels, fused_levels, prolongation, coarse_op)
-    (1, 2, 0, 1, 0), (1, 3, 0, 1, 0), (1, 3, 9, 1, 0),
-    (0, 3, 0, 0, 1), (1, 3, 0, 0, 1), (1, 3, 0, 1, 1),
+VARIANTS = [  # (prec, levels, fused_levels, prolongation, coarse_op, local_sweeps)
+    (1, 2, 0, 1, 0, 0), (1, 3, 0, 1, 0, 0), (1, 3, 9, 1, 0, 1),
+    (0, 3, 0, 0, 1, 0), (1, 3, 0, 0, 1, 0), (1, 3, 0, 1, 1, 1),
+    (1, 3, 0, 0, 0, 1), (1, 3, 0, 1, 0, 2),
 ]
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("prec,levels,fused_levels,prolongation,coarse_op", VARIANTS)
+@pytest.mark.parametrize("prec,levels,fused_levels,prolongation,coarse_op,local",
+                         VARIANTS)
 def test_vcycle_variants_are_the_textbook_cycle(fld, oracle_mod, prec, levels,
                                                 fused_levels, prolongation,
-                                                coarse_op):
+                                                coarse_op, local):
     """The mixed V(1,1) cycle with the trilinear correction (the fused finest
     passes with the interpolated correction of k_tri_fine, the coarse fused or
-    per-half-sweep kernels and the tail), and the series coarse-face rule:
-    the same textbook cycle with those two definitions."""
+    per-half-sweep kernels and the tail), the series coarse-face rule and
+    the local sweeps over the strongly coupled cells: the same textbook cycle
+    with those definitions.  A longer step than the other cycle tests and a
+    lower mask threshold than the default, so that about 6 % of the cells
+    are in the local mask."""
     log_case("vcycle_variant", prec=prec, levels=levels, fused=fused_levels,
-             prolongation=prolongation, coarse_op=coarse_op)
+             prolongation=prolongation, coarse_op=coarse_op, local=local)
     shape = (24, 40, 96)
-    p = synth.random_problem(shape, 62, sigma_ln=1.5, n_src=3, dt_factor=0.5)
+    p = synth.random_problem(shape, 62, sigma_ln=1.5, n_src=3, dt_factor=2.0)
     prm = params(fld, p, precision=prec, mg_levels=levels, nu_pre=1, nu_post=1,
                  cycle_switch=0, fused_tile_z=8, fused_levels=fused_levels,
-                 prolongation=prolongation, coarse_op=coarse_op)
+                 prolongation=prolongation, coarse_op=coarse_op, local_sweeps=local,
+                 local_coupling=0.9)
     S = fld.Solver(p["shape"], p["h"], prm)
     S.assemble(dev(p["E"]), dev(p["kappa"]), dev(p["eta"]), p["dt"], p["a"], 0.0)
     f = np.random.default_rng(8).normal(size=shape)
@@ -259,13 +283,24 @@ def test_vcycle_variants_are_the_textbook_cycle(fld, oracle_mod, prec, levels,
     ops = [(D, (Ax, Ay, Az))]
     for _ in range(levels - 1):
         ops.append(_coarsen(ops[-1], prm.coarse_scale, series=bool(coarse_op)))
-    zr = _vcycle(ops, 0, f, 1, trilinear=bool(prolongation))
+    lc = prm.local_coupling
+    loc = (local, lc) if prec == 1 else (0, lc)
+    zr = _vcycle(ops, 0, f, 1, trilinear=bool(prolongation), local=loc)
     err = rel_l2(z, zr)
-    # the other definition is measurably different (the check has teeth)
+    frac = _local_mask(ops[0], lc).mean()
+    # each of the other definitions is measurably different (the check has
+    # teeth): the other coarse-face rule, the other correction, and (mixed)
+    # one local sweep more or less
     ops2 = [ops[0]]
     for _ in range(levels - 1):
         ops2.append(_coarsen(ops2[-1], prm.coarse_scale, series=not coarse_op))
-    other = rel_l2(z, _vcycle(ops2, 0, f, 1, trilinear=not prolongation))
-    print(f"[vcycle variant] err={err:.2e} other definition={other:.2e}", flush=True)
+    others = [rel_l2(z, _vcycle(ops2, 0, f, 1, trilinear=bool(prolongation), local=loc)),
+              rel_l2(z, _vcycle(ops, 0, f, 1, trilinear=not prolongation, local=loc))]
+    if prec == 1:
+        others.append(rel_l2(z, _vcycle(ops, 0, f, 1, trilinear=bool(prolongation),
+                                        local=(local + 1 if local == 0 else local - 1, lc))))
+    print(f"[vcycle variant] local cells={frac:.3f} err={err:.2e} "
+          f"other definitions={['%.1e' % o for o in others]}", flush=True)
     assert err <= (1e-9 if prec == 0 else 2e-5)
-    assert other > 100 * max(err, 1e-9)
+    assert 0.02 < frac < 0.5
+    assert min(others) > 10 * max(err, 1e-9)
