@@ -30,10 +30,11 @@
  *    is internal.  The caller owns all field memory and the workspace.
  *  - Units are the caller's, but must be consistent: c, dx, 1/kappa, dt, and
  *    D_max (length^2/time), R_min (1/length) in the same length/time units.
- *  - The mesh is comoving with expansion factor a (Sec. 2 takes spatial
- *    derivatives with respect to the comoving position; E and eta are
- *    comoving densities).  Each step's operator uses the proper separation
- *    a*dx of neighbouring cells, and kappa is the proper opacity (per proper
+ *  - The mesh is comoving with expansion factor a: Sec. 2 takes every
+ *    spatial derivative with respect to the comoving position, and E and eta
+ *    are comoving densities, so eq. "fld" is posed on the comoving cell
+ *    sizes dx, dy, dz as printed and a enters the step only through adot/a;
+ *    kappa is the opacity the caller's chemistry gives (proper, per unit
  *    length); a = 1, adot = 0 for a static problem.
  *  - Work is enqueued on the hipStream_t given at create time (NULL = the
  *    default stream).  Calls that report convergence synchronise that stream.
@@ -237,8 +238,8 @@ fld_status fld_create(const fld_grid *g, const fld_params *p, void *hip_stream,
 /* Assemble one step's system (Sec. 2 limiter, Sec. 3.3 theta-method): face
  * coefficients from the limiter at E^n, the diagonal, b = dt (L E^n + eta),
  * and every coarse level of the multigrid hierarchy.  E_n, kappa, eta: device
- * FP64 [nz][ny][nx], read only, kappa >= 0.  dt > 0, a > 0 (cell separation
- * a*dx), adot/a enters the operator.  Enqueued; no synchronisation.
+ * FP64 [nz][ny][nx], read only, kappa >= 0.  dt > 0, a > 0; adot/a enters
+ * the operator.  Enqueued; no synchronisation.
  * Errors: FLD_EINVAL, FLD_EDEVICE. */
 fld_status fld_assemble(fld_handle *h, const double *E_n, const double *kappa,
                         const double *eta, double dt, double a, double adot);

@@ -272,7 +272,8 @@ def eds_expansion(t, H0):
 
 def hii_run(E, x, n_h, eta, h, c, d_max, r_min, sigma, hnu, alpha_b, outputs,
             dt0, tau_tol, e_floor, chem_substeps=1, tol=1e-13, max_cuts=8,
-            dts=None, max_steps=10 ** 7, t0=0.0, H0=None, theta=1.0):
+            dts=None, max_steps=10 ** 7, t0=0.0, H0=None, theta=1.0,
+            spacing="comoving"):
     """Radiation + chemistry in the operator-split order of Sec. 3.4.
 
     Each step t -> t + dt: the radiation step (with its 10x cut-and-subcycle
@@ -283,8 +284,13 @@ def hii_run(E, x, n_h, eta, h, c, d_max, r_min, sigma, hnu, alpha_b, outputs,
     steps land on the output times (absolute times, the run starts at t0).
     ``dts`` replays a given sequence of step sizes instead.  With H0 the
     fields are comoving in an Einstein-de Sitter background: each step uses
-    a and adot at its midpoint.  Returns the final fields, the ionized radius
-    (comoving) at every output time and the step sizes taken."""
+    a and adot at its midpoint.  spacing: "comoving" (the reading the solver
+    takes) poses eq. "fld" as printed, every spatial derivative with respect
+    to the comoving position (Sec. 2); "proper" instead poses the diffusion
+    operator on the proper separation a h of the comoving cells (the step is
+    given a h), for comparing the two readings.
+    Returns the final fields, the ionized radius (comoving) at every output
+    time and the step sizes taken."""
     E = _arr(E).copy()
     x = _arr(x, E.shape).copy()
     n_h = _arr(n_h, E.shape)
@@ -299,7 +305,8 @@ def hii_run(E, x, n_h, eta, h, c, d_max, r_min, sigma, hnu, alpha_b, outputs,
         target = outputs[k]
         step_dt = float(dts[i]) if dts is not None else min(dt, target - t)
         a, adot = eds_expansion(t + 0.5 * step_dt, H0) if H0 else (1.0, 0.0)
-        E, st, s = step(E, kappa, eta, h, c, d_max, r_min, step_dt,
+        hs = h if spacing == "comoving" else tuple(v * a for v in h)
+        E, st, s = step(E, kappa, eta, hs, c, d_max, r_min, step_dt,
                         theta=theta, a=a, adot=adot, tol=tol,
                         tau_tol=tau_tol, e_floor=e_floor, max_cuts=max_cuts)
         if st != OK:

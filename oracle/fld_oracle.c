@@ -35,11 +35,10 @@
  *   - Ebar <= 0 (including E_p = E_q = 0) gives R = R_min.
  *   - kbar = 0 when either cell has kappa = 0 (the limit of the harmonic mean).
  *   - kappa, eta, a, adot are frozen over the step.
- *   - The mesh is comoving (Sec. 2 takes spatial derivatives with respect to
- *     the comoving position and E is the comoving energy density), so the
- *     step's operator uses the proper separation a*dx of neighbouring cells:
- *     every cell size below is multiplied by a (a = 1: static problems),
- *     and a enters otherwise only through adot/a.
+ *   - The mesh is comoving and eq. "fld" is taken as printed: Sec. 2 takes
+ *     every spatial derivative with respect to the comoving position, so
+ *     the limiter's R and the diffusion term use the comoving cell sizes,
+ *     and a enters the step only through adot/a.
  *   - The time-step estimator the paper defers to prior work is replaced by
  *     rho = RMS(dE / max(|E^{n+1}|, e_floor)), dt_next = dt * clamp(tau/rho,
  *     0.1, 2).  This controller is PARITY UNPINNED (only its mechanism is
@@ -251,8 +250,6 @@ static int sys_init(or_system *s, int nx, int ny, int nz, double dx, double dy,
                     double d_max, double r_min, double theta, double dt,
                     double a, double adot) {
   int64_t n = (int64_t)nx * ny * nz;
-  /* proper separation of the comoving cells */
-  dx *= a; dy *= a; dz *= a;
   s->nx = nx; s->ny = ny; s->nz = nz;
   s->dx = dx; s->dy = dy; s->dz = dz;
   s->c = c; s->theta = theta; s->dt = dt; s->adot_over_a = adot / a;
@@ -289,7 +286,7 @@ void oracle_system(int nx, int ny, int nz, double dx, double dy, double dz,
   sys_init(&s, nx, ny, nz, dx, dy, dz, E, kappa, c, d_max, r_min, theta, dt, a,
            adot);
   sys_diag(&s, diag);
-  /* s.dx, s.dy, s.dz: the proper separation used by the operator */
+  /* s.dx, s.dy, s.dz: the cell sizes the operator uses */
   for (int64_t p = 0; p < n; ++p) {
     Ax[p] = theta * dt * s.Dx[p] / (s.dx * s.dx);
     Ay[p] = theta * dt * s.Dy[p] / (s.dy * s.dy);
@@ -348,8 +345,8 @@ void oracle_residual_at(int nx, int ny, int nz, double dx, double dy, double dz,
                         double dt, double a, double adot, const double *x,
                         const int64_t *cells, int64_t ncells, double *res,
                         double *rhs) {
-  /* proper separation of the comoving cells, as in sys_init */
-  double hd[3] = {a * dx, a * dy, a * dz};
+  /* comoving cell sizes, as in sys_init */
+  double hd[3] = {dx, dy, dz};
   double h2[3] = {hd[0] * hd[0], hd[1] * hd[1], hd[2] * hd[2]};
   double aa = adot / a;
   OR_FOR

@@ -543,10 +543,11 @@ void Engine::fill_step(int p, const double *E, const double *kappa,
   S.Eout = nullptr;
   S.dt = dt;
   S.adot_a = adot / a;
-  // the mesh is comoving: the operator uses the proper separation a * dx
-  S.idx = 1.0 / (a * grids[p].dx);
-  S.idy = 1.0 / (a * grids[p].dy);
-  S.idz = 1.0 / (a * grids[p].dz);
+  // comoving mesh, derivatives with respect to the comoving position (Sec.
+  // 2): the comoving cell sizes; a enters only through adot / a
+  S.idx = 1.0 / grids[p].dx;
+  S.idy = 1.0 / grids[p].dy;
+  S.idz = 1.0 / grids[p].dz;
   S.warm = 0.0;
   S.w1 = S.w2 = 0.0;
   S.h1 = S.h2 = nullptr;

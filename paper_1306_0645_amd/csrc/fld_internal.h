@@ -78,7 +78,7 @@ struct StepDev {
   const double *E, *kappa, *eta;
   double *Eout;          // destination of E + dE (may equal E)
   double dt, adot_a;     // dt and adot/a
-  double idx, idy, idz;  // 1 / (a dx), 1 / (a dy), 1 / (a dz)
+  double idx, idy, idz;  // 1 / dx, 1 / dy, 1 / dz (comoving cell sizes)
   // warm start: 0: x0 = 0; 1: x0 = w1 dE(n) + w2 dE(n-1) (extrapolation);
   // 2: x0 = c1 dE(n) + c2 dE(n-1) with c from the Galerkin condition in the
   // new operator, (dE(i), A dE(j)) c_j = (dE(i), b)

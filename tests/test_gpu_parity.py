@@ -372,8 +372,8 @@ def test_adaptive_cycle_switch(fld, oracle_mod, prec):
 @pytest.mark.parametrize("theta", [1.0, 0.5])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_comoving_step_matches_oracle(fld, oracle_mod, theta, prec):
-    """a != 1: the operator on the proper separation a dx of the comoving
-    cells plus adot/a; assembly and the solve against the oracle."""
+    """a != 1: the operator on the comoving cell sizes plus adot/a;
+    assembly and the solve against the oracle."""
     log_case("comoving", theta=theta, prec=prec)
     p = _problem((24, 32, 40), 23, theta=theta, dt_factor=0.1)
     p["a"] = 0.3

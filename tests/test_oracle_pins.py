@@ -158,10 +158,11 @@ def test_fourier_mode_decay(oracle_mod, theta, a):
     ragged anisotropic grid: A is circulant, so the mean and the mode evolve
     separately with growth factors (1 - (1-theta) dt mu)/(1 + theta dt mu),
     mu_k = adot/a + c kappa + D_max sum_d 4 sin^2(k_d h_d / 2) / h_d^2, where
-    h_d = a dx_d is the proper separation of the comoving cells."""
+    h_d = dx_d is the comoving cell size: every spatial derivative is with
+    respect to the comoving position (Sec. 2), so a enters only as adot/a."""
     nz, ny, nx = 8, 12, 10
     hc = (0.9, 1.4, 0.6)
-    h = tuple(a * v for v in hc)  # proper spacing
+    h = hc  # comoving spacing
     m = (2, 1, 3)  # mode numbers along x, y, z
     k0, E0, eps, c = 0.05, 1.0, 0.1, 2.0
     adot, dt = 0.03 * a, 0.7
@@ -199,13 +200,13 @@ def test_fourier_mode_decay(oracle_mod, theta, a):
 @pytest.mark.parametrize("a", [1.0, 0.25])
 def test_nyquist_mode_limiter_active(oracle_mod, a):
     """E = E0 (1 + eps (-1)^i) with D_max out of reach: every x face has
-    Ebar = E0 and |dE| = 2 eps E0, so with the proper spacing hx = a dx,
-    R = 2 eps / hx and D_x = c / sqrt(9 k0^2 + 4 eps^2 / hx^2).  The
-    x-Nyquist mode then has mu_N = c k0 + 4 D_x / hx^2 and the mean
-    mu_0 = c k0 (adot = 0)."""
+    Ebar = E0 and |dE| = 2 eps E0, so with the comoving spacing hx = dx
+    (whatever a is), R = 2 eps / hx and D_x = c / sqrt(9 k0^2 + 4 eps^2 /
+    hx^2).  The x-Nyquist mode then has mu_N = c k0 + 4 D_x / hx^2 and the
+    mean mu_0 = c k0 (adot = 0)."""
     nz, ny, nx = 4, 6, 8
     h = (0.5, 1.0, 1.5)
-    hx = a * h[0]
+    hx = h[0]
     k0, E0, eps, c, dt, theta = 0.4, 3.0, 0.2, 1.5, 0.25, 1.0
     s = (-1.0) ** np.arange(nx)[None, None, :] * np.ones((nz, ny, 1))
     E = E0 * (1 + eps * s)
@@ -283,7 +284,7 @@ def _dense_by_columns(P):
 @pytest.mark.parametrize("a", [1.0, 0.5])
 def test_matrix_structure(oracle_mod, a):
     """Brute-force columns A e_j against the exported system, on a static and
-    on a comoving mesh (proper separation a h)."""
+    on a comoving mesh (a != 1: only adot/a carries it)."""
     rng = np.random.default_rng(4)
     shape = (4, 6, 8)
     E = np.exp(rng.normal(0.0, 1.0, shape))
@@ -310,7 +311,7 @@ def test_matrix_structure(oracle_mod, a):
     lam = np.linalg.eigvalsh(0.5 * (M + M.T))
     assert lam.min() >= 1.0 - 1e-12  # adot >= 0 -> lambda_min(A) >= 1
     gersh = 1 + theta * dt * (c * kap.max() + adot / a
-                              + 4 * d_max * sum(1 / (a * hh) ** 2 for hh in h))
+                              + 4 * d_max * sum(1 / hh ** 2 for hh in h))
     assert lam.max() <= gersh * (1 + 1e-12)
 
 
