@@ -212,6 +212,71 @@ def measured_traffic(kernel, form, workload=None, root=ROOT):
     return None
 
 
+# rocprofv3 kernel names of the finest-level kernels, by (bench name, form)
+PMC_KERNELS = {
+    ("spmv_px", "mixed_dir64"): "fld::k_spmv_p<true, 2>",
+    ("spmv_px", "mixed"): "fld::k_spmv_p<true, 1>",
+    ("spmv_p", "fp64"): "fld::k_spmv_p<false, 0>",
+    ("vup_fine", "mixed"): "fld::k_vup<float, true, false>",
+    ("vup_fine", "fp64"): "fld::k_vup<double, true, false>",
+    ("vdown_fine", "mixed"): "fld::k_vdown<float, true>",
+    ("vdown_fine", "fp64"): "fld::k_vdown<double, true>",
+    ("update", "fp64"): "fld::k_update<0>",
+    ("true_resid", "any"): "fld::k_true_resid",
+    ("assemble", "any"): "fld::k_assemble",
+}
+PMC_SOURCES = {
+    "fld_kernels.hip": ("spmv_px", "spmv_p", "update", "true_resid", "assemble"),
+    "fld_fused.hip": ("vup_fine", "vdown_fine"),
+}
+
+
+def traffic_records(pmc_dir, workload, root=ROOT):
+    """Traffic records (the lines measured_traffic reads) from two rocprofv3
+    counter runs in pmc_dir (FETCH_SIZE_counter_collection.csv and
+    WRITE_SIZE_counter_collection.csv, KiB per dispatch), each scaled by what
+    its counter reads for the copy probe of --copy-probe (2 GiB read, 2 GiB
+    written): HBM bytes per launch, averaged over the kernel's dispatches."""
+    import csv
+    import hashlib
+    per = {}
+    for cn in ("FETCH_SIZE", "WRITE_SIZE"):
+        acc = {}
+        with open(os.path.join(pmc_dir, f"{cn}_counter_collection.csv")) as f:
+            for row in csv.DictReader(f):
+                acc.setdefault((row["Kernel_Name"], int(row["Grid_Size"])), []).append(
+                    float(row["Counter_Value"]))
+        per[cn] = acc
+    probe = [k for k in per["FETCH_SIZE"]
+             if "CUDAFunctorOnSelf_add" in k[0] and k[1] == 1 << 26]
+    if not probe:
+        raise RuntimeError("no copy-probe dispatch in the counter runs")
+    scale = {cn: 2.0 * (1 << 20) / per[cn][probe[0]][0] for cn in per}
+
+    def avg(cn, name):
+        v = [x for (k, _), xs in per[cn].items() if k.split("(")[0].replace("void ", "") == name
+             for x in xs]
+        return sum(v) / len(v) if v else None
+
+    def digest(rel):
+        with open(os.path.join(root, rel), "rb") as f:
+            return hashlib.sha256(f.read()).hexdigest()
+
+    lines = []
+    for (kernel, form), name in PMC_KERNELS.items():
+        fa, wa = avg("FETCH_SIZE", name), avg("WRITE_SIZE", name)
+        if fa is None or wa is None:
+            continue
+        src = next(f for f, ks in PMC_SOURCES.items() if kernel in ks)
+        rels = [f"paper_1306_0645_amd/csrc/{src}", "paper_1306_0645_amd/csrc/fld_device.h",
+                "paper_1306_0645_amd/csrc/fld_internal.h"]
+        nbytes = 1024.0 * (fa * scale["FETCH_SIZE"] + wa * scale["WRITE_SIZE"])
+        lines.append(f"traffic-record: kernel={kernel} form={form} workload={workload} "
+                     f"bytes_per_launch={nbytes:.0f} sources="
+                     + ",".join(f"{r}:{digest(r)}" for r in rels))
+    return scale, lines
+
+
 def copy_bandwidth(torch, n=1 << 27, reps=5):
     """Measured HBM bandwidth of a plain streaming kernel (y = x + 0 over n
     doubles: n*8 bytes read and written), best of reps, for context beside
@@ -302,6 +367,11 @@ def parse():
     ap.add_argument("--hii-cap-s", type=float, default=60.0,
                     help="hii_test1: wall-clock cap per run [s]")
     ap.add_argument("--hii-precision", default="mixed")
+    ap.add_argument("--traffic-records", default=None, metavar="PMC_DIR",
+                    help="print the traffic records of two rocprofv3 counter "
+                         "runs (FETCH_SIZE, WRITE_SIZE) in PMC_DIR for the "
+                         "workload named by --record-workload, and exit")
+    ap.add_argument("--record-workload", default="reionization_share_640")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain copy kernel of 2 GiB read + 2 GiB "
                          "written, to calibrate the HBM byte counters")
@@ -720,6 +790,12 @@ def headline(args, fld, torch, synth):
 
 def main():
     args = parse()
+    if args.traffic_records:
+        scale, lines = traffic_records(args.traffic_records, args.record_workload)
+        print(f"# scales: FETCH_SIZE x {scale['FETCH_SIZE']:.3f}, "
+              f"WRITE_SIZE x {scale['WRITE_SIZE']:.3f}")
+        print("\n".join(lines))
+        return
     if args.warm_start is None:
         # the Galerkin guess (the library default) where it measured faster;
         # the extrapolation for the single source and the batch (1 and about

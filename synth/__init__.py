@@ -385,17 +385,22 @@ def t_reionization_share(n=640, n_src=10000, sigma_ln=2.0, device="cuda",
     rs = stromgren_radius(ndot, nbar) / dx
     cz, rem = np.divmod(cells, n * n)
     cy, cx = np.divmod(rem, n)
-    ionized = torch.zeros(shape, dtype=torch.bool, device=device)
+    # the cells within r of each source (periodic), listed on the host and
+    # marked on the device in one scatter
+    idx = []
     for x0, y0, z0, r in zip(cx, cy, cz, rs):
         ri = int(math.ceil(r))
         if ri < 1:
             continue
-        o = torch.arange(-ri, ri + 1, device=device)
+        o = np.arange(-ri, ri + 1)
         d2 = o[:, None, None] ** 2 + o[None, :, None] ** 2 + o[None, None, :] ** 2
-        iz = ((int(z0) + o) % n)[:, None, None]
-        iy = ((int(y0) + o) % n)[None, :, None]
-        ix = ((int(x0) + o) % n)[None, None, :]
-        ionized[iz, iy, ix] |= d2 <= r * r
+        kz, ky, kx = np.nonzero(d2 <= r * r)
+        idx.append((((int(z0) + o[kz]) % n) * n + (int(y0) + o[ky]) % n) * n
+                   + (int(x0) + o[kx]) % n)
+    ionized = torch.zeros(n * n * n, dtype=torch.bool, device=device)
+    if idx:
+        ionized[torch.as_tensor(np.concatenate(idx), device=device)] = True
+    ionized = ionized.reshape(shape)
     # x_HI = 1e-4 inside the bubbles
     kappa = SIGMA_HI * nH * torch.where(ionized, 1e-4, 1.0)
     ion_frac = float(ionized.double().mean())

@@ -40,6 +40,20 @@ def test_traffic_record_follows_its_sources(tmp_path):
     assert bench.measured_traffic("spmv_px", "mixed", root=str(tmp_path)) is None
 
 
+def test_traffic_record_keyed_by_workload(tmp_path):
+    """A record names its workload: the lookup for one workload ignores the
+    records of another (the same kernel moves other bytes at another size)."""
+    (tmp_path / "a.hip").write_text("kernel a\n")
+    item = "a.hip:" + hashlib.sha256(b"kernel a\n").hexdigest()
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "k.md").write_text(
+        f"traffic-record: kernel=spmv_px form=mixed workload=w256 bytes_per_launch=5 sources={item}\n"
+        f"traffic-record: kernel=spmv_px form=mixed workload=w640 bytes_per_launch=7 sources={item}\n")
+    assert bench.measured_traffic("spmv_px", "mixed", "w640", root=str(tmp_path)) == 7.0
+    assert bench.measured_traffic("spmv_px", "mixed", "w256", root=str(tmp_path)) == 5.0
+    assert bench.measured_traffic("spmv_px", "mixed", "w1024", root=str(tmp_path)) is None
+
+
 def test_committed_records_name_existing_sources():
     """Every record under profiles/ names sources that exist in the tree."""
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
