@@ -44,10 +44,6 @@ BYTES_PER_CELL = {
     "spmv_px": (80.0, 68.0),
     # the deferred x += alpha p when a solve stops iterating
     "xfix": (24.0, 20.0),
-    # trilinear mixed cycle: level 1's correction interpolated to every finest
-    # cell (coarse values at 1/8, FP32 out); the up pass then reads it at the
-    # red cells (2 B/cell, not counted in vup_fine's 32.5)
-    "tri_fine": (0.0, 4.5),
     # Galerkin warm guess: x0 and r = b - A x0 from the operator, b and the
     # two dE (72 B), less the x and r the assembly then leaves to it (16 B)
     "warm_x": (56.0, 56.0),

@@ -194,9 +194,11 @@ void carve_problem(Carver &cv, const Hier &h, const fld_params &p, ProbMem &m) {
       P.q = cv.take<double>(n);
       P.b = cv.take<double>(n);
       P.r2 = lazy_iteration(p) ? cv.take<double>(n) : nullptr;
-      P.lmask = (mixed && p.local_sweeps > 0) ? cv.take<unsigned char>(n) : nullptr;
-      P.ef = (mixed && fused_cycle(p) && p.prolongation != 0) ? cv.take<float>(n)
-                                                               : nullptr;
+      // (a dry run of the carve, base null, must take the same sizes: the
+      // conditions name parameters, never carved pointers)
+      const bool local = mixed && p.local_sweeps > 0;
+      P.llist = local ? cv.take<int>(n) : nullptr;
+      P.lcnt = local ? cv.take<int>(2 * (size_t)h.tiles[0]) : nullptr;
       L.x = mixed ? (void *)cv.take<float>(n) : (void *)P.z;
       L.f = nullptr;
       if (jacobi) L.x2 = mixed ? (void *)cv.take<float>(n) : (void *)cv.take<double>(n);
@@ -246,7 +248,6 @@ static size_t tables_layout(Carver &cv, const std::vector<Hier> &hs,
   Scal *sc = cv.take<Scal>(np);
   double *part = cv.take<double>(2 * std::max<size_t>(nfine, 1));
   double *lpart = cv.take<double>(2 * std::max<size_t>(nfine, 1));
-  int *lcnt = cv.take<int>(std::max<size_t>(nfine, 1));
   CtlDev *ctl = cv.take<CtlDev>(std::max(np, 1));
   double *gpart = cv.take<double>(kAsmSums * std::max<size_t>(nfine, 1));
   Tile *tiles = cv.take<Tile>(std::max<size_t>(ntiles, 1));
@@ -258,7 +259,6 @@ static size_t tables_layout(Carver &cv, const std::vector<Hier> &hs,
     e->T.sc = sc;
     e->T.part = part;
     e->T.lpart = lpart;
-    e->T.lcnt = lcnt;
     e->T.ctl = ctl;
     e->T.gpart = gpart;
     e->T.nprob = np;
@@ -308,7 +308,13 @@ int Engine::setup(const fld_params &p, hipStream_t s,
     Lmax = std::max(Lmax, hier[i].levels);
   }
   tables_layout(tbl, hier, this);
-  for (int i = 0; i < np; ++i) carve_problem(pm[i], hier[i], p, mem[i]);
+  for (int i = 0; i < np; ++i) {
+    // the caller sized each problem's block with the dry run (problem_bytes):
+    // a carve that takes more would write past the block, so refuse it
+    const size_t start = pm[i].off;
+    carve_problem(pm[i], hier[i], p, mem[i]);
+    if (align_up(pm[i].off) - start > problem_bytes(hier[i], p)) return ST_ENOMEM;
+  }
 
   // full tile table, level-major; within a level the standard tiles of every
   // problem, then the fused-cycle tiles, so both finest tilings come first
@@ -585,7 +591,6 @@ void Engine::enqueue_fused_rest(const ListSet &ls) {
     launch_prolong_black(T, ls.gsm[l], l, prec, tri, stream);
     launch_half(T, ls.gsm[l], l, 0, prec, stream);
   }
-  if (tri && mixed && Lmax > 1) launch_tri_fine(T, ls.exist[1], stream);
   launch_vup(T, ls.fsm[0], 0, prec, mixed, tri, stream);
   if (local_on()) {
     for (int k = 0; k < prm.local_sweeps; ++k) {

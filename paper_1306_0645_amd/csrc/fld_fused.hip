@@ -229,13 +229,88 @@ struct QPlane {
   R hd[kHalo], he[kHalo];
 };
 
-// EF (trilinear mixed finest level): ef holds the coarse correction already
-// interpolated to every fine cell (k_tri_fine), read in place of the gathers
-template <typename R, bool L0, bool UP, bool TRI, bool EF = false>
+// Trilinear correction (3/4 own parent, 1/4 the neighbour on the fine cell's
+// side, per direction) from coarse planes staged in LDS: slot c % 3 holds
+// relative coarse plane c, that is plane z0 / 2 - 2 + c, over the tile's
+// coarse columns x0 / 2 - 2 .. (x0 + tx) / 2 + 1 and rows
+// y0 / 2 - 2 .. (y0 + ty) / 2 + 1, which covers the parents and the
+// interpolation neighbours of the tile and its 2-cell halo.  A fine cell at
+// tile-frame offset (ex, ey) of the tile + 2 frame (or a quad cell, offset
+// (2 ci + a + 2, 2 cj + b + 2)) has its parent at (ex / 2 + 1, ey / 2 + 1) of
+// the staged region, since x0 and y0 are even.  c0, c1: the slots of the
+// fine plane's parent plane and of the plane on its side.  The weights are
+// combined in the order coarse_corr uses.
+constexpr int kCX = kFX / 2 + 4, kCY = kFY / 2 + 4, kC = kCX * kCY;
+constexpr int kCR = (kC + kBlock - 1) / kBlock;
+
+template <typename R>
+__device__ __forceinline__ R tri_at(const R *c0, const R *c1, int I, int I2, int J,
+                                    int J2) {
+  const int r0 = J * kCX, r1 = J2 * kCX;
+  const R a = (R)0.75, b = (R)0.25;
+  const R zK = a * (a * c0[r0 + I] + b * c0[r0 + I2]) + b * (a * c0[r1 + I] + b * c0[r1 + I2]);
+  const R zK2 = a * (a * c1[r0 + I] + b * c1[r0 + I2]) + b * (a * c1[r1 + I] + b * c1[r1 + I2]);
+  return a * zK + b * zK2;
+}
+
+// correction at offset (ex, ey) of the tile + 2 frame
+template <typename R>
+__device__ __forceinline__ R tri_frame(const R *c0, const R *c1, int ex, int ey) {
+  const int I = (ex >> 1) + 1, J = (ey >> 1) + 1;
+  return tri_at(c0, c1, I, (ex & 1) ? I + 1 : I - 1, J, (ey & 1) ? J + 1 : J - 1);
+}
+
+// Staging of one coarse plane: thread slot u covers entry q = tid + u kBlock
+// of the kCX x kCY region (row-major, so q is also its LDS offset); its
+// in-plane source offset is the same on every plane and is computed once.
+// The global loads go to registers first and to LDS later, so that their
+// latency overlaps other work.
+template <typename R>
+struct CStage {
+  int off[kCR];
+  R v[kCR];
+};
+
+__device__ __forceinline__ int pmod(int i, int n) {
+  const int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+template <typename R>
+__device__ __forceinline__ void cstage_init(CStage<R> &cv, const Tile &t, int cnx, int cny) {
+  const int I0 = (t.x0 >> 1) - 2, J0 = (t.y0 >> 1) - 2;
+#pragma unroll
+  for (int u = 0; u < kCR; ++u) {
+    const int q = threadIdx.x + u * kBlock, jy = q / kCX, ix = q - jy * kCX;
+    cv.off[u] = pmod(J0 + jy, cny) * cnx + pmod(I0 + ix, cnx);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void cstage_load(CStage<R> &cv, const R *e, int c, int cnx,
+                                            int cny, int cnz) {
+  const R *pl = e + (size_t)pmod(c, cnz) * cny * cnx;
+#pragma unroll
+  for (int u = 0; u < kCR; ++u)
+    if (threadIdx.x + u * kBlock < kC) cv.v[u] = pl[cv.off[u]];
+}
+
+template <typename R>
+__device__ __forceinline__ void cstage_store(const CStage<R> &cv, R *dst) {
+#pragma unroll
+  for (int u = 0; u < kCR; ++u) {
+    const int q = threadIdx.x + u * kBlock;
+    if (q < kC) dst[q] = cv.v[u];
+  }
+}
+
+// the up pass of a trilinear cycle (TRI) takes its coarse correction at the
+// store (q_store_plane), from the staged coarse planes
+template <typename R, bool L0, bool UP, bool TRI>
 __device__ __forceinline__ void q_load_plane(
     QPlane<R, L0, UP> &pl, const Tile &t, int pz, bool qon, int qx, int qy,
     int nx, int ny, int nz, const FSrc<R, L0> &f, const R *d, const R *e,
-    bool has_coarse, int cnx, int cny, int cnz, const R *ef = nullptr) {
+    bool has_coarse, int cnx, int cny, int cnz) {
   const int kz = wrapi(pz, nz);
   if (qon) {
     const int r0 = (kz * ny + qy) * nx + qx, r1 = r0 + nx;
@@ -248,22 +323,8 @@ __device__ __forceinline__ void q_load_plane(
     }
     ld2(d + r0, pl.d00, pl.d10);
     ld2(d + r1, pl.d01, pl.d11);
-    if constexpr (UP) {
-      pl.e0 = pl.e1 = (R)0;
-      if (has_coarse) {
-        if constexpr (TRI) {
-          const int pp = pz & 1;  // red cells: row 0 at a = pp, row 1 at 1 - pp
-          if constexpr (EF) {
-            pl.e0 = ef[r0 + pp];
-            pl.e1 = ef[r1 + 1 - pp];
-          } else {
-            pl.e0 = coarse_corr(e, qx + pp, qy, kz, cnx, cny, cnz, true);
-            pl.e1 = coarse_corr(e, qx + 1 - pp, qy + 1, kz, cnx, cny, cnz, true);
-          }
-        } else {
-          pl.e0 = pl.e1 = coarse_corr(e, qx, qy, kz, cnx, cny, cnz, false);
-        }
-      }
+    if constexpr (UP && !TRI) {
+      pl.e0 = pl.e1 = has_coarse ? coarse_corr(e, qx, qy, kz, cnx, cny, cnz, false) : (R)0;
     }
   }
   const int e2x = t.tx + 4, nh = 4 * e2x + 4 * t.ty;
@@ -279,9 +340,9 @@ __device__ __forceinline__ void q_load_plane(
       if constexpr (L0) pl.hf[u] = f.r[g];
       else pl.hf[u] = f.f[g];
       pl.hd[u] = d[g];
-      if constexpr (UP) {
+      if constexpr (UP && !TRI) {
         pl.he[u] = (has_coarse && ((ux + uy + pz) & 1) == 0)
-                       ? (EF ? ef[g] : coarse_corr(e, gx, gy, kz, cnx, cny, cnz, TRI))
+                       ? coarse_corr(e, gx, gy, kz, cnx, cny, cnz, false)
                        : (R)0;
       }
     }
@@ -320,12 +381,20 @@ __device__ __forceinline__ R scaled(typename QPlane<R, L0, false>::FT v, double 
 }
 
 // y = f / d (+ e at red cells for the up pass) into the LDS plane; returns
-// the quad's diagonal reciprocals
-template <typename R, bool L0, bool UP>
+// the quad's diagonal reciprocals.  TRI (up pass, has_coarse): e from the
+// staged coarse planes cs
+template <typename R, bool L0, bool UP, bool TRI = false>
 __device__ __forceinline__ Q4<R> q_store_plane(const QPlane<R, L0, UP> &pl,
                                                const Tile &t, int pz, bool qon,
                                                int ci, int cj, R *out,
-                                               double inv_s) {
+                                               double inv_s, bool has_coarse = false,
+                                               const R (*cs)[kC] = nullptr) {
+  const R *c0 = nullptr, *c1 = nullptr;
+  if constexpr (TRI) {
+    const int K = (pz >> 1) - (t.z0 >> 1) + 2;
+    c0 = cs[K % 3];
+    c1 = cs[((pz & 1) ? K + 1 : K - 1) % 3];
+  }
   Q4<R> id;
   if (qon) {
     id.v00 = recip(pl.d00);
@@ -337,12 +406,24 @@ __device__ __forceinline__ Q4<R> q_store_plane(const QPlane<R, L0, UP> &pl,
     R y01 = scaled<R, L0>(pl.f01, inv_s) * id.v01;
     R y11 = scaled<R, L0>(pl.f11, inv_s) * id.v11;
     if constexpr (UP) {
+      R e0 = (R)0, e1 = (R)0;
+      if constexpr (TRI) {
+        if (has_coarse) {
+          // red cells: row 0 at a = pp, row 1 at a = 1 - pp
+          const int pp = pz & 1, ex = 2 * ci + 2, ey = 2 * cj + 2;
+          e0 = tri_frame(c0, c1, ex + pp, ey);
+          e1 = tri_frame(c0, c1, ex + 1 - pp, ey + 1);
+        }
+      } else {
+        e0 = pl.e0;
+        e1 = pl.e1;
+      }
       if (pz & 1) {  // red: (1, 0) and (0, 1)
-        y10 += pl.e0;
-        y01 += pl.e1;
+        y10 += e0;
+        y01 += e1;
       } else {       // red: (0, 0) and (1, 1)
-        y00 += pl.e0;
-        y11 += pl.e1;
+        y00 += e0;
+        y11 += e1;
       }
     }
     const int s = (2 * cj + 2) * kE2X + 2 * ci + 2;
@@ -359,7 +440,13 @@ __device__ __forceinline__ Q4<R> q_store_plane(const QPlane<R, L0, UP> &pl,
       int ex, ey;
       halo_cell(q, t.tx, t.ty, ex, ey);
       R v = scaled<R, L0>(pl.hf[u], inv_s) * recip(pl.hd[u]);
-      if constexpr (UP) v += pl.he[u];
+      if constexpr (UP) {
+        if constexpr (TRI) {
+          if (has_coarse && ((ex + ey + pz) & 1) == 0) v += tri_frame(c0, c1, ex, ey);
+        } else {
+          v += pl.he[u];
+        }
+      }
       out[ey * kE2X + ex] = v;
     }
   }
@@ -491,8 +578,12 @@ __global__ __launch_bounds__(kBlock) void k_vdown(Tables T, TileList TL, int l,
   if constexpr (kUpd) write_partials(T, tid, rr, 0.0);
 }
 
+// Three blocks per CU: the mixed trilinear finest instance would otherwise
+// take more registers than that leaves (measured at 640^3: 2.35 ms a launch
+// with three blocks and a few spilled registers, 2.64 ms with two).  The FP64
+// instances need more registers than three blocks allow whatever the bound.
 template <typename R, bool L0, bool TRI>
-__global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
+__global__ __launch_bounds__(kBlock, 3) void k_vup(Tables T, TileList TL, int l,
                                                 int flexible) {
   using FT = typename QPlane<R, L0, true>::FT;
   const int tid = get_tile_index(TL);
@@ -507,11 +598,6 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
   const auto f = fsrc<R, L0>(L, P, sc);
   const double inv_s = sc.inv_s;
   const R *e = (const R *)Cl.x;
-  // mixed trilinear finest level: the correction interpolated to the fine
-  // cells (allocated whenever a mixed fused cycle may go trilinear)
-  constexpr bool kEf = L0 && TRI && sizeof(R) == 4;
-  const R *ef = nullptr;
-  if constexpr (kEf) ef = P.ef;
   R *xout = (R *)L.x;
   const double s_out = sc.s;
   // flexible PCG needs r.z_old, except where the PCG (re)starts (beta = 0);
@@ -520,6 +606,12 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
   const double zs_old = sc.zscale;
   __shared__ R vs[3][kE2];
   __shared__ R xs[3][kE1];
+  // trilinear: the coarse planes under the tile, a ring of 3 (corr_lds); the
+  // fine plane loaded in iteration m needs relative coarse planes m / 2 + 1
+  // and m / 2 + 2, so plane j + 2 is staged in iteration 2j - 1, after the
+  // last read of the slot it replaces (iteration 2j - 3) and a barrier before
+  // its first read (iteration 2j)
+  __shared__ R cs[TRI ? 3 : 1][kC];
   const int nx = L.nx, ny = L.ny, nz = L.nz;
   const int cnx = Cl.nx, cny = Cl.ny, cnz = Cl.nz;
   const int ci = threadIdx.x & 31, cj = threadIdx.x >> 5;
@@ -528,9 +620,21 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
   const int qxl = wrapi(qx - 1, nx), qyb = wrapi(qy - 1, ny);
   const int rq = threadIdx.x / 3;
   const bool ron = threadIdx.x == 3 * rq && rq < t.tx + t.ty;
+  const int cbase = (t.z0 >> 1) - 2;
+  CStage<R> cv;
+  if constexpr (TRI) {
+    if (has_coarse) {
+      cstage_init(cv, t, cnx, cny);
+      for (int c = 0; c < 3; ++c) {
+        cstage_load(cv, e, cbase + c, cnx, cny, cnz);
+        cstage_store(cv, cs[c]);
+      }
+      __syncthreads();
+    }
+  }
   QPlane<R, L0, true> pl;
-  q_load_plane<R, L0, true, TRI, kEf>(pl, t, t.z0 - 2, qon, qx, qy, nx, ny, nz, f,
-                                      C.d, e, has_coarse, cnx, cny, cnz, ef);
+  q_load_plane<R, L0, true, TRI>(pl, t, t.z0 - 2, qon, qx, qy, nx, ny, nz, f, C.d, e,
+                                 has_coarse, cnx, cny, cnz);
   QFace<R> Fb{}, Fr{};
   Q4<R> Zb{}, Zr{}, Zrm{};
   Q4<R> I0{}, I1{}, I2{};   // diagonal reciprocals of planes pz, pz - 1, pz - 2
@@ -546,6 +650,10 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
     if (m >= 2 && ron) load_ring(rc, C, t, rq, pb, nx, ny, nz);
     const bool out = m >= 4 && qon;
     const int o0 = (pr2 * ny + qy) * nx + qx;  // row 0 of the quad on plane pr2
+    // relative coarse plane staged in this iteration (trilinear), 0 if none
+    const int cst = (TRI && has_coarse && (m & 1) && m <= t.tz + 1) ? (m + 1) / 2 + 2 : 0;
+    if (cst) cstage_load(cv, e, cbase + cst, cnx, cny, cnz);
+
     // right-hand side of plane pr2 (read again: keeping it for the three
     // iterations since its first load would cost more registers than the
     // read costs bytes) and, for the flexible dot, the old z
@@ -567,10 +675,12 @@ __global__ __launch_bounds__(kBlock) void k_vup(Tables T, TileList TL, int l,
     // (1) v = y, + e(parent) at red cells, on plane pz
     I2 = I1;
     I1 = I0;
-    I0 = q_store_plane<R, L0, true>(pl, t, pz, qon, ci, cj, vs[m % 3], inv_s);
+    I0 = q_store_plane<R, L0, true, TRI>(pl, t, pz, qon, ci, cj, vs[m % 3], inv_s,
+                                         has_coarse, cs);
     if (m + 1 < t.tz + 4)
-      q_load_plane<R, L0, true, TRI, kEf>(pl, t, pz + 1, qon, qx, qy, nx, ny, nz, f,
-                                          C.d, e, has_coarse, cnx, cny, cnz, ef);
+      q_load_plane<R, L0, true, TRI>(pl, t, pz + 1, qon, qx, qy, nx, ny, nz, f, C.d, e,
+                                     has_coarse, cnx, cny, cnz);
+    if (cst) cstage_store(cv, cs[cst % 3]);
     __syncthreads();
     // (2) new black values of plane pb over the tile + 1
     if (m >= 2) {

@@ -56,14 +56,14 @@ struct ProbDev {
   // the search direction either in FP32 at the scale of the z it was formed
   // from, p = pscale * pf0 (or pf1), or in FP64 in p0 / p1
   float *z32, *pf0, *pf1;
-  // mixed form with trilinear prolongation possible: the finest level's
-  // coarse-grid correction interpolated to every cell (k_tri_fine)
-  float *ef;
   double *r2;            // second residual buffer (fused V(1,1) iteration)
-  // local smoothing (mixed fused cycle): 1 where the coupling to the
-  // neighbours dominates the cell's diagonal (sum of faces > local_coupling
-  // x diagonal), else 0
-  unsigned char *lmask;
+  // local smoothing (mixed fused cycle): the cells whose coupling to the
+  // neighbours dominates the diagonal (sum of faces > local_coupling x
+  // diagonal), listed per finest tile at the tile's own cells, and the
+  // counts per tile and colour, lcnt[2 (t - t0) + colour] (k_lmask); kept
+  // with the problem, since a server's tables are rebuilt between the
+  // assembly and the sweeps that read them
+  int *llist, *lcnt;
   double *cs;            // coarsest-level CG scratch: 4 * n_coarsest doubles
   int levels;            // number of multigrid levels
   int t0, t1;            // range of this problem's tiles in the finest list
@@ -157,7 +157,6 @@ struct Tables {
   Scal *sc;         // [nprob]
   double *part;     // [n finest tiles][2] block partial sums
   double *lpart;    // [n finest tiles][2] the local sweeps' r.z changes
-  int *lcnt;        // [n finest tiles] cells of the tile in the local mask
   CtlDev *ctl;      // [nprob] device-side step control
   double *gpart;    // [n finest tiles][kAsmSums] sums of the assembly
   int nprob;
@@ -181,7 +180,7 @@ enum : int {
   K_UPDATE_E, K_VDOWN_F, K_VDOWN_C, K_VUP_F, K_VUP_C, K_CHEM_H, K_ION_SUM,
   K_WARM_REVERT, K_JACOBI0_F, K_JACOBI_F, K_JACOBI_OUT,
   K_JACOBI_C, K_PROLONG_ADD_F, K_PROLONG_ADD_C, K_SPMV_PX, K_XFIX, K_WARM_X,
-  K_TRI_FINE, K_LMASK, K_LOCAL, K_CONTROL, K_COPY_E, K_NUM
+  K_LMASK, K_LOCAL, K_CONTROL, K_COPY_E, K_NUM
 };
 
 // Brackets one launch with hipEvents when its kernel id is selected.
@@ -245,11 +244,7 @@ void launch_true_resid(const Tables &T, TileList L0, hipStream_t s);
 void launch_warm_revert(const Tables &T, TileList L0, hipStream_t s);
 // x0 = c1 dE(n) + c2 dE(n-1), r = b - A x0 (Galerkin warm guesses)
 void launch_warm_x(const Tables &T, TileList L0, hipStream_t s);
-// ef = the trilinear interpolation of level 1's correction to every finest
-// cell (before the finest up pass of a trilinear mixed cycle); L1: level-1
-// tiles, one thread per level-1 cell
-void launch_tri_fine(const Tables &T, TileList L1, hipStream_t s);
-// local smoothing of the mixed fused cycle: the mask of strongly coupled
+// local smoothing of the mixed fused cycle: the list of strongly coupled
 // finest cells (after the assembly), and one red/black sweep over them
 // (colour 1 = black, then 0 = red) after the finest post-sweep, in z32,
 // with the change of r.z per tile in lpart[2 t + colour]

@@ -1021,64 +1021,6 @@ __global__ __launch_bounds__(kBlock) void k_warm_x(Tables T, TileList TL) {
   write_partials(T, tid, rr, 0.0);
 }
 
-// The finest up pass of a trilinear mixed cycle reads the coarse-grid
-// correction from ef instead of gathering its 8 coarse values per cell: this
-// pass interpolates it to every finest cell.  One thread per level-1 cell
-// loads its 3 x 3 x 3 neighbourhood once and writes its 8 children, each
-// combined in the order coarse_corr uses (the same values).
-__global__ __launch_bounds__(kBlock) void k_tri_fine(Tables T, TileList TL) {
-  const Tile t = get_tile(TL);
-  const Scal &sc = T.sc[t.prob];
-  if (!sc.active) return;
-  const ProbDev P = T.pd[t.prob];
-  if (P.levels < 2 || !P.ef) return;
-  const LevelDev F = T.lv[t.prob];
-  const LevelDev C = T.lv[T.nprob + t.prob];
-  const float *__restrict__ e = (const float *)C.x;
-  float *__restrict__ ef = P.ef;
-  const Col col = tile_col(t);
-  if (!col.on) return;
-  const int cnx = C.nx, cny = C.ny, cnz = C.nz, fnx = F.nx, fny = F.ny;
-  const float A = 0.75f, B = 0.25f;
-  for (int K = t.z0; K < t.z0 + t.tz; ++K) {
-    for (int u = 0; u < t.cpt; ++u) {
-      const int I = col.i + u, J = col.j;
-      const int Im = I == 0 ? cnx - 1 : I - 1, Ip = I + 1 == cnx ? 0 : I + 1;
-      const int Jm = J == 0 ? cny - 1 : J - 1, Jp = J + 1 == cny ? 0 : J + 1;
-      const int Km = K == 0 ? cnz - 1 : K - 1, Kp = K + 1 == cnz ? 0 : K + 1;
-      const int ks[3] = {Km, K, Kp}, js[3] = {Jm, J, Jp};
-      float v[3][3][3];  // [z][y][x] offsets -1, 0, +1
-#pragma unroll
-      for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
-          const int row = (ks[dz] * cny + js[dy]) * cnx;
-          v[dz][dy][0] = e[row + Im];
-          v[dz][dy][1] = e[row + I];
-          v[dz][dy][2] = e[row + Ip];
-        }
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          float out[2];
-#pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            const int x2 = a ? 2 : 0, y2 = b ? 2 : 0, z2 = c ? 2 : 0;
-            const float zK = A * (A * v[1][1][1] + B * v[1][1][x2]) +
-                             B * (A * v[1][y2][1] + B * v[1][y2][x2]);
-            const float zK2 = A * (A * v[z2][1][1] + B * v[z2][1][x2]) +
-                              B * (A * v[z2][y2][1] + B * v[z2][y2][x2]);
-            out[a] = A * zK + B * zK2;
-          }
-          const int o = ((2 * K + c) * fny + 2 * J + b) * fnx + 2 * I;
-          ef[o] = out[0];
-          ef[o + 1] = out[1];
-        }
-    }
-  }
-}
-
 // Local smoothing.  Where a cell's coupling to its neighbours dominates its
 // diagonal (an ionized bubble: little absorption, D near D_max, so the cell
 // is almost a pure diffusion cell), one red/black sweep leaves the error that
@@ -1086,11 +1028,64 @@ __global__ __launch_bounds__(kBlock) void k_tri_fine(Tables T, TileList TL) {
 // cells mix bubble and neutral children, do not represent it; extra sweeps
 // restricted to those cells act on it at a small fraction of a full sweep's
 // cost.  k_lmask marks them once per assembly from the FP64 finest operator
-// (and counts them per tile); k_local runs one half-sweep of colour `colour`
-// over the marked cells of a tile, in place in the cycle's FP32 output z32,
-// with the cycle's scaled right-hand side and FP32 coefficients, and records
-// the change of r.z that the update makes (r the FP64 residual the cycle ran
-// on, z = s z32).
+// and lists them per tile and colour; k_local runs one half-sweep of colour
+// `colour` over a tile's listed cells, in place in the cycle's FP32 output
+// z32, with the cycle's scaled right-hand side and FP32 coefficients, and
+// records the change of r.z that the update makes (r the FP64 residual the
+// cycle ran on, z = s z32).
+//
+// The list of a tile lives in llist at the tile's own cells: entry q (the
+// colour-0 cells first, then the colour-1 cells, each in thread and plane
+// order) is stored at the q-th cell of the tile's box in x, y, z order, so
+// tiles never overlap and one wave reads 64 consecutive entries.  lcnt[2u],
+// lcnt[2u + 1]: the counts per colour of the problem's finest tile u (held
+// with the problem: a server rebuilds its tables between the assembly and
+// the sweeps).  Within one colour the updates are independent (a cell of
+// that colour reads only cells of the other), so k_local gives every listed
+// cell a thread of its own.
+
+// exclusive prefix sums of a and b over the block's threads (thread order)
+// and their totals
+__device__ __forceinline__ void block_scan2(int a, int b, int *sh, int &ea, int &eb,
+                                            int &ta, int &tb) {
+  constexpr int NW = kBlock / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int ia = a, ib = b;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int ua = __shfl_up(ia, d, 64), ub = __shfl_up(ib, d, 64);
+    if (lane >= d) {
+      ia += ua;
+      ib += ub;
+    }
+  }
+  if (lane == 63) {
+    sh[w] = ia;
+    sh[NW + w] = ib;
+  }
+  __syncthreads();
+  int oa = 0, ob = 0;
+  ta = 0;
+  tb = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    if (i < w) {
+      oa += sh[i];
+      ob += sh[NW + i];
+    }
+    ta += sh[i];
+    tb += sh[NW + i];
+  }
+  ea = oa + ia - a;
+  eb = ob + ib - b;
+}
+
+// index of the q-th cell of tile t's box (x fastest)
+__device__ __forceinline__ int box_cell(const Tile &t, int q, int nx, int ny) {
+  const int txy = t.tx * t.ty, lz = q / txy, rm = q - lz * txy, ly = rm / t.tx;
+  return ((t.z0 + lz) * ny + t.y0 + ly) * nx + t.x0 + (rm - ly * t.tx);
+}
+
 __global__ __launch_bounds__(kBlock) void k_lmask(Tables T, TileList TL,
                                                   double coupling) {
   const int tid = get_tile_index(TL);
@@ -1100,20 +1095,34 @@ __global__ __launch_bounds__(kBlock) void k_lmask(Tables T, TileList TL,
   const LevelDev L = T.lv[t.prob];
   const ProbDev P = T.pd[t.prob];
   const Col col = tile_col(t);
-  double cnt = 0.0;
+  unsigned long long bits = 0;  // marked planes of the column: bit k - z0
+  int m0 = 0, m1 = 0;           // marked cells of colour 0, 1
   if (col.on) {
     for (int k = t.z0; k < t.z0 + t.tz; ++k) {
       const Nb n = nbrs(col.i, col.j, k, L.nx, L.ny, L.nz);
       const double faces = L.Tx[n.c] + L.Tx[n.xm] + L.Ty[n.c] + L.Ty[n.ym] +
                            L.Tz[n.c] + L.Tz[n.zm];
-      const bool m = faces > coupling * L.diag[n.c];
-      P.lmask[n.c] = m ? 1 : 0;
-      cnt += m ? 1.0 : 0.0;
+      if (faces > coupling * L.diag[n.c]) {
+        bits |= 1ull << (k - t.z0);
+        if ((col.i + col.j + k) & 1) ++m1;
+        else ++m0;
+      }
     }
   }
-  __shared__ double sh[kBlock / 64];
-  const double c = block_sum<kBlock / 64>(cnt, sh);
-  if (threadIdx.x == 0) T.lcnt[tid] = (int)c;
+  __shared__ int sh[2 * (kBlock / 64)];
+  int e0, e1, n0, n1;
+  block_scan2(m0, m1, sh, e0, e1, n0, n1);
+  while (bits) {
+    const int b = __ffsll((long long)bits) - 1;
+    bits &= bits - 1;
+    const int k = t.z0 + b;
+    const int q = ((col.i + col.j + k) & 1) ? n0 + e1++ : e0++;
+    P.llist[box_cell(t, q, L.nx, L.ny)] = (k * L.ny + col.j) * L.nx + col.i;
+  }
+  if (threadIdx.x == 0) {
+    P.lcnt[2 * (tid - P.t0)] = n0;
+    P.lcnt[2 * (tid - P.t0) + 1] = n1;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_local(Tables T, TileList TL, int colour) {
@@ -1121,30 +1130,36 @@ __global__ __launch_bounds__(kBlock) void k_local(Tables T, TileList TL, int col
   const Tile t = TL.base[tid];
   const Scal &sc = T.sc[t.prob];
   if (!sc.active) return;
+  const ProbDev P = T.pd[t.prob];
+  // the counts come from k_lmask; bounded by the tile's box all the same, so
+  // that no read of the list can leave the tile's own cells
+  const int u = tid - P.t0, box = t.tx * t.ty * t.tz;
+  const int first = colour ? min(max(P.lcnt[2 * u], 0), box) : 0;
+  const int cnt = min(max(P.lcnt[2 * u + colour], 0), box - first);
+  if (cnt == 0) {
+    if (threadIdx.x == 0) T.lpart[2 * tid + colour] = 0.0;
+    return;
+  }
+  const LevelDev L = T.lv[t.prob];
+  const Coef<float> C = coefs<float>(L);
+  const double *r = rcur(P, sc);
+  const double inv_s = sc.inv_s, s = sc.s;
+  float *z = P.z32;
+  const int plane = L.nx * L.ny;
   double dz = 0.0;
-  if (T.lcnt[tid] > 0) {
-    const LevelDev L = T.lv[t.prob];
-    const ProbDev P = T.pd[t.prob];
-    const Coef<float> C = coefs<float>(L);
-    const double *r = rcur(P, sc);
-    const double inv_s = sc.inv_s, s = sc.s;
-    float *z = P.z32;
-    const Col col = tile_col(t);
-    if (col.on) {
-      for (int k = t.z0; k < t.z0 + t.tz; ++k) {
-        if (((col.i + col.j + k) & 1) != colour) continue;
-        const Nb n = nbrs(col.i, col.j, k, L.nx, L.ny, L.nz);
-        if (!P.lmask[n.c]) continue;
-        const float f = (float)(r[n.c] * inv_s);
-        const float sum = C.tx[n.c] * z[n.xp] + C.tx[n.xm] * z[n.xm] +
-                          C.ty[n.c] * z[n.yp] + C.ty[n.ym] * z[n.ym] +
-                          C.tz[n.c] * z[n.zp] + C.tz[n.zm] * z[n.zm];
-        const float xn = (f + sum) * recip(C.d[n.c]);
-        const float xo = z[n.c];
-        z[n.c] = xn;
-        dz += r[n.c] * (s * ((double)xn - (double)xo));
-      }
-    }
+  for (int q = threadIdx.x; q < cnt; q += kBlock) {
+    const int c = P.llist[box_cell(t, first + q, L.nx, L.ny)];
+    if ((unsigned)c >= (unsigned)(plane * L.nz)) continue;  // not a cell
+    const int k = c / plane, rm = c - k * plane, j = rm / L.nx;
+    const Nb n = nbrs(rm - j * L.nx, j, k, L.nx, L.ny, L.nz);
+    const float f = (float)(r[n.c] * inv_s);
+    const float sum = C.tx[n.c] * z[n.xp] + C.tx[n.xm] * z[n.xm] +
+                      C.ty[n.c] * z[n.yp] + C.ty[n.ym] * z[n.ym] +
+                      C.tz[n.c] * z[n.zp] + C.tz[n.zm] * z[n.zm];
+    const float xn = (f + sum) * recip(C.d[n.c]);
+    const float xo = z[n.c];
+    z[n.c] = xn;
+    dz += r[n.c] * (s * ((double)xn - (double)xo));
   }
   __shared__ double sh[kBlock / 64];
   const double v = block_sum<kBlock / 64>(dz, sh);
@@ -1547,7 +1562,7 @@ static const char *kKernelNames[K_NUM] = {
     "vdown_coarse", "vup_fine", "vup_coarse", "chem_h", "ionized_sum",
     "warm_revert", "jacobi0_fine", "jacobi_fine", "jacobi_out",
     "jacobi_coarse", "prolong_add_fine", "prolong_add_coarse", "spmv_px",
-    "xfix", "warm_x", "tri_fine", "lmask", "local", "control", "copy_E"};
+    "xfix", "warm_x", "lmask", "local", "control", "copy_E"};
 
 namespace prof {
 struct Rec {
@@ -1715,9 +1730,6 @@ void launch_true_resid(const Tables &T, TileList L0, hipStream_t s) {
   if (L0.nblocks) LAUNCH(K_TRUE_RESID, k_true_resid, L0.nblocks, kBlock, s, T, L0);
 }
 
-void launch_tri_fine(const Tables &T, TileList L0, hipStream_t s) {
-  if (L0.nblocks) LAUNCH(K_TRI_FINE, k_tri_fine, L0.nblocks, kBlock, s, T, L0);
-}
 
 void launch_lmask(const Tables &T, TileList L0, double coupling, hipStream_t s) {
   if (L0.nblocks) LAUNCH(K_LMASK, k_lmask, L0.nblocks, kBlock, s, T, L0, coupling);

@@ -88,9 +88,8 @@ def test_workspace_sizing_and_validation(fld):
         f = fld.fld_default_params(1.0, 1.0, precision=prec)
         extra = fld.fld_workspace_bytes(g, f) - fld.fld_workspace_bytes(g, r)
         if prec == fld.FLD_PREC_MIXED:
-            # the second residual (FP64) and, since the cycle may go
-            # trilinear, the correction interpolated to the finest level (FP32)
-            assert 12 * 32 ** 3 <= extra <= 12 * 32 ** 3 + (1 << 12), prec
+            # the second residual (FP64)
+            assert 8 * 32 ** 3 <= extra <= 8 * 32 ** 3 + (1 << 12), prec
         else:
             assert extra == 0
 
