@@ -91,7 +91,9 @@ Hier make_hier(const fld_grid &g, const fld_params &p) {
 // cycle 2532, 2537, 2608, 2451; FP64 2203, 2268, 2308, 2217), 32 planes suit
 // a grid that still gives 512 tiles with them; smaller grids halve the depth
 // (down to 2 planes) until they do, since a handful of tiles marching 32
-// planes each leaves the GPU idle (64^3: 8 tiles).  Coarse levels that run
+// planes each leaves the GPU idle (64^3: 8 tiles).  A grid that gives 2048
+// tiles of 64 planes takes those (640^3, mixed, per PCG iteration: down pass
+// 2.74 -> 2.68 ms, up pass 2.36 -> 2.33 ms, fused-tile SpMV 4.21 -> 4.15 ms).  Coarse levels that run
 // the fused passes are 8x smaller and use 4 planes, so that they still give a
 // few tiles per CU (128^3 level of 256^3, Mcell-updates/s with 8 and 4
 // planes: FP32 cycle 2622, 2652; FP64 2367, 2383).
@@ -109,7 +111,8 @@ void fused_shape(const fld_params &p, int l, int nx, int ny, int nz, int &tx,
   }
   const long long xy = (long long)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
   tz = 32;
-  while (tz > 2 && xy * ((nz + tz - 1) / tz) < 512) tz >>= 1;
+  if (xy * ((nz + 63) / 64) >= 2048) tz = 64;
+  else while (tz > 2 && xy * ((nz + tz - 1) / tz) < 512) tz >>= 1;
   tz = std::min(tz, nz);
 }
 
@@ -118,6 +121,13 @@ int count_fused_tiles(const fld_params &p, int l, int nx, int ny, int nz) {
   fused_shape(p, l, nx, ny, nz, tx, ty, tz);
   return ((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz);
 }
+
+// The fused iteration's SpMV runs on the fused tiles (kSpRows rows per
+// thread, 64 x 16 cells a tile) for a problem whose fused finest tiling still
+// gives 2048 tiles; a smaller problem keeps the 64 x 4 tiles, whose one cell
+// per thread and plane leaves more workgroups to hide latency.  A property of
+// the problem alone, as the partial sums' order must be.
+bool spmv_on_fused(const Hier &h) { return h.ftiles[0] >= 2048; }
 
 bool fused_cycle(const fld_params &p) {
   return p.smoother == FLD_SMOOTH_RBGS && p.nu_pre == 1 && p.nu_post == 1;
@@ -239,9 +249,9 @@ static size_t tables_layout(Carver &cv, const std::vector<Hier> &hs,
     for (int l = 0; l < h.levels; ++l) ntiles += h.tiles[l] + h.ftiles[l];
     nfine += h.tiles[0] + h.ftiles[0];  // partial slots: both finest tilings
   }
-  // fine + kListsPerLevel lists per level: at most one range per problem
-  // and list, 2 ints each, kListSlots sets
-  nranges = (size_t)(kListsPerLevel * kMaxLevels + 1) * np * 2 * kListSlots;
+  // fine, the two SpMV lists and kListsPerLevel lists per level: at most
+  // one range per problem and list, 2 ints each, kListSlots sets
+  nranges = (size_t)(kListsPerLevel * kMaxLevels + 3) * np * 2 * kListSlots;
   LevelDev *lv = cv.take<LevelDev>((size_t)kMaxLevels * np);
   ProbDev *pd = cv.take<ProbDev>(np);
   StepDev *sd = cv.take<StepDev>(np);
@@ -388,6 +398,7 @@ int Engine::setup(const fld_params &p, hipStream_t s,
     h_pd[i].t1 = h_pd[i].t0 + hier[i].tiles[0];
     h_pd[i].f0 = fbeg[(size_t)i * kMaxLevels];
     h_pd[i].f1 = h_pd[i].f0 + hier[i].ftiles[0];
+    h_pd[i].spf = spmv_on_fused(hier[i]) ? 1 : 0;
     h_sc[i].phase = PH_DONE;
     h_sc[i].tol2 = prm.rtol * prm.rtol;
     h_sc[i].max_iter = prm.max_iter;
@@ -428,6 +439,8 @@ int Engine::build_lists(const std::vector<char> &member, int slot, ListSet &out)
   };
   auto make = [&](int level, auto pred) { return make_any(level, false, pred); };
   out.fine = make(0, [](int) { return true; });
+  out.spf = make_any(0, true, [&](int i) { return spmv_on_fused(hier[i]); });
+  out.spg = make(0, [&](int i) { return !spmv_on_fused(hier[i]); });
   for (int l = 0; l < kMaxLevels; ++l) {
     // per-level sweeps: every level above the tail (the single level of a
     // one-level hierarchy)
@@ -677,7 +690,8 @@ void Engine::enqueue_iteration(const ListSet &ls) {
   if (lazy) {
     enqueue_fused_rest(ls);
     launch_fin(T, FIN_RZ, mixed, stream, local_on() ? 2 : 1);
-    launch_spmv_p(T, ls.fine, 1, kmode(), stream);
+    launch_spmv_f(T, ls.spf, kmode(), stream);
+    launch_spmv_p(T, ls.spg, 1, kmode(), stream);
     launch_fin(T, FIN_PQ, mixed, stream, 1);
     launch_vdown(T, ls.fdn[0], 0, mixed, VD_CONT, stream);
     launch_fin(T, FIN_RR2, mixed, stream, 1);

@@ -48,6 +48,7 @@ void fused_shape(const fld_params &p, int l, int nx, int ny, int nz, int &tx,
 int count_fused_tiles(const fld_params &p, int l, int nx, int ny, int nz);
 bool fused_cycle(const fld_params &p);
 bool lazy_iteration(const fld_params &p);
+bool spmv_on_fused(const Hier &h);
 size_t problem_bytes(const Hier &h, const fld_params &p);
 size_t tables_bytes(const std::vector<Hier> &hs);
 
@@ -76,6 +77,7 @@ struct Job {
 // Launch lists of every kernel kind for one subset of the problems.
 struct ListSet {
   TileList fine{}, smooth[kMaxLevels]{}, exist[kMaxLevels]{};
+  TileList spf{}, spg{};        // fused-iteration SpMV: fused / standard tiles
   TileList fsm[kMaxLevels]{};   // fused tiles of smoothed levels
   TileList fdn[kMaxLevels]{};   // fused tiles of smoothed levels with a coarser one
   TileList down[kMaxLevels]{};  // levels restricted into from a per-level sweep

@@ -68,6 +68,7 @@ struct ProbDev {
   int levels;            // number of multigrid levels
   int t0, t1;            // range of this problem's tiles in the finest list
   int f0, f1;            // range of its fused-cycle finest tiles
+  int spf;               // the fused iteration's SpMV runs on the fused tiles
   int tail;              // first level of the single-workgroup V-cycle tail
   double *xb[3];         // the dE buffers (iterate and warm-start history)
   double *Ework;         // working copy of E while a step is subcycled
@@ -234,6 +235,9 @@ void launch_prolong_add(const Tables &T, TileList L, int l, int prec,
 // form with FP32 z and an FP64 search direction p
 // lazy = 1 (fused iteration): also x += alpha p_old, the update deferred
 // from the previous iteration (mixed forms only)
+// the fused iteration's SpMV (x += alpha p_old, p = z + beta p_old, q = A p)
+// on the finest fused tiles; its partials sum over the fused range
+void launch_spmv_f(const Tables &T, TileList F0, int km, hipStream_t s);
 void launch_spmv_p(const Tables &T, TileList L0, int lazy, int km, hipStream_t s);
 // out = s * z32 right after a mixed-form V-cycle (the preconditioner alone)
 void launch_z_out(const Tables &T, TileList L0, double *out, hipStream_t s);

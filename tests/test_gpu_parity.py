@@ -272,6 +272,38 @@ def test_subcycling_matches_oracle_substeps(fld, oracle_mod):
     assert rel_l2(host(E), En) <= 1e-6
 
 
+@pytest.mark.parametrize("d64", [1, 0])
+def test_fused_tile_spmv_ragged(fld, oracle_mod, d64):
+    """The fused iteration's SpMV on the fused tiles (4 rows per thread): a
+    ragged 96 x 194 x 320 grid (a 32-wide x tile, a 2-row y tile) with
+    4-plane fused tiles gives 2080 of them, enough for that SpMV; with
+    32-plane tiles (260) the same solve takes the 64 x 4 tiles.  Both meet the
+    gates against the oracle's residual at every cell, and the two solutions
+    differ by no more than their residual norms allow."""
+    log_case("fused_tile_spmv", d64=d64)
+    p = _problem((320, 194, 96), 29, dt_factor=0.05)
+    cells = np.arange(320 * 194 * 96, dtype=np.int64)
+    sols, rnorm = [], []
+    for ftz in (4, 32):
+        S, prm = _solver(fld, p, precision=1, direction_fp64=d64, fused_tile_z=ftz)
+        _assemble(S, p)
+        dE, st = S.solve()
+        dEh = host(dE)
+        O = oracle_problem(oracle_mod, p, prm)
+        res, rhs = O.residual_at(dEh, cells)
+        true_rel = np.linalg.norm(res) / np.linalg.norm(rhs)
+        bound = np.linalg.norm(res) / np.linalg.norm(dEh)
+        print(f"[fused_tile_spmv ftz={ftz} d64={d64}] iters={st['iters']} "
+              f"true_rel={true_rel:.3e} err_bound={bound:.3e}", flush=True)
+        assert st["status"] == 0
+        assert true_rel <= prm.rtol * (1 + 1e-6)
+        assert bound <= GATE[1]
+        sols.append(dEh)
+        rnorm.append(np.linalg.norm(res))
+    # each within ||r|| of the exact solution (||A^-1|| <= 1)
+    assert np.linalg.norm(sols[0] - sols[1]) <= (rnorm[0] + rnorm[1]) * (1 + 1e-6)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_full_size_many_sources_residual(fld, oracle_mod, prec):
     """256^3, 64 sources (the benchmark workload), two successive steps in the
