@@ -93,16 +93,23 @@ Hier make_hier(const fld_grid &g, const fld_params &p) {
 // (down to 2 planes) until they do, since a handful of tiles marching 32
 // planes each leaves the GPU idle (64^3: 8 tiles).  A grid that gives 2048
 // tiles of 64 planes takes those (640^3, mixed, per PCG iteration: down pass
-// 2.74 -> 2.68 ms, up pass 2.36 -> 2.33 ms, fused-tile SpMV 4.21 -> 4.15 ms).  Coarse levels that run
-// the fused passes are 8x smaller and use 4 planes, so that they still give a
-// few tiles per CU (128^3 level of 256^3, Mcell-updates/s with 8 and 4
-// planes: FP32 cycle 2622, 2652; FP64 2367, 2383).
+// 2.74 -> 2.68 ms, up pass 2.36 -> 2.33 ms, fused-tile SpMV 4.21 -> 4.15 ms).
+// Coarse levels that run the fused passes are 8x smaller and use 4 planes
+// where that is needed for a few tiles per CU (128^3 level of 256^3,
+// Mcell-updates/s with 8 and 4 planes: FP32 cycle 2622, 2652; FP64 2367,
+// 2383); a coarse level that still
+// gives 512 tiles of 16 (or 8) planes takes those, for less z-halo (the
+// 320^3 and 160^3 levels of 640^3, mixed, per PCG iteration: coarse up
+// passes 0.38 -> 0.31 ms, down passes 0.32 -> 0.26 ms).
 void fused_shape(const fld_params &p, int l, int nx, int ny, int nz, int &tx,
                  int &ty, int &tz) {
   tx = std::min(nx, 64);
   ty = std::min(ny, 16);
   if (l > 0) {
-    tz = std::min(nz, 4);
+    const long long cxy = (long long)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
+    tz = 16;
+    while (tz > 4 && cxy * ((nz + tz - 1) / tz) < 512) tz >>= 1;
+    tz = std::min(nz, tz);
     return;
   }
   if (p.fused_tile_z > 0) {
