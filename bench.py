@@ -210,19 +210,25 @@ def measured_traffic(kernel, form, workload=None, root=ROOT):
 
 # rocprofv3 kernel names of the finest-level kernels, by (bench name, form)
 PMC_KERNELS = {
-    ("spmv_px", "mixed_dir64"): "fld::k_spmv_p<true, 2>",
-    ("spmv_px", "mixed"): "fld::k_spmv_p<true, 1>",
+    # the fused iteration's SpMV: on the fused tiles where a grid gives 2048
+    # of them, else on the 64 x 4 tiles (the first name that ran is taken)
+    ("spmv_px", "mixed_dir64"): ("fld::k_spmv_f<true, 2>", "fld::k_spmv_p<true, 2>"),
+    ("spmv_px", "mixed"): ("fld::k_spmv_f<true, 1>", "fld::k_spmv_p<true, 1>"),
     ("spmv_p", "fp64"): "fld::k_spmv_p<false, 0>",
     ("vup_fine", "mixed"): "fld::k_vup<float, true, false>",
+    ("vup_fine", "mixed_tri"): "fld::k_vup<float, true, true>",
     ("vup_fine", "fp64"): "fld::k_vup<double, true, false>",
     ("vdown_fine", "mixed"): "fld::k_vdown<float, true>",
     ("vdown_fine", "fp64"): "fld::k_vdown<double, true>",
     ("update", "fp64"): "fld::k_update<0>",
     ("true_resid", "any"): "fld::k_true_resid",
     ("assemble", "any"): "fld::k_assemble",
+    ("local", "mixed"): "fld::k_local",
+    ("lmask", "mixed"): "fld::k_lmask",
 }
 PMC_SOURCES = {
-    "fld_kernels.hip": ("spmv_px", "spmv_p", "update", "true_resid", "assemble"),
+    "fld_kernels.hip": ("spmv_px", "spmv_p", "update", "true_resid", "assemble", "local",
+                        "lmask"),
     "fld_fused.hip": ("vup_fine", "vdown_fine"),
 }
 
@@ -259,8 +265,11 @@ def traffic_records(pmc_dir, workload, root=ROOT):
             return hashlib.sha256(f.read()).hexdigest()
 
     lines = []
-    for (kernel, form), name in PMC_KERNELS.items():
-        fa, wa = avg("FETCH_SIZE", name), avg("WRITE_SIZE", name)
+    for (kernel, form), names in PMC_KERNELS.items():
+        for name in (names if isinstance(names, tuple) else (names,)):
+            fa, wa = avg("FETCH_SIZE", name), avg("WRITE_SIZE", name)
+            if fa is not None and wa is not None:
+                break
         if fa is None or wa is None:
             continue
         src = next(f for f, ks in PMC_SOURCES.items() if kernel in ks)
@@ -700,15 +709,20 @@ def secondary(fld, torch, synth, args):
     return res
 
 
+def copy_probe(torch):
+    """Calibration kernel of the byte-counter runs: y = x + 0 over 2^28
+    doubles, one kernel reading 2 GiB and writing 2 GiB."""
+    x = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+    y = x.add(0.0)
+    torch.cuda.synchronize()
+    del x, y
+
+
 def headline(args, fld, torch, synth):
     n = args.n or 640
     steps = args.steps or 20
     if args.copy_probe:
-        # y = x + 0 over 2^28 doubles: one kernel reading 2 GiB and writing 2 GiB
-        x = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
-        y = x.add(0.0)
-        torch.cuda.synchronize()
-        del x, y
+        copy_probe(torch)
     log(f"[bench] generating the {n}^3 reionization share on the GPU")
     t0 = time.perf_counter()
     p = synth.t_reionization_share(n=n, n_src=int(round(10000 * (n / 640) ** 3)),

@@ -121,6 +121,8 @@ def many_sources(args, fld, torch, synth, log):
     form's extra step checked by the oracle at every cell."""
     import bench
     n = args.n
+    if args.copy_probe:
+        bench.copy_probe(torch)
     log(f"[bench] generating the {n}^3 many-source workload")
     p = synth.many_sources(n)
     q = dict(p)

@@ -260,8 +260,8 @@ def test_vcycle_variants_are_the_textbook_cycle(fld, oracle_mod, prec, levels,
                                                 fused_levels, prolongation,
                                                 coarse_op, local):
     """The mixed V(1,1) cycle with the trilinear correction (the fused finest
-    passes with the interpolated correction of k_tri_fine, the coarse fused or
-    per-half-sweep kernels and the tail), the series coarse-face rule and
+    and coarse up passes interpolating it from the coarse planes they stage,
+    the per-half-sweep kernels and the tail), the series coarse-face rule and
     the local sweeps over the strongly coupled cells: the same textbook cycle
     with those definitions.  A longer step than the other cycle tests and a
     lower mask threshold than the default, so that about 6 % of the cells
