@@ -624,11 +624,15 @@ __global__ __launch_bounds__(kBlock, 3) void k_vup(Tables T, TileList TL, int l,
   CStage<R> cv;
   if constexpr (TRI) {
     if (has_coarse) {
+      // the first three planes: all loads in flight before the first store
       cstage_init(cv, t, cnx, cny);
-      for (int c = 0; c < 3; ++c) {
-        cstage_load(cv, e, cbase + c, cnx, cny, cnz);
-        cstage_store(cv, cs[c]);
-      }
+      CStage<R> c1 = cv, c2 = cv;
+      cstage_load(cv, e, cbase, cnx, cny, cnz);
+      cstage_load(c1, e, cbase + 1, cnx, cny, cnz);
+      cstage_load(c2, e, cbase + 2, cnx, cny, cnz);
+      cstage_store(cv, cs[0]);
+      cstage_store(c1, cs[1]);
+      cstage_store(c2, cs[2]);
       __syncthreads();
     }
   }

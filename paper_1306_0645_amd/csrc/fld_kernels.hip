@@ -882,13 +882,18 @@ __global__ __launch_bounds__(kBlock) void k_spmv_p(Tables T, TileList TL) {
 // each thread takes kSpRows consecutive rows of one column and walks z, so
 // the y neighbours inside its rows come from registers and only the rows
 // just below and above are loaded (2 of 16 rows, against 2 of 4 for the
-// 64 x 4 tiles), as are the z neighbours (2 planes per tile).  Per cell the
+// 64 x 4 tiles), as are the z neighbours (2 planes per tile).  The x
+// neighbours come from the adjacent lanes (a wave is one 64-cell row
+// segment); only the lanes at the tile's x edges load theirs.  Nothing is
+// read twice: a plane's direction and z were loaded one plane earlier and
+// are held, where reading them again a plane later would miss the L2, which
+// holds less than one plane of all the resident tiles.  Per cell the
 // arithmetic is spmv_column's, term by term, so q and p are the same.
 constexpr int kSpRows = 4;
 
 template <bool BETA, bool LAZY, int KM>
 __device__ __forceinline__ double spmv_rows(
-    const Tile &t, int i, int j0, int nr, int nx, int ny, int nz, double beta,
+    const Tile &t, int lx, int i, int j0, int nr, int nx, int ny, int nz, double beta,
     const ZT<KM> *__restrict__ z, double zs, const DirT<KM> *__restrict__ po,
     double ps, DirT<KM> *__restrict__ pn, double *__restrict__ q,
     const double *__restrict__ Tx, const double *__restrict__ Ty,
@@ -896,30 +901,34 @@ __device__ __forceinline__ double spmv_rows(
     double *__restrict__ x) {
   using D = DirT<KM>;
   const double cb = KM == KM_MIX32 ? beta * ps / zs : beta;
-  auto raw = [&](int g) -> D {
+  // p_new as stored, from z and p_old at a cell
+  auto mk = [&](ZT<KM> zv, D pv) -> D {
     if constexpr (KM == KM_MIX32)
-      return BETA ? (float)((double)z[g] + cb * (double)po[g]) : z[g];
+      return BETA ? (float)((double)zv + cb * (double)pv) : zv;
     else if constexpr (KM == KM_MIX64)
-      return BETA ? zs * (double)z[g] + beta * po[g] : zs * (double)z[g];
-    else return BETA ? z[g] + beta * po[g] : z[g];
+      return BETA ? zs * (double)zv + beta * pv : zs * (double)zv;
+    else return BETA ? zv + beta * pv : zv;
   };
+  auto raw = [&](int g) -> D { return mk(z[g], BETA ? po[g] : (D)0); };
   auto val = [&](D v) -> double {
     if constexpr (KM == KM_MIX32) return zs * (double)v;
     else return v;
   };
   const int plane = nx * ny;
   const int dxm = (i == 0) ? nx - 1 : -1, dxp = (i == nx - 1) ? 1 - nx : 1;
+  const bool ledge = lx == 0, redge = lx == t.tx - 1;
   const int rlo = (j0 == 0 ? ny - 1 : j0 - 1) * nx;        // the row below
   const int rhi = (j0 + nr == ny ? 0 : j0 + nr) * nx;      // the row above
   const int km0 = t.z0 == 0 ? nz - 1 : t.z0 - 1;
-  D pm[kSpRows], pc[kSpRows];
+  D pm[kSpRows], pc[kSpRows], oc[kSpRows];  // p_new at k - 1, k; p_old at k
   double tzm[kSpRows];
 #pragma unroll
   for (int r = 0; r < kSpRows; ++r) {
     if (r < nr) {
-      const int o = (j0 + r) * nx + i;
+      const int o = (j0 + r) * nx + i, c = t.z0 * plane + o;
       pm[r] = raw(km0 * plane + o);
-      pc[r] = raw(t.z0 * plane + o);
+      oc[r] = BETA ? po[c] : (D)0;
+      pc[r] = mk(z[c], oc[r]);
       tzm[r] = Tz[km0 * plane + o];
     }
   }
@@ -927,27 +936,34 @@ __device__ __forceinline__ double spmv_rows(
   for (int k = t.z0; k < t.z0 + t.tz; ++k) {
     const int kp = (k == nz - 1) ? 0 : k + 1;
     const int b = k * plane + i;
-    D pp[kSpRows];
+    D pp[kSpRows], op[kSpRows];
 #pragma unroll
-    for (int r = 0; r < kSpRows; ++r)
-      if (r < nr) pp[r] = raw(kp * plane + (j0 + r) * nx + i);
+    for (int r = 0; r < kSpRows; ++r) {
+      if (r < nr) {
+        const int g = kp * plane + (j0 + r) * nx + i;
+        op[r] = BETA ? po[g] : (D)0;
+        pp[r] = mk(z[g], op[r]);
+      }
+    }
     const D plo = raw(b + rlo), phi = raw(b + rhi);
     double tyd = Ty[b + rlo];  // the -y face of the next row
 #pragma unroll
     for (int r = 0; r < kSpRows; ++r) {
       if (r < nr) {
         const int c = b + (j0 + r) * nx;
+        D xl = __shfl_up(pc[r], 1, 64), xr = __shfl_down(pc[r], 1, 64);
+        if (ledge) xl = raw(c + dxm);
+        if (redge) xr = raw(c + dxp);
         const D dn = r == 0 ? plo : pc[r > 0 ? r - 1 : 0];
         const D up = r + 1 == nr ? phi : pc[r + 1 < kSpRows ? r + 1 : r];
         const double tyc = Ty[c];
-        const double sm = Tx[c] * val(raw(c + dxp)) + Tx[c + dxm] * val(raw(c + dxm)) +
-                          tyc * val(up) + tyd * val(dn) + Tz[c] * val(pp[r]) +
-                          tzm[r] * val(pm[r]);
+        const double sm = Tx[c] * val(xr) + Tx[c + dxm] * val(xl) + tyc * val(up) +
+                          tyd * val(dn) + Tz[c] * val(pp[r]) + tzm[r] * val(pm[r]);
         const double p_c = val(pc[r]);
         const double qq = Dg[c] * p_c - sm;
         if constexpr (LAZY) {
-          if constexpr (KM == KM_MIX32) x[c] = x[c] + alpha_old * (ps * (double)po[c]);
-          else x[c] = x[c] + alpha_old * po[c];
+          if constexpr (KM == KM_MIX32) x[c] = x[c] + alpha_old * (ps * (double)oc[r]);
+          else x[c] = x[c] + alpha_old * oc[r];
         }
         pn[c] = pc[r];
         q[c] = qq;
@@ -961,6 +977,7 @@ __device__ __forceinline__ double spmv_rows(
       if (r < nr) {
         pm[r] = pc[r];
         pc[r] = pp[r];
+        oc[r] = op[r];
       }
     }
   }
@@ -995,14 +1012,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv_f(Tables T, TileList TL) {
   if (lx < t.tx && nr > 0) {
     const int i = t.x0 + lx, j0 = t.y0 + kSpRows * g;
     if (LAZY && sc.xlag)
-      pq = spmv_rows<true, true, KM>(t, i, j0, nr, L.nx, L.ny, L.nz, beta, z, zs, po, ps,
-                                     pn, P.q, L.Tx, L.Ty, L.Tz, L.diag, alpha, P.x);
+      pq = spmv_rows<true, true, KM>(t, lx, i, j0, nr, L.nx, L.ny, L.nz, beta, z, zs, po,
+                                     ps, pn, P.q, L.Tx, L.Ty, L.Tz, L.diag, alpha, P.x);
     else if (beta != 0.0)
-      pq = spmv_rows<true, false, KM>(t, i, j0, nr, L.nx, L.ny, L.nz, beta, z, zs, po,
+      pq = spmv_rows<true, false, KM>(t, lx, i, j0, nr, L.nx, L.ny, L.nz, beta, z, zs, po,
                                       ps, pn, P.q, L.Tx, L.Ty, L.Tz, L.diag, 0.0, P.x);
     else
-      pq = spmv_rows<false, false, KM>(t, i, j0, nr, L.nx, L.ny, L.nz, beta, z, zs, po,
-                                       ps, pn, P.q, L.Tx, L.Ty, L.Tz, L.diag, 0.0, P.x);
+      pq = spmv_rows<false, false, KM>(t, lx, i, j0, nr, L.nx, L.ny, L.nz, beta, z, zs,
+                                       po, ps, pn, P.q, L.Tx, L.Ty, L.Tz, L.diag, 0.0, P.x);
   }
   write_partials(T, tid, pq, 0.0);
 }
@@ -1254,68 +1271,45 @@ __global__ __launch_bounds__(kBlock) void k_lmask(Tables T, TileList TL,
   }
 }
 
-// k_local: most tiles list no cell, and a listed tile holds a few dozen, so
-// one workgroup per tile would spend the launch on empty workgroups.  Each
-// wave instead takes kLocalTiles consecutive tiles of the list, one after
-// the other: the tile's count (the same address for every lane), then its
-// cells in rounds of 64, the tile's r.z change summed over the wave.
-constexpr int kLocalTiles = 8;
-
-// the tile of list position v (v < TL.nblocks), as get_tile_index maps a
-// workgroup
-__device__ __forceinline__ int list_tile(const TileList &L, int v) {
-  int lo = 0;
-  if (L.nranges > 1) {
-    int hi = L.nranges - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (L.ranges[2 * mid] <= v) lo = mid; else hi = mid - 1;
-    }
-  }
-  return L.ranges[2 * lo + 1] + (v - L.ranges[2 * lo]);
-}
-
 __global__ __launch_bounds__(kBlock) void k_local(Tables T, TileList TL, int colour) {
-  const int lane = threadIdx.x & 63;
-  const int v0 = (blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * kLocalTiles;
-  for (int v = v0; v < v0 + kLocalTiles && v < TL.nblocks; ++v) {
-    const int tid = list_tile(TL, v);
-    const Tile t = TL.base[tid];
-    const Scal &sc = T.sc[t.prob];
-    if (!sc.active) continue;
-    const ProbDev &P = T.pd[t.prob];
-    // the counts come from k_lmask; bounded by the tile's box all the same, so
-    // that no read of the list can leave the tile's own cells
-    const int u = tid - P.t0, box = t.tx * t.ty * t.tz;
-    const int first = colour ? min(max(P.lcnt[2 * u], 0), box) : 0;
-    const int cnt = min(max(P.lcnt[2 * u + colour], 0), box - first);
-    double dz = 0.0;
-    if (cnt > 0) {
-      const LevelDev &L = T.lv[t.prob];
-      const Coef<float> C = coefs<float>(L);
-      const double *r = rcur(P, sc);
-      const double inv_s = sc.inv_s, s = sc.s;
-      float *z = P.z32;
-      const int *llist = P.llist;
-      const int nx = L.nx, ny = L.ny, nz = L.nz, plane = nx * ny;
-      for (int q = lane; q < cnt; q += 64) {
-        const int c = llist[box_cell(t, first + q, nx, ny)];
-        if ((unsigned)c >= (unsigned)(plane * nz)) continue;  // not a cell
-        const int k = c / plane, rm = c - k * plane, j = rm / nx;
-        const Nb n = nbrs(rm - j * nx, j, k, nx, ny, nz);
-        const float f = (float)(r[n.c] * inv_s);
-        const float sum = C.tx[n.c] * z[n.xp] + C.tx[n.xm] * z[n.xm] +
-                          C.ty[n.c] * z[n.yp] + C.ty[n.ym] * z[n.ym] +
-                          C.tz[n.c] * z[n.zp] + C.tz[n.zm] * z[n.zm];
-        const float xn = (f + sum) * recip(C.d[n.c]);
-        const float xo = z[n.c];
-        z[n.c] = xn;
-        dz += r[n.c] * (s * ((double)xn - (double)xo));
-      }
-      dz = wave_sum(dz);
-    }
-    if (lane == 0) T.lpart[2 * tid + colour] = dz;
+  const int tid = get_tile_index(TL);
+  const Tile t = TL.base[tid];
+  const Scal &sc = T.sc[t.prob];
+  if (!sc.active) return;
+  const ProbDev P = T.pd[t.prob];
+  // the counts come from k_lmask; bounded by the tile's box all the same, so
+  // that no read of the list can leave the tile's own cells
+  const int u = tid - P.t0, box = t.tx * t.ty * t.tz;
+  const int first = colour ? min(max(P.lcnt[2 * u], 0), box) : 0;
+  const int cnt = min(max(P.lcnt[2 * u + colour], 0), box - first);
+  if (cnt == 0) {
+    if (threadIdx.x == 0) T.lpart[2 * tid + colour] = 0.0;
+    return;
   }
+  const LevelDev L = T.lv[t.prob];
+  const Coef<float> C = coefs<float>(L);
+  const double *r = rcur(P, sc);
+  const double inv_s = sc.inv_s, s = sc.s;
+  float *z = P.z32;
+  const int plane = L.nx * L.ny;
+  double dz = 0.0;
+  for (int q = threadIdx.x; q < cnt; q += kBlock) {
+    const int c = P.llist[box_cell(t, first + q, L.nx, L.ny)];
+    if ((unsigned)c >= (unsigned)(plane * L.nz)) continue;  // not a cell
+    const int k = c / plane, rm = c - k * plane, j = rm / L.nx;
+    const Nb n = nbrs(rm - j * L.nx, j, k, L.nx, L.ny, L.nz);
+    const float f = (float)(r[n.c] * inv_s);
+    const float sum = C.tx[n.c] * z[n.xp] + C.tx[n.xm] * z[n.xm] +
+                      C.ty[n.c] * z[n.yp] + C.ty[n.ym] * z[n.ym] +
+                      C.tz[n.c] * z[n.zp] + C.tz[n.zm] * z[n.zm];
+    const float xn = (f + sum) * recip(C.d[n.c]);
+    const float xo = z[n.c];
+    z[n.c] = xn;
+    dz += r[n.c] * (s * ((double)xn - (double)xo));
+  }
+  __shared__ double sh[kBlock / 64];
+  const double v = block_sum<kBlock / 64>(dz, sh);
+  if (threadIdx.x == 0) T.lpart[2 * tid + colour] = v;
 }
 
 // Warm-started problems whose guess was dropped (by FIN_BB or FIN_WARM: it
@@ -1897,10 +1891,7 @@ void launch_lmask(const Tables &T, TileList L0, double coupling, hipStream_t s) 
 }
 
 void launch_local(const Tables &T, TileList L0, int colour, hipStream_t s) {
-  constexpr int per_block = (kBlock / 64) * kLocalTiles;
-  if (L0.nblocks)
-    LAUNCH(K_LOCAL, k_local, (L0.nblocks + per_block - 1) / per_block, kBlock, s, T, L0,
-           colour);
+  if (L0.nblocks) LAUNCH(K_LOCAL, k_local, L0.nblocks, kBlock, s, T, L0, colour);
 }
 
 void launch_warm_x(const Tables &T, TileList L0, hipStream_t s) {
