@@ -56,6 +56,34 @@ def test_batch_equals_single_and_oracle(fld, oracle_mod, prec, smoother):
         assert rel_l2(host(E), p["E"] + dEo) <= (1e-6 if prec == 0 else 1e-5)
 
 
+def test_batch_mixes_fused_tile_and_standard_spmv(fld):
+    """A batch whose problems take different SpMV tilings in the fused mixed
+    iteration: a ragged 96 x 194 x 320 grid with 4-plane fused tiles (2080 of
+    them: the fused-tile SpMV) beside two small grids (the 64 x 4 tiles).
+    Each problem's partial sums are gathered over its own tiling, so every
+    problem stays bit-identical to its single handle."""
+    log_case("batch_spmv_tilings")
+    shapes = [(320, 194, 96), (32, 32, 32), (24, 40, 48)]
+    ps = [synth.random_problem(sh, 90 + i, sigma_ln=1.0, n_src=2, dt_factor=0.05)
+          for i, sh in enumerate(shapes)]
+    prm = params(fld, ps[0], precision=1, cycle_switch=0, fused_tile_z=4)
+    singles = []
+    for p in ps:
+        S = fld.Solver(p["shape"], p["h"], prm)
+        E = dev(p["E"])
+        st = S.step(E, dev(p["kappa"]), dev(p["eta"]), p["dt"])
+        assert st["status"] == 0
+        singles.append((host(E), st))
+    B = fld.Batch([p["shape"] for p in ps], [p["h"] for p in ps], prm)
+    Es = [dev(p["E"]) for p in ps]
+    sts = B.step(Es, [dev(p["kappa"]) for p in ps], [dev(p["eta"]) for p in ps],
+                 [p["dt"] for p in ps])
+    for E, st, (Es1, st1) in zip(Es, sts, singles):
+        assert st["status"] == 0
+        assert st["iters"] == st1["iters"]
+        assert np.array_equal(host(E), Es1)
+
+
 @pytest.mark.parametrize("warm", [1, 2])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_batch_warm_steps_equal_single(fld, oracle_mod, prec, warm):
