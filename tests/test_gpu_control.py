@@ -66,6 +66,33 @@ def test_advance_equals_host_steps(fld, oracle_mod, prec, warm):
     assert rel_l2(host(Ed), En) <= GATE[prec]
 
 
+def test_advance_on_the_fused_tile_spmv(fld):
+    """Device control on a grid whose fused iteration runs the fused-tile SpMV
+    (ragged 96 x 194 x 320, 4-plane fused tiles: 2080 of them), with the
+    cycle switch and the local sweeps on: three steps equal three fld_step
+    calls bit for bit."""
+    log_case("advance_spmv_f")
+    p = _problem((320, 194, 96), 84, dtf=0.05)
+    prm = params(fld, p, precision=1, fused_tile_z=4)
+    kap, eta = dev(p["kappa"]), dev(p["eta"])
+    H = fld.Solver(p["shape"], p["h"], prm)
+    Eh = dev(p["E"])
+    its = 0
+    for _ in range(3):
+        st = H.step(Eh, kap, eta, p["dt"])
+        assert st["status"] == 0
+        its += st["iters"]
+    H.close()
+    D = fld.Solver(p["shape"], p["h"], prm)
+    Ed = dev(p["E"])
+    sd = D.advance(Ed, kap, eta, p["dt"], n_steps=3, units=5)
+    D.close()
+    print(f"[advance spmv_f] iters host={its} device={sd['iters']}", flush=True)
+    assert sd["status"] == 0 and sd["steps"] == 3
+    assert sd["iters"] == its
+    assert np.array_equal(host(Ed), host(Eh))
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_advance_subcycles_like_the_host(fld, prec):
     """Solves capped at a few iterations fail at the full step: both drivers
