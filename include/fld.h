@@ -117,7 +117,10 @@ typedef struct fld_params {
   int32_t use_graph;   /* 1 (default) = replay the PCG iteration from a captured
                           hipGraph; 0 = launch its kernels one by one */
   int32_t fused_tile_z;/* z-depth of the fused finest-level V-cycle tiles (even);
-                          0 = automatic */
+                          0 = automatic (64 planes where 2048 such tiles
+                          remain, else 32 halved until 512 remain).  A grid
+                          with 2048 fused finest tiles also runs the mixed
+                          fused iteration's SpMV on them */
   int32_t cycle_switch;/* > 0 and nu_pre = nu_post = 1: when a solve needs
                           more PCG iterations than this, later solves of the
                           handle switch cycle, until one needs at most a
@@ -179,8 +182,9 @@ typedef struct fld_params {
                           finest post-sweep, this many more red/black sweeps
                           (black, then red) restricted to the finest cells
                           whose coupling dominates their diagonal (sum of the
-                          6 faces > local_coupling x diagonal, marked at each
-                          assembly): in ionized bubbles, where absorption is
+                          6 faces > local_coupling x diagonal, listed at each
+                          assembly; the lists take 4 B per finest cell of the
+                          workspace): in ionized bubbles, where absorption is
                           weak and D reaches D_max, one sweep leaves the error
                           that is smooth inside the bubble and the coarse
                           levels miss it.  0 = none.  Default 1 */
